@@ -1,0 +1,157 @@
+"""Python access to the CPU oracle (bdref.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and
+the benchmark's CPU-baseline leg, never by the library.  The oracle shares no
+code with the GPU path; this module only marshals numpy arrays into the C
+functions declared in bdref.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bdref.c")
+_LIB_PATH = os.path.join(_HERE, "libbdref.so")
+
+KEYPOINT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("scale", "<f4"), ("angle", "<f4")])
+BOX_PAIR_DTYPE = np.dtype([("x1", "i1"), ("y1", "i1"), ("x2", "i1"), ("y2", "i1"),
+                           ("radius", "u1"), ("pad", "u1", (3,)), ("threshold", "<f4")])
+
+
+def build() -> str:
+    """Compile bdref.c with plain IEEE FP64 semantics (no contraction, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-Wextra", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        L.bdref_build_integral.argtypes = [P, i32, i32, i64, P, i64]
+        L.bdref_build_integral.restype = None
+        L.bdref_describe_bad.argtypes = [P, i32, i32, i64, P, i32, P, i32, P]
+        L.bdref_describe_bad.restype = i64
+        L.bdref_hashsift_hist.argtypes = [P, i32, i32, i32, i64, P, i32, P]
+        L.bdref_hashsift_hist.restype = None
+        L.bdref_hashsift_project.argtypes = [P, i32, P, P, i32, P, P, P]
+        L.bdref_hashsift_project.restype = None
+        L.bdref_keypoint_valid.argtypes = [P]
+        L.bdref_keypoint_valid.restype = i32
+        L.bdref_match_knn.argtypes = [P, i32, P, i32, i32, i32, P, P]
+        L.bdref_match_knn.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _as_keypoints(kp) -> np.ndarray:
+    kp = np.ascontiguousarray(kp)
+    if kp.dtype != KEYPOINT_DTYPE:
+        kp = np.ascontiguousarray(np.asarray(kp, dtype=np.float32).reshape(-1, 4)).view(KEYPOINT_DTYPE).reshape(-1)
+    return kp
+
+
+def _as_pairs(pairs) -> np.ndarray:
+    pairs = np.ascontiguousarray(pairs)
+    assert pairs.dtype.itemsize == 12
+    return pairs
+
+
+def build_integral(img: np.ndarray) -> np.ndarray:
+    """(H, W) u8 -> (H+1, W+1) u32 integral image."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    ii = np.empty((H + 1, W + 1), dtype=np.uint32)
+    lib().bdref_build_integral(_ptr(img), W, H, W, _ptr(ii), W + 1)
+    return ii
+
+
+def describe_bad(ii: np.ndarray, kps, pairs, n_bits: int | None = None):
+    """BAD codes from an integral image.  Returns (codes (n, n_bits/64) u64, near_tie_count)."""
+    ii = np.ascontiguousarray(ii, dtype=np.uint32)
+    kp = _as_keypoints(kps)
+    pr = _as_pairs(pairs)
+    n_bits = len(pr) if n_bits is None else n_bits
+    assert n_bits % 64 == 0 and len(pr) >= n_bits
+    H, W = ii.shape[0] - 1, ii.shape[1] - 1
+    codes = np.zeros((len(kp), n_bits // 64), dtype=np.uint64)
+    ties = lib().bdref_describe_bad(_ptr(ii), W, H, ii.shape[1], _ptr(kp), len(kp), _ptr(pr),
+                                    n_bits, _ptr(codes))
+    return codes, int(ties)
+
+
+def hashsift_hist(img: np.ndarray, kps) -> np.ndarray:
+    """(n, 128) FP64 L2-normalized 4x4x8 histograms; img is u8 or f32 (H, W)."""
+    img = np.ascontiguousarray(img)
+    if img.dtype == np.uint8:
+        dtype = 0
+    elif img.dtype == np.float32:
+        dtype = 1
+    else:
+        raise TypeError("image must be uint8 or float32")
+    kp = _as_keypoints(kps)
+    H, W = img.shape
+    hist = np.zeros((len(kp), 128), dtype=np.float64)
+    lib().bdref_hashsift_hist(_ptr(img), dtype, W, H, img.strides[0], _ptr(kp), len(kp), _ptr(hist))
+    return hist
+
+
+def keypoint_valid(kps) -> np.ndarray:
+    kp = _as_keypoints(kps)
+    L = lib()
+    return np.array([L.bdref_keypoint_valid(_ptr(kp[i:i + 1])) for i in range(len(kp))], dtype=np.uint8)
+
+
+def hashsift_project(hist: np.ndarray, B: np.ndarray, t: np.ndarray, valid=None):
+    """Responses r = B f - t (FP64) and codes (bit set when r > 0)."""
+    hist = np.ascontiguousarray(hist, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    n_bits = B.shape[0]
+    assert B.shape[1] == 128 and t.shape == (n_bits,) and n_bits % 64 == 0
+    n = hist.shape[0]
+    resp = np.zeros((n, n_bits), dtype=np.float64)
+    codes = np.zeros((n, n_bits // 64), dtype=np.uint64)
+    vptr = None
+    if valid is not None:
+        valid = np.ascontiguousarray(valid, dtype=np.uint8)
+        vptr = _ptr(valid)
+    lib().bdref_hashsift_project(_ptr(hist), n, _ptr(B), _ptr(t), n_bits, vptr, _ptr(resp), _ptr(codes))
+    return resp, codes
+
+
+def describe_hashsift(img: np.ndarray, kps, B: np.ndarray, t: np.ndarray):
+    """Histogram, responses and codes of the HashSIFT descriptor."""
+    hist = hashsift_hist(img, kps)
+    resp, codes = hashsift_project(hist, B, t, keypoint_valid(kps))
+    return hist, resp, codes
+
+
+def match_knn(query: np.ndarray, train: np.ndarray, k: int):
+    """Brute-force Hamming k-NN; returns (idx (n_q, k) i32, dist (n_q, k) u32)."""
+    q = np.ascontiguousarray(query, dtype=np.uint64)
+    t = np.ascontiguousarray(train, dtype=np.uint64)
+    n_words = q.shape[1]
+    assert t.shape[1] == n_words
+    idx = np.empty((q.shape[0], k), dtype=np.int32)
+    dist = np.empty((q.shape[0], k), dtype=np.uint32)
+    lib().bdref_match_knn(_ptr(q), q.shape[0], _ptr(t), t.shape[0], n_words, k, _ptr(idx), _ptr(dist))
+    return idx, dist

@@ -1,0 +1,317 @@
+/*
+ * bdref.c -- plain CPU oracle (TEST INFRASTRUCTURE ONLY; see bdref.h).
+ *
+ * Each function writes out the definition it follows as directly as
+ * possible.  Floating point is FP64 throughout and is compiled without
+ * contraction (-ffp-contract=off), so every rounding step is a plain IEEE
+ * operation in the order written here.
+ *
+ * Readings where the paper is silent (pixel grid, rounding of box centres,
+ * image-border policy, histogram layout) are stated at each function.
+ */
+#include "bdref.h"
+
+#include <math.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ integral image */
+
+/* Sec. III-A: box averages come from an integral image.  Reading: the integral
+ * image has a zero first row and column, and entry (y+1, x+1) is the sum of
+ * all pixels above and to the left of (y, x) inclusive.  Built row by row with
+ * the four-term recurrence, in u32 arithmetic (modulo 2^32). */
+void bdref_build_integral(const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch,
+                          uint32_t* ii, int64_t ii_pitch)
+{
+    for (int32_t x = 0; x <= W; ++x) ii[x] = 0u;
+    for (int32_t y = 0; y < H; ++y) {
+        uint32_t* above = ii + (int64_t)y * ii_pitch;
+        uint32_t* row = ii + (int64_t)(y + 1) * ii_pitch;
+        row[0] = 0u;
+        for (int32_t x = 0; x < W; ++x) {
+            uint32_t pixel = img[(int64_t)y * img_pitch + x];
+            row[x + 1] = pixel + above[x + 1] + row[x] - above[x];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ keypoints */
+
+int32_t bdref_keypoint_valid(const bdref_keypoint* kp)
+{
+    return isfinite(kp->x) && isfinite(kp->y) && isfinite(kp->scale) && isfinite(kp->angle) &&
+           kp->scale > 0.0f;
+}
+
+/* Reading of the patch frame (the paper only says boxes are centred at pixels
+ * u of the normalized patch): a normalized-patch offset u = (ux, uy) maps to
+ * the image point p = c + scale * R(angle) u, with R the rotation taking the
+ * patch x axis to (cos a, sin a).  Evaluated in FP64 in exactly this order. */
+static void patch_to_image(double cx, double cy, double sa, double sb, double ux, double uy,
+                           double* px, double* py)
+{
+    /* sa = scale*cos(angle), sb = scale*sin(angle) */
+    *px = cx + (sa * ux - sb * uy);
+    *py = cy + (sb * ux + sa * uy);
+}
+
+/* ------------------------------------------------------------------ BAD */
+
+/* Sum of the (2R+1)^2 pixels centred at (cx, cy), from four integral-image
+ * corners.  The true sum is below 2^32, so u32 wrap-around cancels. */
+static int64_t box_sum(const uint32_t* ii, int64_t pitch, int64_t cx, int64_t cy, int64_t R)
+{
+    uint32_t top_left = ii[(cy - R) * pitch + (cx - R)];
+    uint32_t top_right = ii[(cy - R) * pitch + (cx + R + 1)];
+    uint32_t bottom_left = ii[(cy + R + 1) * pitch + (cx - R)];
+    uint32_t bottom_right = ii[(cy + R + 1) * pitch + (cx + R + 1)];
+    uint32_t s = bottom_right - top_right - bottom_left + top_left;
+    return (int64_t)s;
+}
+
+/* distance of v to the nearest integer, for the near-tie audit */
+static double dist_to_integer(double v) { return fabs(v - floor(v + 0.5)); }
+
+/* Box centre from a patch point: round half up to the pixel grid, then
+ * clamp so that the whole box of radius R lies inside [0, n). */
+static int64_t box_centre(double p, int64_t R, int64_t n, int64_t* near_ties)
+{
+    double q = p + 0.5;
+    double d = dist_to_integer(q);
+    if (d > 0.0 && d < 1e-9) ++*near_ties;
+    double c = floor(q);
+    if (c < (double)R) c = (double)R;
+    if (c > (double)(n - 1 - R)) c = (double)(n - 1 - R);
+    return (int64_t)c;
+}
+
+/* Sec. III-A.  Weak descriptor h(x; f, theta) = +1 if f(x) <= theta else -1,
+ * where f(x; u1, u2, s) = mean grey level of the box of side s at u1 minus the
+ * mean of the box of side s at u2.  The bit stored is 1 for h = +1.
+ *
+ * Readings: the box radius in image pixels is R = floor(r*scale + 0.5),
+ * capped so a box fits the image; both boxes share it (side s = 2R+1).  The
+ * box centres are the patch points rounded half up and clamped so the box
+ * stays inside the image.  With area A = s^2, f <= theta is evaluated exactly
+ * as S1 - S2 <= theta * A (S = box sums; theta*A is exact in FP64).
+ * Keypoints with non-finite fields or scale <= 0 get an all-zero code. */
+int64_t bdref_describe_bad(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch,
+                           const bdref_keypoint* kps, int32_t n_kp,
+                           const bdref_box_pair* pairs, int32_t n_bits, uint64_t* codes)
+{
+    const int32_t n_words = n_bits / 64;
+    const int64_t r_cap = ((W < H ? W : H) - 1) / 2;
+    int64_t near_ties = 0;
+    for (int32_t i = 0; i < n_kp; ++i) {
+        uint64_t* code = codes + (int64_t)i * n_words;
+        memset(code, 0, sizeof(uint64_t) * (size_t)n_words);
+        const bdref_keypoint* kp = &kps[i];
+        if (!bdref_keypoint_valid(kp)) continue;
+        double scale = (double)kp->scale;
+        double angle = (double)kp->angle;
+        double sa = scale * cos(angle);
+        double sb = scale * sin(angle);
+        for (int32_t j = 0; j < n_bits; ++j) {
+            const bdref_box_pair* pr = &pairs[j];
+            double rr = floor((double)pr->radius * scale + 0.5);
+            int64_t R = rr > (double)r_cap ? r_cap : (int64_t)rr;
+            double p1x, p1y, p2x, p2y;
+            patch_to_image(kp->x, kp->y, sa, sb, pr->x1, pr->y1, &p1x, &p1y);
+            patch_to_image(kp->x, kp->y, sa, sb, pr->x2, pr->y2, &p2x, &p2y);
+            int64_t c1x = box_centre(p1x, R, W, &near_ties);
+            int64_t c1y = box_centre(p1y, R, H, &near_ties);
+            int64_t c2x = box_centre(p2x, R, W, &near_ties);
+            int64_t c2y = box_centre(p2y, R, H, &near_ties);
+            int64_t s1 = box_sum(ii, ii_pitch, c1x, c1y, R);
+            int64_t s2 = box_sum(ii, ii_pitch, c2x, c2y, R);
+            int64_t side = 2 * R + 1;
+            double area = (double)(side * side);
+            int bit = (double)(s1 - s2) <= (double)pr->threshold * area;
+            if (bit) code[j / 64] |= (uint64_t)1 << (j % 64);
+        }
+    }
+    return near_ties;
+}
+
+/* ------------------------------------------------------------------ HashSIFT */
+
+static double pixel_value(const void* img, int32_t dtype, int64_t pitch, int64_t x, int64_t y)
+{
+    const unsigned char* row = (const unsigned char*)img + y * pitch;
+    if (dtype == 0) return (double)row[x] / 255.0;
+    float v;
+    memcpy(&v, row + 4 * x, sizeof v);
+    return (double)v;
+}
+
+static int64_t clamp_index(double v, int64_t n)
+{
+    if (v < 0.0) return 0;
+    if (v > (double)(n - 1)) return n - 1;
+    return (int64_t)v;
+}
+
+/* Bilinear interpolation at (px, py) with clamp-to-edge addressing, written
+ * as nested linear interpolation a + t (b - a): the same polynomial as the
+ * weighted four-tap form, but exact wherever the four pixels are equal, so a
+ * flat image region gives exactly zero gradients. */
+static double bilinear(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t pitch,
+                       double px, double py)
+{
+    double x0 = floor(px), y0 = floor(py);
+    double fx = px - x0, fy = py - y0;
+    int64_t xa = clamp_index(x0, W), xb = clamp_index(x0 + 1.0, W);
+    int64_t ya = clamp_index(y0, H), yb = clamp_index(y0 + 1.0, H);
+    double v00 = pixel_value(img, dtype, pitch, xa, ya);
+    double v01 = pixel_value(img, dtype, pitch, xb, ya);
+    double v10 = pixel_value(img, dtype, pitch, xa, yb);
+    double v11 = pixel_value(img, dtype, pitch, xb, yb);
+    double top = v00 + fx * (v01 - v00);
+    double bottom = v10 + fx * (v11 - v10);
+    return top + fy * (bottom - top);
+}
+
+#define PATCH 32
+#define APRON 34 /* 32x32 patch plus a one-pixel apron for central differences */
+
+/* Sec. III-B takes the SIFT feature vector of the normalized 32x32 patch
+ * (the timing experiment describes only that patch, with no image pyramid).
+ * The paper fixes no further detail; the reading here is Lowe's descriptor
+ * layout on that patch:
+ *   1. patch pixel (i, j), i, j in -1..32, is the bilinear sample at patch
+ *      offset u = (j - 15.5, i - 15.5), clamp-to-edge;
+ *   2. central differences gx = P[i][j+1] - P[i][j-1], gy = P[i+1][j] - P[i-1][j];
+ *      magnitude m and angle phi = atan2(gy, gx) in [0, 2 pi) (the patch is
+ *      sampled in the rotated frame, so phi is relative to the keypoint angle);
+ *   3. weight m * exp(-((j-15.5)^2 + (i-15.5)^2) / (2 * 16^2));
+ *   4. trilinear vote into 4x4 spatial cells (cell centres at 8c + 3.5) and 8
+ *      orientation bins (bin centres at 2 pi o / 8, circular); cells outside
+ *      0..3 are dropped; index (cy * 4 + cx) * 8 + o;
+ *   5. L2 normalization (a zero histogram stays zero); no clipping.
+ * Keypoints with non-finite fields or scale <= 0 give a zero histogram. */
+void bdref_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
+                         const bdref_keypoint* kps, int32_t n_kp, double* hist)
+{
+    const double two_pi = 2.0 * M_PI;
+    double patch[APRON][APRON];
+    for (int32_t n = 0; n < n_kp; ++n) {
+        double* h = hist + (int64_t)n * 128;
+        for (int b = 0; b < 128; ++b) h[b] = 0.0;
+        const bdref_keypoint* kp = &kps[n];
+        if (!bdref_keypoint_valid(kp)) continue;
+        double scale = (double)kp->scale;
+        double sa = scale * cos((double)kp->angle);
+        double sb = scale * sin((double)kp->angle);
+
+        for (int i = -1; i <= PATCH; ++i)
+            for (int j = -1; j <= PATCH; ++j) {
+                double px, py;
+                patch_to_image(kp->x, kp->y, sa, sb, j - 15.5, i - 15.5, &px, &py);
+                patch[i + 1][j + 1] = bilinear(img, dtype, W, H, img_pitch, px, py);
+            }
+
+        for (int i = 0; i < PATCH; ++i)
+            for (int j = 0; j < PATCH; ++j) {
+                double gx = patch[i + 1][j + 2] - patch[i + 1][j];
+                double gy = patch[i + 2][j + 1] - patch[i][j + 1];
+                double m = sqrt(gx * gx + gy * gy);
+                double phi = atan2(gy, gx);
+                if (phi < 0.0) phi += two_pi;
+                double du = j - 15.5, dv = i - 15.5;
+                double w = m * exp(-(du * du + dv * dv) / (2.0 * 16.0 * 16.0));
+
+                double bx = (j + 0.5) / 8.0 - 0.5;
+                double by = (i + 0.5) / 8.0 - 0.5;
+                double bo = phi * 8.0 / two_pi;
+                double x0 = floor(bx), y0 = floor(by), o0 = floor(bo);
+                double dx = bx - x0, dy = by - y0, dor = bo - o0;
+                for (int ky = 0; ky < 2; ++ky) {
+                    int cy = (int)y0 + ky;
+                    if (cy < 0 || cy > 3) continue;
+                    double wy = ky ? dy : 1.0 - dy;
+                    for (int kx = 0; kx < 2; ++kx) {
+                        int cx = (int)x0 + kx;
+                        if (cx < 0 || cx > 3) continue;
+                        double wx = kx ? dx : 1.0 - dx;
+                        for (int ko = 0; ko < 2; ++ko) {
+                            int o = ((int)o0 + ko) % 8;
+                            double wo = ko ? dor : 1.0 - dor;
+                            h[(cy * 4 + cx) * 8 + o] += w * wy * wx * wo;
+                        }
+                    }
+                }
+            }
+
+        double ss = 0.0;
+        for (int b = 0; b < 128; ++b) ss += h[b] * h[b];
+        if (ss > 0.0) {
+            double norm = sqrt(ss);
+            for (int b = 0; b < 128; ++b) h[b] /= norm;
+        }
+    }
+}
+
+/* Sec. III-B: D(x) = sgn(B [f(x); 1]).  Reading: the last column of the
+ * paper's B is stored as -t, so the response is r = B f - t, and the bit is
+ * 1 when r > 0 (sgn(0) maps to 0). */
+void bdref_hashsift_project(const double* hist, int32_t n_kp, const float* B, const float* t,
+                            int32_t n_bits, const uint8_t* valid, double* resp, uint64_t* codes)
+{
+    const int32_t n_words = n_bits / 64;
+    for (int32_t n = 0; n < n_kp; ++n) {
+        const double* f = hist + (int64_t)n * 128;
+        uint64_t* code = codes + (int64_t)n * n_words;
+        memset(code, 0, sizeof(uint64_t) * (size_t)n_words);
+        for (int32_t j = 0; j < n_bits; ++j) {
+            double r = 0.0;
+            for (int k = 0; k < 128; ++k) r += (double)B[(int64_t)j * 128 + k] * f[k];
+            r -= (double)t[j];
+            if (resp) resp[(int64_t)n * n_bits + j] = r;
+            if ((valid == NULL || valid[n]) && r > 0.0) code[j / 64] |= (uint64_t)1 << (j % 64);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ Hamming k-NN */
+
+static uint32_t popcount64(uint64_t v)
+{
+    uint32_t c = 0;
+    while (v) {
+        v &= v - 1;
+        ++c;
+    }
+    return c;
+}
+
+/* Sec. III-A: S(x, y) = h(x)^T h(y) = K - 2 d_H(x, y), so the most similar
+ * train code is the one at the smallest Hamming distance.  Reading: ties in
+ * distance go to the lower train index (lexicographic (d, index) order). */
+void bdref_match_knn(const uint64_t* query, int32_t n_q, const uint64_t* train, int32_t n_t,
+                     int32_t n_words, int32_t k, int32_t* idx, uint32_t* dist)
+{
+    for (int32_t i = 0; i < n_q; ++i) {
+        int32_t* bi = idx + (int64_t)i * k;
+        uint32_t* bd = dist + (int64_t)i * k;
+        for (int32_t s = 0; s < k; ++s) {
+            bi[s] = -1;
+            bd[s] = 0xFFFFFFFFu;
+        }
+        const uint64_t* q = query + (int64_t)i * n_words;
+        for (int32_t j = 0; j < n_t; ++j) {
+            const uint64_t* tr = train + (int64_t)j * n_words;
+            uint32_t d = 0;
+            for (int32_t w = 0; w < n_words; ++w) d += popcount64(q[w] ^ tr[w]);
+            /* j increases, so an equal distance never displaces an earlier index */
+            if (bi[k - 1] >= 0 && d >= bd[k - 1]) continue;
+            int32_t s = k - 1;
+            while (s > 0 && (bi[s - 1] < 0 || d < bd[s - 1])) {
+                bi[s] = bi[s - 1];
+                bd[s] = bd[s - 1];
+                --s;
+            }
+            bi[s] = j;
+            bd[s] = d;
+        }
+    }
+}

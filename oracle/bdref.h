@@ -1,0 +1,76 @@
+/*
+ * bdref.h -- plain CPU oracle for the describe-and-match path of
+ * "Revisiting Binary Local Image Description for Resource Limited Devices"
+ * (Suarez, Buenaposada, Baumela; RA-L 2021).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code with the
+ * GPU library: its own types, its own loops, FP64 for every floating-point
+ * step, no blocking and no reordering beyond the definitions it follows.
+ * All pointers are host pointers.  Nothing is allocated for the caller.
+ */
+#ifndef BDREF_H
+#define BDREF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Keypoint: centre (x right, y down, pixel centres on integer coordinates),
+ * scale = image pixels per normalized-patch pixel, angle in radians. */
+typedef struct { float x, y, scale, angle; } bdref_keypoint;
+
+/* BAD weak descriptor: box centres u1 = (x1, y1), u2 = (x2, y2) as offsets
+ * from the keypoint in normalized-patch pixels, box radius r (side 2r+1 before
+ * scaling) and threshold theta in grey levels.  12 bytes. */
+typedef struct {
+    int8_t x1, y1, x2, y2;
+    uint8_t radius;
+    uint8_t pad[3];
+    float threshold;
+} bdref_box_pair;
+
+/* Integral image (Sec. III-A: box averages in constant time): ii is
+ * (H+1) x (W+1) with row stride ii_pitch elements, ii[0][*] = ii[*][0] = 0 and
+ * ii[y+1][x+1] = sum of img[y'][x'] over y' <= y, x' <= x, modulo 2^32. */
+void bdref_build_integral(const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch,
+                          uint32_t* ii, int64_t ii_pitch);
+
+/* BAD codes (Sec. III-A, weak descriptor h(x; f, theta) and the binary vector
+ * h(x)).  codes is n_kp x (n_bits/64) words, bit j of a keypoint in word j/64
+ * at position j%64, set when f <= theta.  Returns the number of box centres
+ * whose rounding lies within 1e-9 of a half-integer tie (near-tie audit). */
+int64_t bdref_describe_bad(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch,
+                           const bdref_keypoint* kps, int32_t n_kp,
+                           const bdref_box_pair* pairs, int32_t n_bits, uint64_t* codes);
+
+/* HashSIFT features (Sec. III-B: SIFT features of the normalized 32x32
+ * patch): hist is n_kp x 128, L2-normalized 4x4x8 gradient-orientation
+ * histograms in FP64.  dtype 0 = u8 image (read as v/255), 1 = f32 image.
+ * img_pitch is in bytes. */
+void bdref_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
+                         const bdref_keypoint* kps, int32_t n_kp, double* hist);
+
+/* HashSIFT binarization (Sec. III-B, D(x) = sgn(B [f; 1])): resp[i][j] =
+ * sum_k B[j][k] f_i[k] - t[j] in FP64, bit j set when resp > 0.  B is
+ * n_bits x 128 (f32, row major), t has n_bits entries.  resp may be NULL.
+ * valid (may be NULL) marks keypoints whose code is forced to zero when 0. */
+void bdref_hashsift_project(const double* hist, int32_t n_kp, const float* B, const float* t,
+                            int32_t n_bits, const uint8_t* valid, double* resp, uint64_t* codes);
+
+/* 1 when the keypoint has finite fields and a positive scale. */
+int32_t bdref_keypoint_valid(const bdref_keypoint* kp);
+
+/* Brute-force Hamming k-NN (Sec. III-A similarity S = h(x)^T h(y), i.e. K
+ * minus twice the Hamming distance): for each query the k smallest
+ * (distance, train index) pairs in lexicographic order.  Slots beyond n_t
+ * get idx = -1, dist = 0xFFFFFFFF. */
+void bdref_match_knn(const uint64_t* query, int32_t n_q, const uint64_t* train, int32_t n_t,
+                     int32_t n_words, int32_t k, int32_t* idx, uint32_t* dist);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
