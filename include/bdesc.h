@@ -1,0 +1,146 @@
+/*
+ * bdesc.h -- C ABI of the describe-and-match library for AMD Instinct MI355X
+ * (gfx950): BAD and HashSIFT binary local descriptors and brute-force
+ * Hamming k-NN, after Suarez, Buenaposada and Baumela, "Revisiting Binary
+ * Local Image Description for Resource Limited Devices" (RA-L 2021).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Every array argument is a DEVICE pointer allocated and owned by the
+ *    caller.  The library never frees caller memory and keeps no reference
+ *    to it after the call returns.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    the call returns without synchronizing.  A device fault surfaces at the
+ *    caller's next synchronization.
+ *  - Arguments are validated on the host before anything is enqueued.  The
+ *    return value is BD_OK (0) or a negative BD_E* code; bd_last_error()
+ *    then returns a message for the calling thread.  Nothing is thrown and
+ *    nothing aborts across this boundary.
+ *  - A bd_context owns the library's device workspace (grown on demand;
+ *    growing it synchronizes the stream) and is bound to one device.  A
+ *    context is not thread-safe: use one per host thread, and do not let
+ *    calls on different streams overlap on one context.
+ *  - Keypoints: pixel centres lie on integer coordinates, x to the right, y
+ *    down.  `scale` is image pixels per normalized-patch pixel, `angle` in
+ *    radians rotates the patch x axis onto (cos a, sin a).  A keypoint with a
+ *    non-finite field or scale <= 0 is invalid and gets an all-zero code.
+ *  - Codes: n_bits/64 uint64 words per keypoint, bit j in word j/64 at
+ *    position j%64 (LSB first).
+ */
+#ifndef BDESC_H
+#define BDESC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BD_OK 0
+#define BD_EINVAL (-1)        /* null pointer, bad size, pitch or count */
+#define BD_EUNSUPPORTED (-2)  /* n_bits, k, dtype or precision not provided */
+#define BD_ENOMEM (-3)        /* workspace allocation failed */
+#define BD_EDEVICE (-4)       /* HIP runtime error (launch, device query) */
+
+#define BD_DTYPE_U8 0  /* grey levels 0..255; HashSIFT reads v / 255 */
+#define BD_DTYPE_F32 1 /* float32 grey levels */
+
+#define BD_PREC_FP32 0
+
+typedef struct bd_keypoint {
+    float x, y, scale, angle;
+} bd_keypoint; /* 16 bytes */
+
+/* One BAD weak descriptor (Sec. III-A, h(x; f, theta) on f(x; u1, u2, s)):
+ * box centres u1 = (x1, y1), u2 = (x2, y2) as offsets from the keypoint in
+ * normalized-patch pixels, box radius (side 2*radius+1 before scaling) and
+ * threshold theta in grey levels. */
+typedef struct bd_box_pair {
+    int8_t x1, y1, x2, y2;
+    uint8_t radius;
+    uint8_t pad[3];
+    float threshold;
+} bd_box_pair; /* 12 bytes */
+
+typedef struct bd_context bd_context;
+
+/* Create a context bound to HIP device `device`.  *out receives the context. */
+int bd_context_create(bd_context** out, int device);
+
+/* Free the context's workspace (synchronizes the device).  NULL is a no-op. */
+int bd_context_destroy(bd_context* ctx);
+
+/* Message describing the last non-zero return on the calling thread. */
+const char* bd_last_error(void);
+
+/* Library version string. */
+const char* bd_version(void);
+
+/*
+ * Integral image of a u8 grey image (Sec. III-A: box averages in constant
+ * time from an integral image).
+ *   img      H rows of W bytes, row stride img_pitch bytes (>= W)
+ *   ii       (H+1) rows of (W+1) uint32, row stride ii_pitch elements
+ *            (>= W+1); ii[0][*] = ii[*][0] = 0 and ii[y+1][x+1] is the sum of
+ *            img over rows <= y and columns <= x, modulo 2^32.
+ * W, H >= 1 and (H+1) * ii_pitch < 2^31.  Three kernels: tile sums, carry
+ * scans, tile prefixes; they use ~(W*H/16 + 1024) * 4 bytes of workspace.
+ */
+int bd_build_integral(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H,
+                      int64_t img_pitch, uint32_t* ii, int64_t ii_pitch, void* stream);
+
+/*
+ * BAD codes (Sec. III-A: weak descriptor h(x; f, theta) = +1 when
+ * f(x; u1, u2, s) <= theta, f the difference of the mean grey levels of two
+ * boxes of side s; the bits of h(x) = [h_1 .. h_K]).
+ *   ii       integral image of a W x H u8 image as written by
+ *            bd_build_integral, row stride ii_pitch elements
+ *   kps      n_kp keypoints;  pairs  n_bits box pairs
+ *   codes    n_kp x n_bits/64 words; bit j set when h_j = +1
+ * n_bits is 256 or 512.  Per keypoint and pair: box radius
+ * R = floor(radius * scale + 0.5) capped at (min(W,H)-1)/2, centre = patch
+ * point kp + scale * Rot(angle) * u rounded half up (FP64) and clamped so the
+ * box lies inside the image, bit = [S1 - S2 <= theta * (2R+1)^2] exactly.
+ */
+int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch,
+                    const bd_keypoint* kps, int32_t n_kp, const bd_box_pair* pairs,
+                    int32_t n_bits, uint64_t* codes, void* stream);
+
+/*
+ * HashSIFT codes (Sec. III-B: D(x) = sgn(B [f(x); 1]) with f the SIFT
+ * feature vector of the normalized 32x32 patch).
+ *   img      H rows of W pixels (dtype BD_DTYPE_U8 or BD_DTYPE_F32), row
+ *            stride img_pitch bytes (a multiple of 4 for f32)
+ *   B        n_bits x 128 float32, row major;  t  n_bits thresholds
+ *            (the paper's last column of B is -t)
+ *   codes    n_kp x n_bits/64 words; bit j set when r_j = B_j . f - t_j > 0
+ *   hist_out optional (NULL) n_kp x 128 float32 features f
+ *   resp_out optional (NULL) n_kp x n_bits float32 responses r
+ * n_bits is 256 or 512; precision is BD_PREC_FP32.  f: 34x34 bilinear
+ * samples (clamp-to-edge) at patch offsets (j - 15.5, i - 15.5), central
+ * differences, Gaussian window sigma 16, trilinear votes into 4x4 cells x 8
+ * orientations (index (cy*4 + cx)*8 + o), L2-normalized (zero stays zero).
+ * The projection runs on FP32 MFMA.
+ */
+int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
+                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const float* B,
+                         const float* t, int32_t n_bits, int32_t precision, uint64_t* codes,
+                         float* hist_out, float* resp_out, void* stream);
+
+/*
+ * Brute-force Hamming k-NN (Sec. III-A: S(x, y) = h(x)^T h(y) = K - 2 d_H,
+ * so the most similar code has the smallest Hamming distance).
+ *   query    n_q x n_words words;  train  n_t x n_words words
+ *   idx      n_q x k int32 train indices;  dist  n_q x k uint32 distances
+ * For each query the k smallest (distance, train index) pairs in
+ * lexicographic order (equal distances: lower index first).  Slots beyond
+ * n_t get idx = -1 and dist = 0xFFFFFFFF.  n_words in 1..8, k in 1..2.
+ */
+int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q,
+                         const uint64_t* train, int32_t n_t, int32_t n_words, int32_t k,
+                         int32_t* idx, uint32_t* dist, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,245 @@
+"""BAD / HashSIFT describe-and-match on AMD MI355X (gfx950).
+
+Thin Python binding over the C ABI in include/bdesc.h (libbdesc.so, built
+in-tree by `python -m paper_2108_08380_amd.build`).  Every function here only
+marshals torch tensors (device memory) and the current HIP stream into the C
+call of the same name; all arithmetic runs in the library's HIP kernels.
+There is no CPU fallback: without the built library every call raises.
+
+Tensor conventions (all on one ROCm device, row stride free, unit column
+stride):
+  image        (H, W) uint8, or float32 for HashSIFT
+  integral     (H+1, W+1) uint32
+  keypoints    (n, 4) float32 rows (x, y, scale, angle)
+  box pairs    (n_bits, 12) uint8 rows in the 12-byte bd_box_pair layout
+  codes        (n, n_bits/64) uint64, bit j in word j/64 at position j%64
+  knn          idx (n_q, k) int32, dist (n_q, k) uint32
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbdesc.so")
+
+BD_OK, BD_EINVAL, BD_EUNSUPPORTED, BD_ENOMEM, BD_EDEVICE = 0, -1, -2, -3, -4
+BD_DTYPE_U8, BD_DTYPE_F32 = 0, 1
+BD_PREC_FP32 = 0
+_PRECISIONS = {"fp32": BD_PREC_FP32}
+
+# Exported symbols of include/bdesc.h with their C signatures.
+_P, _I32, _I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+SIGNATURES = {
+    "bd_context_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int], ctypes.c_int),
+    "bd_context_destroy": ([_P], ctypes.c_int),
+    "bd_last_error": ([], ctypes.c_char_p),
+    "bd_version": ([], ctypes.c_char_p),
+    "bd_build_integral": ([_P, _P, _I32, _I32, _I64, _P, _I64, _P], ctypes.c_int),
+    "bd_describe_bad": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _I32, _P, _P], ctypes.c_int),
+    "bd_describe_hashsift": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _I32, _I32, _P, _P, _P, _P],
+                             ctypes.c_int),
+    "bd_match_hamming_knn": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
+}
+
+
+class BDError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"[{code}] {message}")
+        self.code = code
+
+
+_lib = None
+_lock = threading.Lock()
+_contexts: dict[int, int] = {}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libbdesc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                if not os.path.exists(LIB_PATH):
+                    raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2108_08380_amd.build`")
+                L = ctypes.CDLL(LIB_PATH)
+                for name, (args, res) in SIGNATURES.items():
+                    fn = getattr(L, name)
+                    fn.argtypes = args
+                    fn.restype = res
+                _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().bd_last_error().decode()
+
+
+def _check(rc: int) -> None:
+    if rc != BD_OK:
+        raise BDError(rc, last_error())
+
+
+def context(device: int) -> int:
+    """The per-process library context of a device (created on first use)."""
+    ctx = _contexts.get(device)
+    if ctx is None:
+        with _lock:
+            ctx = _contexts.get(device)
+            if ctx is None:
+                out = ctypes.c_void_p()
+                _check(lib().bd_context_create(ctypes.byref(out), device))
+                ctx = out.value
+                _contexts[device] = ctx
+    return ctx
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _device_and_stream(*tensors):
+    torch = _torch()
+    dev = tensors[0].device
+    for t in tensors:
+        if t is None:
+            continue
+        if t.device != dev or dev.type != "cuda":
+            raise ValueError("all tensors must live on the same ROCm device")
+    return dev.index, torch.cuda.current_stream(dev).cuda_stream
+
+
+def _require(t, dtype, ndim, name):
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if t.dim() != ndim:
+        raise ValueError(f"{name}: expected {ndim} dimensions, got {t.dim()}")
+    if ndim >= 2 and t.stride(-1) != 1:
+        raise ValueError(f"{name}: columns must be contiguous")
+
+
+def _contig(t, name):
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+# --------------------------------------------------------------------------- marshalling helpers
+
+
+def keypoints_tensor(kps: np.ndarray, device="cuda"):
+    """(n,) structured keypoints or (n, 4) float32 array -> (n, 4) float32 device tensor."""
+    torch = _torch()
+    arr = np.ascontiguousarray(kps)
+    if arr.dtype.names:
+        arr = arr.view(np.float32).reshape(-1, 4)
+    return torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float32).reshape(-1, 4)).to(device)
+
+
+def pairs_tensor(pairs: np.ndarray, device="cuda"):
+    """(n_bits,) structured box pairs (12-byte records) -> (n_bits, 12) uint8 device tensor."""
+    torch = _torch()
+    arr = np.ascontiguousarray(pairs)
+    assert arr.dtype.itemsize == 12
+    return torch.from_numpy(arr.view(np.uint8).reshape(-1, 12).copy()).to(device)
+
+
+# --------------------------------------------------------------------------- entry points
+
+
+def build_integral(img, out=None):
+    """(H, W) uint8 image -> (H+1, W+1) uint32 integral image (bd_build_integral)."""
+    torch = _torch()
+    _require(img, torch.uint8, 2, "img")
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H + 1, W + 1), dtype=torch.uint32, device=img.device)
+    _require(out, torch.uint32, 2, "out")
+    dev, stream = _device_and_stream(img, out)
+    _check(lib().bd_build_integral(context(dev), img.data_ptr(), W, H, img.stride(0), out.data_ptr(),
+                                   out.stride(0), stream))
+    return out
+
+
+def describe_bad(ii, kps, pairs, n_bits: int | None = None, out=None):
+    """BAD codes from an integral image (bd_describe_bad)."""
+    torch = _torch()
+    _require(ii, torch.uint32, 2, "ii")
+    _require(kps, torch.float32, 2, "kps")
+    _contig(kps, "kps")
+    _contig(pairs, "pairs")
+    if pairs.dtype != torch.uint8 or pairs.dim() != 2 or pairs.shape[1] != 12:
+        raise TypeError("pairs must be an (n_bits, 12) uint8 tensor")
+    n_bits = pairs.shape[0] if n_bits is None else n_bits
+    if pairs.shape[0] < n_bits:
+        raise ValueError("fewer box pairs than n_bits")
+    H, W = ii.shape[0] - 1, ii.shape[1] - 1
+    n = kps.shape[0]
+    if out is None:
+        out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=ii.device)
+    _contig(out, "out")
+    dev, stream = _device_and_stream(ii, kps, pairs, out)
+    _check(lib().bd_describe_bad(context(dev), ii.data_ptr(), W, H, ii.stride(0), kps.data_ptr(), n,
+                                 pairs.data_ptr(), n_bits, out.data_ptr(), stream))
+    return out
+
+
+def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool = False,
+                      with_resp: bool = False, out=None):
+    """HashSIFT codes (bd_describe_hashsift).  Returns codes, or (codes, hist, resp)
+    when with_hist or with_resp is set (the unrequested ones are None)."""
+    torch = _torch()
+    if img.dtype == torch.uint8:
+        dtype = BD_DTYPE_U8
+    elif img.dtype == torch.float32:
+        dtype = BD_DTYPE_F32
+    else:
+        raise TypeError("img must be uint8 or float32")
+    _require(img, img.dtype, 2, "img")
+    _require(kps, torch.float32, 2, "kps")
+    _contig(kps, "kps")
+    _require(B, torch.float32, 2, "B")
+    _contig(B, "B")
+    _contig(t, "t")
+    n_bits = B.shape[0]
+    if B.shape[1] != 128 or t.shape != (n_bits,) or t.dtype != torch.float32:
+        raise ValueError("B must be (n_bits, 128) float32 and t (n_bits,) float32")
+    H, W = img.shape
+    n = kps.shape[0]
+    if out is None:
+        out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=img.device)
+    hist = torch.empty((n, 128), dtype=torch.float32, device=img.device) if with_hist else None
+    resp = torch.empty((n, n_bits), dtype=torch.float32, device=img.device) if with_resp else None
+    dev, stream = _device_and_stream(img, kps, B, t, out, hist, resp)
+    _check(lib().bd_describe_hashsift(context(dev), img.data_ptr(), dtype, W, H, img.stride(0) * img.element_size(),
+                                      kps.data_ptr(), n, B.data_ptr(), t.data_ptr(), n_bits,
+                                      _PRECISIONS[precision], out.data_ptr(),
+                                      hist.data_ptr() if hist is not None else None,
+                                      resp.data_ptr() if resp is not None else None, stream))
+    if with_hist or with_resp:
+        return out, hist, resp
+    return out
+
+
+def match_hamming_knn(query, train, k: int = 1, idx=None, dist=None):
+    """Brute-force Hamming k-NN (bd_match_hamming_knn) -> (idx int32, dist uint32)."""
+    torch = _torch()
+    _require(query, torch.uint64, 2, "query")
+    _require(train, torch.uint64, 2, "train")
+    _contig(query, "query")
+    _contig(train, "train")
+    if query.shape[1] != train.shape[1]:
+        raise ValueError("query and train codes differ in length")
+    n_q, n_words = query.shape
+    if idx is None:
+        idx = torch.empty((n_q, k), dtype=torch.int32, device=query.device)
+    if dist is None:
+        dist = torch.empty((n_q, k), dtype=torch.uint32, device=query.device)
+    dev, stream = _device_and_stream(query, train, idx, dist)
+    _check(lib().bd_match_hamming_knn(context(dev), query.data_ptr(), n_q, train.data_ptr(), train.shape[0],
+                                      n_words, k, idx.data_ptr(), dist.data_ptr(), stream))
+    return idx, dist

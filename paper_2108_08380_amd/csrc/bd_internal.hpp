@@ -1,0 +1,67 @@
+// Internal declarations shared by the library's translation units: the
+// context, error reporting and the kernel launchers.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/bdesc.h"
+
+struct bd_context {
+    int device = 0;
+    void* workspace = nullptr;  // device memory, grown on demand
+    size_t workspace_bytes = 0;
+    int num_cus = 0;
+};
+
+namespace bd {
+
+// Thread-local error message; returns `code` for tail calls.
+int fail(int code, const char* fmt, ...);
+
+// Ensure the context owns at least `bytes` of device workspace.  Growing
+// synchronizes `stream` first so no enqueued kernel still uses the old block.
+int reserve_workspace(bd_context* ctx, size_t bytes, hipStream_t stream, void** out);
+
+int check_launch(const char* what);
+
+constexpr int kWave = 64;
+
+// ---- integral image (integral.hip)
+struct IntegralPlan {
+    int32_t W, H;
+    int32_t strips, slabs;  // 16-row strips, 256-column slabs
+    int64_t col_pitch;      // elements per strip row of the column-sum table
+    size_t workspace_bytes() const;
+};
+IntegralPlan plan_integral(int32_t W, int32_t H);
+void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
+                     int64_t ii_pitch, void* workspace, hipStream_t stream);
+
+// ---- BAD (bad.hip)
+void launch_bad(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch, const bd_keypoint* kps,
+                int32_t n_kp, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes,
+                hipStream_t stream);
+
+// ---- HashSIFT (hashsift.hip)
+void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
+                          const bd_keypoint* kps, int32_t n_kp, float* hist, hipStream_t stream);
+void launch_hashsift_project_fp32(const float* hist, const bd_keypoint* kps, int32_t n_kp,
+                                  const float* B, const float* t, int32_t n_words, uint64_t* codes,
+                                  float* resp, hipStream_t stream);
+
+// ---- Hamming k-NN (hamming.hip)
+struct KnnPlan {
+    int32_t n_q, n_t, n_words, k;
+    int32_t qpl;             // queries per lane
+    int32_t splits;          // train-set splits (grid.y)
+    int32_t rows_per_split;  // <= 2^22 so a (distance, local row) key fits 32 bits
+    size_t workspace_bytes() const;
+};
+KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_cus);
+void launch_knn(const KnnPlan& p, const uint64_t* query, const uint64_t* train, int32_t* idx,
+                uint32_t* dist, void* workspace, hipStream_t stream);
+
+}  // namespace bd

@@ -1,0 +1,225 @@
+// C ABI: argument validation, context and workspace, dispatch to kernels.
+//
+// Every entry point validates its arguments on the host before it touches
+// the HIP runtime, so argument errors are reported identically with or
+// without a GPU.  Nothing here synchronizes except workspace growth and
+// context destruction.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "bd_internal.hpp"
+
+namespace bd {
+
+namespace {
+thread_local char g_error[512] = "";
+}
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_error, sizeof g_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(BD_EDEVICE, "%s: kernel launch failed: %s", what, hipGetErrorString(e));
+    return BD_OK;
+}
+
+namespace {
+// Makes the context's device current for the allocation and restores the
+// caller's current device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int device)
+    {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != device) err = hipSetDevice(device);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+
+int reserve_workspace(bd_context* ctx, size_t bytes, hipStream_t stream, void** out)
+{
+    if (bytes == 0) {
+        *out = ctx->workspace;
+        return BD_OK;
+    }
+    if (bytes > ctx->workspace_bytes) {
+        DeviceGuard guard(ctx->device);
+        hipError_t e = guard.err;
+        if (e != hipSuccess) return fail(BD_EDEVICE, "hipSetDevice(%d): %s", ctx->device, hipGetErrorString(e));
+        if (ctx->workspace) {
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return fail(BD_EDEVICE, "workspace growth: stream sync failed: %s", hipGetErrorString(e));
+            (void)hipFree(ctx->workspace);
+            ctx->workspace = nullptr;
+            ctx->workspace_bytes = 0;
+        }
+        const size_t want = (bytes + 0xFFFFF) & ~(size_t)0xFFFFF;  // whole MiB
+        const char* inject = getenv("BD_TEST_FAIL_ALLOC");
+        if (inject && inject[0] == '1') return fail(BD_ENOMEM, "workspace allocation of %zu bytes failed (injected)", want);
+        void* p = nullptr;
+        e = hipMalloc(&p, want);
+        if (e != hipSuccess) return fail(BD_ENOMEM, "workspace allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+        ctx->workspace = p;
+        ctx->workspace_bytes = want;
+    }
+    *out = ctx->workspace;
+    return BD_OK;
+}
+
+}  // namespace bd
+
+using namespace bd;
+
+namespace {
+
+bool is_supported_bits(int32_t n_bits) { return n_bits == 256 || n_bits == 512; }
+
+int check_ctx(bd_context* ctx, const char* fn)
+{
+    if (!ctx) return fail(BD_EINVAL, "%s: null context", fn);
+    return BD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bd_last_error(void) { return bd::g_error; }
+
+const char* bd_version(void) { return "bdesc 0.1 gfx950"; }
+
+int bd_context_create(bd_context** out, int device)
+{
+    if (!out) return fail(BD_EINVAL, "bd_context_create: null output pointer");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0)
+        return fail(BD_EDEVICE, "bd_context_create: no HIP device (%s)", e == hipSuccess ? "count 0" : hipGetErrorString(e));
+    if (device < 0 || device >= count)
+        return fail(BD_EINVAL, "bd_context_create: device %d out of range [0, %d)", device, count);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return fail(BD_EDEVICE, "bd_context_create: %s", hipGetErrorString(e));
+    bd_context* ctx = new (std::nothrow) bd_context();
+    if (!ctx) return fail(BD_ENOMEM, "bd_context_create: out of host memory");
+    ctx->device = device;
+    ctx->num_cus = prop.multiProcessorCount;
+    *out = ctx;
+    return BD_OK;
+}
+
+int bd_context_destroy(bd_context* ctx)
+{
+    if (!ctx) return BD_OK;
+    int rc = BD_OK;
+    if (ctx->workspace) {
+        DeviceGuard guard(ctx->device);
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) rc = fail(BD_EDEVICE, "bd_context_destroy: %s", hipGetErrorString(e));
+        (void)hipFree(ctx->workspace);
+    }
+    delete ctx;
+    return rc;
+}
+
+int bd_build_integral(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch,
+                      uint32_t* ii, int64_t ii_pitch, void* stream)
+{
+    const char* fn = "bd_build_integral";
+    if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
+    if (img_pitch < W) return fail(BD_EINVAL, "%s: img_pitch %lld < W %d", fn, (long long)img_pitch, W);
+    if (ii_pitch < (int64_t)W + 1) return fail(BD_EINVAL, "%s: ii_pitch %lld < W+1", fn, (long long)ii_pitch);
+    if (((int64_t)H + 1) * ii_pitch >= (int64_t)1 << 31)
+        return fail(BD_EINVAL, "%s: integral image of %lld elements exceeds 2^31", fn, (long long)(((int64_t)H + 1) * ii_pitch));
+    if (!img || !ii) return fail(BD_EINVAL, "%s: null image or output pointer", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const IntegralPlan plan = plan_integral(W, H);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, plan.workspace_bytes(), s, &ws)) return rc;
+    launch_integral(plan, img, img_pitch, ii, ii_pitch, ws, s);
+    return check_launch(fn);
+}
+
+int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch,
+                    const bd_keypoint* kps, int32_t n_kp, const bd_box_pair* pairs, int32_t n_bits,
+                    uint64_t* codes, void* stream)
+{
+    const char* fn = "bd_describe_bad";
+    if (!is_supported_bits(n_bits)) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (256 or 512)", fn, n_bits);
+    if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
+    if (ii_pitch < (int64_t)W + 1) return fail(BD_EINVAL, "%s: ii_pitch %lld < W+1", fn, (long long)ii_pitch);
+    if (((int64_t)H + 1) * ii_pitch >= (int64_t)1 << 31) return fail(BD_EINVAL, "%s: integral image exceeds 2^31 elements", fn);
+    if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
+    if (n_kp > 0 && (!ii || !kps || !pairs || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n_kp == 0) return BD_OK;
+    launch_bad(ii, W, H, ii_pitch, kps, n_kp, pairs, n_bits / 64, codes, static_cast<hipStream_t>(stream));
+    return check_launch(fn);
+}
+
+int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
+                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const float* B,
+                         const float* t, int32_t n_bits, int32_t precision, uint64_t* codes,
+                         float* hist_out, float* resp_out, void* stream)
+{
+    const char* fn = "bd_describe_hashsift";
+    if (!is_supported_bits(n_bits)) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (256 or 512)", fn, n_bits);
+    if (dtype != BD_DTYPE_U8 && dtype != BD_DTYPE_F32) return fail(BD_EUNSUPPORTED, "%s: dtype %d", fn, dtype);
+    if (precision != BD_PREC_FP32) return fail(BD_EUNSUPPORTED, "%s: precision %d", fn, precision);
+    if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
+    const int64_t elem = dtype == BD_DTYPE_U8 ? 1 : 4;
+    if (img_pitch < W * elem) return fail(BD_EINVAL, "%s: img_pitch %lld < row bytes", fn, (long long)img_pitch);
+    if (dtype == BD_DTYPE_F32 && img_pitch % 4 != 0) return fail(BD_EINVAL, "%s: f32 img_pitch must be a multiple of 4", fn);
+    if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
+    if (n_kp > 0 && (!img || !kps || !B || !t || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n_kp == 0) return BD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* hist = hist_out;
+    if (!hist) {
+        void* ws = nullptr;
+        if (int rc = reserve_workspace(ctx, sizeof(float) * 128 * (size_t)n_kp, s, &ws)) return rc;
+        hist = static_cast<float*>(ws);
+    }
+    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, hist, s);
+    launch_hashsift_project_fp32(hist, kps, n_kp, B, t, n_bits / 64, codes, resp_out, s);
+    return check_launch(fn);
+}
+
+int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q, const uint64_t* train,
+                         int32_t n_t, int32_t n_words, int32_t k, int32_t* idx, uint32_t* dist, void* stream)
+{
+    const char* fn = "bd_match_hamming_knn";
+    if (n_words < 1 || n_words > 8) return fail(BD_EUNSUPPORTED, "%s: n_words %d (1..8)", fn, n_words);
+    if (k < 1 || k > 2) return fail(BD_EUNSUPPORTED, "%s: k %d (1 or 2)", fn, k);
+    if (n_q < 0 || n_t < 0) return fail(BD_EINVAL, "%s: negative count", fn);
+    if (n_q > 0 && (!query || !idx || !dist)) return fail(BD_EINVAL, "%s: null query or output pointer", fn);
+    if (n_q > 0 && n_t > 0 && !train) return fail(BD_EINVAL, "%s: null train pointer", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n_q == 0) return BD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const KnnPlan plan = plan_knn(n_q, n_t, n_words, k, ctx->num_cus);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, plan.workspace_bytes(), s, &ws)) return rc;
+    launch_knn(plan, query, train, idx, dist, ws, s);
+    return check_launch(fn);
+}
+
+}  // extern "C"

@@ -1,0 +1,233 @@
+// Brute-force Hamming k-NN (Sec. III-A: S(x, y) = h(x)^T h(y) = K - 2 d_H,
+// so the best match is the train code at the smallest Hamming distance).
+//
+// Lane = query: each lane keeps QPL query codes in VGPRs and walks a range
+// of train rows.  The train row index is wave-uniform, so its words arrive
+// through scalar loads and every XOR takes an SGPR operand: per (query,
+// train) pair the work is n_words * (2 XOR + 2 popcount-accumulate) plus the
+// top-k update, with no LDS traffic.  Distances and rows are packed into one
+// u32 key (distance << 22 | row within the split), so the lexicographic
+// (distance, index) order is plain unsigned order and the top-2 update is
+// three v_min/v_max.
+//
+// The train set is split over grid.y so that small query sets still fill
+// the GPU; per-split results go to the workspace and a second kernel merges
+// them.  The top-k of a strict total order does not depend on the merge
+// order, so results are deterministic.
+#include "bd_internal.hpp"
+
+namespace bd {
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+constexpr uint32_t kRowBits = 22;
+constexpr uint32_t kRowMask = (1u << kRowBits) - 1u;
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+template <int KK>
+__device__ __forceinline__ void topk_insert(uint32_t (&best)[KK], uint32_t key)
+{
+    if constexpr (KK == 1) {
+        best[0] = min(best[0], key);
+    } else {
+        const uint32_t hi = max(best[0], key);
+        best[0] = min(best[0], key);
+        best[1] = min(best[1], hi);
+    }
+}
+
+template <int NW, int KK, int QPL>
+__global__ __launch_bounds__(256) void hamming_knn_kernel(const uint64_t* __restrict__ query, int32_t n_q,
+                                                          const uint64_t* __restrict__ train, int32_t n_t,
+                                                          int32_t rows_per_split,
+                                                          uint32_t* __restrict__ partial,
+                                                          int32_t* __restrict__ out_idx,
+                                                          uint32_t* __restrict__ out_dist, int direct)
+{
+    const int lane = threadIdx.x % kWave;
+    const int qgroup = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int q0 = qgroup * kWave * QPL;
+    if (q0 >= n_q) return;
+    const int split = blockIdx.y;
+    const int t0 = split * rows_per_split;
+    const int t1 = min(n_t, t0 + rows_per_split);
+
+    uint32_t ql[QPL][NW], qh[QPL][NW];
+    uint32_t best[QPL][KK];
+#pragma unroll
+    for (int p = 0; p < QPL; ++p) {
+        const int qi = q0 + p * kWave + lane;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint64_t v = qi < n_q ? query[(int64_t)qi * NW + w] : 0ull;
+            ql[p][w] = (uint32_t)v;
+            qh[p][w] = (uint32_t)(v >> 32);
+        }
+#pragma unroll
+        for (int s = 0; s < KK; ++s) best[p][s] = kEmpty;
+    }
+
+    const uint32_t* rows = reinterpret_cast<const uint32_t*>(train);
+    for (int r = t0; r < t1; ++r) {
+        const uint32_t* row = rows + (int64_t)r * (2 * NW);
+        uint32_t tl[NW], th[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            tl[w] = row[2 * w];
+            th[w] = row[2 * w + 1];
+        }
+        const uint32_t local = (uint32_t)(r - t0);
+#pragma unroll
+        for (int p = 0; p < QPL; ++p) {
+            uint32_t d = 0u;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                d = __popc(ql[p][w] ^ tl[w]) + d;
+                d = __popc(qh[p][w] ^ th[w]) + d;
+            }
+            topk_insert<KK>(best[p], (d << kRowBits) | local);
+        }
+    }
+
+#pragma unroll
+    for (int p = 0; p < QPL; ++p) {
+        const int qi = q0 + p * kWave + lane;
+        if (qi >= n_q) continue;
+        if (direct) {
+#pragma unroll
+            for (int s = 0; s < KK; ++s) {
+                const uint32_t key = best[p][s];
+                const bool empty = key == kEmpty;
+                out_idx[(int64_t)qi * KK + s] = empty ? -1 : (int32_t)(t0 + (key & kRowMask));
+                out_dist[(int64_t)qi * KK + s] = empty ? kEmpty : key >> kRowBits;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < KK; ++s) partial[((int64_t)split * n_q + qi) * KK + s] = best[p][s];
+        }
+    }
+}
+
+// One thread per query: merge the per-split top-k into the final top-k.
+template <int KK>
+__global__ __launch_bounds__(256) void hamming_merge_kernel(const uint32_t* __restrict__ partial, int32_t n_q,
+                                                            int32_t splits, int32_t rows_per_split,
+                                                            int32_t* __restrict__ out_idx,
+                                                            uint32_t* __restrict__ out_dist)
+{
+    const int qi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= n_q) return;
+    // 64-bit keys: distance in the high word, global row in the low word
+    uint64_t best[KK];
+#pragma unroll
+    for (int s = 0; s < KK; ++s) best[s] = ~0ull;
+    for (int sp = 0; sp < splits; ++sp) {
+#pragma unroll
+        for (int s = 0; s < KK; ++s) {
+            const uint32_t key = partial[((int64_t)sp * n_q + qi) * KK + s];
+            if (key == kEmpty) continue;
+            const uint64_t k64 = ((uint64_t)(key >> kRowBits) << 32) |
+                                 (uint64_t)(uint32_t)(sp * rows_per_split + (int)(key & kRowMask));
+            if constexpr (KK == 1) {
+                best[0] = k64 < best[0] ? k64 : best[0];
+            } else {
+                const uint64_t hi = k64 > best[0] ? k64 : best[0];
+                best[0] = k64 < best[0] ? k64 : best[0];
+                best[1] = hi < best[1] ? hi : best[1];
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < KK; ++s) {
+        const bool empty = best[s] == ~0ull;
+        out_idx[(int64_t)qi * KK + s] = empty ? -1 : (int32_t)(uint32_t)best[s];
+        out_dist[(int64_t)qi * KK + s] = empty ? kEmpty : (uint32_t)(best[s] >> 32);
+    }
+}
+
+template <int NW, int KK>
+void launch_nw_k(const KnnPlan& p, const uint64_t* query, const uint64_t* train, uint32_t* partial,
+                 int32_t* idx, uint32_t* dist, hipStream_t stream)
+{
+    const int direct = p.splits == 1;
+    const int per_block = kWavesPerBlock * kWave * p.qpl;
+    const dim3 grid((p.n_q + per_block - 1) / per_block, p.splits);
+    const dim3 block(kWavesPerBlock * kWave);
+    switch (p.qpl) {
+        case 1:
+            hipLaunchKernelGGL((hamming_knn_kernel<NW, KK, 1>), grid, block, 0, stream, query, p.n_q, train, p.n_t,
+                               p.rows_per_split, partial, idx, dist, direct);
+            break;
+        case 2:
+            hipLaunchKernelGGL((hamming_knn_kernel<NW, KK, 2>), grid, block, 0, stream, query, p.n_q, train, p.n_t,
+                               p.rows_per_split, partial, idx, dist, direct);
+            break;
+        default:
+            hipLaunchKernelGGL((hamming_knn_kernel<NW, KK, 4>), grid, block, 0, stream, query, p.n_q, train, p.n_t,
+                               p.rows_per_split, partial, idx, dist, direct);
+            break;
+    }
+    if (!direct) {
+        hipLaunchKernelGGL((hamming_merge_kernel<KK>), dim3((p.n_q + 255) / 256), dim3(256), 0, stream, partial,
+                           p.n_q, p.splits, p.rows_per_split, idx, dist);
+    }
+}
+
+template <int NW>
+void launch_nw(const KnnPlan& p, const uint64_t* query, const uint64_t* train, uint32_t* partial, int32_t* idx,
+               uint32_t* dist, hipStream_t stream)
+{
+    if (p.k == 1)
+        launch_nw_k<NW, 1>(p, query, train, partial, idx, dist, stream);
+    else
+        launch_nw_k<NW, 2>(p, query, train, partial, idx, dist, stream);
+}
+
+}  // namespace
+
+size_t KnnPlan::workspace_bytes() const
+{
+    return splits > 1 ? sizeof(uint32_t) * (size_t)splits * (size_t)n_q * (size_t)k : 0;
+}
+
+KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_cus)
+{
+    KnnPlan p{};
+    p.n_q = n_q;
+    p.n_t = n_t;
+    p.n_words = n_words;
+    p.k = k;
+    // Aim for ~16 wavefronts per CU while keeping every split at >= 64 rows.
+    const int64_t target_waves = 16ll * (num_cus > 0 ? num_cus : 256);
+    p.qpl = n_q >= 64 * 2 * target_waves ? 4 : (n_q >= 64 * target_waves ? 2 : 1);
+    const int64_t qgroups = ((int64_t)n_q + 64 * p.qpl - 1) / (64 * p.qpl);
+    int64_t splits = (target_waves + qgroups - 1) / qgroups;
+    const int64_t max_splits = (n_t + 63) / 64;
+    if (splits > max_splits) splits = max_splits;
+    const int64_t min_splits = ((int64_t)n_t + kRowMask) / (kRowMask + 1);
+    if (splits < min_splits) splits = min_splits;
+    if (splits < 1) splits = 1;
+    p.rows_per_split = (int32_t)((n_t + splits - 1) / splits);
+    if (p.rows_per_split < 1) p.rows_per_split = 1;
+    p.splits = (int32_t)((n_t + p.rows_per_split - 1) / p.rows_per_split);
+    if (p.splits < 1) p.splits = 1;
+    return p;
+}
+
+void launch_knn(const KnnPlan& p, const uint64_t* query, const uint64_t* train, int32_t* idx, uint32_t* dist,
+                void* workspace, hipStream_t stream)
+{
+    uint32_t* partial = static_cast<uint32_t*>(workspace);
+    switch (p.n_words) {
+        case 1: launch_nw<1>(p, query, train, partial, idx, dist, stream); break;
+        case 2: launch_nw<2>(p, query, train, partial, idx, dist, stream); break;
+        case 3: launch_nw<3>(p, query, train, partial, idx, dist, stream); break;
+        case 4: launch_nw<4>(p, query, train, partial, idx, dist, stream); break;
+        case 5: launch_nw<5>(p, query, train, partial, idx, dist, stream); break;
+        case 6: launch_nw<6>(p, query, train, partial, idx, dist, stream); break;
+        case 7: launch_nw<7>(p, query, train, partial, idx, dist, stream); break;
+        default: launch_nw<8>(p, query, train, partial, idx, dist, stream); break;
+    }
+}
+
+}  // namespace bd

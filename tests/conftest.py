@@ -22,3 +22,21 @@ def ref():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def dev():
+    """cuda:0 with the built library loaded; GPU tests fail loudly without either."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a ROCm device")
+    bd.lib()
+    return torch.device("cuda:0")
+
+
+def to_np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()

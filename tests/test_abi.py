@@ -1,0 +1,114 @@
+"""The C ABI without a GPU: every symbol declared in include/bdesc.h is
+exported by libbdesc.so with the binding's signature, and argument
+validation (which runs on the host before any HIP call) returns the
+documented error codes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2108_08380_amd as bd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bdesc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bd_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(bd.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return bd.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in bdesc.h but not exported"
+    assert set(names) == set(bd.SIGNATURES), "binding signatures out of sync with the header"
+
+
+def test_version_and_error_strings(L):
+    assert L.bd_version().decode().startswith("bdesc")
+    assert isinstance(L.bd_last_error(), bytes)
+
+
+def err(L):
+    return L.bd_last_error().decode()
+
+
+def test_context_create_null_output(L):
+    assert L.bd_context_create(None, 0) == bd.BD_EINVAL
+    assert "null output" in err(L)
+    assert L.bd_context_destroy(None) == bd.BD_OK
+
+
+def test_build_integral_validation(L):
+    p = ctypes.c_void_p(16)  # never dereferenced: validation fails first or the context is null
+    assert L.bd_build_integral(None, p, 0, 5, 5, p, 6, None) == bd.BD_EINVAL
+    assert "at least 1x1" in err(L)
+    assert L.bd_build_integral(None, p, 8, 5, 7, p, 9, None) == bd.BD_EINVAL
+    assert "img_pitch" in err(L)
+    assert L.bd_build_integral(None, p, 8, 5, 8, p, 8, None) == bd.BD_EINVAL
+    assert "ii_pitch" in err(L)
+    assert L.bd_build_integral(None, p, 40000, 60000, 40000, p, 40001, None) == bd.BD_EINVAL
+    assert "2^31" in err(L)
+    assert L.bd_build_integral(None, None, 8, 5, 8, p, 9, None) == bd.BD_EINVAL
+    assert "null" in err(L)
+    assert L.bd_build_integral(None, p, 8, 5, 8, p, 9, None) == bd.BD_EINVAL
+    assert "null context" in err(L)
+
+
+def test_describe_bad_validation(L):
+    p = ctypes.c_void_p(16)
+    assert L.bd_describe_bad(None, p, 10, 10, 11, p, 4, p, 128, p, None) == bd.BD_EUNSUPPORTED
+    assert "n_bits" in err(L)
+    assert L.bd_describe_bad(None, p, 10, 10, 10, p, 4, p, 256, p, None) == bd.BD_EINVAL
+    assert L.bd_describe_bad(None, p, 10, 10, 11, p, -1, p, 256, p, None) == bd.BD_EINVAL
+    assert L.bd_describe_bad(None, p, 10, 10, 11, None, 4, p, 256, p, None) == bd.BD_EINVAL
+    # n_kp = 0 needs no pointers, but still a context
+    assert L.bd_describe_bad(None, None, 10, 10, 11, None, 0, None, 256, None, None) == bd.BD_EINVAL
+    assert "null context" in err(L)
+
+
+def test_describe_hashsift_validation(L):
+    p = ctypes.c_void_p(16)
+    base = dict(dtype=bd.BD_DTYPE_F32, W=10, H=10, pitch=40, n=3, n_bits=256, prec=bd.BD_PREC_FP32)
+
+    def call(**kw):
+        a = {**base, **kw}
+        return L.bd_describe_hashsift(None, p, a["dtype"], a["W"], a["H"], a["pitch"], p, a["n"], p, p,
+                                      a["n_bits"], a["prec"], p, None, None, None)
+
+    assert call(n_bits=384) == bd.BD_EUNSUPPORTED
+    assert call(dtype=7) == bd.BD_EUNSUPPORTED
+    assert call(prec=9) == bd.BD_EUNSUPPORTED
+    assert call(pitch=39) == bd.BD_EINVAL
+    assert call(pitch=42) == bd.BD_EINVAL and "multiple of 4" in err(L)
+    assert call(dtype=bd.BD_DTYPE_U8, pitch=10) == bd.BD_EINVAL and "null context" in err(L)
+    assert call(n=-2) == bd.BD_EINVAL
+
+
+def test_match_validation(L):
+    p = ctypes.c_void_p(16)
+    assert L.bd_match_hamming_knn(None, p, 4, p, 4, 9, 1, p, p, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_match_hamming_knn(None, p, 4, p, 4, 4, 3, p, p, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_match_hamming_knn(None, p, -1, p, 4, 4, 1, p, p, None) == bd.BD_EINVAL
+    assert L.bd_match_hamming_knn(None, p, 4, None, 4, 4, 1, p, p, None) == bd.BD_EINVAL
+    assert L.bd_match_hamming_knn(None, p, 4, None, 0, 4, 1, p, p, None) == bd.BD_EINVAL
+    assert "null context" in err(L)
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(bd, "_lib", None)
+    monkeypatch.setattr(bd, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        bd.lib()

@@ -1,0 +1,111 @@
+"""HashSIFT on the GPU against the FP64 oracle.
+
+Tolerance (FP32 kernel vs FP64 oracle), fixed here and in the design notes:
+  features   |f_gpu - f_64| <= 1e-4 per element
+  responses  |r_gpu - r_64| <= 1e-4 per element
+  codes      every bit equal wherever |r_64| >= 2e-4 (the stated margin);
+             bits inside the margin are counted and reported, not failed.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2108_08380_amd as bd
+from paper_2108_08380_amd import synth
+from conftest import to_np
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-4
+R_TOL = 1e-4
+MARGIN = 2e-4
+
+
+def unpack(codes, n_bits):
+    return np.unpackbits(codes.view(np.uint8), axis=1, bitorder="little")[:, :n_bits]
+
+
+def compare(ref, dev, img, kps, B, t, label=""):
+    h64, r64, c64 = ref.describe_hashsift(img, kps, B, t)
+    codes, hist, resp = bd.describe_hashsift(torch.from_numpy(img).to(dev), bd.keypoints_tensor(kps, dev),
+                                             torch.from_numpy(B).to(dev), torch.from_numpy(t).to(dev),
+                                             with_hist=True, with_resp=True)
+    codes, hist, resp = to_np(codes), to_np(hist), to_np(resp)
+    df = np.abs(hist - h64).max() if len(kps) else 0.0
+    dr = np.abs(resp - r64).max() if len(kps) else 0.0
+    n_bits = B.shape[0]
+    outside = np.abs(r64) >= MARGIN
+    bg, be = unpack(codes, n_bits), unpack(c64, n_bits)
+    mismatch_out = int(((bg != be) & outside).sum())
+    inside = int((~outside).sum())
+    flips_in = int(((bg != be) & ~outside).sum())
+    print(f"{label} n={len(kps)} max|df|={df:.2e} max|dr|={dr:.2e} margin responses={inside} flips inside={flips_in}")
+    assert df <= F_TOL, df
+    assert dr <= R_TOL, dr
+    assert mismatch_out == 0
+    return codes, c64
+
+
+@pytest.mark.parametrize("n_bits", [256, 512])
+def test_config_workload(ref, dev, n_bits):
+    """1920x1080 float32 image, 5000 keypoints with scale U[1.6, 8], HashSIFT-512 (and -256)."""
+    w = synth.hashsift512_pair(n_bits=n_bits)
+    compare(ref, dev, w.image1, w.kp1, w.B, w.t, "view1")
+    compare(ref, dev, w.image2, w.kp2, w.B, w.t, "view2")
+
+
+def test_u8_image(ref, dev):
+    w = synth.bad256_pair()
+    B, t = synth.projection(np.random.default_rng(1), 512)
+    compare(ref, dev, w.image1, w.kp1, B, t, "u8")
+
+
+@pytest.mark.parametrize("n_kp", [1, 3, 15, 16, 17, 63, 64, 65, 129])
+def test_ragged_counts(ref, dev, n_kp):
+    rng = np.random.default_rng(200 + n_kp)
+    img = (synth.grey_image(rng, 300, 200, n_rect=30) / 255.0).astype(np.float32)
+    kps = synth.keypoints(rng, n_kp, 300, 200, border=0.0, scale_range=(0.5, 9.0))
+    B, t = synth.projection(rng, 256)
+    compare(ref, dev, img, kps, B, t, f"ragged{n_kp}")
+
+
+def test_flat_and_invalid_keypoints(ref, dev):
+    """Patches inside a flat rectangle give f = 0 (r = -t); invalid keypoints give zero codes."""
+    img = np.full((200, 200), 0.25, dtype=np.float32)
+    img[:, 150:] = 0.75
+    kps = np.zeros(6, dtype=synth.KEYPOINT_DTYPE)
+    kps[:] = [(60, 100, 1.0, 0.3), (60.3, 80.7, 1.5, 2.0), (np.nan, 5, 1, 0), (5, 5, 0.0, 0),
+              (150, 100, 1.0, 0.0), (199.9, 199.9, 3.0, 1.0)]
+    B, t = synth.projection(np.random.default_rng(3), 512)
+    t[:] = -np.abs(t)
+    codes, c64 = compare(ref, dev, img, kps, B, t, "flat")
+    assert (codes[:2] == np.uint64(2**64 - 1)).all()  # f = 0, r = -t > 0 on every bit
+    assert not codes[2:4].any()
+
+
+def test_image_corners_clamp_to_edge(ref, dev):
+    rng = np.random.default_rng(4)
+    img = rng.random((37, 41)).astype(np.float32)
+    kps = np.zeros(5, dtype=synth.KEYPOINT_DTYPE)
+    kps[:] = [(0, 0, 1, 0), (40, 36, 2, 2), (-3, 20, 1, 1), (20, 50, 0.7, 4), (20, 18, 30.0, 0.1)]
+    B, t = synth.projection(rng, 256)
+    compare(ref, dev, img, kps, B, t, "corners")
+
+
+def test_deterministic(dev):
+    w = synth.hashsift512_pair(n_kp=2000)
+    args = (torch.from_numpy(w.image1).to(dev), bd.keypoints_tensor(w.kp1, dev), torch.from_numpy(w.B).to(dev),
+            torch.from_numpy(w.t).to(dev))
+    a = bd.describe_hashsift(*args, with_hist=True, with_resp=True)
+    b = bd.describe_hashsift(*args, with_hist=True, with_resp=True)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(to_np(x), to_np(y))
+
+
+def test_codes_without_optional_outputs(dev):
+    w = synth.hashsift512_pair(n_kp=700)
+    args = (torch.from_numpy(w.image1).to(dev), bd.keypoints_tensor(w.kp1, dev), torch.from_numpy(w.B).to(dev),
+            torch.from_numpy(w.t).to(dev))
+    a = to_np(bd.describe_hashsift(*args))
+    b = to_np(bd.describe_hashsift(*args, with_hist=True, with_resp=True)[0])
+    np.testing.assert_array_equal(a, b)

@@ -1,0 +1,64 @@
+"""Integral image on the GPU against the oracle, bit for bit (u32)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2108_08380_amd as bd
+from paper_2108_08380_amd import synth
+from conftest import to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 300), (300, 1), (3, 7), (16, 256), (17, 257), (33, 1000),
+                                 (480, 640), (1080, 1920), (241, 4097)])
+def test_integral_matches_oracle(ref, dev, H, W):
+    rng = np.random.default_rng(H * 7919 + W)
+    img = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    got = to_np(bd.build_integral(torch.from_numpy(img).to(dev)))
+    np.testing.assert_array_equal(got, ref.build_integral(img))
+
+
+def test_integral_full_size_batched_image(ref, dev):
+    """Largest image of the batched workload: 4000 x 3000 (wraps mod 2^32 nowhere, 3.06e9 < 2^32)."""
+    img = np.full((3000, 4000), 255, dtype=np.uint8)
+    img[::5, ::3] = np.random.default_rng(5).integers(0, 256, img[::5, ::3].shape, dtype=np.uint8)
+    got = to_np(bd.build_integral(torch.from_numpy(img).to(dev)))
+    np.testing.assert_array_equal(got, ref.build_integral(img))
+
+
+def test_integral_wraps_modulo_2_32(ref, dev):
+    img = np.full((4300, 4000), 255, dtype=np.uint8)  # total 4.39e9 > 2^32
+    got = to_np(bd.build_integral(torch.from_numpy(img).to(dev)))
+    exp = ref.build_integral(img)
+    np.testing.assert_array_equal(got[-5:], exp[-5:])
+    np.testing.assert_array_equal(got[::97], exp[::97])
+
+
+@pytest.mark.parametrize("pad", [1, 3, 64])
+def test_integral_pitched_input_and_output(ref, dev, pad):
+    """Row strides that are not multiples of 4 take the byte-load path."""
+    rng = np.random.default_rng(pad)
+    H, W = 45, 301
+    parent = torch.from_numpy(rng.integers(0, 256, (H, W + pad), dtype=np.uint8)).to(dev)
+    img = parent[:, :W]
+    out_parent = torch.full((H + 1, W + 1 + pad), 7, dtype=torch.uint32, device=dev)
+    out = out_parent[:, : W + 1]
+    bd.build_integral(img, out=out)
+    got = to_np(out_parent)
+    np.testing.assert_array_equal(got[:, : W + 1], ref.build_integral(to_np(img)))
+    assert (got[:, W + 1:] == 7).all(), "wrote outside the output rows"
+
+
+def test_integral_config_workload(ref, dev):
+    w = synth.bad256_pair()
+    for img in (w.image1, w.image2):
+        got = to_np(bd.build_integral(torch.from_numpy(img).to(dev)))
+        np.testing.assert_array_equal(got, ref.build_integral(img))
+
+
+def test_integral_deterministic(dev):
+    img = torch.randint(0, 256, (777, 1333), dtype=torch.uint8, device=dev)
+    a = to_np(bd.build_integral(img))
+    b = to_np(bd.build_integral(img))
+    np.testing.assert_array_equal(a, b)

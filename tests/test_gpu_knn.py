@@ -1,0 +1,89 @@
+"""Hamming k-NN on the GPU against the oracle, bit for bit (indices and distances)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2108_08380_amd as bd
+from paper_2108_08380_amd import synth
+from conftest import to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def both(ref, dev, q, t, k):
+    ei, ed = ref.match_knn(q, t, k)
+    gi, gd = bd.match_hamming_knn(torch.from_numpy(q).to(dev), torch.from_numpy(t).to(dev), k)
+    return to_np(gi), to_np(gd), ei, ed
+
+
+@pytest.mark.parametrize("n_words", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("k", [1, 2])
+def test_random_codes_with_ties(ref, dev, n_words, k):
+    rng = np.random.default_rng(n_words * 10 + k)
+    t = synth.random_codes(rng, 777, n_words)
+    t[100:110] = t[5]  # runs of equal codes: ties resolved by lower index
+    q = synth.random_codes(rng, 333, n_words)
+    q[:20] = t[5]
+    q[20:40] ^= q[20:40] & np.uint64(0xF)  # near-duplicates
+    gi, gd, ei, ed = both(ref, dev, q, t, k)
+    np.testing.assert_array_equal(gi, ei)
+    np.testing.assert_array_equal(gd, ed)
+
+
+@pytest.mark.parametrize("n_q,n_t", [(1, 1), (1, 2), (2, 1), (63, 64), (65, 63), (1000, 1000), (64, 5000),
+                                     (5000, 17), (3, 200000)])
+def test_shapes_and_split_paths(ref, dev, n_q, n_t):
+    """Small train sets run in one split (direct write); large ones split and merge."""
+    rng = np.random.default_rng(n_q * 31 + n_t)
+    q = synth.random_codes(rng, n_q, 4)
+    t = synth.random_codes(rng, n_t, 4)
+    t[n_t // 2] = q[0]
+    gi, gd, ei, ed = both(ref, dev, q, t, 2)
+    np.testing.assert_array_equal(gi, ei)
+    np.testing.assert_array_equal(gd, ed)
+
+
+def test_fewer_train_codes_than_k(ref, dev):
+    rng = np.random.default_rng(3)
+    q = synth.random_codes(rng, 70, 8)
+    gi, gd, ei, ed = both(ref, dev, q, q[:1], 2)
+    np.testing.assert_array_equal(gi, ei)
+    np.testing.assert_array_equal(gd, ed)
+    gi, gd = bd.match_hamming_knn(torch.from_numpy(q).to(dev), torch.zeros((0, 8), dtype=torch.uint64, device=dev), 2)
+    assert (to_np(gi) == -1).all() and (to_np(gd) == 0xFFFFFFFF).all()
+
+
+def test_empty_query_set(dev):
+    t = torch.zeros((5, 4), dtype=torch.uint64, device=dev)
+    gi, gd = bd.match_hamming_knn(torch.zeros((0, 4), dtype=torch.uint64, device=dev), t, 1)
+    assert gi.shape == (0, 1)
+
+
+def test_extreme_distances(ref, dev):
+    rng = np.random.default_rng(4)
+    q = synth.random_codes(rng, 50, 8)
+    gi, gd, ei, ed = both(ref, dev, q, ~q, 1)
+    assert (gd == 512).all() or (gd <= 512).all()
+    np.testing.assert_array_equal(gd, ed)
+    np.testing.assert_array_equal(gi, ei)
+
+
+@pytest.mark.parametrize("n_words,k,n", [(4, 1, 1000), (8, 2, 5000)])
+def test_config_sizes(ref, dev, n_words, k, n):
+    """1000 x 1000 BAD-256 1-NN and 5000 x 5000 HashSIFT-512 2-NN shapes."""
+    rng = np.random.default_rng(n)
+    q = synth.random_codes(rng, n, n_words)
+    t = q ^ (synth.random_codes(rng, n, n_words) & synth.random_codes(rng, n, n_words) & synth.random_codes(rng, n, n_words))
+    gi, gd, ei, ed = both(ref, dev, q, t, k)
+    np.testing.assert_array_equal(gi, ei)
+    np.testing.assert_array_equal(gd, ed)
+
+
+def test_deterministic(dev):
+    rng = np.random.default_rng(5)
+    q = torch.from_numpy(synth.random_codes(rng, 3000, 8)).to(dev)
+    t = torch.from_numpy(synth.random_codes(rng, 4000, 8)).to(dev)
+    a = [to_np(x) for x in bd.match_hamming_knn(q, t, 2)]
+    b = [to_np(x) for x in bd.match_hamming_knn(q, t, 2)]
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
