@@ -1,0 +1,271 @@
+"""Describe-and-match throughput on one MI355X.
+
+One step is the whole hot path over one image pair of 1920x1080 pixels
+with 5000 keypoints per view (keypoint scale U[1.6, 8], random angle):
+  integral image of both u8 views, BAD-256 codes for both views,
+  HashSIFT-512 codes for both float32 views (features + FP32-MFMA
+  projection), Hamming 2-NN of view 1 against view 2 for both code types.
+Inputs are seeded synthetic images shaped like the paper's timing workload
+and are resident in HBM before timing starts.  `value` counts keypoints
+described (both descriptors) and matched per second.
+
+The JSON line also carries per-stage HIP-event timings, the roofline of the
+dominant kernel and the CPU oracle timed on a bounded sample of the same
+workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 64 lanes x 2.4 GHz: one 32-bit VALU op per lane per clock (not packed)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+W, H, N_KP = 1920, 1080, 5000
+BAD_BITS, HS_BITS, K = 256, 512, 2
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph (1) or eager (0)")
+    p.add_argument("--stage-reps", type=int, default=50)
+    p.add_argument("--cpu-sample", type=int, default=2500, help="keypoints per view for the CPU oracle sample")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--only", default="", help="profile helper: run only this stage in the step loop")
+    return p.parse_args()
+
+
+class Workload:
+    def __init__(self, dev):
+        import torch
+
+        import paper_2108_08380_amd as bd
+        from paper_2108_08380_amd import synth
+
+        w = synth.hashsift512_pair(synth.SEED_BASE + 1, W, H, N_KP, HS_BITS, with_bad_bits=BAD_BITS)
+        self.host = w
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.u8 = [T(w.extra["image1_u8"]), T(w.extra["image2_u8"])]
+        self.f32 = [T(w.image1), T(w.image2)]
+        self.kps = [bd.keypoints_tensor(w.kp1, dev), bd.keypoints_tensor(w.kp2, dev)]
+        self.pairs = bd.pairs_tensor(w.pairs, dev)
+        self.B, self.t = T(w.B), T(w.t)
+        self.ii = [torch.empty((H + 1, W + 1), dtype=torch.uint32, device=dev) for _ in range(2)]
+        self.bad = [torch.empty((N_KP, BAD_BITS // 64), dtype=torch.uint64, device=dev) for _ in range(2)]
+        self.hist = [torch.empty((N_KP, 128), dtype=torch.float32, device=dev) for _ in range(2)]
+        self.hs = [torch.empty((N_KP, HS_BITS // 64), dtype=torch.uint64, device=dev) for _ in range(2)]
+        self.idx = [torch.empty((N_KP, K), dtype=torch.int32, device=dev) for _ in range(2)]
+        self.dist = [torch.empty((N_KP, K), dtype=torch.uint32, device=dev) for _ in range(2)]
+
+    # the stages of one step, each a list of library calls
+    def stages(self):
+        import paper_2108_08380_amd as bd
+
+        s = self
+        return {
+            "integral": lambda: [bd.build_integral(s.u8[v], out=s.ii[v]) for v in (0, 1)],
+            "bad_describe": lambda: [bd.describe_bad(s.ii[v], s.kps[v], s.pairs, out=s.bad[v]) for v in (0, 1)],
+            "hashsift_features": lambda: [bd.hashsift_features(s.f32[v], s.kps[v], out=s.hist[v]) for v in (0, 1)],
+            "hashsift_project": lambda: [bd.hashsift_project(s.hist[v], s.B, s.t, s.kps[v], out=s.hs[v]) for v in (0, 1)],
+            "match_bad256": lambda: bd.match_hamming_knn(s.bad[0], s.bad[1], K, s.idx[0], s.dist[0]),
+            "match_hashsift512": lambda: bd.match_hamming_knn(s.hs[0], s.hs[1], K, s.idx[1], s.dist[1]),
+        }
+
+    def step(self, only=""):
+        for name, fn in self.stages().items():
+            if not only or name == only:
+                fn()
+
+
+# algorithmic work per launch of each stage's main kernel (definitions in the design doc)
+def stage_work():
+    px = W * H
+    return {
+        # integral image: 1 byte read + 4 bytes written per pixel, per view
+        "integral": ("hbm", 5.0 * px, "GB/s"),
+        # BAD: HBM-unique bytes are keypoints + codes + the integral image once
+        "bad_describe": ("hbm", 16.0 * N_KP + BAD_BITS / 8 * N_KP + 4.0 * (px + W + H + 1), "GB/s"),
+        # HashSIFT features: ~67k ALU ops per keypoint (1156 bilinear samples x 14, 1024 pixels x 50)
+        "hashsift_features": ("alu", (1156 * 14 + 1024 * 50) * N_KP, "TOP/s"),
+        # projection: 2 * n_bits * 128 flops per keypoint on FP32 MFMA
+        "hashsift_project": ("mfma", 2.0 * HS_BITS * 128 * N_KP, "TFLOP/s"),
+        # Hamming: per pair 4 ops per 64-bit word (2 xor + 2 popcount) + 4 for the top-2 key update
+        "match_bad256": ("alu", (4 * BAD_BITS / 64 + 4) * float(N_KP) * N_KP, "TOP/s"),
+        "match_hashsift512": ("alu", (4 * HS_BITS / 64 + 4) * float(N_KP) * N_KP, "TOP/s"),
+    }
+
+
+def peak_of(bound):
+    return {"hbm": HBM_PEAK_GBS, "alu": ALU_PEAK_TOPS, "mfma": FP32_MFMA_PEAK_TFLOPS}[bound]
+
+
+def time_stages(wl, reps):
+    """Average duration of each stage's launches, with HIP events on the launch stream."""
+    import torch
+
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, fn in wl.stages().items():
+        fn()
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(reps):
+            fn()
+        end.record(stream)
+        end.synchronize()
+        ms = start.elapsed_time(end) / reps
+        # two launches per rep for per-view stages
+        per_launch = ms / (2 if name in ("integral", "bad_describe", "hashsift_features", "hashsift_project") else 1)
+        out[name] = per_launch
+    return out
+
+
+def cpu_baseline(sample: int):
+    """The oracle on `sample` keypoints per view (full integral images), scaled to the full step."""
+    import oracle
+    from paper_2108_08380_amd import synth
+
+    w = synth.hashsift512_pair(synth.SEED_BASE + 1, W, H, N_KP, HS_BITS, with_bad_bits=BAD_BITS)
+    oracle.lib()
+    t0 = time.perf_counter()
+    ii = [oracle.build_integral(w.extra["image1_u8"]), oracle.build_integral(w.extra["image2_u8"])]
+    t_int = time.perf_counter() - t0
+    kps = [w.kp1[:sample], w.kp2[:sample]]
+    t0 = time.perf_counter()
+    bad = [oracle.describe_bad(ii[v], kps[v], w.pairs)[0] for v in (0, 1)]
+    hs = [oracle.describe_hashsift([w.image1, w.image2][v], kps[v], w.B, w.t)[2] for v in (0, 1)]
+    t_desc = time.perf_counter() - t0
+    # the sample's queries against the full train set of the other view
+    bad_train = oracle.describe_bad(ii[1], w.kp2, w.pairs)[0]
+    hs_train = oracle.describe_hashsift(w.image2, w.kp2, w.B, w.t)[2]
+    t0 = time.perf_counter()
+    oracle.match_knn(bad[0], bad_train, K)
+    oracle.match_knn(hs[0], hs_train, K)
+    t_match = time.perf_counter() - t0
+    scale = N_KP / sample
+    t_step = t_int + scale * t_desc + scale * t_match
+    return {
+        "value": round(2 * N_KP / t_step, 1),
+        "unit": "keypoints/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"full integral images of both views; BAD-256 + HashSIFT-512 of {sample} keypoints per view; "
+                  f"{sample} queries x {N_KP} train codes 2-NN per code type; scaled to {N_KP} keypoints per view",
+        "seconds": round(t_int + t_desc + t_match, 2),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is described "
+                                   "in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import torch
+
+    dev = torch.device("cuda:0")
+    wl = Workload(dev)
+    torch.cuda.synchronize()
+
+    # warm-up (allocates the library workspace before any graph capture)
+    for _ in range(max(1, args.warmup)):
+        wl.step(args.only)
+    torch.cuda.synchronize()
+
+    graph = None
+    if args.graph and not args.only:
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            wl.step()
+        torch.cuda.current_stream().wait_stream(stream)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            wl.step()
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        if graph is not None:
+            graph.replay()
+        else:
+            wl.step(args.only)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # the replayed graph must reproduce the eager results; also the sanity rate of
+    # true matches (keypoint i of view 1 is keypoint i of view 2)
+    check = {}
+    if not args.only:
+        snap = [x.clone() for x in (wl.bad[0], wl.hs[0], wl.idx[0], wl.idx[1])]
+        wl.step()
+        torch.cuda.synchronize()
+        check["graph_equals_eager"] = all(torch.equal(a, b) for a, b in
+                                          zip(snap, (wl.bad[0], wl.hs[0], wl.idx[0], wl.idx[1])))
+        ar = torch.arange(N_KP, device=dev, dtype=torch.int32)
+        check["true_match_rate_bad256"] = round(float((wl.idx[0][:, 0] == ar).float().mean()), 4)
+        check["true_match_rate_hashsift512"] = round(float((wl.idx[1][:, 0] == ar).float().mean()), 4)
+
+    stage_ms = time_stages(wl, args.stage_reps) if not args.only else {}
+    work = stage_work()
+    stages = {}
+    for name, ms in stage_ms.items():
+        bound, units, unit = work[name]
+        achieved = units / (ms * 1e-3) / 1e9 if bound == "hbm" else units / (ms * 1e-3) / 1e12
+        stages[name] = {"ms_per_launch": round(ms, 5), "bound": bound, "achieved": round(achieved, 2),
+                        "unit": unit, "frac": round(achieved / peak_of(bound), 4)}
+    roofline = None
+    if stages:
+        dom = max(stages, key=lambda n: stages[n]["ms_per_launch"])
+        d = stages[dom]
+        roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": peak_of(d["bound"]),
+                    "unit": d["unit"], "frac": d["frac"], "traffic": None}
+
+    result = {
+        "metric": "keypoints described/s (BAD-256, HashSIFT-512) + Hamming pairs/s, 1 MI355X",
+        "value": round(2 * N_KP / (ms_per_step * 1e-3), 1),
+        "unit": "keypoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8/u32 integer (integral, BAD, Hamming); f32 (HashSIFT, FP32 MFMA projection)",
+        "data": "synthetic",
+        "config": {"workload": f"describe-and-match, {W}x{H} image pair, {N_KP} keypoints per view, BAD-256 + "
+                               f"HashSIFT-512, Hamming 2-NN {N_KP}x{N_KP} per code type",
+                   "graph": bool(graph is not None), "only": args.only or None},
+        "hamming_pairs_per_s": round(2 * N_KP * N_KP / (ms_per_step * 1e-3), 1),
+        "stages": stages,
+        "checks": check,
+        "roofline": roofline,
+    }
+    if not args.no_cpu and not args.only:
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

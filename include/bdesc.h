@@ -128,6 +128,27 @@ int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_
                          float* hist_out, float* resp_out, void* stream);
 
 /*
+ * HashSIFT features only (the f(x) of Sec. III-B, exactly as computed inside
+ * bd_describe_hashsift): hist receives n_kp x 128 float32, L2-normalized;
+ * invalid keypoints give zero rows.  Arguments as bd_describe_hashsift.
+ */
+int bd_hashsift_features(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
+                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, float* hist,
+                         void* stream);
+
+/*
+ * HashSIFT binarization of given features (Sec. III-B, D = sgn(B [f; 1])):
+ * r = B f - t on FP32 MFMA, bit j set when r_j > 0.
+ *   hist     n_kp x 128 float32 features (row stride 128)
+ *   kps      optional (NULL = all valid): keypoints whose codes are forced
+ *            to zero when invalid, as in bd_describe_hashsift
+ *   resp_out optional (NULL) n_kp x n_bits float32 responses
+ */
+int bd_hashsift_project(bd_context* ctx, const float* hist, const bd_keypoint* kps, int32_t n_kp,
+                        const float* B, const float* t, int32_t n_bits, int32_t precision,
+                        uint64_t* codes, float* resp_out, void* stream);
+
+/*
  * Brute-force Hamming k-NN (Sec. III-A: S(x, y) = h(x)^T h(y) = K - 2 d_H,
  * so the most similar code has the smallest Hamming distance).
  *   query    n_q x n_words words;  train  n_t x n_words words

@@ -42,6 +42,8 @@ SIGNATURES = {
     "bd_describe_bad": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _I32, _P, _P], ctypes.c_int),
     "bd_describe_hashsift": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _I32, _I32, _P, _P, _P, _P],
                              ctypes.c_int),
+    "bd_hashsift_features": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P], ctypes.c_int),
+    "bd_hashsift_project": ([_P, _P, _P, _I32, _P, _P, _I32, _I32, _P, _P, _P], ctypes.c_int),
     "bd_match_hamming_knn": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
 }
 
@@ -223,6 +225,58 @@ def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool =
     if with_hist or with_resp:
         return out, hist, resp
     return out
+
+
+def _image_dtype(img):
+    torch = _torch()
+    if img.dtype == torch.uint8:
+        return BD_DTYPE_U8
+    if img.dtype == torch.float32:
+        return BD_DTYPE_F32
+    raise TypeError("img must be uint8 or float32")
+
+
+def hashsift_features(img, kps, out=None):
+    """(n, 128) float32 L2-normalized HashSIFT features (bd_hashsift_features)."""
+    torch = _torch()
+    dtype = _image_dtype(img)
+    _require(img, img.dtype, 2, "img")
+    _require(kps, torch.float32, 2, "kps")
+    _contig(kps, "kps")
+    H, W = img.shape
+    n = kps.shape[0]
+    if out is None:
+        out = torch.empty((n, 128), dtype=torch.float32, device=img.device)
+    _contig(out, "out")
+    dev, stream = _device_and_stream(img, kps, out)
+    _check(lib().bd_hashsift_features(context(dev), img.data_ptr(), dtype, W, H, img.stride(0) * img.element_size(),
+                                      kps.data_ptr(), n, out.data_ptr(), stream))
+    return out
+
+
+def hashsift_project(hist, B, t, kps=None, precision: str = "fp32", with_resp: bool = False, out=None):
+    """Codes (and optionally responses) of given features (bd_hashsift_project)."""
+    torch = _torch()
+    _require(hist, torch.float32, 2, "hist")
+    _contig(hist, "hist")
+    _require(B, torch.float32, 2, "B")
+    _contig(B, "B")
+    _contig(t, "t")
+    n, n_bits = hist.shape[0], B.shape[0]
+    if hist.shape[1] != 128 or B.shape[1] != 128 or t.shape != (n_bits,):
+        raise ValueError("hist (n, 128), B (n_bits, 128), t (n_bits,)")
+    if kps is not None:
+        _contig(kps, "kps")
+        if kps.shape[0] != n:
+            raise ValueError("kps must have one row per feature row")
+    if out is None:
+        out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=hist.device)
+    resp = torch.empty((n, n_bits), dtype=torch.float32, device=hist.device) if with_resp else None
+    dev, stream = _device_and_stream(hist, B, t, out, kps, resp)
+    _check(lib().bd_hashsift_project(context(dev), hist.data_ptr(), kps.data_ptr() if kps is not None else None, n,
+                                     B.data_ptr(), t.data_ptr(), n_bits, _PRECISIONS[precision], out.data_ptr(),
+                                     resp.data_ptr() if resp is not None else None, stream))
+    return (out, resp) if with_resp else out
 
 
 def match_hamming_knn(query, train, k: int = 1, idx=None, dist=None):

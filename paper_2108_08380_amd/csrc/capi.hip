@@ -174,19 +174,58 @@ int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, i
     return check_launch(fn);
 }
 
+int check_image(const char* fn, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch)
+{
+    if (dtype != BD_DTYPE_U8 && dtype != BD_DTYPE_F32) return fail(BD_EUNSUPPORTED, "%s: dtype %d", fn, dtype);
+    if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
+    const int64_t elem = dtype == BD_DTYPE_U8 ? 1 : 4;
+    if (img_pitch < W * elem) return fail(BD_EINVAL, "%s: img_pitch %lld < row bytes", fn, (long long)img_pitch);
+    if (dtype == BD_DTYPE_F32 && img_pitch % 4 != 0) return fail(BD_EINVAL, "%s: f32 img_pitch must be a multiple of 4", fn);
+    return BD_OK;
+}
+
+int check_projection(const char* fn, int32_t n_bits, int32_t precision)
+{
+    if (!is_supported_bits(n_bits)) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (256 or 512)", fn, n_bits);
+    if (precision != BD_PREC_FP32) return fail(BD_EUNSUPPORTED, "%s: precision %d", fn, precision);
+    return BD_OK;
+}
+
+int bd_hashsift_features(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
+                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, float* hist, void* stream)
+{
+    const char* fn = "bd_hashsift_features";
+    if (int rc = check_image(fn, dtype, W, H, img_pitch)) return rc;
+    if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
+    if (n_kp > 0 && (!img || !kps || !hist)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n_kp == 0) return BD_OK;
+    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, hist, static_cast<hipStream_t>(stream));
+    return check_launch(fn);
+}
+
+int bd_hashsift_project(bd_context* ctx, const float* hist, const bd_keypoint* kps, int32_t n_kp, const float* B,
+                        const float* t, int32_t n_bits, int32_t precision, uint64_t* codes, float* resp_out,
+                        void* stream)
+{
+    const char* fn = "bd_hashsift_project";
+    if (int rc = check_projection(fn, n_bits, precision)) return rc;
+    if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
+    if (n_kp > 0 && (!hist || !B || !t || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n_kp == 0) return BD_OK;
+    launch_hashsift_project_fp32(hist, kps, n_kp, B, t, n_bits / 64, codes, resp_out, static_cast<hipStream_t>(stream));
+    return check_launch(fn);
+}
+
 int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
                          int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const float* B,
                          const float* t, int32_t n_bits, int32_t precision, uint64_t* codes,
                          float* hist_out, float* resp_out, void* stream)
 {
     const char* fn = "bd_describe_hashsift";
-    if (!is_supported_bits(n_bits)) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (256 or 512)", fn, n_bits);
-    if (dtype != BD_DTYPE_U8 && dtype != BD_DTYPE_F32) return fail(BD_EUNSUPPORTED, "%s: dtype %d", fn, dtype);
-    if (precision != BD_PREC_FP32) return fail(BD_EUNSUPPORTED, "%s: precision %d", fn, precision);
-    if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
-    const int64_t elem = dtype == BD_DTYPE_U8 ? 1 : 4;
-    if (img_pitch < W * elem) return fail(BD_EINVAL, "%s: img_pitch %lld < row bytes", fn, (long long)img_pitch);
-    if (dtype == BD_DTYPE_F32 && img_pitch % 4 != 0) return fail(BD_EINVAL, "%s: f32 img_pitch must be a multiple of 4", fn);
+    if (int rc = check_projection(fn, n_bits, precision)) return rc;
+    if (int rc = check_image(fn, dtype, W, H, img_pitch)) return rc;
     if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
     if (n_kp > 0 && (!img || !kps || !B || !t || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
     if (int rc = check_ctx(ctx, fn)) return rc;

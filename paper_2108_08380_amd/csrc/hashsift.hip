@@ -281,8 +281,11 @@ __global__ __launch_bounds__(256) void hashsift_project_fp32_kernel(const float*
     // validity of the keypoint whose word this lane stores (lanes 0..15)
     bool valid = false;
     if (lane < 16 && wave_kp + lane < n_kp) {
-        const bd_keypoint kp = kps[wave_kp + lane];
-        valid = finite_f(kp.x) && finite_f(kp.y) && finite_f(kp.scale) && finite_f(kp.angle) && kp.scale > 0.0f;
+        valid = true;
+        if (kps) {
+            const bd_keypoint kp = kps[wave_kp + lane];
+            valid = finite_f(kp.x) && finite_f(kp.y) && finite_f(kp.scale) && finite_f(kp.angle) && kp.scale > 0.0f;
+        }
     }
 
     for (int chunk = 0; chunk < n_words; ++chunk) {
