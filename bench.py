@@ -2,6 +2,7 @@
 
 One step is the whole hot path over one image pair of 1920x1080 pixels
 with 5000 keypoints per view (keypoint scale U[1.6, 8], random angle):
+  spatial processing order of both keypoint sets,
   integral image of both u8 views, BAD-256 codes for both views,
   HashSIFT-512 codes for both float32 views (features + FP32-MFMA
   projection), Hamming 2-NN of view 1 against view 2 for both code types.
@@ -45,6 +46,8 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=2500, help="keypoints per view for the CPU oracle sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--only", default="", help="profile helper: run only this stage in the step loop")
+    p.add_argument("--copy-calibration-mb", type=int, default=0,
+                   help="run a plain device copy of this many MiB five times and exit (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -63,6 +66,7 @@ class Workload:
         self.kps = [bd.keypoints_tensor(w.kp1, dev), bd.keypoints_tensor(w.kp2, dev)]
         self.pairs = bd.pairs_tensor(w.pairs, dev)
         self.B, self.t = T(w.B), T(w.t)
+        self.order = [torch.empty((N_KP,), dtype=torch.int32, device=dev) for _ in range(2)]
         self.ii = [torch.empty((H + 1, W + 1), dtype=torch.uint32, device=dev) for _ in range(2)]
         self.bad = [torch.empty((N_KP, BAD_BITS // 64), dtype=torch.uint64, device=dev) for _ in range(2)]
         self.hist = [torch.empty((N_KP, 128), dtype=torch.float32, device=dev) for _ in range(2)]
@@ -76,9 +80,12 @@ class Workload:
 
         s = self
         return {
+            "keypoint_order": lambda: [bd.keypoint_order(s.kps[v], W, H, out=s.order[v]) for v in (0, 1)],
             "integral": lambda: [bd.build_integral(s.u8[v], out=s.ii[v]) for v in (0, 1)],
-            "bad_describe": lambda: [bd.describe_bad(s.ii[v], s.kps[v], s.pairs, out=s.bad[v]) for v in (0, 1)],
-            "hashsift_features": lambda: [bd.hashsift_features(s.f32[v], s.kps[v], out=s.hist[v]) for v in (0, 1)],
+            "bad_describe": lambda: [bd.describe_bad(s.ii[v], s.kps[v], s.pairs, out=s.bad[v], order=s.order[v])
+                                     for v in (0, 1)],
+            "hashsift_features": lambda: [bd.hashsift_features(s.f32[v], s.kps[v], out=s.hist[v], order=s.order[v])
+                                          for v in (0, 1)],
             "hashsift_project": lambda: [bd.hashsift_project(s.hist[v], s.B, s.t, s.kps[v], out=s.hs[v]) for v in (0, 1)],
             "match_bad256": lambda: bd.match_hamming_knn(s.bad[0], s.bad[1], K, s.idx[0], s.dist[0]),
             "match_hashsift512": lambda: bd.match_hamming_knn(s.hs[0], s.hs[1], K, s.idx[1], s.dist[1]),
@@ -94,6 +101,8 @@ class Workload:
 def stage_work():
     px = W * H
     return {
+        # keypoint order: 16 bytes read + 4 bytes written per keypoint
+        "keypoint_order": ("hbm", 20.0 * N_KP, "GB/s"),
         # integral image: 1 byte read + 4 bytes written per pixel, per view
         "integral": ("hbm", 5.0 * px, "GB/s"),
         # BAD: HBM-unique bytes are keypoints + codes + the integral image once
@@ -129,7 +138,8 @@ def time_stages(wl, reps):
         end.synchronize()
         ms = start.elapsed_time(end) / reps
         # two launches per rep for per-view stages
-        per_launch = ms / (2 if name in ("integral", "bad_describe", "hashsift_features", "hashsift_project") else 1)
+        per_launch = ms / (2 if name in ("keypoint_order", "integral", "bad_describe", "hashsift_features",
+                                         "hashsift_project") else 1)
         out[name] = per_launch
     return out
 
@@ -178,6 +188,15 @@ def main():
     import torch
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb << 20
+        src = torch.randint(0, 255, (n,), dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "reps": 5}))
+        return
     wl = Workload(dev)
     torch.cuda.synchronize()
 

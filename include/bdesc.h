@@ -90,12 +90,26 @@ int bd_build_integral(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H,
                       int64_t img_pitch, uint32_t* ii, int64_t ii_pitch, void* stream);
 
 /*
+ * Spatial processing order for a keypoint set: order receives a permutation
+ * of 0..n_kp-1 that groups keypoints by cell of a 64 x 64 grid over the W x H
+ * image, cells in Morton order (keypoints within a cell in no fixed order).
+ * Passing it to the describe calls makes each XCD of the GPU work on one
+ * image region, which keeps its gathers in that XCD's L2.  It never changes
+ * the codes: every code is still written at its keypoint's own index.  One
+ * order serves BAD and HashSIFT of the same keypoints.  n_kp <= 2^31 - 1.
+ */
+int bd_keypoint_order(bd_context* ctx, const bd_keypoint* kps, int32_t n_kp, int32_t W, int32_t H,
+                      int32_t* order, void* stream);
+
+/*
  * BAD codes (Sec. III-A: weak descriptor h(x; f, theta) = +1 when
  * f(x; u1, u2, s) <= theta, f the difference of the mean grey levels of two
  * boxes of side s; the bits of h(x) = [h_1 .. h_K]).
  *   ii       integral image of a W x H u8 image as written by
  *            bd_build_integral, row stride ii_pitch elements
  *   kps      n_kp keypoints;  pairs  n_bits box pairs
+ *   order    optional (NULL): processing order from bd_keypoint_order (any
+ *            permutation of 0..n_kp-1; entries outside that range are skipped)
  *   codes    n_kp x n_bits/64 words; bit j set when h_j = +1
  * n_bits is 256 or 512.  Per keypoint and pair: box radius
  * R = floor(radius * scale + 0.5) capped at (min(W,H)-1)/2, centre = patch
@@ -103,14 +117,15 @@ int bd_build_integral(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H,
  * box lies inside the image, bit = [S1 - S2 <= theta * (2R+1)^2] exactly.
  */
 int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch,
-                    const bd_keypoint* kps, int32_t n_kp, const bd_box_pair* pairs,
-                    int32_t n_bits, uint64_t* codes, void* stream);
+                    const bd_keypoint* kps, int32_t n_kp, const int32_t* order,
+                    const bd_box_pair* pairs, int32_t n_bits, uint64_t* codes, void* stream);
 
 /*
  * HashSIFT codes (Sec. III-B: D(x) = sgn(B [f(x); 1]) with f the SIFT
  * feature vector of the normalized 32x32 patch).
  *   img      H rows of W pixels (dtype BD_DTYPE_U8 or BD_DTYPE_F32), row
  *            stride img_pitch bytes (a multiple of 4 for f32)
+ *   order    optional (NULL) processing order, as for bd_describe_bad
  *   B        n_bits x 128 float32, row major;  t  n_bits thresholds
  *            (the paper's last column of B is -t)
  *   codes    n_kp x n_bits/64 words; bit j set when r_j = B_j . f - t_j > 0
@@ -123,9 +138,9 @@ int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, i
  * The projection runs on FP32 MFMA.
  */
 int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
-                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const float* B,
-                         const float* t, int32_t n_bits, int32_t precision, uint64_t* codes,
-                         float* hist_out, float* resp_out, void* stream);
+                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const int32_t* order,
+                         const float* B, const float* t, int32_t n_bits, int32_t precision,
+                         uint64_t* codes, float* hist_out, float* resp_out, void* stream);
 
 /*
  * HashSIFT features only (the f(x) of Sec. III-B, exactly as computed inside
@@ -133,8 +148,8 @@ int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_
  * invalid keypoints give zero rows.  Arguments as bd_describe_hashsift.
  */
 int bd_hashsift_features(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
-                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, float* hist,
-                         void* stream);
+                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const int32_t* order,
+                         float* hist, void* stream);
 
 /*
  * HashSIFT binarization of given features (Sec. III-B, D = sgn(B [f; 1])):

@@ -39,10 +39,11 @@ SIGNATURES = {
     "bd_last_error": ([], ctypes.c_char_p),
     "bd_version": ([], ctypes.c_char_p),
     "bd_build_integral": ([_P, _P, _I32, _I32, _I64, _P, _I64, _P], ctypes.c_int),
-    "bd_describe_bad": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _I32, _P, _P], ctypes.c_int),
-    "bd_describe_hashsift": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _I32, _I32, _P, _P, _P, _P],
+    "bd_keypoint_order": ([_P, _P, _I32, _I32, _I32, _P, _P], ctypes.c_int),
+    "bd_describe_bad": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _P, _I32, _P, _P], ctypes.c_int),
+    "bd_describe_hashsift": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P, _I32, _I32, _P, _P, _P, _P],
                              ctypes.c_int),
-    "bd_hashsift_features": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P], ctypes.c_int),
+    "bd_hashsift_features": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P], ctypes.c_int),
     "bd_hashsift_project": ([_P, _P, _P, _I32, _P, _P, _I32, _I32, _P, _P, _P], ctypes.c_int),
     "bd_match_hamming_knn": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
 }
@@ -167,7 +168,29 @@ def build_integral(img, out=None):
     return out
 
 
-def describe_bad(ii, kps, pairs, n_bits: int | None = None, out=None):
+def _order_arg(order, n):
+    torch = _torch()
+    if order is None:
+        return None
+    if order.dtype != torch.int32 or order.shape != (n,) or not order.is_contiguous():
+        raise ValueError("order must be a contiguous (n_kp,) int32 tensor")
+    return order.data_ptr()
+
+
+def keypoint_order(kps, width: int, height: int, out=None):
+    """Spatial processing order of keypoints (bd_keypoint_order) -> (n,) int32 permutation."""
+    torch = _torch()
+    _require(kps, torch.float32, 2, "kps")
+    _contig(kps, "kps")
+    n = kps.shape[0]
+    if out is None:
+        out = torch.empty((n,), dtype=torch.int32, device=kps.device)
+    dev, stream = _device_and_stream(kps, out)
+    _check(lib().bd_keypoint_order(context(dev), kps.data_ptr(), n, width, height, out.data_ptr(), stream))
+    return out
+
+
+def describe_bad(ii, kps, pairs, n_bits: int | None = None, out=None, order=None):
     """BAD codes from an integral image (bd_describe_bad)."""
     torch = _torch()
     _require(ii, torch.uint32, 2, "ii")
@@ -184,14 +207,14 @@ def describe_bad(ii, kps, pairs, n_bits: int | None = None, out=None):
     if out is None:
         out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=ii.device)
     _contig(out, "out")
-    dev, stream = _device_and_stream(ii, kps, pairs, out)
+    dev, stream = _device_and_stream(ii, kps, pairs, out, order)
     _check(lib().bd_describe_bad(context(dev), ii.data_ptr(), W, H, ii.stride(0), kps.data_ptr(), n,
-                                 pairs.data_ptr(), n_bits, out.data_ptr(), stream))
+                                 _order_arg(order, n), pairs.data_ptr(), n_bits, out.data_ptr(), stream))
     return out
 
 
 def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool = False,
-                      with_resp: bool = False, out=None):
+                      with_resp: bool = False, out=None, order=None):
     """HashSIFT codes (bd_describe_hashsift).  Returns codes, or (codes, hist, resp)
     when with_hist or with_resp is set (the unrequested ones are None)."""
     torch = _torch()
@@ -216,9 +239,9 @@ def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool =
         out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=img.device)
     hist = torch.empty((n, 128), dtype=torch.float32, device=img.device) if with_hist else None
     resp = torch.empty((n, n_bits), dtype=torch.float32, device=img.device) if with_resp else None
-    dev, stream = _device_and_stream(img, kps, B, t, out, hist, resp)
+    dev, stream = _device_and_stream(img, kps, B, t, out, hist, resp, order)
     _check(lib().bd_describe_hashsift(context(dev), img.data_ptr(), dtype, W, H, img.stride(0) * img.element_size(),
-                                      kps.data_ptr(), n, B.data_ptr(), t.data_ptr(), n_bits,
+                                      kps.data_ptr(), n, _order_arg(order, n), B.data_ptr(), t.data_ptr(), n_bits,
                                       _PRECISIONS[precision], out.data_ptr(),
                                       hist.data_ptr() if hist is not None else None,
                                       resp.data_ptr() if resp is not None else None, stream))
@@ -236,7 +259,7 @@ def _image_dtype(img):
     raise TypeError("img must be uint8 or float32")
 
 
-def hashsift_features(img, kps, out=None):
+def hashsift_features(img, kps, out=None, order=None):
     """(n, 128) float32 L2-normalized HashSIFT features (bd_hashsift_features)."""
     torch = _torch()
     dtype = _image_dtype(img)
@@ -248,9 +271,9 @@ def hashsift_features(img, kps, out=None):
     if out is None:
         out = torch.empty((n, 128), dtype=torch.float32, device=img.device)
     _contig(out, "out")
-    dev, stream = _device_and_stream(img, kps, out)
+    dev, stream = _device_and_stream(img, kps, out, order)
     _check(lib().bd_hashsift_features(context(dev), img.data_ptr(), dtype, W, H, img.stride(0) * img.element_size(),
-                                      kps.data_ptr(), n, out.data_ptr(), stream))
+                                      kps.data_ptr(), n, _order_arg(order, n), out.data_ptr(), stream))
     return out
 
 

@@ -28,6 +28,21 @@ int reserve_workspace(bd_context* ctx, size_t bytes, hipStream_t stream, void** 
 int check_launch(const char* what);
 
 constexpr int kWave = 64;
+constexpr int kXcds = 8;
+
+// XCD-aware block mapping.  Workgroups of one dispatch go to the 8 XCDs in
+// round-robin order of their block index, so block b runs on XCD b % 8.
+// Logical block (b % 8) * ceil(nb / 8) + b / 8 gives XCD x the contiguous
+// logical range [x * ceil(nb/8), (x+1) * ceil(nb/8)); with keypoints in
+// spatial order that range is one region of the image, which then fits the
+// XCD's own L2.  The grid is padded to a multiple of 8 and blocks whose
+// logical index reaches nb exit.
+inline int xcd_grid(int nb) { return (nb + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ int xcd_logical_block(int b, int nb)
+{
+    const int per = (nb + kXcds - 1) / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
 
 // ---- integral image (integral.hip)
 struct IntegralPlan {
@@ -42,12 +57,17 @@ void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitc
 
 // ---- BAD (bad.hip)
 void launch_bad(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch, const bd_keypoint* kps,
-                int32_t n_kp, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes,
+                int32_t n_kp, const int32_t* order, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes,
                 hipStream_t stream);
+
+// ---- spatial keypoint order (order.hip)
+void launch_keypoint_order(const bd_keypoint* kps, int32_t n_kp, int32_t W, int32_t H, int32_t* order,
+                           hipStream_t stream);
 
 // ---- HashSIFT (hashsift.hip)
 void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
-                          const bd_keypoint* kps, int32_t n_kp, float* hist, hipStream_t stream);
+                          const bd_keypoint* kps, int32_t n_kp, const int32_t* order, float* hist,
+                          hipStream_t stream);
 void launch_hashsift_project_fp32(const float* hist, const bd_keypoint* kps, int32_t n_kp,
                                   const float* B, const float* t, int32_t n_words, uint64_t* codes,
                                   float* resp, hipStream_t stream);

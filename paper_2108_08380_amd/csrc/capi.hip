@@ -157,9 +157,22 @@ int bd_build_integral(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H,
     return check_launch(fn);
 }
 
+int bd_keypoint_order(bd_context* ctx, const bd_keypoint* kps, int32_t n_kp, int32_t W, int32_t H,
+                      int32_t* order, void* stream)
+{
+    const char* fn = "bd_keypoint_order";
+    if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
+    if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
+    if (n_kp > 0 && (!kps || !order)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n_kp == 0) return BD_OK;
+    launch_keypoint_order(kps, n_kp, W, H, order, static_cast<hipStream_t>(stream));
+    return check_launch(fn);
+}
+
 int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch,
-                    const bd_keypoint* kps, int32_t n_kp, const bd_box_pair* pairs, int32_t n_bits,
-                    uint64_t* codes, void* stream)
+                    const bd_keypoint* kps, int32_t n_kp, const int32_t* order, const bd_box_pair* pairs,
+                    int32_t n_bits, uint64_t* codes, void* stream)
 {
     const char* fn = "bd_describe_bad";
     if (!is_supported_bits(n_bits)) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (256 or 512)", fn, n_bits);
@@ -170,7 +183,7 @@ int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, i
     if (n_kp > 0 && (!ii || !kps || !pairs || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
     if (int rc = check_ctx(ctx, fn)) return rc;
     if (n_kp == 0) return BD_OK;
-    launch_bad(ii, W, H, ii_pitch, kps, n_kp, pairs, n_bits / 64, codes, static_cast<hipStream_t>(stream));
+    launch_bad(ii, W, H, ii_pitch, kps, n_kp, order, pairs, n_bits / 64, codes, static_cast<hipStream_t>(stream));
     return check_launch(fn);
 }
 
@@ -192,7 +205,8 @@ int check_projection(const char* fn, int32_t n_bits, int32_t precision)
 }
 
 int bd_hashsift_features(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
-                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, float* hist, void* stream)
+                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const int32_t* order,
+                         float* hist, void* stream)
 {
     const char* fn = "bd_hashsift_features";
     if (int rc = check_image(fn, dtype, W, H, img_pitch)) return rc;
@@ -200,7 +214,7 @@ int bd_hashsift_features(bd_context* ctx, const void* img, int32_t dtype, int32_
     if (n_kp > 0 && (!img || !kps || !hist)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
     if (int rc = check_ctx(ctx, fn)) return rc;
     if (n_kp == 0) return BD_OK;
-    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, hist, static_cast<hipStream_t>(stream));
+    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, order, hist, static_cast<hipStream_t>(stream));
     return check_launch(fn);
 }
 
@@ -219,8 +233,8 @@ int bd_hashsift_project(bd_context* ctx, const float* hist, const bd_keypoint* k
 }
 
 int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
-                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const float* B,
-                         const float* t, int32_t n_bits, int32_t precision, uint64_t* codes,
+                         int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const int32_t* order,
+                         const float* B, const float* t, int32_t n_bits, int32_t precision, uint64_t* codes,
                          float* hist_out, float* resp_out, void* stream)
 {
     const char* fn = "bd_describe_hashsift";
@@ -237,7 +251,7 @@ int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_
         if (int rc = reserve_workspace(ctx, sizeof(float) * 128 * (size_t)n_kp, s, &ws)) return rc;
         hist = static_cast<float*>(ws);
     }
-    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, hist, s);
+    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, order, hist, s);
     launch_hashsift_project_fp32(hist, kps, n_kp, B, t, n_bits / 64, codes, resp_out, s);
     return check_launch(fn);
 }

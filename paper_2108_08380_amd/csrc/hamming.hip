@@ -68,6 +68,7 @@ __global__ __launch_bounds__(256) void hamming_knn_kernel(const uint64_t* __rest
     }
 
     const uint32_t* rows = reinterpret_cast<const uint32_t*>(train);
+#pragma unroll 2
     for (int r = t0; r < t1; ++r) {
         const uint32_t* row = rows + (int64_t)r * (2 * NW);
         uint32_t tl[NW], th[NW];
@@ -108,35 +109,65 @@ __global__ __launch_bounds__(256) void hamming_knn_kernel(const uint64_t* __rest
     }
 }
 
-// One thread per query: merge the per-split top-k into the final top-k.
+// Merge of the per-split top-k: a block covers 64 queries, its four
+// wavefronts take every fourth split each (eight loads in flight per lane),
+// and the four partial results meet in LDS.  Keys become 64-bit (distance in
+// the high word, global row in the low word) so the order stays
+// lexicographic in (distance, index).
+template <int KK>
+__device__ __forceinline__ void topk_insert64(uint64_t (&best)[KK], uint64_t k64)
+{
+    if constexpr (KK == 1) {
+        best[0] = k64 < best[0] ? k64 : best[0];
+    } else {
+        const uint64_t hi = k64 > best[0] ? k64 : best[0];
+        best[0] = k64 < best[0] ? k64 : best[0];
+        best[1] = hi < best[1] ? hi : best[1];
+    }
+}
+
 template <int KK>
 __global__ __launch_bounds__(256) void hamming_merge_kernel(const uint32_t* __restrict__ partial, int32_t n_q,
                                                             int32_t splits, int32_t rows_per_split,
                                                             int32_t* __restrict__ out_idx,
                                                             uint32_t* __restrict__ out_dist)
 {
-    const int qi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (qi >= n_q) return;
-    // 64-bit keys: distance in the high word, global row in the low word
+    __shared__ uint64_t part[4][kWave][KK];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int qi = blockIdx.x * kWave + lane;
     uint64_t best[KK];
 #pragma unroll
     for (int s = 0; s < KK; ++s) best[s] = ~0ull;
-    for (int sp = 0; sp < splits; ++sp) {
+    if (qi < n_q) {
+        constexpr int kBatch = 8;
+        for (int sp0 = wave; sp0 < splits; sp0 += 4 * kBatch) {
+            uint32_t key[kBatch][KK];
 #pragma unroll
-        for (int s = 0; s < KK; ++s) {
-            const uint32_t key = partial[((int64_t)sp * n_q + qi) * KK + s];
-            if (key == kEmpty) continue;
-            const uint64_t k64 = ((uint64_t)(key >> kRowBits) << 32) |
-                                 (uint64_t)(uint32_t)(sp * rows_per_split + (int)(key & kRowMask));
-            if constexpr (KK == 1) {
-                best[0] = k64 < best[0] ? k64 : best[0];
-            } else {
-                const uint64_t hi = k64 > best[0] ? k64 : best[0];
-                best[0] = k64 < best[0] ? k64 : best[0];
-                best[1] = hi < best[1] ? hi : best[1];
+            for (int b = 0; b < kBatch; ++b) {
+                const int sp = sp0 + 4 * b;
+#pragma unroll
+                for (int s = 0; s < KK; ++s) key[b][s] = sp < splits ? partial[((int64_t)sp * n_q + qi) * KK + s] : kEmpty;
+            }
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const int sp = sp0 + 4 * b;
+#pragma unroll
+                for (int s = 0; s < KK; ++s) {
+                    if (key[b][s] == kEmpty) continue;
+                    const uint32_t row = (uint32_t)(sp * rows_per_split) + (key[b][s] & kRowMask);
+                    topk_insert64<KK>(best, ((uint64_t)(key[b][s] >> kRowBits) << 32) | row);
+                }
             }
         }
     }
+#pragma unroll
+    for (int s = 0; s < KK; ++s) part[wave][lane][s] = best[s];
+    __syncthreads();
+    if (wave != 0 || qi >= n_q) return;
+#pragma unroll
+    for (int w = 1; w < 4; ++w)
+#pragma unroll
+        for (int s = 0; s < KK; ++s) topk_insert64<KK>(best, part[w][lane][s]);
 #pragma unroll
     for (int s = 0; s < KK; ++s) {
         const bool empty = best[s] == ~0ull;
@@ -168,8 +199,8 @@ void launch_nw_k(const KnnPlan& p, const uint64_t* query, const uint64_t* train,
             break;
     }
     if (!direct) {
-        hipLaunchKernelGGL((hamming_merge_kernel<KK>), dim3((p.n_q + 255) / 256), dim3(256), 0, stream, partial,
-                           p.n_q, p.splits, p.rows_per_split, idx, dist);
+        hipLaunchKernelGGL((hamming_merge_kernel<KK>), dim3((p.n_q + kWave - 1) / kWave), dim3(4 * kWave), 0, stream,
+                           partial, p.n_q, p.splits, p.rows_per_split, idx, dist);
     }
 }
 

@@ -1,7 +1,9 @@
 // HashSIFT (Sec. III-B): SIFT features f of the normalized 32x32 patch,
 // then D = sgn(B [f; 1]) with the last column of B written as -t.
 //
-// hashsift_hist: one wavefront per keypoint.
+// hashsift_hist: one wavefront per keypoint, in the caller's spatial order
+// (optional) with an XCD-aware block mapping so an XCD's samples stay within
+// one image region.
 //   1. 34x34 bilinear samples of the rotated, scaled patch (positions in
 //      FP64, clamp-to-edge, nested linear interpolation so flat regions give
 //      exactly zero gradients) go to LDS, stored relative to the pixel under
@@ -20,9 +22,8 @@
 //   4. L2 normalization by a wavefront reduction.
 //
 // hashsift_project_fp32: responses r = B f - t on FP32 MFMA
-// (v_mfma_f32_16x16x4_f32), 16 keypoints x 64 bits per wavefront step, B
-// staged through LDS one 64-bit chunk at a time; the signs are packed into
-// code words with 16 ballots per chunk.
+// (v_mfma_f32_16x16x4_f32), 16 keypoints x 64 bits per wavefront, operands
+// read from L2; the signs are packed into code words with 16 ballots.
 #include "bd_internal.hpp"
 
 namespace bd {
@@ -105,6 +106,43 @@ __device__ __forceinline__ float pixel(const uint8_t* __restrict__ img, int64_t 
     }
 }
 
+// Orientation-bin coordinate of the gradient (gx, gy): atan2(gy, gx) * 8/(2 pi)
+// in [0, 8].  Octant reduction to t = min/max in [0, 1], then
+// atan(t) * 4/pi = t * P(t^2) with P of degree 7, whose coefficients are a
+// weighted least-squares (Lawson-iterated, near-minimax) fit on Chebyshev
+// nodes of u = t^2 in [0, 1]; the float32 evaluation is within 2.4e-7 bins
+// (1.9e-7 rad) of the exact angle.  A zero gradient gives 0.
+__device__ __forceinline__ float orientation_bin(float gx, float gy)
+{
+    const float ax = fabsf(gx), ay = fabsf(gy);
+    const float mn = fminf(ax, ay), mx = fmaxf(ax, ay);
+    const float t = mn * __builtin_amdgcn_rcpf(fmaxf(mx, 1e-30f));
+    const float u = t * t;
+    float p = -0.005162429064512253f;
+    p = fmaf(p, u, 0.027836760506033897f);
+    p = fmaf(p, u, -0.0711897537112236f);
+    p = fmaf(p, u, 0.12276824563741684f);
+    p = fmaf(p, u, -0.17709016799926758f);
+    p = fmaf(p, u, 0.2539675533771515f);
+    p = fmaf(p, u, -0.4243689775466919f);
+    p = fmaf(p, u, 1.2732386589050293f);
+    float b = t * p;                 // [0, 1]: angle of the reduced octant in bins
+    b = ay > ax ? 2.0f - b : b;      // [0, 2]: first quadrant
+    b = gx < 0.0f ? 4.0f - b : b;    // [0, 4]: upper half plane
+    b = gy < 0.0f ? 8.0f - b : b;    // [0, 8]
+    return b;
+}
+
+template <int DT>
+__device__ __forceinline__ float pixel_at(const uint8_t* __restrict__ img, uint32_t row_off, int x)
+{
+    if constexpr (DT == BD_DTYPE_U8) {
+        return (float)img[row_off + (uint32_t)x];
+    } else {
+        return *reinterpret_cast<const float*>(img + row_off + 4u * (uint32_t)x);
+    }
+}
+
 __device__ __forceinline__ float wave_sum_f(float v)
 {
 #pragma unroll
@@ -116,13 +154,19 @@ template <int DT>
 __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __restrict__ img, int32_t W,
                                                             int32_t H, int64_t pitch,
                                                             const bd_keypoint* __restrict__ kps,
-                                                            int32_t n_kp, float* __restrict__ hist)
+                                                            int32_t n_kp, const int32_t* __restrict__ order,
+                                                            float* __restrict__ hist)
 {
     __shared__ float smem[kHistWaves][kWaveLds];
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
-    const int n = blockIdx.x * kHistWaves + wave;
-    if (n >= n_kp) return;
+    const int nb = (n_kp + kHistWaves - 1) / kHistWaves;
+    const int lb = xcd_logical_block(blockIdx.x, nb);
+    if (lb >= nb) return;
+    const int pos = lb * kHistWaves + wave;
+    if (pos >= n_kp) return;
+    const int n = order ? order[pos] : pos;
+    if (n < 0 || n >= n_kp) return;  // malformed order entries are skipped
     float* P = smem[wave];
     float* out = hist + (int64_t)n * 128;
 
@@ -142,25 +186,48 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
     const int by = (int)fmin(fmax(rint(ky), 0.0), (double)(H - 1));
     const float base = pixel<DT>(img, pitch, bx, by);
 
-    // 1. resample the 34x34 patch
-    for (int s = lane; s < kSamples; s += kWave) {
-        const int i = s / kApron - 1, j = s % kApron - 1;
-        const double ux = j - 15.5, uy = i - 15.5;
-        const double px = kx + (sa * ux - sb * uy);
-        const double py = ky + (sb * ux + sa * uy);
-        const double x0 = floor(px), y0 = floor(py);
-        const float fx = (float)(px - x0), fy = (float)(py - y0);
-        const int xa = (int)fmin(fmax(x0, 0.0), (double)(W - 1));
-        const int xb = (int)fmin(fmax(x0 + 1.0, 0.0), (double)(W - 1));
-        const int ya = (int)fmin(fmax(y0, 0.0), (double)(H - 1));
-        const int yb = (int)fmin(fmax(y0 + 1.0, 0.0), (double)(H - 1));
-        const float v00 = pixel<DT>(img, pitch, xa, ya) - base;
-        const float v01 = pixel<DT>(img, pitch, xb, ya) - base;
-        const float v10 = pixel<DT>(img, pitch, xa, yb) - base;
-        const float v11 = pixel<DT>(img, pitch, xb, yb) - base;
-        const float top = v00 + fx * (v01 - v00);
-        const float bot = v10 + fx * (v11 - v10);
-        P[s] = top + fy * (bot - top);
+    // 1. resample the 34x34 patch.  Sample s = (i+1)*34 + (j+1) sits at patch
+    // offset (j - 15.5, i - 15.5); its image position is the row origin
+    // (kx - sb*uy, ky + sa*uy) plus (sa, sb) * ux, two FP64 FMAs per axis.
+    // Three samples per lane are in flight at a time.
+    const uint32_t upitch = (uint32_t)pitch;
+    const int wm1 = W - 1, hm1 = H - 1;
+    constexpr int kIters = (kSamples + kWave - 1) / kWave;  // 19
+    constexpr int kGroup = 3;
+#pragma unroll 1
+    for (int it0 = 0; it0 < kIters; it0 += kGroup) {
+        float v[kGroup][4], fxs[kGroup], fys[kGroup];
+        int sidx[kGroup];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            const int s = lane + (it0 + g) * kWave;
+            sidx[g] = s;
+            const int sc = s < kSamples ? s : kSamples - 1;
+            const int i = sc / kApron, j = sc - i * kApron;
+            const double uy = (double)((float)i - 16.5f), ux = (double)((float)j - 16.5f);
+            const double px = fma(sa, ux, fma(-sb, uy, kx));
+            const double py = fma(sb, ux, fma(sa, uy, ky));
+            const double x0 = floor(px), y0 = floor(py);
+            fxs[g] = (float)(px - x0);
+            fys[g] = (float)(py - y0);
+            // keep the conversion in range for far-off keypoints; clamping follows
+            const int xi = (int)fmin(fmax(x0, -1.0e9), 1.0e9), yi = (int)fmin(fmax(y0, -1.0e9), 1.0e9);
+            const int xa = min(max(xi, 0), wm1), xb = min(max(xi + 1, 0), wm1);
+            const uint32_t ra = (uint32_t)min(max(yi, 0), hm1) * upitch;
+            const uint32_t rb = (uint32_t)min(max(yi + 1, 0), hm1) * upitch;
+            v[g][0] = pixel_at<DT>(img, ra, xa);
+            v[g][1] = pixel_at<DT>(img, ra, xb);
+            v[g][2] = pixel_at<DT>(img, rb, xa);
+            v[g][3] = pixel_at<DT>(img, rb, xb);
+        }
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            const float v00 = v[g][0] - base, v01 = v[g][1] - base;
+            const float v10 = v[g][2] - base, v11 = v[g][3] - base;
+            const float top = v00 + fxs[g] * (v01 - v00);
+            const float bot = v10 + fxs[g] * (v11 - v10);
+            if (sidx[g] < kSamples) P[sidx[g]] = top + fys[g] * (bot - top);
+        }
     }
     wave_sync();
 
@@ -171,16 +238,14 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
     for (int s = 0; s < 3; ++s)
 #pragma unroll
         for (int o = 0; o < 8; ++o) acc[s][o] = 0.0f;
-    constexpr float kBinScale = (float)(8.0 / (2.0 * 3.14159265358979323846));
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int i = half ? 31 - k : k;
         const int c = (i + 1) * kApron + (j + 1);
         const float gx = P[c + 1] - P[c - 1];
         const float gy = P[c + kApron] - P[c - kApron];
-        const float m = sqrtf(gx * gx + gy * gy);
-        float bo = atan2f(gy, gx) * kBinScale;
-        if (bo < 0.0f) bo += 8.0f;
+        const float m = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);
+        const float bo = orientation_bin(gx, gy);
         float tri[8];
 #pragma unroll
         for (int o = 0; o < 8; ++o) tri[o] = fmaxf(0.0f, 1.0f - fabsf(bo - (float)o));
@@ -239,11 +304,17 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
 
 // ---------------------------------------------------------------- projection
 
-constexpr int kProjKp = 64;          // keypoints per block (16 per wavefront)
-constexpr int kBStride = 132;        // padded LDS row of B (floats)
+constexpr int kProjKp = 16;      // keypoints per block (one MFMA row tile)
+constexpr int kProjChunks = 4;   // 64-bit chunks per block, one per wavefront
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// grid = (ceil(n_kp / 16), ceil(n_words / 4)); wavefront w of a block computes
+// the 64 responses of chunk blockIdx.y*4 + w for the block's 16 keypoints.
+// Operands come straight from L2 (B is 128 or 256 KiB and shared by every
+// block); lane (g, m) holds features 32g..32g+31 of keypoint row m and of
+// B row m of each 16-bit subtile, so the k order of the MFMA chain is a
+// permutation applied identically to both operands.
 __global__ __launch_bounds__(256) void hashsift_project_fp32_kernel(const float* __restrict__ hist,
                                                                    const bd_keypoint* __restrict__ kps,
                                                                    int32_t n_kp, const float* __restrict__ B,
@@ -252,22 +323,21 @@ __global__ __launch_bounds__(256) void hashsift_project_fp32_kernel(const float*
                                                                    uint64_t* __restrict__ codes,
                                                                    float* __restrict__ resp)
 {
-    __shared__ float Bs[64 * kBStride];
     const int lane = threadIdx.x % kWave;
-    const int wave = threadIdx.x / kWave;
+    const int chunk = blockIdx.y * kProjChunks + threadIdx.x / kWave;
+    if (chunk >= n_words) return;
     const int g = lane >> 4, m = lane & 15;
-    const int wave_kp = blockIdx.x * kProjKp + wave * 16;
+    const int kp0 = blockIdx.x * kProjKp;
     const int n_bits = n_words * 64;
 
-    // A operand: row m of this wavefront's 16 keypoints, features 32g .. 32g+31
     float a[32];
     {
-        const int row = wave_kp + m;
+        const int row = kp0 + m;
         if (row < n_kp) {
             const float4* src = reinterpret_cast<const float4*>(hist + (int64_t)row * 128 + 32 * g);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                float4 v = src[q];
+                const float4 v = src[q];
                 a[4 * q] = v.x;
                 a[4 * q + 1] = v.y;
                 a[4 * q + 2] = v.z;
@@ -278,61 +348,43 @@ __global__ __launch_bounds__(256) void hashsift_project_fp32_kernel(const float*
             for (int q = 0; q < 32; ++q) a[q] = 0.0f;
         }
     }
-    // validity of the keypoint whose word this lane stores (lanes 0..15)
-    bool valid = false;
-    if (lane < 16 && wave_kp + lane < n_kp) {
-        valid = true;
-        if (kps) {
-            const bd_keypoint kp = kps[wave_kp + lane];
-            valid = finite_f(kp.x) && finite_f(kp.y) && finite_f(kp.scale) && finite_f(kp.angle) && kp.scale > 0.0f;
+
+    uint64_t mask[4][4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int bit = chunk * 64 + 16 * nt + m;
+        const float4* brow = reinterpret_cast<const float4*>(B + (int64_t)bit * 128 + 32 * g);
+        float4 b[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) b[q] = brow[q];
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q], b[q].x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q + 1], b[q].y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q + 2], b[q].z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q + 3], b[q].w, acc, 0, 0, 0);
+        }
+        // lane holds D[kp = 4g + i][bit = m] of this 16-bit subtile
+        const float tv = t[bit];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float r = acc[i] - tv;
+            if (resp) {
+                const int kp = kp0 + 4 * g + i;
+                if (kp < n_kp) resp[(int64_t)kp * n_bits + bit] = r;
+            }
+            mask[nt][i] = __ballot(r > 0.0f);
         }
     }
-
-    for (int chunk = 0; chunk < n_words; ++chunk) {
-        __syncthreads();
-        {
-            const float4* src = reinterpret_cast<const float4*>(B + (int64_t)chunk * 64 * 128);
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int e = threadIdx.x + 256 * r;  // float4 index within the 64 x 128 chunk
-                const int row = e >> 5, col = (e & 31) * 4;
-                *reinterpret_cast<float4*>(&Bs[row * kBStride + col]) = src[e];
+    if (lane < 16) {
+        const int kp = kp0 + lane;
+        if (kp < n_kp) {
+            bool valid = true;
+            if (kps) {
+                const bd_keypoint k = kps[kp];
+                valid = finite_f(k.x) && finite_f(k.y) && finite_f(k.scale) && finite_f(k.angle) && k.scale > 0.0f;
             }
-        }
-        __syncthreads();
-
-        floatx4 acc[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            acc[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-            const float* brow = &Bs[(16 * nt + m) * kBStride + 32 * g];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const float4 b = *reinterpret_cast<const float4*>(brow + 4 * q);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q], b.x, acc[nt], 0, 0, 0);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q + 1], b.y, acc[nt], 0, 0, 0);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q + 2], b.z, acc[nt], 0, 0, 0);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q + 3], b.w, acc[nt], 0, 0, 0);
-            }
-        }
-
-        // lane holds D[kp = 4g + i][bit = m] of each 16-bit subtile nt
-        uint64_t mask[4][4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int bit = chunk * 64 + 16 * nt + m;
-            const float tv = t[bit];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float r = acc[nt][i] - tv;
-                if (resp) {
-                    const int kp = wave_kp + 4 * g + i;
-                    if (kp < n_kp) resp[(int64_t)kp * n_bits + bit] = r;
-                }
-                mask[nt][i] = __ballot(r > 0.0f);
-            }
-        }
-        if (lane < 16) {
             const int gq = lane >> 2, iq = lane & 3;
             uint64_t word = 0ull;
 #pragma unroll
@@ -340,8 +392,7 @@ __global__ __launch_bounds__(256) void hashsift_project_fp32_kernel(const float*
                 const uint64_t mk = iq == 0 ? mask[nt][0] : iq == 1 ? mask[nt][1] : iq == 2 ? mask[nt][2] : mask[nt][3];
                 word |= ((mk >> (16 * gq)) & 0xffffull) << (16 * nt);
             }
-            const int kp = wave_kp + lane;
-            if (kp < n_kp) codes[(int64_t)kp * n_words + chunk] = valid ? word : 0ull;
+            codes[(int64_t)kp * n_words + chunk] = valid ? word : 0ull;
         }
     }
 }
@@ -349,25 +400,26 @@ __global__ __launch_bounds__(256) void hashsift_project_fp32_kernel(const float*
 }  // namespace
 
 void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
-                          const bd_keypoint* kps, int32_t n_kp, float* hist, hipStream_t stream)
+                          const bd_keypoint* kps, int32_t n_kp, const int32_t* order, float* hist,
+                          hipStream_t stream)
 {
-    const int blocks = (n_kp + kHistWaves - 1) / kHistWaves;
+    const int blocks = xcd_grid((n_kp + kHistWaves - 1) / kHistWaves);
     const uint8_t* p = static_cast<const uint8_t*>(img);
     if (dtype == BD_DTYPE_U8)
         hipLaunchKernelGGL(hashsift_hist_kernel<BD_DTYPE_U8>, dim3(blocks), dim3(kHistWaves * kWave), 0, stream,
-                           p, W, H, img_pitch, kps, n_kp, hist);
+                           p, W, H, img_pitch, kps, n_kp, order, hist);
     else
         hipLaunchKernelGGL(hashsift_hist_kernel<BD_DTYPE_F32>, dim3(blocks), dim3(kHistWaves * kWave), 0,
-                           stream, p, W, H, img_pitch, kps, n_kp, hist);
+                           stream, p, W, H, img_pitch, kps, n_kp, order, hist);
 }
 
 void launch_hashsift_project_fp32(const float* hist, const bd_keypoint* kps, int32_t n_kp, const float* B,
                                   const float* t, int32_t n_words, uint64_t* codes, float* resp,
                                   hipStream_t stream)
 {
-    const int blocks = (n_kp + kProjKp - 1) / kProjKp;
-    hipLaunchKernelGGL(hashsift_project_fp32_kernel, dim3(blocks), dim3(256), 0, stream, hist, kps, n_kp, B, t,
-                       n_words, codes, resp);
+    const dim3 grid((n_kp + kProjKp - 1) / kProjKp, (n_words + kProjChunks - 1) / kProjChunks);
+    hipLaunchKernelGGL(hashsift_project_fp32_kernel, grid, dim3(kProjChunks * kWave), 0, stream, hist, kps, n_kp,
+                       B, t, n_words, codes, resp);
 }
 
 }  // namespace bd

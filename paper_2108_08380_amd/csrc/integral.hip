@@ -26,27 +26,25 @@ constexpr int kTileRows = 16;
 constexpr int kTileCols = 256;  // 64 lanes x 4 columns
 constexpr int kWavesPerBlock = 4;
 
-struct Quad {
-    uint32_t v[4];
-};
-
-// Four pixels starting at column x of row y; columns >= W read as zero.
-__device__ __forceinline__ Quad load_quad(const uint8_t* __restrict__ img, int64_t pitch, int32_t y,
-                                          int32_t x, int32_t W, bool aligned)
+// Four pixels of row `y` starting at column x, packed little-endian into one
+// u32 (a byte per pixel); columns >= W read as zero.
+__device__ __forceinline__ uint32_t load_quad(const uint8_t* __restrict__ img, int64_t pitch, int32_t y,
+                                              int32_t x, int32_t W, bool aligned)
 {
-    Quad q;
     const uint8_t* row = img + (int64_t)y * pitch;
-    if (aligned && x + 3 < W) {
-        uint32_t w = *reinterpret_cast<const uint32_t*>(row + x);
-        q.v[0] = w & 0xffu;
-        q.v[1] = (w >> 8) & 0xffu;
-        q.v[2] = (w >> 16) & 0xffu;
-        q.v[3] = w >> 24;
-    } else {
+    if (aligned && x + 3 < W) return *reinterpret_cast<const uint32_t*>(row + x);
+    uint32_t w = 0u;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) q.v[k] = (x + k < W) ? row[x + k] : 0u;
-    }
-    return q;
+    for (int k = 0; k < 4; ++k)
+        if (x + k < W) w |= (uint32_t)row[x + k] << (8 * k);
+    return w;
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int k) { return (w >> (8 * k)) & 0xffu; }
+
+__device__ __forceinline__ uint32_t quad_sum(uint32_t w)
+{
+    return byte_of(w, 0) + byte_of(w, 1) + byte_of(w, 2) + byte_of(w, 3);
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
@@ -56,16 +54,63 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     return v;
 }
 
-// Exclusive prefix sum over the 64 lanes.
+// Exclusive prefix sum over the 64 lanes: inclusive scans inside each row of
+// 16 lanes with DPP row shifts, then the totals of the earlier rows (read
+// from lanes 15, 31, 47) are added.
 __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, int lane)
 {
-    uint32_t incl = v;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane(x, 15);
+    const uint32_t r1 = r0 + (uint32_t)__builtin_amdgcn_readlane(x, 31);
+    const uint32_t r2 = r1 + (uint32_t)__builtin_amdgcn_readlane(x, 47);
+    const int row = lane >> 4;
+    const uint32_t before = row == 0 ? 0u : row == 1 ? r0 : row == 2 ? r1 : r2;
+    return (uint32_t)x + before - v;
+}
+
+// Sums of rs[r] over the 64 lanes for r = 0..15 with a halving butterfly
+// (17 shuffles); lane l ends with the total of row l >> 2.
+__device__ __forceinline__ uint32_t wave_sum16(const uint32_t (&rs)[16], int lane)
+{
+    uint32_t a[8];
+    {
+        const bool hi = lane & 32;
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t o = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += o;
+        for (int r = 0; r < 8; ++r) {
+            const uint32_t keep = hi ? rs[8 + r] : rs[r];
+            const uint32_t send = hi ? rs[r] : rs[8 + r];
+            a[r] = keep + __shfl_xor(send, 32, kWave);
+        }
     }
-    return incl - v;
+    uint32_t b[4];
+    {
+        const bool hi = lane & 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t keep = hi ? a[4 + r] : a[r];
+            const uint32_t send = hi ? a[r] : a[4 + r];
+            b[r] = keep + __shfl_xor(send, 16, kWave);
+        }
+    }
+    uint32_t c[2];
+    {
+        const bool hi = lane & 8;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const uint32_t keep = hi ? b[2 + r] : b[r];
+            const uint32_t send = hi ? b[r] : b[2 + r];
+            c[r] = keep + __shfl_xor(send, 8, kWave);
+        }
+    }
+    const bool hi = lane & 4;
+    uint32_t d = (hi ? c[1] : c[0]) + __shfl_xor(hi ? c[0] : c[1], 4, kWave);
+    d += __shfl_xor(d, 2, kWave);
+    d += __shfl_xor(d, 1, kWave);
+    return d;
 }
 
 __global__ __launch_bounds__(256) void integral_tile_sums(const uint8_t* __restrict__ img, int64_t pitch,
@@ -79,54 +124,64 @@ __global__ __launch_bounds__(256) void integral_tile_sums(const uint8_t* __restr
     if (tile >= strips * slabs) return;
     const int s = tile / slabs, c = tile % slabs;
     const int y0 = s * kTileRows, x = c * kTileCols + 4 * lane;
-    uint32_t col[4] = {0u, 0u, 0u, 0u};
-    uint32_t tile_total = 0u;
-    for (int r = 0; r < kTileRows; ++r) {
-        const int y = y0 + r;
-        if (y >= H) break;
-        Quad q = load_quad(img, pitch, y, x, W, aligned);
-        uint32_t part = 0u;
+    const int rows = min(kTileRows, H - y0);
+    uint32_t q[kTileRows];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            col[k] += q.v[k];
-            part += q.v[k];
-        }
-        uint32_t row_total = wave_sum(part);
-        tile_total += row_total;
-        if (lane == 0) rowsum[(int64_t)y * slabs + c] = row_total;
+    for (int r = 0; r < kTileRows; ++r) q[r] = r < rows ? load_quad(img, pitch, y0 + r, x, W, aligned) : 0u;
+    uint32_t col[4] = {0u, 0u, 0u, 0u};
+    uint32_t rs[kTileRows];
+#pragma unroll
+    for (int r = 0; r < kTileRows; ++r) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) col[k] += byte_of(q[r], k);
+        rs[r] = quad_sum(q[r]);
     }
+    const uint32_t row_total = wave_sum16(rs, lane);  // row lane >> 2 of the tile
+    const uint32_t tile_total = wave_sum((lane & 3) == 0 ? row_total : 0u);
+    if ((lane & 3) == 0 && (lane >> 2) < rows) rowsum[(int64_t)(y0 + (lane >> 2)) * slabs + c] = row_total;
     uint32_t* dst = colsum + (int64_t)s * col_pitch + x;
     *reinterpret_cast<uint4*>(dst) = make_uint4(col[0], col[1], col[2], col[3]);
     if (lane == 0) colsum[(int64_t)s * col_pitch + (int64_t)slabs * kTileCols + c] = tile_total;
 }
 
 // Blocks [0, col_blocks): exclusive scan down the strips for every column of
-// the column table (pixel columns and the tile-total columns).  Remaining
-// blocks: exclusive scan across the slabs for every image row.
+// the column table (pixel columns and the tile-total columns), eight strips
+// loaded per round.  Remaining blocks: exclusive scan across the slabs for
+// every image row.
 __global__ __launch_bounds__(256) void integral_carry_scan(uint32_t* __restrict__ colsum,
                                                            uint32_t* __restrict__ rowsum, int32_t H,
                                                            int32_t strips, int32_t slabs,
                                                            int64_t col_pitch, int32_t col_blocks)
 {
+    constexpr int kBatch = 8;
     if ((int)blockIdx.x < col_blocks) {
         const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         if (x >= col_pitch) return;
         uint32_t acc = 0u;
-        for (int s = 0; s < strips; ++s) {
-            uint32_t* p = colsum + (int64_t)s * col_pitch + x;
-            uint32_t v = *p;
-            *p = acc;
-            acc += v;
+        for (int s0 = 0; s0 < strips; s0 += kBatch) {
+            uint32_t v[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                v[k] = s0 + k < strips ? colsum[(int64_t)(s0 + k) * col_pitch + x] : 0u;
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                if (s0 + k < strips) colsum[(int64_t)(s0 + k) * col_pitch + x] = acc;
+                acc += v[k];
+            }
         }
     } else {
         const int64_t y = (int64_t)(blockIdx.x - col_blocks) * blockDim.x + threadIdx.x;
         if (y >= H) return;
         uint32_t acc = 0u;
-        for (int c = 0; c < slabs; ++c) {
-            uint32_t* p = rowsum + y * slabs + c;
-            uint32_t v = *p;
-            *p = acc;
-            acc += v;
+        for (int c0 = 0; c0 < slabs; c0 += kBatch) {
+            uint32_t v[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) v[k] = c0 + k < slabs ? rowsum[y * slabs + c0 + k] : 0u;
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                if (c0 + k < slabs) rowsum[y * slabs + c0 + k] = acc;
+                acc += v[k];
+            }
         }
     }
 }
@@ -143,15 +198,22 @@ __global__ __launch_bounds__(256) void integral_tile_write(const uint8_t* __rest
     if (tile >= strips * slabs) return;
     const int s = tile / slabs, c = tile % slabs;
     const int y0 = s * kTileRows, x0 = c * kTileCols, x = x0 + 4 * lane;
+    const int rows = min(kTileRows, H - y0);
 
-    // corner = sum over tiles above-left: the scanned tile totals of this strip, slabs < c
+    // every load of the tile is issued before any arithmetic
+    uint32_t q[kTileRows], rc[kTileRows];
+#pragma unroll
+    for (int r = 0; r < kTileRows; ++r) {
+        q[r] = r < rows ? load_quad(img, pitch, y0 + r, x, W, aligned) : 0u;
+        rc[r] = r < rows ? rowcarry[(int64_t)(y0 + r) * slabs + c] : 0u;
+    }
     const uint32_t* strip_row = colcarry + (int64_t)s * col_pitch;
+    const uint4 cv = *reinterpret_cast<const uint4*>(strip_row + x);
     uint32_t corner_part = 0u;
     for (int cc = lane; cc < c; cc += kWave) corner_part += strip_row[(int64_t)slabs * kTileCols + cc];
-    const uint32_t corner = wave_sum(corner_part);
 
-    // pixels above the strip, summed over the slab's columns up to each column
-    uint4 cv = *reinterpret_cast<const uint4*>(strip_row + x);
+    // corner (tiles above-left) plus the pixels above the strip, summed along the slab
+    const uint32_t corner = wave_sum(corner_part);
     uint32_t above[4];
     above[0] = cv.x;
     above[1] = above[0] + cv.y;
@@ -169,18 +231,17 @@ __global__ __launch_bounds__(256) void integral_tile_write(const uint8_t* __rest
 
     uint32_t acc[4] = {0u, 0u, 0u, 0u};
     uint32_t left = 0u;
+#pragma unroll
     for (int r = 0; r < kTileRows; ++r) {
-        const int y = y0 + r;
-        if (y >= H) break;
-        left += rowcarry[(int64_t)y * slabs + c];
-        Quad q = load_quad(img, pitch, y, x, W, aligned);
+        if (r >= rows) break;
+        left += rc[r];
         uint32_t p[4];
-        p[0] = q.v[0];
-        p[1] = p[0] + q.v[1];
-        p[2] = p[1] + q.v[2];
-        p[3] = p[2] + q.v[3];
+        p[0] = byte_of(q[r], 0);
+        p[1] = p[0] + byte_of(q[r], 1);
+        p[2] = p[1] + byte_of(q[r], 2);
+        p[3] = p[2] + byte_of(q[r], 3);
         const uint32_t off = wave_exclusive_scan(p[3], lane);
-        uint32_t* out = ii + (int64_t)(y + 1) * ii_pitch;
+        uint32_t* out = ii + (int64_t)(y0 + r + 1) * ii_pitch;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             acc[k] += p[k] + off;

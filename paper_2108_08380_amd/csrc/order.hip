@@ -1,0 +1,82 @@
+// Spatial processing order of keypoints.
+//
+// Describing keypoints in a spatially coherent order lets every XCD's L2
+// hold the part of the image its workgroups touch: with the XCD-aware block
+// mapping of the describe kernels, XCD x processes the x-th eighth of the
+// ordered list, i.e. one compact region of the image.  The order is a
+// counting sort of keypoints by the Morton index of their cell in a 64 x 64
+// grid laid over the image.  It only changes which workgroup describes a
+// keypoint, never the code written for it.
+#include "bd_internal.hpp"
+
+namespace bd {
+namespace {
+
+constexpr int kGridBits = 6;                 // 64 x 64 cells
+constexpr int kBins = 1 << (2 * kGridBits);  // 4096
+constexpr int kThreads = 1024;
+
+__device__ __forceinline__ uint32_t spread_bits(uint32_t v)  // 6 bits -> even positions
+{
+    v &= 0x3fu;
+    v = (v | (v << 4)) & 0x30fu;
+    v = (v | (v << 2)) & 0x333u;
+    v = (v | (v << 1)) & 0x555u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t cell_key(const bd_keypoint& k, float inv_cell)
+{
+    // non-finite coordinates land in cell 0; the describe kernels handle them
+    const float fx = k.x * inv_cell, fy = k.y * inv_cell;
+    const int cx = (fx >= 0.0f && fx < 64.0f) ? (int)fx : (fx >= 64.0f ? 63 : 0);
+    const int cy = (fy >= 0.0f && fy < 64.0f) ? (int)fy : (fy >= 64.0f ? 63 : 0);
+    return spread_bits((uint32_t)cx) | (spread_bits((uint32_t)cy) << 1);
+}
+
+// One workgroup: histogram of cell keys in LDS, exclusive scan, scatter.
+// Keypoints sharing a cell are placed in arbitrary order.
+__global__ __launch_bounds__(kThreads) void keypoint_order_kernel(const bd_keypoint* __restrict__ kps, int32_t n,
+                                                                 float inv_cell, int32_t* __restrict__ order)
+{
+    __shared__ uint32_t bins[kBins];
+    __shared__ uint32_t part[kThreads];
+    const int t = threadIdx.x;
+    for (int b = t; b < kBins; b += kThreads) bins[b] = 0u;
+    __syncthreads();
+    for (int i = t; i < n; i += kThreads) atomicAdd(&bins[cell_key(kps[i], inv_cell)], 1u);
+    __syncthreads();
+    // exclusive scan of 4096 bins: 4 consecutive bins per thread, then the 1024 thread sums
+    constexpr int kPer = kBins / kThreads;
+    uint32_t local[kPer], sum = 0u;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        local[k] = sum;
+        sum += bins[t * kPer + k];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < kThreads; d <<= 1) {
+        const uint32_t v = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const uint32_t base = part[t] - sum;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) bins[t * kPer + k] = base + local[k];
+    __syncthreads();
+    for (int i = t; i < n; i += kThreads) order[atomicAdd(&bins[cell_key(kps[i], inv_cell)], 1u)] = i;
+}
+
+}  // namespace
+
+void launch_keypoint_order(const bd_keypoint* kps, int32_t n_kp, int32_t W, int32_t H, int32_t* order,
+                           hipStream_t stream)
+{
+    const int side = W > H ? W : H;
+    const float cell = (float)((side + 63) / 64 > 0 ? (side + 63) / 64 : 1);
+    hipLaunchKernelGGL(keypoint_order_kernel, dim3(1), dim3(kThreads), 0, stream, kps, n_kp, 1.0f / cell, order);
+}
+
+}  // namespace bd

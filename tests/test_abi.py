@@ -69,13 +69,13 @@ def test_build_integral_validation(L):
 
 def test_describe_bad_validation(L):
     p = ctypes.c_void_p(16)
-    assert L.bd_describe_bad(None, p, 10, 10, 11, p, 4, p, 128, p, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_describe_bad(None, p, 10, 10, 11, p, 4, None, p, 128, p, None) == bd.BD_EUNSUPPORTED
     assert "n_bits" in err(L)
-    assert L.bd_describe_bad(None, p, 10, 10, 10, p, 4, p, 256, p, None) == bd.BD_EINVAL
-    assert L.bd_describe_bad(None, p, 10, 10, 11, p, -1, p, 256, p, None) == bd.BD_EINVAL
-    assert L.bd_describe_bad(None, p, 10, 10, 11, None, 4, p, 256, p, None) == bd.BD_EINVAL
+    assert L.bd_describe_bad(None, p, 10, 10, 10, p, 4, None, p, 256, p, None) == bd.BD_EINVAL
+    assert L.bd_describe_bad(None, p, 10, 10, 11, p, -1, None, p, 256, p, None) == bd.BD_EINVAL
+    assert L.bd_describe_bad(None, p, 10, 10, 11, None, 4, None, p, 256, p, None) == bd.BD_EINVAL
     # n_kp = 0 needs no pointers, but still a context
-    assert L.bd_describe_bad(None, None, 10, 10, 11, None, 0, None, 256, None, None) == bd.BD_EINVAL
+    assert L.bd_describe_bad(None, None, 10, 10, 11, None, 0, None, None, 256, None, None) == bd.BD_EINVAL
     assert "null context" in err(L)
 
 
@@ -85,7 +85,7 @@ def test_describe_hashsift_validation(L):
 
     def call(**kw):
         a = {**base, **kw}
-        return L.bd_describe_hashsift(None, p, a["dtype"], a["W"], a["H"], a["pitch"], p, a["n"], p, p,
+        return L.bd_describe_hashsift(None, p, a["dtype"], a["W"], a["H"], a["pitch"], p, a["n"], None, p, p,
                                       a["n_bits"], a["prec"], p, None, None, None)
 
     assert call(n_bits=384) == bd.BD_EUNSUPPORTED
@@ -95,6 +95,27 @@ def test_describe_hashsift_validation(L):
     assert call(pitch=42) == bd.BD_EINVAL and "multiple of 4" in err(L)
     assert call(dtype=bd.BD_DTYPE_U8, pitch=10) == bd.BD_EINVAL and "null context" in err(L)
     assert call(n=-2) == bd.BD_EINVAL
+
+
+def test_keypoint_order_validation(L):
+    p = ctypes.c_void_p(16)
+    assert L.bd_keypoint_order(None, p, 5, 0, 10, p, None) == bd.BD_EINVAL
+    assert L.bd_keypoint_order(None, p, -1, 10, 10, p, None) == bd.BD_EINVAL
+    assert L.bd_keypoint_order(None, None, 5, 10, 10, p, None) == bd.BD_EINVAL
+    assert L.bd_keypoint_order(None, p, 5, 10, 10, p, None) == bd.BD_EINVAL and "null context" in err(L)
+
+
+def test_hashsift_features_and_project_validation(L):
+    p = ctypes.c_void_p(16)
+    assert L.bd_hashsift_features(None, p, 5, 10, 10, 40, p, 3, None, p, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_hashsift_features(None, p, bd.BD_DTYPE_F32, 10, 10, 40, None, 3, None, p, None) == bd.BD_EINVAL
+    assert L.bd_hashsift_features(None, p, bd.BD_DTYPE_F32, 10, 10, 40, p, 3, None, p, None) == bd.BD_EINVAL
+    assert "null context" in err(L)
+    assert L.bd_hashsift_project(None, p, None, 3, p, p, 128, bd.BD_PREC_FP32, p, None, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_hashsift_project(None, p, None, 3, p, p, 256, 7, p, None, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_hashsift_project(None, None, None, 3, p, p, 256, bd.BD_PREC_FP32, p, None, None) == bd.BD_EINVAL
+    assert L.bd_hashsift_project(None, p, None, 3, p, p, 256, bd.BD_PREC_FP32, p, None, None) == bd.BD_EINVAL
+    assert "null context" in err(L)
 
 
 def test_match_validation(L):

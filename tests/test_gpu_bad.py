@@ -99,3 +99,57 @@ def test_large_image_many_keypoints(ref, dev):
     got, exp, ties = run_both(ref, dev, img, kps, pairs)
     assert ties == 0
     np.testing.assert_array_equal(got, exp)
+
+
+def test_keypoint_order_is_a_permutation(dev):
+    for (W, H, n) in [(640, 480, 1000), (1920, 1080, 5000), (4000, 3000, 20000), (50, 30, 7), (64, 64, 1)]:
+        kps = synth.keypoints(np.random.default_rng(n), n, W, H, border=0.0)
+        order = to_np(bd.keypoint_order(bd.keypoints_tensor(kps, dev), W, H))
+        np.testing.assert_array_equal(np.sort(order), np.arange(n))
+
+
+def test_keypoint_order_groups_cells(dev):
+    """Consecutive entries of the order are spatial neighbours: the mean step
+    between consecutive keypoints is far below that of the input order."""
+    W, H, n = 1920, 1080, 5000
+    kps = synth.keypoints(np.random.default_rng(1), n, W, H)
+    order = to_np(bd.keypoint_order(bd.keypoints_tensor(kps, dev), W, H))
+    xy = np.stack([kps["x"], kps["y"]], 1)
+    step = lambda p: np.linalg.norm(np.diff(p, axis=0), axis=1).mean()
+    assert step(xy[order]) < 0.2 * step(xy)
+
+
+def test_ordered_describe_equals_unordered(ref, dev):
+    w = synth.hashsift512_pair(n_kp=3000, n_bits=512, with_bad_bits=512)
+    img = torch.from_numpy(w.extra["image1_u8"]).to(dev)
+    kps = bd.keypoints_tensor(w.kp1, dev)
+    pairs = bd.pairs_tensor(w.pairs, dev)
+    ii = bd.build_integral(img)
+    order = bd.keypoint_order(kps, img.shape[1], img.shape[0])
+    a = to_np(bd.describe_bad(ii, kps, pairs))
+    b = to_np(bd.describe_bad(ii, kps, pairs, order=order))
+    np.testing.assert_array_equal(a, b)
+    exp, _ = ref.describe_bad(to_np(ii), w.kp1, w.pairs)
+    np.testing.assert_array_equal(b, exp)
+
+
+def test_order_entries_out_of_range_are_skipped(dev):
+    """An order with invalid entries neither faults nor touches other codes:
+    keypoints it names are described, the rest keep their prior contents."""
+    w = synth.bad256_pair()
+    img = torch.from_numpy(w.image1).to(dev)
+    kps = bd.keypoints_tensor(w.kp1, dev)
+    pairs = bd.pairs_tensor(w.pairs, dev)
+    ii = bd.build_integral(img)
+    n = len(w.kp1)
+    good = to_np(bd.describe_bad(ii, kps, pairs))
+    bad_order = np.arange(n, dtype=np.int32)
+    bad_order[::3] = -1
+    bad_order[1::7] = n + 5
+    out = torch.zeros((n, 4), dtype=torch.uint64, device=dev)
+    bd.describe_bad(ii, kps, pairs, out=out, order=torch.from_numpy(bad_order).to(dev))
+    got = to_np(out)
+    named = np.zeros(n, bool)
+    named[bad_order[(bad_order >= 0) & (bad_order < n)]] = True
+    np.testing.assert_array_equal(got[named], good[named])
+    assert not got[~named].any()

@@ -109,3 +109,18 @@ def test_codes_without_optional_outputs(dev):
     a = to_np(bd.describe_hashsift(*args))
     b = to_np(bd.describe_hashsift(*args, with_hist=True, with_resp=True)[0])
     np.testing.assert_array_equal(a, b)
+
+
+def test_ordered_features_equal_unordered(dev):
+    w = synth.hashsift512_pair(n_kp=3000)
+    img = torch.from_numpy(w.image1).to(dev)
+    kps = bd.keypoints_tensor(w.kp1, dev)
+    order = bd.keypoint_order(kps, img.shape[1], img.shape[0])
+    a = to_np(bd.hashsift_features(img, kps))
+    b = to_np(bd.hashsift_features(img, kps, order=order))
+    np.testing.assert_array_equal(a, b)
+    B, t = torch.from_numpy(w.B).to(dev), torch.from_numpy(w.t).to(dev)
+    c1 = to_np(bd.describe_hashsift(img, kps, B, t))
+    c2 = to_np(bd.describe_hashsift(img, kps, B, t, order=order))
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_array_equal(c1, to_np(bd.hashsift_project(torch.from_numpy(b).to(dev), B, t, kps)))
