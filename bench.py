@@ -144,6 +144,44 @@ def time_stages(wl, reps):
     return out
 
 
+def precision_projection(wl, n_rows=200000, reps=20):
+    """HashSIFT-512 projection of 200000 feature rows (the bench features tiled)
+    in FP32, BF16 and FP8 with the 1e-3 FP32 re-check margin: time per launch,
+    flipped bits and largest response change against the FP32 path."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+
+    f = torch.cat(wl.hist, 0)
+    f = f.repeat((n_rows + f.shape[0] - 1) // f.shape[0], 1)[:n_rows].contiguous()
+    out = {}
+    ref_codes = ref_resp = None
+    for prec in ("fp32", "bf16", "fp8"):
+        cnt = torch.zeros(1, dtype=torch.uint32, device=f.device)
+        codes, resp = bd.hashsift_project(f, wl.B, wl.t, precision=prec, with_resp=True, recheck_count=cnt)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            bd.hashsift_project(f, wl.B, wl.t, precision=prec, out=codes)
+        e.record()
+        e.synchronize()
+        ms = s.elapsed_time(e) / reps
+        flops = 2.0 * HS_BITS * 128 * n_rows
+        item = {"ms_per_launch": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2)}
+        if ref_codes is None:
+            ref_codes, ref_resp = codes, resp
+        else:
+            x = (codes.view(torch.int64) ^ ref_codes.view(torch.int64)).cpu().numpy()
+            flips = int(np.unpackbits(x.view(np.uint8)).sum())
+            item["flipped_bits_vs_fp32"] = flips
+            item["flip_rate_vs_fp32"] = flips / (n_rows * HS_BITS)
+            item["rechecked_responses"] = int(cnt.cpu()[0])
+            item["max_abs_response_change_vs_fp32"] = float((resp - ref_resp).abs().max())
+        out[prec] = item
+    return out
+
+
 def cpu_baseline(sample: int):
     """The oracle on `sample` keypoints per view (full integral images), scaled to the full step."""
     import oracle
@@ -281,6 +319,8 @@ def main():
         "checks": check,
         "roofline": roofline,
     }
+    if not args.only:
+        result["precision_projection_200k"] = precision_projection(wl)
     if not args.no_cpu and not args.only:
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(result))

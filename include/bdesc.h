@@ -45,7 +45,9 @@ extern "C" {
 #define BD_DTYPE_U8 0  /* grey levels 0..255; HashSIFT reads v / 255 */
 #define BD_DTYPE_F32 1 /* float32 grey levels */
 
-#define BD_PREC_FP32 0
+#define BD_PREC_FP32 0 /* FP32 operands, FP32 MFMA */
+#define BD_PREC_BF16 1 /* bfloat16 operands (round to nearest even), FP32 accumulation */
+#define BD_PREC_FP8 2  /* OCP float8 e4m3 operands with per-row scales, FP32 accumulation */
 
 typedef struct bd_keypoint {
     float x, y, scale, angle;
@@ -131,7 +133,15 @@ int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, i
  *   codes    n_kp x n_bits/64 words; bit j set when r_j = B_j . f - t_j > 0
  *   hist_out optional (NULL) n_kp x 128 float32 features f
  *   resp_out optional (NULL) n_kp x n_bits float32 responses r
- * n_bits is 256 or 512; precision is BD_PREC_FP32.  f: 34x34 bilinear
+ *   precision BD_PREC_FP32, BD_PREC_BF16 or BD_PREC_FP8 (the reduced-precision
+ *            forms are an extension: the paper fixes no precision).  With
+ *            BF16/FP8 every response with |r| < margin is recomputed from the
+ *            unrounded FP32 operands (products summed by a fixed pairwise
+ *            tree; in FP64 when that FP32 value is within 1e-6 of the
+ *            threshold) and decides the bit;
+ *            recheck_count (optional device u32, caller-zeroed) is increased
+ *            by the number of such responses.  margin is ignored for FP32.
+ * n_bits is 256 or 512.  f: 34x34 bilinear
  * samples (clamp-to-edge) at patch offsets (j - 15.5, i - 15.5), central
  * differences, Gaussian window sigma 16, trilinear votes into 4x4 cells x 8
  * orientations (index (cy*4 + cx)*8 + o), L2-normalized (zero stays zero).
@@ -139,8 +149,9 @@ int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, i
  */
 int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
                          int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const int32_t* order,
-                         const float* B, const float* t, int32_t n_bits, int32_t precision,
-                         uint64_t* codes, float* hist_out, float* resp_out, void* stream);
+                         const float* B, const float* t, int32_t n_bits, int32_t precision, float margin,
+                         uint64_t* codes, float* hist_out, float* resp_out, uint32_t* recheck_count,
+                         void* stream);
 
 /*
  * HashSIFT features only (the f(x) of Sec. III-B, exactly as computed inside
@@ -153,15 +164,16 @@ int bd_hashsift_features(bd_context* ctx, const void* img, int32_t dtype, int32_
 
 /*
  * HashSIFT binarization of given features (Sec. III-B, D = sgn(B [f; 1])):
- * r = B f - t on FP32 MFMA, bit j set when r_j > 0.
+ * r = B f - t on MFMA in the given precision (as bd_describe_hashsift, with
+ * the same margin re-check), bit j set when r_j > 0.
  *   hist     n_kp x 128 float32 features (row stride 128)
  *   kps      optional (NULL = all valid): keypoints whose codes are forced
  *            to zero when invalid, as in bd_describe_hashsift
  *   resp_out optional (NULL) n_kp x n_bits float32 responses
  */
 int bd_hashsift_project(bd_context* ctx, const float* hist, const bd_keypoint* kps, int32_t n_kp,
-                        const float* B, const float* t, int32_t n_bits, int32_t precision,
-                        uint64_t* codes, float* resp_out, void* stream);
+                        const float* B, const float* t, int32_t n_bits, int32_t precision, float margin,
+                        uint64_t* codes, float* resp_out, uint32_t* recheck_count, void* stream);
 
 /*
  * Brute-force Hamming k-NN (Sec. III-A: S(x, y) = h(x)^T h(y) = K - 2 d_H,

@@ -54,6 +54,12 @@ def lib():
         L.bdref_keypoint_valid.restype = i32
         L.bdref_match_knn.argtypes = [P, i32, P, i32, i32, i32, P, P]
         L.bdref_match_knn.restype = None
+        L.bdref_round_bf16.argtypes = [ctypes.c_float]
+        L.bdref_round_bf16.restype = ctypes.c_float
+        L.bdref_round_e4m3.argtypes = [ctypes.c_float]
+        L.bdref_round_e4m3.restype = ctypes.c_float
+        L.bdref_project_lowp.argtypes = [P, i32, P, P, i32, i32, P]
+        L.bdref_project_lowp.restype = None
         _lib = L
     return _lib
 
@@ -155,3 +161,24 @@ def match_knn(query: np.ndarray, train: np.ndarray, k: int):
     dist = np.empty((q.shape[0], k), dtype=np.uint32)
     lib().bdref_match_knn(_ptr(q), q.shape[0], _ptr(t), t.shape[0], n_words, k, _ptr(idx), _ptr(dist))
     return idx, dist
+
+
+PRECISIONS = {"bf16": 1, "fp8": 2}
+
+
+def round_bf16(x: float) -> float:
+    return float(lib().bdref_round_bf16(float(x)))
+
+
+def round_e4m3(x: float) -> float:
+    return float(lib().bdref_round_e4m3(float(x)))
+
+
+def project_lowp(hist32: np.ndarray, B: np.ndarray, t: np.ndarray, precision: str) -> np.ndarray:
+    """FP64 responses of the projection with BF16- or FP8-rounded operands."""
+    h = np.ascontiguousarray(hist32, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    resp = np.zeros((h.shape[0], B.shape[0]), dtype=np.float64)
+    lib().bdref_project_lowp(_ptr(h), h.shape[0], _ptr(B), _ptr(t), B.shape[0], PRECISIONS[precision], _ptr(resp))
+    return resp

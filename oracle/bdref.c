@@ -315,3 +315,74 @@ void bdref_match_knn(const uint64_t* query, int32_t n_q, const uint64_t* train, 
         }
     }
 }
+
+/* ------------------------------------------------------------------ reduced precision */
+
+float bdref_round_bf16(float x)
+{
+    uint32_t bits;
+    memcpy(&bits, &x, sizeof bits);
+    if ((bits & 0x7f800000u) == 0x7f800000u) return x; /* inf / nan unchanged */
+    uint32_t lsb = (bits >> 16) & 1u;
+    bits += 0x7fffu + lsb; /* round to nearest, ties to even */
+    bits &= 0xffff0000u;
+    float y;
+    memcpy(&y, &bits, sizeof y);
+    return y;
+}
+
+/* e4m3: normal numbers 2^e * (1 + m/8) for e in [-6, 8] (m <= 6 at e = 8),
+ * subnormals k * 2^-9.  The quantum below 2^-6 is 2^-9; from 2^e to 2^(e+1)
+ * it is 2^(e-3).  rint rounds ties to even. */
+float bdref_round_e4m3(float x)
+{
+    double a = fabs((double)x);
+    if (a != a) return x;
+    double q;
+    if (a < ldexp(1.0, -6)) {
+        q = rint(a / ldexp(1.0, -9)) * ldexp(1.0, -9);
+    } else {
+        int e;
+        frexp(a, &e); /* a = f * 2^e, f in [0.5, 1): 2^(e-1) <= a < 2^e */
+        double quantum = ldexp(1.0, (e - 1) - 3);
+        q = rint(a / quantum) * quantum;
+    }
+    if (q > 448.0) q = 448.0;
+    return (float)(x < 0 ? -q : q);
+}
+
+static float row_scale_e4m3(const float* row, int len)
+{
+    float m = 0.0f;
+    for (int i = 0; i < len; ++i) {
+        float v = fabsf(row[i]);
+        if (v > m) m = v;
+    }
+    return m > 0.0f ? m / 448.0f : 1.0f;
+}
+
+void bdref_project_lowp(const float* hist, int32_t n_kp, const float* B, const float* t, int32_t n_bits,
+                        int32_t precision, double* resp)
+{
+    for (int32_t n = 0; n < n_kp; ++n) {
+        const float* f = hist + (int64_t)n * 128;
+        float sf = precision == 2 ? row_scale_e4m3(f, 128) : 1.0f;
+        for (int32_t j = 0; j < n_bits; ++j) {
+            const float* b = B + (int64_t)j * 128;
+            float sb = precision == 2 ? row_scale_e4m3(b, 128) : 1.0f;
+            double acc = 0.0;
+            for (int k = 0; k < 128; ++k) {
+                double qb, qf;
+                if (precision == 1) {
+                    qb = bdref_round_bf16(b[k]);
+                    qf = bdref_round_bf16(f[k]);
+                } else {
+                    qb = bdref_round_e4m3(b[k] / sb);
+                    qf = bdref_round_e4m3(f[k] / sf);
+                }
+                acc += qb * qf;
+            }
+            resp[(int64_t)n * n_bits + j] = (double)sf * (double)sb * acc - (double)t[j];
+        }
+    }
+}

@@ -60,6 +60,21 @@ void bdref_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, i
 void bdref_hashsift_project(const double* hist, int32_t n_kp, const float* B, const float* t,
                             int32_t n_bits, const uint8_t* valid, double* resp, uint64_t* codes);
 
+/* Reduced-precision operand rounding (not in the paper; the precision
+ * extension of the projection).  Round-to-nearest-even to bfloat16, and to
+ * OCP float8 e4m3 (4 exponent bits, bias 7, 3 mantissa bits, largest finite
+ * 448), saturating at +-448. */
+float bdref_round_bf16(float x);
+float bdref_round_e4m3(float x);
+
+/* Responses of the projection with rounded operands, accumulated exactly in
+ * FP64: precision 1 = BF16 (both operands rounded to bfloat16), 2 = FP8
+ * (per-row scales s = max|row| / 448 computed in float32 for every feature
+ * row and every B row, operands x / s rounded to e4m3; response =
+ * s_f * s_B * sum q_B q_f - t).  hist is n_kp x 128 float32. */
+void bdref_project_lowp(const float* hist, int32_t n_kp, const float* B, const float* t, int32_t n_bits,
+                        int32_t precision, double* resp);
+
 /* 1 when the keypoint has finite fields and a positive scale. */
 int32_t bdref_keypoint_valid(const bdref_keypoint* kp);
 

@@ -28,8 +28,9 @@ LIB_PATH = os.path.join(_HERE, "libbdesc.so")
 
 BD_OK, BD_EINVAL, BD_EUNSUPPORTED, BD_ENOMEM, BD_EDEVICE = 0, -1, -2, -3, -4
 BD_DTYPE_U8, BD_DTYPE_F32 = 0, 1
-BD_PREC_FP32 = 0
-_PRECISIONS = {"fp32": BD_PREC_FP32}
+BD_PREC_FP32, BD_PREC_BF16, BD_PREC_FP8 = 0, 1, 2
+_PRECISIONS = {"fp32": BD_PREC_FP32, "bf16": BD_PREC_BF16, "fp8": BD_PREC_FP8}
+DEFAULT_MARGIN = 1e-3
 
 # Exported symbols of include/bdesc.h with their C signatures.
 _P, _I32, _I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -41,10 +42,10 @@ SIGNATURES = {
     "bd_build_integral": ([_P, _P, _I32, _I32, _I64, _P, _I64, _P], ctypes.c_int),
     "bd_keypoint_order": ([_P, _P, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "bd_describe_bad": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _P, _I32, _P, _P], ctypes.c_int),
-    "bd_describe_hashsift": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P, _I32, _I32, _P, _P, _P, _P],
-                             ctypes.c_int),
+    "bd_describe_hashsift": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P, _I32, _I32, ctypes.c_float,
+                              _P, _P, _P, _P, _P], ctypes.c_int),
     "bd_hashsift_features": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P], ctypes.c_int),
-    "bd_hashsift_project": ([_P, _P, _P, _I32, _P, _P, _I32, _I32, _P, _P, _P], ctypes.c_int),
+    "bd_hashsift_project": ([_P, _P, _P, _I32, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_match_hamming_knn": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
 }
 
@@ -214,16 +215,14 @@ def describe_bad(ii, kps, pairs, n_bits: int | None = None, out=None, order=None
 
 
 def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool = False,
-                      with_resp: bool = False, out=None, order=None):
+                      with_resp: bool = False, out=None, order=None, margin: float = DEFAULT_MARGIN,
+                      recheck_count=None):
     """HashSIFT codes (bd_describe_hashsift).  Returns codes, or (codes, hist, resp)
-    when with_hist or with_resp is set (the unrequested ones are None)."""
+    when with_hist or with_resp is set (the unrequested ones are None).
+    recheck_count: optional (1,) uint32 device tensor increased by the number of
+    responses re-checked in FP32 (BF16/FP8 only)."""
     torch = _torch()
-    if img.dtype == torch.uint8:
-        dtype = BD_DTYPE_U8
-    elif img.dtype == torch.float32:
-        dtype = BD_DTYPE_F32
-    else:
-        raise TypeError("img must be uint8 or float32")
+    dtype = _image_dtype(img)
     _require(img, img.dtype, 2, "img")
     _require(kps, torch.float32, 2, "kps")
     _contig(kps, "kps")
@@ -239,15 +238,25 @@ def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool =
         out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=img.device)
     hist = torch.empty((n, 128), dtype=torch.float32, device=img.device) if with_hist else None
     resp = torch.empty((n, n_bits), dtype=torch.float32, device=img.device) if with_resp else None
-    dev, stream = _device_and_stream(img, kps, B, t, out, hist, resp, order)
+    dev, stream = _device_and_stream(img, kps, B, t, out, hist, resp, order, recheck_count)
     _check(lib().bd_describe_hashsift(context(dev), img.data_ptr(), dtype, W, H, img.stride(0) * img.element_size(),
                                       kps.data_ptr(), n, _order_arg(order, n), B.data_ptr(), t.data_ptr(), n_bits,
-                                      _PRECISIONS[precision], out.data_ptr(),
+                                      _PRECISIONS[precision], margin, out.data_ptr(),
                                       hist.data_ptr() if hist is not None else None,
-                                      resp.data_ptr() if resp is not None else None, stream))
+                                      resp.data_ptr() if resp is not None else None,
+                                      _counter_arg(recheck_count), stream))
     if with_hist or with_resp:
         return out, hist, resp
     return out
+
+
+def _counter_arg(c):
+    torch = _torch()
+    if c is None:
+        return None
+    if c.dtype != torch.uint32 or c.numel() < 1:
+        raise ValueError("recheck_count must be a uint32 device tensor")
+    return c.data_ptr()
 
 
 def _image_dtype(img):
@@ -277,7 +286,8 @@ def hashsift_features(img, kps, out=None, order=None):
     return out
 
 
-def hashsift_project(hist, B, t, kps=None, precision: str = "fp32", with_resp: bool = False, out=None):
+def hashsift_project(hist, B, t, kps=None, precision: str = "fp32", with_resp: bool = False, out=None,
+                     margin: float = DEFAULT_MARGIN, recheck_count=None):
     """Codes (and optionally responses) of given features (bd_hashsift_project)."""
     torch = _torch()
     _require(hist, torch.float32, 2, "hist")
@@ -295,10 +305,11 @@ def hashsift_project(hist, B, t, kps=None, precision: str = "fp32", with_resp: b
     if out is None:
         out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=hist.device)
     resp = torch.empty((n, n_bits), dtype=torch.float32, device=hist.device) if with_resp else None
-    dev, stream = _device_and_stream(hist, B, t, out, kps, resp)
+    dev, stream = _device_and_stream(hist, B, t, out, kps, resp, recheck_count)
     _check(lib().bd_hashsift_project(context(dev), hist.data_ptr(), kps.data_ptr() if kps is not None else None, n,
-                                     B.data_ptr(), t.data_ptr(), n_bits, _PRECISIONS[precision], out.data_ptr(),
-                                     resp.data_ptr() if resp is not None else None, stream))
+                                     B.data_ptr(), t.data_ptr(), n_bits, _PRECISIONS[precision], margin,
+                                     out.data_ptr(), resp.data_ptr() if resp is not None else None,
+                                     _counter_arg(recheck_count), stream))
     return (out, resp) if with_resp else out
 
 

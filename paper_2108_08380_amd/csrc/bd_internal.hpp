@@ -68,9 +68,9 @@ void launch_keypoint_order(const bd_keypoint* kps, int32_t n_kp, int32_t W, int3
 void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
                           const bd_keypoint* kps, int32_t n_kp, const int32_t* order, float* hist,
                           hipStream_t stream);
-void launch_hashsift_project_fp32(const float* hist, const bd_keypoint* kps, int32_t n_kp,
-                                  const float* B, const float* t, int32_t n_words, uint64_t* codes,
-                                  float* resp, hipStream_t stream);
+void launch_hashsift_project(int32_t precision, const float* hist, const bd_keypoint* kps, int32_t n_kp,
+                             const float* B, const float* t, int32_t n_words, float margin, uint64_t* codes,
+                             float* resp, uint32_t* recheck_count, hipStream_t stream);
 
 // ---- Hamming k-NN (hamming.hip)
 struct KnnPlan {

@@ -197,10 +197,12 @@ int check_image(const char* fn, int32_t dtype, int32_t W, int32_t H, int64_t img
     return BD_OK;
 }
 
-int check_projection(const char* fn, int32_t n_bits, int32_t precision)
+int check_projection(const char* fn, int32_t n_bits, int32_t precision, float margin)
 {
     if (!is_supported_bits(n_bits)) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (256 or 512)", fn, n_bits);
-    if (precision != BD_PREC_FP32) return fail(BD_EUNSUPPORTED, "%s: precision %d", fn, precision);
+    if (precision != BD_PREC_FP32 && precision != BD_PREC_BF16 && precision != BD_PREC_FP8)
+        return fail(BD_EUNSUPPORTED, "%s: precision %d", fn, precision);
+    if (!(margin >= 0.0f) || margin > 1e30f) return fail(BD_EINVAL, "%s: margin must be finite and >= 0", fn);
     return BD_OK;
 }
 
@@ -219,26 +221,27 @@ int bd_hashsift_features(bd_context* ctx, const void* img, int32_t dtype, int32_
 }
 
 int bd_hashsift_project(bd_context* ctx, const float* hist, const bd_keypoint* kps, int32_t n_kp, const float* B,
-                        const float* t, int32_t n_bits, int32_t precision, uint64_t* codes, float* resp_out,
-                        void* stream)
+                        const float* t, int32_t n_bits, int32_t precision, float margin, uint64_t* codes,
+                        float* resp_out, uint32_t* recheck_count, void* stream)
 {
     const char* fn = "bd_hashsift_project";
-    if (int rc = check_projection(fn, n_bits, precision)) return rc;
+    if (int rc = check_projection(fn, n_bits, precision, margin)) return rc;
     if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
     if (n_kp > 0 && (!hist || !B || !t || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
     if (int rc = check_ctx(ctx, fn)) return rc;
     if (n_kp == 0) return BD_OK;
-    launch_hashsift_project_fp32(hist, kps, n_kp, B, t, n_bits / 64, codes, resp_out, static_cast<hipStream_t>(stream));
+    launch_hashsift_project(precision, hist, kps, n_kp, B, t, n_bits / 64, margin, codes, resp_out, recheck_count,
+                            static_cast<hipStream_t>(stream));
     return check_launch(fn);
 }
 
 int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_t W, int32_t H,
                          int64_t img_pitch, const bd_keypoint* kps, int32_t n_kp, const int32_t* order,
-                         const float* B, const float* t, int32_t n_bits, int32_t precision, uint64_t* codes,
-                         float* hist_out, float* resp_out, void* stream)
+                         const float* B, const float* t, int32_t n_bits, int32_t precision, float margin,
+                         uint64_t* codes, float* hist_out, float* resp_out, uint32_t* recheck_count, void* stream)
 {
     const char* fn = "bd_describe_hashsift";
-    if (int rc = check_projection(fn, n_bits, precision)) return rc;
+    if (int rc = check_projection(fn, n_bits, precision, margin)) return rc;
     if (int rc = check_image(fn, dtype, W, H, img_pitch)) return rc;
     if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
     if (n_kp > 0 && (!img || !kps || !B || !t || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
@@ -252,7 +255,7 @@ int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_
         hist = static_cast<float*>(ws);
     }
     launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, order, hist, s);
-    launch_hashsift_project_fp32(hist, kps, n_kp, B, t, n_bits / 64, codes, resp_out, s);
+    launch_hashsift_project(precision, hist, kps, n_kp, B, t, n_bits / 64, margin, codes, resp_out, recheck_count, s);
     return check_launch(fn);
 }
 

@@ -21,9 +21,10 @@
 //      its cell (horizontal cell weight times the column's Gaussian weight).
 //   4. L2 normalization by a wavefront reduction.
 //
-// hashsift_project_fp32: responses r = B f - t on FP32 MFMA
-// (v_mfma_f32_16x16x4_f32), 16 keypoints x 64 bits per wavefront, operands
-// read from L2; the signs are packed into code words with 16 ballots.
+// hashsift_project: responses r = B f - t on MFMA (FP32, or BF16 / FP8 with
+// FP32 accumulation and an FP32 re-check near the threshold), 16 keypoints x
+// 64 bits per wavefront, operands read from L2; the signs are packed into
+// code words with 16 ballots.
 #include "bd_internal.hpp"
 
 namespace bd {
@@ -308,6 +309,84 @@ constexpr int kProjKp = 16;      // keypoints per block (one MFMA row tile)
 constexpr int kProjChunks = 4;   // 64-bit chunks per block, one per wavefront
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Largest |value| of a 128-float row held as 32 floats by each of the four
+// lanes m, m+16, m+32, m+48.
+__device__ __forceinline__ float row_maxabs(const float (&v)[32])
+{
+    float m = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) m = fmaxf(m, fabsf(v[i]));
+    m = fmaxf(m, __shfl_xor(m, 16, kWave));
+    m = fmaxf(m, __shfl_xor(m, 32, kWave));
+    return m;
+}
+
+// float8 e4m3 scale of a row: max|row| / 448 (1 for an all-zero row).
+__device__ __forceinline__ float e4m3_scale(float maxabs) { return maxabs > 0.0f ? maxabs / 448.0f : 1.0f; }
+
+// Eight consecutive values (starting at v[8s]) scaled by 1/scale, rounded to
+// e4m3 (round to nearest even) and packed into 64 bits.
+__device__ __forceinline__ long pack_e4m3(const float (&v)[32], int s, float scale)
+{
+    int lo = 0, hi = 0;
+    float q[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) q[e] = fminf(fmaxf(v[8 * s + e] / scale, -448.0f), 448.0f);
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], lo, false);
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], lo, true);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[4], q[5], hi, false);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[6], q[7], hi, true);
+    return (long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ bf16x8 pack_bf16(const float (&v)[32], int s)
+{
+    bf16x8 r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = (__bf16)v[8 * s + e];
+    return r;
+}
+
+// Wavefront-cooperative FP32 re-check of one (keypoint, bit) response from
+// the unrounded operands: lane l multiplies elements 2l and 2l+1, and the 64
+// partial sums are added by a fixed xor tree.  When that FP32 value is within
+// 1e-6 of the threshold the same sum is redone in FP64.  Called by the whole
+// wavefront with uniform arguments; every lane returns the response.
+__device__ __forceinline__ float wave_dot_tree(float v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_dot_tree64(double v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+template <int N>
+__device__ __forceinline__ void recheck_batch(const float* __restrict__ hist, const float* __restrict__ B,
+                                              const float* __restrict__ t, const int (&kp)[N], const int (&bit)[N],
+                                              int lane, float (&r)[N])
+{
+    float2 fv[N], bv[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        fv[c] = reinterpret_cast<const float2*>(hist + (int64_t)kp[c] * 128)[lane];
+        bv[c] = reinterpret_cast<const float2*>(B + (int64_t)bit[c] * 128)[lane];
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        r[c] = wave_dot_tree(fmaf(fv[c].y, bv[c].y, fv[c].x * bv[c].x)) - t[bit[c]];
+        if (fabsf(r[c]) < 1e-6f) {
+            const double p = (double)fv[c].x * (double)bv[c].x + (double)fv[c].y * (double)bv[c].y;
+            r[c] = (float)(wave_dot_tree64(p) - (double)t[bit[c]]);
+        }
+    }
+}
 
 // grid = (ceil(n_kp / 16), ceil(n_words / 4)); wavefront w of a block computes
 // the 64 responses of chunk blockIdx.y*4 + w for the block's 16 keypoints.
@@ -315,13 +394,20 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // block); lane (g, m) holds features 32g..32g+31 of keypoint row m and of
 // B row m of each 16-bit subtile, so the k order of the MFMA chain is a
 // permutation applied identically to both operands.
-__global__ __launch_bounds__(256) void hashsift_project_fp32_kernel(const float* __restrict__ hist,
-                                                                   const bd_keypoint* __restrict__ kps,
-                                                                   int32_t n_kp, const float* __restrict__ B,
-                                                                   const float* __restrict__ t,
-                                                                   int32_t n_words,
-                                                                   uint64_t* __restrict__ codes,
-                                                                   float* __restrict__ resp)
+//   PREC = FP32: v_mfma_f32_16x16x4_f32, 32 steps per subtile.
+//   PREC = BF16: operands rounded to bfloat16, v_mfma_f32_16x16x32_bf16.
+//   PREC = FP8:  operands scaled per row (max|row| / 448) and rounded to
+//                OCP e4m3, v_mfma_f32_16x16x32_fp8_fp8, response rescaled.
+// With BF16/FP8 every response within `margin` of its threshold is
+// recomputed from the unrounded operands (recheck_response) and counted.
+template <int PREC>
+__global__ __launch_bounds__(256) void hashsift_project_kernel(const float* __restrict__ hist,
+                                                              const bd_keypoint* __restrict__ kps, int32_t n_kp,
+                                                              const float* __restrict__ B,
+                                                              const float* __restrict__ t, int32_t n_words,
+                                                              float margin, uint64_t* __restrict__ codes,
+                                                              float* __restrict__ resp,
+                                                              uint32_t* __restrict__ recheck_count)
 {
     const int lane = threadIdx.x % kWave;
     const int chunk = blockIdx.y * kProjChunks + threadIdx.x / kWave;
@@ -348,33 +434,120 @@ __global__ __launch_bounds__(256) void hashsift_project_fp32_kernel(const float*
             for (int q = 0; q < 32; ++q) a[q] = 0.0f;
         }
     }
+    float b[4][32];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const float4* brow = reinterpret_cast<const float4*>(B + (int64_t)(chunk * 64 + 16 * nt + m) * 128 + 32 * g);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float4 v = brow[q];
+            b[nt][4 * q] = v.x;
+            b[nt][4 * q + 1] = v.y;
+            b[nt][4 * q + 2] = v.z;
+            b[nt][4 * q + 3] = v.w;
+        }
+    }
 
+    floatx4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    float scale[4][4];  // per (subtile, register): factor applied to the accumulator
+    if constexpr (PREC == BD_PREC_FP32) {
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[nt][k], acc[nt], 0, 0, 0);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) scale[nt][i] = 1.0f;
+    } else if constexpr (PREC == BD_PREC_BF16) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bf16x8 av = pack_bf16(a, s);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, pack_bf16(b[nt], s), acc[nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) scale[nt][i] = 1.0f;
+    } else {
+        const float sa = e4m3_scale(row_maxabs(a));  // scale of keypoint row m
+        float sb[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) sb[nt] = e4m3_scale(row_maxabs(b[nt]));  // scale of B row 16nt + m
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const long av = pack_e4m3(a, s, sa);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, pack_e4m3(b[nt], s, sb[nt]), acc[nt], 0, 0, 0);
+        }
+        // the accumulator of register i belongs to keypoint row 4g + i, whose
+        // scale lane 4g + i computed
+        float sk[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sk[i] = __shfl(sa, 4 * g + i, kWave);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) scale[nt][i] = sk[i] * sb[nt];
+    }
+
+    // lane holds D[kp = 4g + i][bit = m] of each 16-bit subtile nt
+    float rv[4][4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const float tv = t[chunk * 64 + 16 * nt + m];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rv[nt][i] = acc[nt][i] * scale[nt][i] - tv;
+    }
+    if constexpr (PREC != BD_PREC_FP32) {
+        // responses within the margin: the wavefront recomputes them one after
+        // another (four candidates' operands in flight at a time)
+        uint32_t rechecked = 0;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool need = fabsf(rv[nt][i]) < margin && kp0 + 4 * g + i < n_kp;
+                uint64_t cand = __ballot(need);
+                rechecked += (uint32_t)__popcll(cand);
+                while (cand) {
+                    constexpr int kB = 4;
+                    int ln[kB], kp[kB], bit[kB];
+                    int cnt = 0;
+#pragma unroll
+                    for (int c = 0; c < kB; ++c) {
+                        const int L = cand ? (int)__builtin_ctzll(cand) : -1;
+                        if (cand) cand &= cand - 1;
+                        ln[c] = L;
+                        const int Ls = L >= 0 ? L : ln[0];
+                        kp[c] = kp0 + 4 * (Ls >> 4) + i;
+                        bit[c] = chunk * 64 + 16 * nt + (Ls & 15);
+                        cnt += L >= 0;
+                    }
+                    float r[kB];
+                    recheck_batch<kB>(hist, B, t, kp, bit, lane, r);
+#pragma unroll
+                    for (int c = 0; c < kB; ++c)
+                        if (c < cnt && lane == ln[c]) rv[nt][i] = r[c];
+                }
+            }
+        }
+        if (recheck_count && lane == 0 && rechecked) atomicAdd(recheck_count, rechecked);
+    }
     uint64_t mask[4][4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int bit = chunk * 64 + 16 * nt + m;
-        const float4* brow = reinterpret_cast<const float4*>(B + (int64_t)bit * 128 + 32 * g);
-        float4 b[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) b[q] = brow[q];
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q], b[q].x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q + 1], b[q].y, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q + 2], b[q].z, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q + 3], b[q].w, acc, 0, 0, 0);
-        }
-        // lane holds D[kp = 4g + i][bit = m] of this 16-bit subtile
-        const float tv = t[bit];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const float r = acc[i] - tv;
-            if (resp) {
-                const int kp = kp0 + 4 * g + i;
-                if (kp < n_kp) resp[(int64_t)kp * n_bits + bit] = r;
-            }
-            mask[nt][i] = __ballot(r > 0.0f);
+            const int kp = kp0 + 4 * g + i;
+            if (resp && kp < n_kp) resp[(int64_t)kp * n_bits + bit] = rv[nt][i];
+            mask[nt][i] = __ballot(rv[nt][i] > 0.0f);
         }
     }
     if (lane < 16) {
@@ -413,13 +586,21 @@ void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, 
                            stream, p, W, H, img_pitch, kps, n_kp, order, hist);
 }
 
-void launch_hashsift_project_fp32(const float* hist, const bd_keypoint* kps, int32_t n_kp, const float* B,
-                                  const float* t, int32_t n_words, uint64_t* codes, float* resp,
-                                  hipStream_t stream)
+void launch_hashsift_project(int32_t precision, const float* hist, const bd_keypoint* kps, int32_t n_kp,
+                             const float* B, const float* t, int32_t n_words, float margin, uint64_t* codes,
+                             float* resp, uint32_t* recheck_count, hipStream_t stream)
 {
     const dim3 grid((n_kp + kProjKp - 1) / kProjKp, (n_words + kProjChunks - 1) / kProjChunks);
-    hipLaunchKernelGGL(hashsift_project_fp32_kernel, grid, dim3(kProjChunks * kWave), 0, stream, hist, kps, n_kp,
-                       B, t, n_words, codes, resp);
+    const dim3 block(kProjChunks * kWave);
+    if (precision == BD_PREC_BF16)
+        hipLaunchKernelGGL(hashsift_project_kernel<BD_PREC_BF16>, grid, block, 0, stream, hist, kps, n_kp, B, t,
+                           n_words, margin, codes, resp, recheck_count);
+    else if (precision == BD_PREC_FP8)
+        hipLaunchKernelGGL(hashsift_project_kernel<BD_PREC_FP8>, grid, block, 0, stream, hist, kps, n_kp, B, t,
+                           n_words, margin, codes, resp, recheck_count);
+    else
+        hipLaunchKernelGGL(hashsift_project_kernel<BD_PREC_FP32>, grid, block, 0, stream, hist, kps, n_kp, B, t,
+                           n_words, margin, codes, resp, recheck_count);
 }
 
 }  // namespace bd

@@ -86,7 +86,7 @@ def test_describe_hashsift_validation(L):
     def call(**kw):
         a = {**base, **kw}
         return L.bd_describe_hashsift(None, p, a["dtype"], a["W"], a["H"], a["pitch"], p, a["n"], None, p, p,
-                                      a["n_bits"], a["prec"], p, None, None, None)
+                                      a["n_bits"], a["prec"], a.get("margin", 1e-3), p, None, None, None, None)
 
     assert call(n_bits=384) == bd.BD_EUNSUPPORTED
     assert call(dtype=7) == bd.BD_EUNSUPPORTED
@@ -95,6 +95,9 @@ def test_describe_hashsift_validation(L):
     assert call(pitch=42) == bd.BD_EINVAL and "multiple of 4" in err(L)
     assert call(dtype=bd.BD_DTYPE_U8, pitch=10) == bd.BD_EINVAL and "null context" in err(L)
     assert call(n=-2) == bd.BD_EINVAL
+    assert call(prec=bd.BD_PREC_BF16, margin=-1.0) == bd.BD_EINVAL and "margin" in err(L)
+    assert call(prec=bd.BD_PREC_FP8, margin=float("nan")) == bd.BD_EINVAL
+    assert call(prec=bd.BD_PREC_FP8) == bd.BD_EINVAL and "null context" in err(L)
 
 
 def test_keypoint_order_validation(L):
@@ -111,10 +114,10 @@ def test_hashsift_features_and_project_validation(L):
     assert L.bd_hashsift_features(None, p, bd.BD_DTYPE_F32, 10, 10, 40, None, 3, None, p, None) == bd.BD_EINVAL
     assert L.bd_hashsift_features(None, p, bd.BD_DTYPE_F32, 10, 10, 40, p, 3, None, p, None) == bd.BD_EINVAL
     assert "null context" in err(L)
-    assert L.bd_hashsift_project(None, p, None, 3, p, p, 128, bd.BD_PREC_FP32, p, None, None) == bd.BD_EUNSUPPORTED
-    assert L.bd_hashsift_project(None, p, None, 3, p, p, 256, 7, p, None, None) == bd.BD_EUNSUPPORTED
-    assert L.bd_hashsift_project(None, None, None, 3, p, p, 256, bd.BD_PREC_FP32, p, None, None) == bd.BD_EINVAL
-    assert L.bd_hashsift_project(None, p, None, 3, p, p, 256, bd.BD_PREC_FP32, p, None, None) == bd.BD_EINVAL
+    assert L.bd_hashsift_project(None, p, None, 3, p, p, 128, bd.BD_PREC_FP32, 0.0, p, None, None, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_hashsift_project(None, p, None, 3, p, p, 256, 7, 0.0, p, None, None, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_hashsift_project(None, None, None, 3, p, p, 256, bd.BD_PREC_FP32, 0.0, p, None, None, None) == bd.BD_EINVAL
+    assert L.bd_hashsift_project(None, p, None, 3, p, p, 256, bd.BD_PREC_FP32, 0.0, p, None, None, None) == bd.BD_EINVAL
     assert "null context" in err(L)
 
 

@@ -1,0 +1,98 @@
+"""Reduced-precision HashSIFT projection (BF16 and FP8-e4m3 MFMA with FP32
+accumulation and an FP32 re-check of responses within the margin).
+
+Two parities, as the extension defines them:
+  * operand rounding + accumulation: with margin 0 the GPU responses equal
+    the FP64 dot products of the same rounded operands (oracle emulation of
+    the rounding) up to FP32 accumulation error;
+  * against the exact FP64 oracle: the error of responses outside the margin
+    and the flipped-bit rate are measured and bounded (BF16) or reported (FP8).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2108_08380_amd as bd
+from paper_2108_08380_amd import synth
+from conftest import to_np
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-3
+
+
+def unpack(codes, n_bits):
+    return np.unpackbits(codes.view(np.uint8), axis=1, bitorder="little")[:, :n_bits]
+
+
+def features(dev, w, n=None):
+    img = torch.from_numpy(w.image1).to(dev)
+    kp = w.kp1 if n is None else w.kp1[:n]
+    kps = bd.keypoints_tensor(kp, dev)
+    return kp, kps, bd.hashsift_features(img, kps)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+@pytest.mark.parametrize("n_bits", [256, 512])
+def test_rounded_operands_and_accumulation(ref, dev, precision, n_bits):
+    w = synth.hashsift512_pair(n_kp=1500, n_bits=n_bits)
+    _, kps, f = features(dev, w)
+    B, t = torch.from_numpy(w.B).to(dev), torch.from_numpy(w.t).to(dev)
+    _, resp = bd.hashsift_project(f, B, t, kps, precision=precision, with_resp=True, margin=0.0)
+    exp = ref.project_lowp(to_np(f), w.B, w.t, precision)
+    err = np.abs(to_np(resp) - exp).max()
+    print(f"{precision} K={n_bits} max|r_gpu - r_rounded64| = {err:.2e}")
+    # A single operand rounded differently from the emulation would move a
+    # response by ~1e-3.  BF16 MFMA accumulation matches FP32 rounding (~1e-7);
+    # the FP8 instruction's internal sums are coarser (measured up to 2.3e-5).
+    assert err <= (2e-5 if precision == "bf16" else 1e-4)
+
+
+@pytest.mark.parametrize("precision,max_err,max_flip", [("bf16", 5e-3, 1e-4), ("fp8", 6e-2, 5e-2)])
+def test_against_fp64_with_recheck(ref, dev, precision, max_err, max_flip):
+    w = synth.hashsift512_pair(n_kp=3000)
+    kp, kps, f = features(dev, w)
+    B, t = torch.from_numpy(w.B).to(dev), torch.from_numpy(w.t).to(dev)
+    count = torch.zeros(1, dtype=torch.uint32, device=dev)
+    codes, resp = bd.hashsift_project(f, B, t, kps, precision=precision, with_resp=True, margin=MARGIN,
+                                      recheck_count=count)
+    _, raw = bd.hashsift_project(f, B, t, kps, precision=precision, with_resp=True, margin=0.0)
+    codes, resp, raw, count = to_np(codes), to_np(resp), to_np(raw), int(to_np(count)[0])
+    h64, r64, c64 = ref.describe_hashsift(w.image1, kp, w.B, w.t)
+    inside = np.abs(raw) < MARGIN
+    assert count == int(inside.sum())
+    # re-checked responses are FP32 results of the unrounded operands
+    assert np.abs(resp[inside] - r64[inside]).max(initial=0) <= 1e-4
+    err_out = np.abs(raw[~inside] - r64[~inside]).max()
+    flips = (unpack(codes, 512) != unpack(c64, 512)).mean()
+    print(f"{precision}: max|r - r64| outside margin {err_out:.2e}, flipped bits {flips:.2e}, "
+          f"re-checked {count} of {raw.size} ({count / raw.size:.2e})")
+    assert err_out <= max_err
+    assert flips <= max_flip
+
+
+def test_full_size_200k_keypoints(dev):
+    """16 images of 1920x1080, 12500 keypoints each (200000): low-precision codes
+    against the FP32 path (itself within 4e-7 of FP64)."""
+    B = t = None
+    stats = {p: [0, 0, 0, 0.0] for p in ("bf16", "fp8")}  # flips, bits, rechecked, max err
+    for i in range(16):
+        w = synth.hashsift512_pair(synth.SEED_BASE + 3 + 1000 * i, n_kp=12500)
+        if B is None:
+            B, t = torch.from_numpy(w.B).to(dev), torch.from_numpy(w.t).to(dev)
+        _, kps, f = features(dev, w)
+        c32, r32 = bd.hashsift_project(f, B, t, kps, precision="fp32", with_resp=True)
+        c32, r32 = to_np(c32), to_np(r32)
+        for p in stats:
+            cnt = torch.zeros(1, dtype=torch.uint32, device=dev)
+            c, r = bd.hashsift_project(f, B, t, kps, precision=p, with_resp=True, margin=MARGIN, recheck_count=cnt)
+            c, r = to_np(c), to_np(r)
+            s = stats[p]
+            s[0] += int((unpack(c, 512) != unpack(c32, 512)).sum())
+            s[1] += c.size * 64
+            s[2] += int(to_np(cnt)[0])
+            s[3] = max(s[3], float(np.abs(r - r32).max()))
+    for p, (fl, nb, rc, e) in stats.items():
+        print(f"{p}: flipped {fl}/{nb} = {fl / nb:.2e}, re-checked {rc} ({rc / nb:.2e}), max|r - r32| {e:.2e}")
+    assert stats["bf16"][0] / stats["bf16"][1] <= 1e-4
+    assert stats["fp8"][0] / stats["fp8"][1] <= 5e-2
