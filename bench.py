@@ -182,6 +182,68 @@ def precision_projection(wl, n_rows=200000, reps=20):
     return out
 
 
+def differentiation_step(dev, n=8192, reps=5):
+    """One training step of the differentiation extension on 8192 triplets of
+    32x32 patches: relaxed BAD-512 and HashSIFT-512 descriptors of anchors and
+    positives, hardest-negative triplet loss (8192 x 8192 similarities), and
+    the full backward pass to the parameters.  Times per step (HIP events)."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+    from paper_2108_08380_amd import autograd as ag
+    from paper_2108_08380_amd import synth
+
+    b = synth.triplets(synth.SEED_BASE + 4, n=n)
+    rng = np.random.default_rng(0)
+    pairs = bd.pairs_tensor(synth.box_pairs(rng, 512), dev)
+    an = torch.from_numpy(b.anchor).to(dev)
+    po = torch.from_numpy(b.positive).to(dev)
+    w1 = torch.ones(512, device=dev, requires_grad=True)
+    w2 = torch.ones(512, device=dev, requires_grad=True)
+    th = torch.zeros(512, device=dev, requires_grad=True)
+    Bm, tv = synth.projection(rng, 512)
+    B = torch.from_numpy(Bm).to(dev).requires_grad_()
+    t = torch.from_numpy(tv).to(dev).requires_grad_()
+    fa, fp = bd.hashsift_patch_features(an), bd.hashsift_patch_features(po)
+
+    def bad_step():
+        loss = ag.bad_triplet_loss(an, po, w1, w2, th, pairs)
+        loss.backward()
+        return loss
+
+    def hs_step():
+        loss = ag.hashsift_triplet_loss(fa, fp, B, t)
+        loss.backward()
+        return loss
+
+    out = {}
+    for name, fn in (("bad512", bad_step), ("hashsift512", hs_step)):
+        loss = fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        out[name] = {"ms_per_step": round(s.elapsed_time(e) / reps, 3), "loss": round(float(loss.detach()), 6)}
+    # the similarity tiles alone: 2 * n^2 * K flops on FP32 MFMA
+    D_a = torch.tanh(torch.randn(n, 512, device=dev))
+    D_p = torch.tanh(torch.randn(n, 512, device=dev))
+    bd.trl_hnm_fwd(D_a, D_p, 0.5)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        bd.trl_hnm_fwd(D_a, D_p, 0.5)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    out["trl_forward_ms"] = round(ms, 3)
+    out["trl_forward_tflops"] = round(2.0 * n * n * 512 / (ms * 1e-3) / 1e12, 2)
+    return out
+
+
 def cpu_baseline(sample: int):
     """The oracle on `sample` keypoints per view (full integral images), scaled to the full step."""
     import oracle
@@ -321,6 +383,7 @@ def main():
     }
     if not args.only:
         result["precision_projection_200k"] = precision_projection(wl)
+        result["differentiation_8192_triplets"] = differentiation_step(dev)
     if not args.no_cpu and not args.only:
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(result))

@@ -188,6 +188,59 @@ int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q,
                          const uint64_t* train, int32_t n_t, int32_t n_words, int32_t k,
                          int32_t* idx, uint32_t* dist, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Differentiation extension (not proposed by the paper): relaxed descriptors
+ * D = tanh(beta * rho) and the triplet ranking loss with in-batch hardest
+ * negatives (Sec. III-A Eq. 1, Sec. III-B Eq. 3; HNM and anchor swap as in
+ * the training of Sec. III), with hand-written backward passes.  Patches are
+ * n 32x32 float32 images (1024 values each, row-major); per-sample arrays
+ * are n x n_bits float32, row-major.  All reductions have a fixed order.
+ * ---------------------------------------------------------------------- */
+
+/* HashSIFT features of 32x32 patches: each patch is an image with its
+ * keypoint at the centre (15.5, 15.5), scale 1, angle 0.  hist: n x 128. */
+int bd_hashsift_patch_features(bd_context* ctx, const float* patches, int32_t n, float* hist, void* stream);
+
+/* Relaxed BAD: with box means m1, m2 of pair j on the patch (boxes centred at
+ * 16 + u, radius r, clamped to [r, 31 - r]),
+ *   rho_j = theta_j - (w1_j m1_j - w2_j m2_j),  D_j = tanh(beta rho_j).
+ * With w1 = w2 = 1 the sign of rho_j is the BAD stump of Sec. III-A.
+ * m1, m2 (n x n_bits, optional) keep the box means for the backward pass.
+ * n_bits: a multiple of 64 (<= 4096); beta > 0. */
+int bd_relaxed_bad_fwd(bd_context* ctx, const float* patches, int32_t n, const bd_box_pair* pairs, const float* w1,
+                       const float* w2, const float* theta, int32_t n_bits, float beta, float* D, float* m1,
+                       float* m2, void* stream);
+
+/* Gradients of the relaxed BAD parameters from dL/dD (gD): with
+ * g = gD * beta * (1 - D^2): dL/dtheta_j = sum g_j, dL/dw1_j = -sum g_j m1_j,
+ * dL/dw2_j = sum g_j m2_j over the n patches (outputs overwritten). */
+int bd_relaxed_bad_bwd(bd_context* ctx, const float* gD, const float* D, const float* m1, const float* m2, int32_t n,
+                       int32_t n_bits, float beta, float* g_w1, float* g_w2, float* g_theta, void* stream);
+
+/* Relaxed HashSIFT: rho = B f - t (FP32 MFMA), D = tanh(beta rho); f is
+ * n x 128, B n_bits x 128, t n_bits; rho (optional) receives rho. */
+int bd_relaxed_hashsift_fwd(bd_context* ctx, const float* f, int32_t n, const float* B, const float* t, int32_t n_bits,
+                            float beta, float* rho, float* D, void* stream);
+
+/* dL/dB = sum_x g f^T (n_bits x 128), dL/dt = -sum_x g, g = gD beta (1 - D^2). */
+int bd_relaxed_hashsift_bwd(bd_context* ctx, const float* gD, const float* D, const float* f, int32_t n,
+                            int32_t n_bits, float beta, float* gB, float* gt, void* stream);
+
+/* Triplet ranking loss with in-batch hardest negatives and anchor swap:
+ * s(x, y) = D(x) . D(y) / n_bits for anchors A and positives P (n x n_bits),
+ * s_neg(i) = max(max_{j != i} s(a_i, p_j), max_{j != i} s(a_j, p_i)) (ties:
+ * the row candidate, then the lowest j), loss = mean_i [tau - s(a_i, p_i) +
+ * s_neg(i)]_+ (one float at *loss).  neg[i] = j for a row candidate, -1 - j
+ * for a column candidate; hinge[i] = tau - s(a_i, p_i) + s_neg(i).  The
+ * n x n similarity is formed in 128 x 128 MFMA tiles and never stored. */
+int bd_trl_hnm_fwd(bd_context* ctx, const float* A, const float* P, int32_t n, int32_t n_bits, float tau, float* loss,
+                   int32_t* neg, float* hinge, void* stream);
+
+/* dL/dA, dL/dP (n x n_bits) for upstream gradient *grad_loss (device), from
+ * the neg and hinge arrays of the forward pass; zero subgradient at the kink. */
+int bd_trl_hnm_bwd(bd_context* ctx, const float* A, const float* P, int32_t n, int32_t n_bits, const int32_t* neg,
+                   const float* hinge, const float* grad_loss, float* gA, float* gP, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,19 @@ def lib():
         L.bdref_round_e4m3.restype = ctypes.c_float
         L.bdref_project_lowp.argtypes = [P, i32, P, P, i32, i32, P]
         L.bdref_project_lowp.restype = None
+        d = ctypes.c_double
+        L.bdref_relaxed_bad.argtypes = [P, i32, P, P, P, P, i32, d, P, P, P, P]
+        L.bdref_relaxed_bad.restype = None
+        L.bdref_relaxed_hashsift.argtypes = [P, i32, P, P, i32, d, P, P]
+        L.bdref_relaxed_hashsift.restype = None
+        L.bdref_trl_hnm.argtypes = [P, P, i32, i32, d, P, P, P]
+        L.bdref_trl_hnm.restype = d
+        L.bdref_relaxed_bad_grad.argtypes = [P, P, P, P, i32, i32, d, P, P, P]
+        L.bdref_relaxed_bad_grad.restype = None
+        L.bdref_relaxed_hashsift_grad.argtypes = [P, P, P, i32, i32, d, P, P]
+        L.bdref_relaxed_hashsift_grad.restype = None
+        L.bdref_hashsift_patch_features.argtypes = [P, i32, P]
+        L.bdref_hashsift_patch_features.restype = None
         _lib = L
     return _lib
 
@@ -182,3 +195,65 @@ def project_lowp(hist32: np.ndarray, B: np.ndarray, t: np.ndarray, precision: st
     resp = np.zeros((h.shape[0], B.shape[0]), dtype=np.float64)
     lib().bdref_project_lowp(_ptr(h), h.shape[0], _ptr(B), _ptr(t), B.shape[0], PRECISIONS[precision], _ptr(resp))
     return resp
+
+
+# --------------------------------------------------------------------------- differentiation
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def relaxed_bad(patches, pairs, w1, w2, theta, beta):
+    """(rho, D, m1, m2), each (n, K) FP64."""
+    pt = np.ascontiguousarray(patches, dtype=np.float32).reshape(-1, 1024)
+    pr = _as_pairs(pairs)
+    n, K = pt.shape[0], len(pr)
+    w1, w2, theta = _f64(w1), _f64(w2), _f64(theta)
+    out = [np.zeros((n, K)) for _ in range(4)]
+    lib().bdref_relaxed_bad(_ptr(pt), n, _ptr(pr), _ptr(w1), _ptr(w2), _ptr(theta), K, float(beta),
+                            *[_ptr(o) for o in out])
+    return tuple(out)
+
+
+def relaxed_hashsift(f, B, t, beta):
+    """(rho, D), each (n, K) FP64, for features f (n, 128)."""
+    f, B, t = _f64(f), _f64(B), _f64(t)
+    n, K = f.shape[0], B.shape[0]
+    rho, dt = np.zeros((n, K)), np.zeros((n, K))
+    lib().bdref_relaxed_hashsift(_ptr(f), n, _ptr(B), _ptr(t), K, float(beta), _ptr(rho), _ptr(dt))
+    return rho, dt
+
+
+def trl_hnm(A, P, tau, grads=True):
+    """(loss, neg, gA, gP) of the in-batch hardest-negative triplet ranking loss."""
+    A, P = _f64(A), _f64(P)
+    n, K = A.shape
+    neg = np.zeros(n, dtype=np.int32)
+    gA, gP = (np.zeros((n, K)), np.zeros((n, K))) if grads else (None, None)
+    loss = lib().bdref_trl_hnm(_ptr(A), _ptr(P), n, K, float(tau), _ptr(neg),
+                               _ptr(gA) if grads else None, _ptr(gP) if grads else None)
+    return loss, neg, gA, gP
+
+
+def relaxed_bad_grad(gD, dt, m1, m2, beta):
+    gD, dt, m1, m2 = _f64(gD), _f64(dt), _f64(m1), _f64(m2)
+    n, K = gD.shape
+    g = [np.zeros(K) for _ in range(3)]
+    lib().bdref_relaxed_bad_grad(_ptr(gD), _ptr(dt), _ptr(m1), _ptr(m2), n, K, float(beta), *[_ptr(x) for x in g])
+    return tuple(g)  # (g_w1, g_w2, g_theta)
+
+
+def relaxed_hashsift_grad(gD, dt, f, beta):
+    gD, dt, f = _f64(gD), _f64(dt), _f64(f)
+    n, K = gD.shape
+    gB, gt = np.zeros((K, 128)), np.zeros(K)
+    lib().bdref_relaxed_hashsift_grad(_ptr(gD), _ptr(dt), _ptr(f), n, K, float(beta), _ptr(gB), _ptr(gt))
+    return gB, gt
+
+
+def hashsift_patch_features(patches):
+    pt = np.ascontiguousarray(patches, dtype=np.float32).reshape(-1, 1024)
+    f = np.zeros((pt.shape[0], 128))
+    lib().bdref_hashsift_patch_features(_ptr(pt), pt.shape[0], _ptr(f))
+    return f

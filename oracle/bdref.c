@@ -386,3 +386,139 @@ void bdref_project_lowp(const float* hist, int32_t n_kp, const float* B, const f
         }
     }
 }
+
+/* ------------------------------------------------------------------ differentiation */
+
+static double patch_box_mean(const float* patch, int cx, int cy, int R)
+{
+    double sum = 0.0;
+    for (int y = cy - R; y <= cy + R; ++y)
+        for (int x = cx - R; x <= cx + R; ++x) sum += (double)patch[y * 32 + x];
+    return sum / (double)((2 * R + 1) * (2 * R + 1));
+}
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+void bdref_relaxed_bad(const float* patches, int32_t n, const bdref_box_pair* pairs, const double* w1,
+                       const double* w2, const double* theta, int32_t n_bits, double beta, double* rho,
+                       double* dt, double* m1, double* m2)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        const float* patch = patches + (int64_t)i * 1024;
+        for (int32_t j = 0; j < n_bits; ++j) {
+            const bdref_box_pair* p = &pairs[j];
+            int R = p->radius > 15 ? 15 : p->radius;
+            double a = patch_box_mean(patch, clampi(16 + p->x1, R, 31 - R), clampi(16 + p->y1, R, 31 - R), R);
+            double b = patch_box_mean(patch, clampi(16 + p->x2, R, 31 - R), clampi(16 + p->y2, R, 31 - R), R);
+            double r = theta[j] - (w1[j] * a - w2[j] * b);
+            int64_t o = (int64_t)i * n_bits + j;
+            if (rho) rho[o] = r;
+            if (dt) dt[o] = tanh(beta * r);
+            if (m1) m1[o] = a;
+            if (m2) m2[o] = b;
+        }
+    }
+}
+
+void bdref_relaxed_hashsift(const double* f, int32_t n, const double* B, const double* t, int32_t n_bits,
+                            double beta, double* rho, double* dt)
+{
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < n_bits; ++j) {
+            double r = 0.0;
+            for (int k = 0; k < 128; ++k) r += B[(int64_t)j * 128 + k] * f[(int64_t)i * 128 + k];
+            r -= t[j];
+            int64_t o = (int64_t)i * n_bits + j;
+            if (rho) rho[o] = r;
+            if (dt) dt[o] = tanh(beta * r);
+        }
+}
+
+static double sim(const double* x, const double* y, int32_t K)
+{
+    double s = 0.0;
+    for (int32_t k = 0; k < K; ++k) s += x[k] * y[k];
+    return s / (double)K;
+}
+
+double bdref_trl_hnm(const double* A, const double* P, int32_t n, int32_t n_bits, double tau, int32_t* neg,
+                     double* gA, double* gP)
+{
+    const int32_t K = n_bits;
+    if (gA) memset(gA, 0, sizeof(double) * (size_t)n * (size_t)K);
+    if (gP) memset(gP, 0, sizeof(double) * (size_t)n * (size_t)K);
+    double loss = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        const double* ai = A + (int64_t)i * K;
+        const double* pi = P + (int64_t)i * K;
+        double best = -INFINITY;
+        int32_t choice = 0;
+        for (int32_t j = 0; j < n; ++j) { /* row candidates s(a_i, p_j) */
+            if (j == i) continue;
+            double v = sim(ai, P + (int64_t)j * K, K);
+            if (v > best) { best = v; choice = j; }
+        }
+        for (int32_t j = 0; j < n; ++j) { /* column candidates s(a_j, p_i) */
+            if (j == i) continue;
+            double v = sim(A + (int64_t)j * K, pi, K);
+            if (v > best) { best = v; choice = -1 - j; }
+        }
+        if (neg) neg[i] = choice;
+        double margin = tau - sim(ai, pi, K) + best;
+        if (margin <= 0.0 || n < 2) continue;
+        loss += margin / (double)n;
+        if (!gA || !gP) continue;
+        double c = 1.0 / ((double)n * (double)K);
+        for (int32_t k = 0; k < K; ++k) { /* d(-s(a_i, p_i)) */
+            gA[(int64_t)i * K + k] -= c * pi[k];
+            gP[(int64_t)i * K + k] -= c * ai[k];
+        }
+        if (choice >= 0) { /* d s(a_i, p_j) */
+            const double* pj = P + (int64_t)choice * K;
+            for (int32_t k = 0; k < K; ++k) {
+                gA[(int64_t)i * K + k] += c * pj[k];
+                gP[(int64_t)choice * K + k] += c * ai[k];
+            }
+        } else { /* d s(a_j, p_i) */
+            int32_t j = -1 - choice;
+            const double* aj = A + (int64_t)j * K;
+            for (int32_t k = 0; k < K; ++k) {
+                gA[(int64_t)j * K + k] += c * pi[k];
+                gP[(int64_t)i * K + k] += c * aj[k];
+            }
+        }
+    }
+    return loss;
+}
+
+void bdref_relaxed_bad_grad(const double* gD, const double* dt, const double* m1, const double* m2, int32_t n,
+                            int32_t n_bits, double beta, double* g_w1, double* g_w2, double* g_theta)
+{
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < n_bits; ++j) {
+            int64_t o = (int64_t)i * n_bits + j;
+            double g = gD[o] * beta * (1.0 - dt[o] * dt[o]);
+            g_theta[j] += g;
+            g_w1[j] -= g * m1[o];
+            g_w2[j] += g * m2[o];
+        }
+}
+
+void bdref_relaxed_hashsift_grad(const double* gD, const double* dt, const double* f, int32_t n, int32_t n_bits,
+                                 double beta, double* gB, double* gt)
+{
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < n_bits; ++j) {
+            int64_t o = (int64_t)i * n_bits + j;
+            double g = gD[o] * beta * (1.0 - dt[o] * dt[o]);
+            gt[j] -= g;
+            for (int k = 0; k < 128; ++k) gB[(int64_t)j * 128 + k] += g * f[(int64_t)i * 128 + k];
+        }
+}
+
+void bdref_hashsift_patch_features(const float* patches, int32_t n, double* f)
+{
+    bdref_keypoint kp = {15.5f, 15.5f, 1.0f, 0.0f};
+    for (int32_t i = 0; i < n; ++i)
+        bdref_hashsift_hist(patches + (int64_t)i * 1024, 1, 32, 32, 128, &kp, 1, f + (int64_t)i * 128);
+}

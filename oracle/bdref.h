@@ -75,6 +75,50 @@ float bdref_round_e4m3(float x);
 void bdref_project_lowp(const float* hist, int32_t n_kp, const float* B, const float* t, int32_t n_bits,
                         int32_t precision, double* resp);
 
+/* ---- Relaxed descriptors and the triplet ranking loss (Sec. III-A Eq. 1,
+ * Sec. III-B Eq. 3; the differentiation extension).  Patches are n 32x32
+ * float32 images (row-major, 1024 values each).
+ *
+ * Relaxed BAD on a patch: the patch is an image with keypoint (15.5, 15.5),
+ * scale 1, angle 0, so pair j's box of radius R = r_j is centred at
+ * (16 + u_x, 16 + u_y) clamped to [R, 31 - R]; m1, m2 are the two box means
+ * (FP64 pixel sums / (2R+1)^2) and
+ *   rho_j = theta_j - (w1_j m1_j - w2_j m2_j),   D_j = tanh(beta rho_j).
+ * With w1 = w2 = 1 the bit [rho_j >= 0] is the BAD stump [f <= theta].
+ * rho, dt, m1, m2 are n x K (any may be NULL). */
+void bdref_relaxed_bad(const float* patches, int32_t n, const bdref_box_pair* pairs, const double* w1,
+                       const double* w2, const double* theta, int32_t n_bits, double beta, double* rho,
+                       double* dt, double* m1, double* m2);
+
+/* Relaxed HashSIFT: rho = B f - t for features f (n x 128, FP64),
+ * D = tanh(beta rho).  B is K x 128, t has K entries (FP64). */
+void bdref_relaxed_hashsift(const double* f, int32_t n, const double* B, const double* t, int32_t n_bits,
+                            double beta, double* rho, double* dt);
+
+/* Triplet ranking loss with in-batch hardest negatives and anchor swap:
+ * s(x, y) = D(x) . D(y) / K for anchors A (n x K) and positives P (n x K);
+ * s_neg(i) = max(max_{j != i} s(a_i, p_j), max_{j != i} s(a_j, p_i)) (ties:
+ * the row candidate first, then the lowest j); loss = mean_i
+ * [tau - s(a_i, p_i) + s_neg(i)]_+.  Outputs: the loss; for each i the
+ * chosen negative neg[i] = j for a row candidate s(a_i, p_j) or -1 - j for a
+ * column candidate s(a_j, p_i); and the analytic gradients dL/dA, dL/dP
+ * (n x K, may be NULL) with a zero subgradient at the hinge kink. */
+double bdref_trl_hnm(const double* A, const double* P, int32_t n, int32_t n_bits, double tau, int32_t* neg,
+                     double* gA, double* gP);
+
+/* Chain rule through the relaxed descriptors: from dL/dD (n x K) and D,
+ *   BAD:      dL/dtheta_j = sum_x g_j, dL/dw1_j = -sum_x g_j m1_j, dL/dw2_j = sum_x g_j m2_j
+ *   HashSIFT: dL/dB = sum_x g f^T (K x 128), dL/dt = -sum_x g
+ * with g = dL/dD * beta * (1 - D^2).  Outputs are accumulated (+=). */
+void bdref_relaxed_bad_grad(const double* gD, const double* dt, const double* m1, const double* m2, int32_t n,
+                            int32_t n_bits, double beta, double* g_w1, double* g_w2, double* g_theta);
+void bdref_relaxed_hashsift_grad(const double* gD, const double* dt, const double* f, int32_t n, int32_t n_bits,
+                                 double beta, double* gB, double* gt);
+
+/* HashSIFT features of 32x32 patches (keypoint (15.5, 15.5), scale 1,
+ * angle 0, so every sample is a patch pixel, clamp-to-edge in the apron). */
+void bdref_hashsift_patch_features(const float* patches, int32_t n, double* f);
+
 /* 1 when the keypoint has finite fields and a positive scale. */
 int32_t bdref_keypoint_valid(const bdref_keypoint* kp);
 

@@ -47,6 +47,13 @@ SIGNATURES = {
     "bd_hashsift_features": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P], ctypes.c_int),
     "bd_hashsift_project": ([_P, _P, _P, _I32, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_match_hamming_knn": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
+    "bd_hashsift_patch_features": ([_P, _P, _I32, _P, _P], ctypes.c_int),
+    "bd_relaxed_bad_fwd": ([_P, _P, _I32, _P, _P, _P, _P, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
+    "bd_relaxed_bad_bwd": ([_P, _P, _P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
+    "bd_relaxed_hashsift_fwd": ([_P, _P, _I32, _P, _P, _I32, ctypes.c_float, _P, _P, _P], ctypes.c_int),
+    "bd_relaxed_hashsift_bwd": ([_P, _P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P], ctypes.c_int),
+    "bd_trl_hnm_fwd": ([_P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
+    "bd_trl_hnm_bwd": ([_P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
 }
 
 
@@ -331,3 +338,115 @@ def match_hamming_knn(query, train, k: int = 1, idx=None, dist=None):
     _check(lib().bd_match_hamming_knn(context(dev), query.data_ptr(), n_q, train.data_ptr(), train.shape[0],
                                       n_words, k, idx.data_ptr(), dist.data_ptr(), stream))
     return idx, dist
+
+
+# --------------------------------------------------------------------------- differentiation extension
+
+
+def _f32_contig(t, name, shape=None):
+    torch = _torch()
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def hashsift_patch_features(patches, out=None):
+    """(n, 128) HashSIFT features of (n, 32, 32) float32 patches (bd_hashsift_patch_features)."""
+    torch = _torch()
+    _f32_contig(patches, "patches")
+    n = patches.shape[0]
+    if patches.numel() != n * 1024:
+        raise ValueError("patches must be (n, 32, 32)")
+    if out is None:
+        out = torch.empty((n, 128), dtype=torch.float32, device=patches.device)
+    dev, stream = _device_and_stream(patches, out)
+    _check(lib().bd_hashsift_patch_features(context(dev), patches.data_ptr(), n, out.data_ptr(), stream))
+    return out
+
+
+def relaxed_bad_fwd(patches, pairs, w1, w2, theta, beta: float):
+    """(D, m1, m2), each (n, K): relaxed BAD descriptors and the box means (bd_relaxed_bad_fwd)."""
+    torch = _torch()
+    _f32_contig(patches, "patches")
+    n, K = patches.shape[0], pairs.shape[0]
+    for v, name in ((w1, "w1"), (w2, "w2"), (theta, "theta")):
+        _f32_contig(v, name, (K,))
+    D = torch.empty((n, K), dtype=torch.float32, device=patches.device)
+    m1, m2 = torch.empty_like(D), torch.empty_like(D)
+    dev, stream = _device_and_stream(patches, pairs, w1, w2, theta)
+    _check(lib().bd_relaxed_bad_fwd(context(dev), patches.data_ptr(), n, pairs.data_ptr(), w1.data_ptr(),
+                                    w2.data_ptr(), theta.data_ptr(), K, beta, D.data_ptr(), m1.data_ptr(),
+                                    m2.data_ptr(), stream))
+    return D, m1, m2
+
+
+def relaxed_bad_bwd(gD, D, m1, m2, beta: float):
+    """(g_w1, g_w2, g_theta) from dL/dD (bd_relaxed_bad_bwd)."""
+    torch = _torch()
+    n, K = D.shape
+    for v, name in ((gD, "gD"), (D, "D"), (m1, "m1"), (m2, "m2")):
+        _f32_contig(v, name, (n, K))
+    g = [torch.empty((K,), dtype=torch.float32, device=D.device) for _ in range(3)]
+    dev, stream = _device_and_stream(gD, D, m1, m2)
+    _check(lib().bd_relaxed_bad_bwd(context(dev), gD.data_ptr(), D.data_ptr(), m1.data_ptr(), m2.data_ptr(), n, K,
+                                    beta, g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(), stream))
+    return tuple(g)
+
+
+def relaxed_hashsift_fwd(f, B, t, beta: float):
+    """(rho, D), each (n, K), of the relaxed HashSIFT descriptor (bd_relaxed_hashsift_fwd)."""
+    torch = _torch()
+    n, K = f.shape[0], B.shape[0]
+    _f32_contig(f, "f", (n, 128))
+    _f32_contig(B, "B", (K, 128))
+    _f32_contig(t, "t", (K,))
+    rho = torch.empty((n, K), dtype=torch.float32, device=f.device)
+    D = torch.empty_like(rho)
+    dev, stream = _device_and_stream(f, B, t)
+    _check(lib().bd_relaxed_hashsift_fwd(context(dev), f.data_ptr(), n, B.data_ptr(), t.data_ptr(), K, beta,
+                                         rho.data_ptr(), D.data_ptr(), stream))
+    return rho, D
+
+
+def relaxed_hashsift_bwd(gD, D, f, beta: float):
+    """(gB, gt) from dL/dD (bd_relaxed_hashsift_bwd)."""
+    torch = _torch()
+    n, K = D.shape
+    _f32_contig(gD, "gD", (n, K))
+    _f32_contig(D, "D", (n, K))
+    _f32_contig(f, "f", (n, 128))
+    gB = torch.empty((K, 128), dtype=torch.float32, device=D.device)
+    gt = torch.empty((K,), dtype=torch.float32, device=D.device)
+    dev, stream = _device_and_stream(gD, D, f)
+    _check(lib().bd_relaxed_hashsift_bwd(context(dev), gD.data_ptr(), D.data_ptr(), f.data_ptr(), n, K, beta,
+                                         gB.data_ptr(), gt.data_ptr(), stream))
+    return gB, gt
+
+
+def trl_hnm_fwd(A, P, tau: float):
+    """(loss (1,), neg (n,) int32, hinge (n,)) of the hardest-negative triplet loss (bd_trl_hnm_fwd)."""
+    torch = _torch()
+    n, K = A.shape
+    _f32_contig(A, "A", (n, K))
+    _f32_contig(P, "P", (n, K))
+    loss = torch.empty((1,), dtype=torch.float32, device=A.device)
+    neg = torch.empty((n,), dtype=torch.int32, device=A.device)
+    hinge = torch.empty((n,), dtype=torch.float32, device=A.device)
+    dev, stream = _device_and_stream(A, P)
+    _check(lib().bd_trl_hnm_fwd(context(dev), A.data_ptr(), P.data_ptr(), n, K, tau, loss.data_ptr(), neg.data_ptr(),
+                                hinge.data_ptr(), stream))
+    return loss, neg, hinge
+
+
+def trl_hnm_bwd(A, P, neg, hinge, grad_loss):
+    """(gA, gP) for the upstream gradient grad_loss (a (1,) device tensor) (bd_trl_hnm_bwd)."""
+    torch = _torch()
+    n, K = A.shape
+    gA, gP = torch.empty_like(A), torch.empty_like(P)
+    grad_loss = _f32_contig(grad_loss.reshape(1).contiguous(), "grad_loss")
+    dev, stream = _device_and_stream(A, P, neg, hinge, grad_loss)
+    _check(lib().bd_trl_hnm_bwd(context(dev), A.data_ptr(), P.data_ptr(), n, K, neg.data_ptr(), hinge.data_ptr(),
+                                grad_loss.data_ptr(), gA.data_ptr(), gP.data_ptr(), stream))
+    return gA, gP

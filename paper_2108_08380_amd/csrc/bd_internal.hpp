@@ -68,9 +68,28 @@ void launch_keypoint_order(const bd_keypoint* kps, int32_t n_kp, int32_t W, int3
 void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
                           const bd_keypoint* kps, int32_t n_kp, const int32_t* order, float* hist,
                           hipStream_t stream);
+void launch_hashsift_patch_features(const float* patches, int32_t n, float* hist, hipStream_t stream);
 void launch_hashsift_project(int32_t precision, const float* hist, const bd_keypoint* kps, int32_t n_kp,
                              const float* B, const float* t, int32_t n_words, float margin, uint64_t* codes,
                              float* resp, uint32_t* recheck_count, hipStream_t stream);
+
+// ---- differentiation (relaxed.hip)
+void launch_relaxed_bad_fwd(const float* patches, int32_t n, const bd_box_pair* pairs, const float* w1,
+                            const float* w2, const float* theta, int32_t n_bits, float beta, float* D, float* m1,
+                            float* m2, hipStream_t stream);
+size_t relaxed_bad_bwd_workspace(int32_t n, int32_t n_bits);
+void launch_relaxed_bad_bwd(const float* gD, const float* D, const float* m1, const float* m2, int32_t n,
+                            int32_t n_bits, float beta, float* g_w1, float* g_w2, float* g_theta, void* workspace,
+                            hipStream_t stream);
+void launch_tanh_scale(const float* rho, int64_t count, float beta, float* D, hipStream_t stream);
+size_t relaxed_hs_bwd_workspace(int32_t n, int32_t n_bits);
+void launch_relaxed_hs_bwd(const float* gD, const float* D, const float* f, int32_t n, int32_t n_bits, float beta,
+                           float* gB, float* gt, void* workspace, hipStream_t stream);
+size_t trl_workspace(int32_t n);
+void launch_trl_fwd(const float* A, const float* P, int32_t n, int32_t K, float tau, float* loss, int32_t* neg,
+                    float* hinge, void* workspace, hipStream_t stream);
+void launch_trl_bwd(const float* A, const float* P, int32_t n, int32_t K, const int32_t* neg, const float* hinge,
+                    const float* grad_loss, float* gA, float* gP, void* workspace, hipStream_t stream);
 
 // ---- Hamming k-NN (hamming.hip)
 struct KnnPlan {

@@ -278,4 +278,122 @@ int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q, co
     return check_launch(fn);
 }
 
+int bd_hashsift_patch_features(bd_context* ctx, const float* patches, int32_t n, float* hist, void* stream)
+{
+    const char* fn = "bd_hashsift_patch_features";
+    if (n < 0) return fail(BD_EINVAL, "%s: n %d < 0", fn, n);
+    if (n > 0 && (!patches || !hist)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n == 0) return BD_OK;
+    launch_hashsift_patch_features(patches, n, hist, static_cast<hipStream_t>(stream));
+    return check_launch(fn);
+}
+
+static int check_relaxed(const char* fn, int32_t n, int32_t n_bits, float beta)
+{
+    if (n_bits < 64 || n_bits % 64 != 0 || n_bits > 4096)
+        return fail(BD_EUNSUPPORTED, "%s: n_bits %d (a multiple of 64 up to 4096)", fn, n_bits);
+    if (n < 0) return fail(BD_EINVAL, "%s: n %d < 0", fn, n);
+    if (!(beta > 0.0f) || beta > 1e30f) return fail(BD_EINVAL, "%s: beta must be finite and > 0", fn);
+    return BD_OK;
+}
+
+int bd_relaxed_bad_fwd(bd_context* ctx, const float* patches, int32_t n, const bd_box_pair* pairs, const float* w1,
+                       const float* w2, const float* theta, int32_t n_bits, float beta, float* D, float* m1, float* m2,
+                       void* stream)
+{
+    const char* fn = "bd_relaxed_bad_fwd";
+    if (int rc = check_relaxed(fn, n, n_bits, beta)) return rc;
+    if (n > 0 && (!patches || !pairs || !w1 || !w2 || !theta || !D)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n == 0) return BD_OK;
+    launch_relaxed_bad_fwd(patches, n, pairs, w1, w2, theta, n_bits, beta, D, m1, m2, static_cast<hipStream_t>(stream));
+    return check_launch(fn);
+}
+
+int bd_relaxed_bad_bwd(bd_context* ctx, const float* gD, const float* D, const float* m1, const float* m2, int32_t n,
+                       int32_t n_bits, float beta, float* g_w1, float* g_w2, float* g_theta, void* stream)
+{
+    const char* fn = "bd_relaxed_bad_bwd";
+    if (int rc = check_relaxed(fn, n, n_bits, beta)) return rc;
+    if (!g_w1 || !g_w2 || !g_theta) return fail(BD_EINVAL, "%s: null gradient output", fn);
+    if (n > 0 && (!gD || !D || !m1 || !m2)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, relaxed_bad_bwd_workspace(n > 0 ? n : 1, n_bits), s, &ws)) return rc;
+    launch_relaxed_bad_bwd(gD, D, m1, m2, n, n_bits, beta, g_w1, g_w2, g_theta, ws, s);
+    return check_launch(fn);
+}
+
+int bd_relaxed_hashsift_fwd(bd_context* ctx, const float* f, int32_t n, const float* B, const float* t, int32_t n_bits,
+                            float beta, float* rho, float* D, void* stream)
+{
+    const char* fn = "bd_relaxed_hashsift_fwd";
+    if (int rc = check_relaxed(fn, n, n_bits, beta)) return rc;
+    if (n_bits != 256 && n_bits != 512) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (256 or 512)", fn, n_bits);
+    if (n > 0 && (!f || !B || !t || !D)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n == 0) return BD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* r = rho;
+    void* ws = nullptr;
+    const size_t codes_bytes = sizeof(uint64_t) * (size_t)n * (size_t)(n_bits / 64);
+    const size_t rho_bytes = rho ? 0 : sizeof(float) * (size_t)n * (size_t)n_bits;
+    if (int rc = reserve_workspace(ctx, codes_bytes + rho_bytes, s, &ws)) return rc;
+    uint64_t* codes = static_cast<uint64_t*>(ws);
+    if (!r) r = reinterpret_cast<float*>(codes + (size_t)n * (size_t)(n_bits / 64));
+    launch_hashsift_project(BD_PREC_FP32, f, nullptr, n, B, t, n_bits / 64, 0.0f, codes, r, nullptr, s);
+    launch_tanh_scale(r, (int64_t)n * n_bits, beta, D, s);
+    return check_launch(fn);
+}
+
+int bd_relaxed_hashsift_bwd(bd_context* ctx, const float* gD, const float* D, const float* f, int32_t n,
+                            int32_t n_bits, float beta, float* gB, float* gt, void* stream)
+{
+    const char* fn = "bd_relaxed_hashsift_bwd";
+    if (int rc = check_relaxed(fn, n, n_bits, beta)) return rc;
+    if (!gB || !gt) return fail(BD_EINVAL, "%s: null gradient output", fn);
+    if (n > 0 && (!gD || !D || !f)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, relaxed_hs_bwd_workspace(n > 0 ? n : 1, n_bits), s, &ws)) return rc;
+    launch_relaxed_hs_bwd(gD, D, f, n, n_bits, beta, gB, gt, ws, s);
+    return check_launch(fn);
+}
+
+int bd_trl_hnm_fwd(bd_context* ctx, const float* A, const float* P, int32_t n, int32_t n_bits, float tau, float* loss,
+                   int32_t* neg, float* hinge, void* stream)
+{
+    const char* fn = "bd_trl_hnm_fwd";
+    if (n_bits < 64 || n_bits % 64 != 0 || n_bits > 4096)
+        return fail(BD_EUNSUPPORTED, "%s: n_bits %d (a multiple of 64 up to 4096)", fn, n_bits);
+    if (n < 1) return fail(BD_EINVAL, "%s: n %d < 1", fn, n);
+    if (!(tau == tau) || tau > 1e30f || tau < -1e30f) return fail(BD_EINVAL, "%s: tau must be finite", fn);
+    if (!A || !P || !loss || !neg || !hinge) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, trl_workspace(n), s, &ws)) return rc;
+    launch_trl_fwd(A, P, n, n_bits, tau, loss, neg, hinge, ws, s);
+    return check_launch(fn);
+}
+
+int bd_trl_hnm_bwd(bd_context* ctx, const float* A, const float* P, int32_t n, int32_t n_bits, const int32_t* neg,
+                   const float* hinge, const float* grad_loss, float* gA, float* gP, void* stream)
+{
+    const char* fn = "bd_trl_hnm_bwd";
+    if (n_bits < 64 || n_bits % 64 != 0 || n_bits > 4096)
+        return fail(BD_EUNSUPPORTED, "%s: n_bits %d (a multiple of 64 up to 4096)", fn, n_bits);
+    if (n < 1) return fail(BD_EINVAL, "%s: n %d < 1", fn, n);
+    if (!A || !P || !neg || !hinge || !grad_loss || !gA || !gP) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, trl_workspace(n), s, &ws)) return rc;
+    launch_trl_bwd(A, P, n, n_bits, neg, hinge, grad_loss, gA, gP, ws, s);
+    return check_launch(fn);
+}
+
 }  // extern "C"

@@ -151,27 +151,12 @@ __device__ __forceinline__ float wave_sum_f(float v)
     return v;
 }
 
+// The histogram of one keypoint, computed by one wavefront with a
+// kWaveLds-float LDS slice P; writes the 128 features to out.
 template <int DT>
-__global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __restrict__ img, int32_t W,
-                                                            int32_t H, int64_t pitch,
-                                                            const bd_keypoint* __restrict__ kps,
-                                                            int32_t n_kp, const int32_t* __restrict__ order,
-                                                            float* __restrict__ hist)
+__device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_t W, int32_t H, int64_t pitch,
+                                         const bd_keypoint kp, float* __restrict__ out, float* P, int lane)
 {
-    __shared__ float smem[kHistWaves][kWaveLds];
-    const int lane = threadIdx.x % kWave;
-    const int wave = threadIdx.x / kWave;
-    const int nb = (n_kp + kHistWaves - 1) / kHistWaves;
-    const int lb = xcd_logical_block(blockIdx.x, nb);
-    if (lb >= nb) return;
-    const int pos = lb * kHistWaves + wave;
-    if (pos >= n_kp) return;
-    const int n = order ? order[pos] : pos;
-    if (n < 0 || n >= n_kp) return;  // malformed order entries are skipped
-    float* P = smem[wave];
-    float* out = hist + (int64_t)n * 128;
-
-    const bd_keypoint kp = kps[n];
     if (!(finite_f(kp.x) && finite_f(kp.y) && finite_f(kp.scale) && finite_f(kp.angle) && kp.scale > 0.0f)) {
         out[lane] = 0.0f;
         out[lane + kWave] = 0.0f;
@@ -301,6 +286,42 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
     }
     out[lane] = h[0];
     out[lane + kWave] = h[1];
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __restrict__ img, int32_t W,
+                                                            int32_t H, int64_t pitch,
+                                                            const bd_keypoint* __restrict__ kps,
+                                                            int32_t n_kp, const int32_t* __restrict__ order,
+                                                            float* __restrict__ hist)
+{
+    __shared__ float smem[kHistWaves][kWaveLds];
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int nb = (n_kp + kHistWaves - 1) / kHistWaves;
+    const int lb = xcd_logical_block(blockIdx.x, nb);
+    if (lb >= nb) return;
+    const int pos = lb * kHistWaves + wave;
+    if (pos >= n_kp) return;
+    const int n = order ? order[pos] : pos;
+    if (n < 0 || n >= n_kp) return;  // malformed order entries are skipped
+    hist_one<DT>(img, W, H, pitch, kps[n], hist + (int64_t)n * 128, smem[wave], lane);
+}
+
+// Features of 32x32 float32 patches: each patch is an image whose keypoint
+// sits at its centre (15.5, 15.5) with scale 1 and angle 0, so every sample
+// falls on a patch pixel (the apron clamps to the edge).
+__global__ __launch_bounds__(256) void hashsift_patch_kernel(const float* __restrict__ patches, int32_t n,
+                                                             float* __restrict__ hist)
+{
+    __shared__ float smem[kHistWaves][kWaveLds];
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int i = blockIdx.x * kHistWaves + wave;
+    if (i >= n) return;
+    const bd_keypoint kp{15.5f, 15.5f, 1.0f, 0.0f};
+    hist_one<BD_DTYPE_F32>(reinterpret_cast<const uint8_t*>(patches + (int64_t)i * 1024), 32, 32, 128, kp,
+                           hist + (int64_t)i * 128, smem[wave], lane);
 }
 
 // ---------------------------------------------------------------- projection
@@ -584,6 +605,12 @@ void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, 
     else
         hipLaunchKernelGGL(hashsift_hist_kernel<BD_DTYPE_F32>, dim3(blocks), dim3(kHistWaves * kWave), 0,
                            stream, p, W, H, img_pitch, kps, n_kp, order, hist);
+}
+
+void launch_hashsift_patch_features(const float* patches, int32_t n, float* hist, hipStream_t stream)
+{
+    hipLaunchKernelGGL(hashsift_patch_kernel, dim3((n + kHistWaves - 1) / kHistWaves), dim3(kHistWaves * kWave), 0,
+                       stream, patches, n, hist);
 }
 
 void launch_hashsift_project(int32_t precision, const float* hist, const bd_keypoint* kps, int32_t n_kp,

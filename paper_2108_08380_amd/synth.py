@@ -221,3 +221,59 @@ def batched_sizes(rng: np.random.Generator, n_images: int = 64, w_range=(320, 40
         h = int(round(0.75 * w))
         out.append((w, h, int(rng.integers(kp_range[0], kp_range[1] + 1))))
     return out
+
+
+# --------------------------------------------------------------------------- training triplets
+
+
+@dataclass
+class TripletBatch:
+    """n triplets of 32x32 float32 patches (anchor, positive, negative), values in [0, 1]."""
+
+    anchor: np.ndarray
+    positive: np.ndarray
+    negative: np.ndarray
+
+
+def _resample_patches(img: np.ndarray, cx, cy, scale, angle) -> np.ndarray:
+    """32x32 bilinear crops (scipy.ndimage.map_coordinates, edge-replicated) of img
+    around (cx, cy), one image pixel per `scale` patch pixels... i.e. patch offset
+    u maps to c + scale * Rot(angle) u, offsets (j - 15.5, i - 15.5)."""
+    from scipy import ndimage
+
+    n = len(cx)
+    u = np.arange(32, dtype=np.float64) - 15.5
+    uy, ux = np.meshgrid(u, u, indexing="ij")
+    c, s = np.cos(angle)[:, None, None], np.sin(angle)[:, None, None]
+    sc = scale[:, None, None]
+    px = cx[:, None, None] + sc * (c * ux[None] - s * uy[None])
+    py = cy[:, None, None] + sc * (s * ux[None] + c * uy[None])
+    out = ndimage.map_coordinates(img, [py.reshape(-1), px.reshape(-1)], order=1, mode="nearest")
+    return out.reshape(n, 32, 32).astype(np.float32)
+
+
+def triplets(seed: int = SEED_BASE + 4, n: int = 8192, width: int = 1024, height: int = 768,
+             scale_range=(1.0, 4.0), warp_scale=(0.9, 1.1), warp_deg: float = 10.0,
+             noise_sigma: float = 0.02) -> TripletBatch:
+    """Anchor: crop of a synthetic image at a random keypoint (scale U[1, 4], random
+    angle).  Positive: crop of the same source at the keypoint warped by a random
+    similarity (scale x U[0.9, 1.1], rotation U[-10, 10] degrees) plus N(0, 0.02^2)
+    noise.  Negative: crop at another random keypoint.  Crops are resampled from the
+    source image, not from the anchor crop, so warps never extrapolate."""
+    r_img, r_kp, r_warp, r_noise, r_neg = streams(seed)[:5]
+    img = grey_image(r_img, width, height) / 255.0
+    border = 4.0 * 32.0
+    cx = r_kp.uniform(border, width - border, n)
+    cy = r_kp.uniform(border, height - border, n)
+    sc = r_kp.uniform(scale_range[0], scale_range[1], n)
+    an = r_kp.uniform(0.0, 2.0 * math.pi, n)
+    anchor = _resample_patches(img, cx, cy, sc, an)
+    sc2 = sc * r_warp.uniform(warp_scale[0], warp_scale[1], n)
+    an2 = an + np.deg2rad(r_warp.uniform(-warp_deg, warp_deg, n))
+    positive = _resample_patches(img, cx, cy, sc2, an2)
+    positive = np.clip(positive + r_noise.normal(0.0, noise_sigma, positive.shape), 0.0, 1.0).astype(np.float32)
+    nx = r_neg.uniform(border, width - border, n)
+    ny = r_neg.uniform(border, height - border, n)
+    negative = _resample_patches(img, nx, ny, r_neg.uniform(scale_range[0], scale_range[1], n),
+                                 r_neg.uniform(0.0, 2.0 * math.pi, n))
+    return TripletBatch(anchor, positive, negative)
