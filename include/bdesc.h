@@ -241,6 +241,102 @@ int bd_trl_hnm_fwd(bd_context* ctx, const float* A, const float* P, int32_t n, i
 int bd_trl_hnm_bwd(bd_context* ctx, const float* A, const float* P, int32_t n, int32_t n_bits, const int32_t* neg,
                    const float* hinge, const float* grad_loss, float* gA, float* gP, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batching extension (not proposed by the paper): many images of uneven
+ * sizes and keypoint counts described and matched together.  Every stage of
+ * the single-image path above (spatial order, integral image, BAD, HashSIFT
+ * histogram and projection, Hamming k-NN) runs as one persistent, XCD-aware
+ * launch over the whole batch, and bd_batch_run can replay the sequence as
+ * one captured HIP graph.  Codes and matches are identical, bit for bit, to
+ * the single-image calls on each image, under every tuning.
+ * ---------------------------------------------------------------------- */
+
+/* One image of a batch.  img is a device u8 grey image (H rows, `pitch`
+ * bytes apart) that feeds the integral image and BAD, and HashSIFT unless
+ * hs_img is set: then HashSIFT reads hs_img (BD_DTYPE_U8 or BD_DTYPE_F32,
+ * hs_pitch bytes between rows) instead.  The image's n_kp keypoints follow
+ * those of the previous images in the flat keypoint array. */
+typedef struct bd_batch_image {
+    const uint8_t* img;
+    int64_t pitch;
+    const void* hs_img;
+    int64_t hs_pitch;
+    int32_t hs_dtype;
+    int32_t W, H;
+    int32_t n_kp;
+} bd_batch_image;
+
+/* One k-NN problem: the codes of query_image's keypoints against those of
+ * train_image (indices into the image array).  Its n_kp(query_image) x k
+ * results follow those of the previous problems; idx counts keypoints of
+ * train_image from 0. */
+typedef struct bd_batch_match {
+    int32_t query_image, train_image;
+} bd_batch_match;
+
+/* Schedule knobs.  Grids are blocks_per_cu x CUs (capped by the stage's
+ * work units, rounded to a multiple of the 8 XCDs).  knn_*[0] set the BAD
+ * matcher, knn_*[1] the HashSIFT matcher: queries per lane (1, 2, 4) and
+ * train rows per work unit (BD_BATCH_MIN_ROWS .. BD_BATCH_MAX_ROWS). */
+typedef struct bd_batch_tuning {
+    int32_t order_blocks_per_cu;
+    int32_t integral_blocks_per_cu;
+    int32_t bad_blocks_per_cu;
+    int32_t hist_blocks_per_cu;
+    int32_t knn_qpl[2];
+    int32_t knn_rows[2];
+    int32_t knn_blocks_per_cu[2];
+} bd_batch_tuning;
+
+#define BD_BATCH_MIN_ROWS 256
+#define BD_BATCH_MAX_ROWS (1 << 22)
+
+typedef struct bd_batch bd_batch;
+
+/* Plans a batch: validates the host arrays `images` (n_images >= 1) and
+ * `matches` (n_matches >= 0), allocates the batch's own device memory
+ * (integral images with their tile tables, keypoint order, 128-float
+ * features per keypoint, partial k-NN results, unit prefixes) and uploads
+ * the plan; synchronous.  bad_bits and hs_bits are 0 (stage off), 256 or
+ * 512, not both 0; hs_precision and hs_margin as in bd_describe_hashsift;
+ * k is 1 or 2.  At most 2^22 keypoints in total.  The image memory must stay
+ * valid until bd_batch_destroy.  Errors: BD_EINVAL, BD_EUNSUPPORTED,
+ * BD_ENOMEM, BD_EDEVICE; *out is NULL on error. */
+int bd_batch_create(bd_context* ctx, const bd_batch_image* images, int32_t n_images, const bd_batch_match* matches,
+                    int32_t n_matches, int32_t bad_bits, int32_t hs_bits, int32_t hs_precision, float hs_margin,
+                    int32_t k, bd_batch** out);
+
+/* Synchronizes the device, then frees the batch and its graph. */
+int bd_batch_destroy(bd_batch* b);
+
+/* Describes and matches the whole batch on `stream`.  Device arrays:
+ * kps (total keypoints), pairs (bad_bits entries), B (hs_bits x 128), t
+ * (hs_bits); outputs bad_codes (total x bad_bits/64 u64), hs_codes (total x
+ * hs_bits/64 u64), bad_idx/bad_dist and hs_idx/hs_dist (match rows x k).
+ * Arrays of a disabled stage may be NULL.  With use_graph != 0 the launch
+ * sequence is captured once per distinct argument set (on the batch's own
+ * stream) and replayed with one hipGraphLaunch; otherwise the kernels are
+ * enqueued directly.  Runs on one batch must not overlap. */
+int bd_batch_run(bd_batch* b, const bd_keypoint* kps, const bd_box_pair* pairs, const float* B, const float* t,
+                 uint64_t* bad_codes, uint64_t* hs_codes, int32_t* bad_idx, uint32_t* bad_dist, int32_t* hs_idx,
+                 uint32_t* hs_dist, int32_t use_graph, void* stream);
+
+/* Autotuner: with the arguments of bd_batch_run, times every stage alone
+ * (reps launches per candidate, HIP events on `stream`) over the candidate
+ * grids, queries per lane and rows per unit, keeps the fastest and leaves
+ * that tuning's outputs in place.  Synchronizes `stream`. */
+int bd_batch_autotune(bd_batch* b, const bd_keypoint* kps, const bd_box_pair* pairs, const float* B, const float* t,
+                      uint64_t* bad_codes, uint64_t* hs_codes, int32_t* bad_idx, uint32_t* bad_dist,
+                      int32_t* hs_idx, uint32_t* hs_dist, int32_t reps, void* stream);
+
+/* The tuning a new batch starts with (no device needed). */
+int bd_batch_default_tuning(bd_batch_tuning* out);
+int bd_batch_get_tuning(const bd_batch* b, bd_batch_tuning* out);
+/* Validates and applies a tuning; synchronizes the device. */
+int bd_batch_set_tuning(bd_batch* b, const bd_batch_tuning* t);
+/* Total keypoints and total match rows of the batch (either pointer may be NULL). */
+int bd_batch_info(const bd_batch* b, int64_t* total_kp, int32_t* match_rows);
+
 #ifdef __cplusplus
 }
 #endif

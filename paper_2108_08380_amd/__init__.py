@@ -54,7 +54,46 @@ SIGNATURES = {
     "bd_relaxed_hashsift_bwd": ([_P, _P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P], ctypes.c_int),
     "bd_trl_hnm_fwd": ([_P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_trl_hnm_bwd": ([_P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "bd_batch_create": ([_P, _P, _I32, _P, _I32, _I32, _I32, _I32, ctypes.c_float, _I32,
+                         ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "bd_batch_destroy": ([_P], ctypes.c_int),
+    "bd_batch_run": ([_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _P], ctypes.c_int),
+    "bd_batch_autotune": ([_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _P], ctypes.c_int),
+    "bd_batch_default_tuning": ([_P], ctypes.c_int),
+    "bd_batch_get_tuning": ([_P, _P], ctypes.c_int),
+    "bd_batch_set_tuning": ([_P, _P], ctypes.c_int),
+    "bd_batch_info": ([_P, _P, _P], ctypes.c_int),
 }
+
+
+class BatchImageRec(ctypes.Structure):
+    """bd_batch_image."""
+    _fields_ = [("img", ctypes.c_void_p), ("pitch", ctypes.c_int64), ("hs_img", ctypes.c_void_p),
+                ("hs_pitch", ctypes.c_int64), ("hs_dtype", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("H", ctypes.c_int32), ("n_kp", ctypes.c_int32)]
+
+
+class BatchMatchRec(ctypes.Structure):
+    """bd_batch_match."""
+    _fields_ = [("query_image", ctypes.c_int32), ("train_image", ctypes.c_int32)]
+
+
+class BatchTuning(ctypes.Structure):
+    """bd_batch_tuning; index 0 of the knn_* pairs is the BAD matcher, 1 the HashSIFT matcher."""
+    _fields_ = [("order_blocks_per_cu", ctypes.c_int32), ("integral_blocks_per_cu", ctypes.c_int32),
+                ("bad_blocks_per_cu", ctypes.c_int32), ("hist_blocks_per_cu", ctypes.c_int32),
+                ("knn_qpl", ctypes.c_int32 * 2), ("knn_rows", ctypes.c_int32 * 2),
+                ("knn_blocks_per_cu", ctypes.c_int32 * 2)]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if isinstance(v, ctypes.Array) else int(v)
+        return out
+
+
+assert ctypes.sizeof(BatchImageRec) == 48 and ctypes.sizeof(BatchTuning) == 40
 
 
 class BDError(RuntimeError):
@@ -450,3 +489,146 @@ def trl_hnm_bwd(A, P, neg, hinge, grad_loss):
     _check(lib().bd_trl_hnm_bwd(context(dev), A.data_ptr(), P.data_ptr(), n, K, neg.data_ptr(), hinge.data_ptr(),
                                 grad_loss.data_ptr(), gA.data_ptr(), gP.data_ptr(), stream))
     return gA, gP
+
+
+# --------------------------------------------------------------------------- batching extension
+
+
+class Batch:
+    """A planned batch of images (bd_batch_create ... bd_batch_destroy).
+
+    images:   list of (H, W) uint8 device tensors (integral image, BAD, and
+              HashSIFT unless hs_images is given)
+    n_kp:     keypoints per image; the flat keypoint array holds image 0's
+              keypoints first, then image 1's, ...
+    matches:  list of (query_image, train_image) index pairs
+    hs_images: optional list of (H, W) uint8 or float32 tensors for HashSIFT
+    The image tensors are kept alive by the batch."""
+
+    def __init__(self, images, n_kp, matches=(), bad_bits: int = 512, hs_bits: int = 256,
+                 precision: str = "fp32", margin: float = DEFAULT_MARGIN, k: int = 2, hs_images=None):
+        torch = _torch()
+        if len(images) != len(n_kp):
+            raise ValueError("one keypoint count per image")
+        if hs_images is not None and len(hs_images) != len(images):
+            raise ValueError("one HashSIFT image per image")
+        self._images = list(images)
+        self._hs_images = list(hs_images) if hs_images is not None else None
+        recs = (BatchImageRec * len(images))()
+        for i, img in enumerate(images):
+            _require(img, torch.uint8, 2, f"images[{i}]")
+            H, W = img.shape
+            recs[i].img, recs[i].pitch, recs[i].W, recs[i].H, recs[i].n_kp = img.data_ptr(), img.stride(0), W, H, int(n_kp[i])
+            if hs_images is not None:
+                h = hs_images[i]
+                if tuple(h.shape) != (H, W):
+                    raise ValueError(f"hs_images[{i}] must match images[{i}] in shape")
+                recs[i].hs_img = h.data_ptr()
+                recs[i].hs_pitch = h.stride(0) * h.element_size()
+                recs[i].hs_dtype = _image_dtype(h)
+        mrecs = (BatchMatchRec * max(len(matches), 1))()
+        for i, (q, t) in enumerate(matches):
+            mrecs[i].query_image, mrecs[i].train_image = int(q), int(t)
+        dev = images[0].device.index
+        self.device = dev
+        self.n_kp = [int(v) for v in n_kp]
+        self.kp_offsets = np.concatenate([[0], np.cumsum(self.n_kp)]).astype(np.int64)
+        self.matches = [(int(q), int(t)) for q, t in matches]
+        self.match_offsets = np.concatenate([[0], np.cumsum([self.n_kp[q] for q, _ in self.matches])]).astype(np.int64)
+        self.bad_bits, self.hs_bits, self.k = bad_bits, hs_bits, k
+        out = ctypes.c_void_p()
+        _check(lib().bd_batch_create(context(dev), recs, len(images), mrecs, len(matches), bad_bits, hs_bits,
+                                     _PRECISIONS[precision], margin, k, ctypes.byref(out)))
+        self._h = out.value
+
+    @property
+    def total_kp(self) -> int:
+        return int(self.kp_offsets[-1])
+
+    @property
+    def match_rows(self) -> int:
+        return int(self.match_offsets[-1])
+
+    def allocate_outputs(self) -> dict:
+        """Device output tensors of run(): codes per descriptor and idx/dist per matcher."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        out = {}
+        if self.bad_bits:
+            out["bad_codes"] = torch.empty((self.total_kp, self.bad_bits // 64), dtype=torch.uint64, device=dev)
+            out["bad_idx"] = torch.empty((self.match_rows, self.k), dtype=torch.int32, device=dev)
+            out["bad_dist"] = torch.empty((self.match_rows, self.k), dtype=torch.uint32, device=dev)
+        if self.hs_bits:
+            out["hs_codes"] = torch.empty((self.total_kp, self.hs_bits // 64), dtype=torch.uint64, device=dev)
+            out["hs_idx"] = torch.empty((self.match_rows, self.k), dtype=torch.int32, device=dev)
+            out["hs_dist"] = torch.empty((self.match_rows, self.k), dtype=torch.uint32, device=dev)
+        return out
+
+    def _args(self, kps, pairs, B, t, out):
+        torch = _torch()
+        _require(kps, torch.float32, 2, "kps")
+        _contig(kps, "kps")
+        if kps.shape[0] != self.total_kp:
+            raise ValueError(f"kps must have {self.total_kp} rows")
+        if self.bad_bits and (pairs is None or pairs.shape[0] < self.bad_bits):
+            raise ValueError("need a BAD table of bad_bits pairs")
+        if self.hs_bits and (B is None or tuple(B.shape) != (self.hs_bits, 128) or t is None):
+            raise ValueError("need B (hs_bits, 128) and t (hs_bits,)")
+        ptr = lambda x: x.data_ptr() if x is not None else None
+        for v in out.values():
+            _contig(v, "output")
+        tensors = [kps, pairs, B, t] + list(out.values())
+        _, stream = _device_and_stream(*[x for x in tensors if x is not None])
+        return [kps.data_ptr(), ptr(pairs), ptr(B), ptr(t), ptr(out.get("bad_codes")), ptr(out.get("hs_codes")),
+                ptr(out.get("bad_idx")), ptr(out.get("bad_dist")), ptr(out.get("hs_idx")),
+                ptr(out.get("hs_dist"))], stream
+
+    def run(self, kps, pairs=None, B=None, t=None, out=None, graph: bool = True) -> dict:
+        """Describe and match the batch (bd_batch_run); returns the output dict."""
+        out = self.allocate_outputs() if out is None else out
+        args, stream = self._args(kps, pairs, B, t, out)
+        _check(lib().bd_batch_run(self._h, *args, 1 if graph else 0, stream))
+        return out
+
+    def autotune(self, kps, pairs=None, B=None, t=None, out=None, reps: int = 3) -> dict:
+        """Pick the fastest tuning on these inputs (bd_batch_autotune); returns the tuning."""
+        out = self.allocate_outputs() if out is None else out
+        args, stream = self._args(kps, pairs, B, t, out)
+        _check(lib().bd_batch_autotune(self._h, *args, reps, stream))
+        return self.tuning
+
+    @property
+    def tuning(self) -> dict:
+        tn = BatchTuning()
+        _check(lib().bd_batch_get_tuning(self._h, ctypes.byref(tn)))
+        return tn.as_dict()
+
+    @tuning.setter
+    def tuning(self, values: dict) -> None:
+        tn = BatchTuning()
+        _check(lib().bd_batch_get_tuning(self._h, ctypes.byref(tn)))
+        for name, v in values.items():
+            cur = getattr(tn, name)
+            if isinstance(cur, ctypes.Array):
+                for i, x in enumerate(v):
+                    cur[i] = int(x)
+            else:
+                setattr(tn, name, int(v))
+        _check(lib().bd_batch_set_tuning(self._h, ctypes.byref(tn)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(lib().bd_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_batch_tuning() -> dict:
+    tn = BatchTuning()
+    _check(lib().bd_batch_default_tuning(ctypes.byref(tn)))
+    return tn.as_dict()

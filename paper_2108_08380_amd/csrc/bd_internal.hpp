@@ -44,6 +44,65 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb)
     return (b % kXcds) * per + b / kXcds;
 }
 
+// Persistent kernels: work units [0, total) are cut into 8 contiguous ranges,
+// one per XCD, and the blocks of an XCD (b % 8 == x) take its range in a
+// grid-stride loop.  gridDim.x must be a multiple of 8.
+struct UnitRange {
+    int first, end, stride;
+};
+__device__ __forceinline__ UnitRange xcd_units(int total)
+{
+    const int x = (int)blockIdx.x % kXcds, r = (int)blockIdx.x / kXcds;
+    const int begin = (int)((int64_t)total * x / kXcds);
+    const int end = (int)((int64_t)total * (x + 1) / kXcds);
+    return UnitRange{begin + r, end, (int)gridDim.x / kXcds};
+}
+
+// Index i of the segment holding unit u for an inclusive-exclusive prefix
+// array pre[0..n] (pre[0] = 0, nondecreasing): pre[i] <= u < pre[i+1].
+__device__ __forceinline__ int segment_of(const int32_t* __restrict__ pre, int n, int u)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Device-side record of one image of a batch.
+struct BatchImage {
+    const uint8_t* img_u8;  // pixels for the integral image and BAD
+    int64_t pitch_u8;
+    const uint8_t* img_hs;  // pixels for HashSIFT (u8 or f32)
+    int64_t pitch_hs;
+    int32_t hs_dtype;
+    int32_t W, H;
+    int32_t kp_offset, n_kp;  // range of the flat keypoint array
+    uint32_t* ii;             // integral image, (H+1) x ii_pitch
+    int64_t ii_pitch;
+    uint32_t* colsum;  // integral tile tables
+    uint32_t* rowsum;
+    int32_t strips, slabs;
+    int64_t col_pitch;
+    int32_t aligned;
+    float inv_cell;  // 1 / cell size of the spatial order grid
+};
+
+// Device-side record of one k-NN problem of a batch.  Offsets are rows of
+// the flat code array (q_off, t_off), rows of the flat result arrays
+// (out_off) and u32 elements of the partial-result buffer (part_off).
+struct BatchMatch {
+    int32_t q_off, n_q;
+    int32_t t_off, n_t;
+    int32_t out_off;
+    int32_t splits;   // ceil(n_t / rows_per_split), at least 1
+    int32_t qgroups;  // ceil(n_q / (64 * queries per lane))
+    int32_t pad;
+    int64_t part_off;  // splits x n_q x k keys when splits > 1
+};
+
 // ---- integral image (integral.hip)
 struct IntegralPlan {
     int32_t W, H;
@@ -54,21 +113,34 @@ struct IntegralPlan {
 IntegralPlan plan_integral(int32_t W, int32_t H);
 void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
                      int64_t ii_pitch, void* workspace, hipStream_t stream);
+int integral_tile_blocks(const IntegralPlan& p);   // units of the tile passes
+int integral_carry_blocks(const IntegralPlan& p);  // units of the carry pass
+void launch_integral_batch(const BatchImage* imgs, int32_t n_img, const int32_t* tile_pre, const int32_t* carry_pre,
+                           int grid, hipStream_t stream);
 
 // ---- BAD (bad.hip)
 void launch_bad(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch, const bd_keypoint* kps,
                 int32_t n_kp, const int32_t* order, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes,
                 hipStream_t stream);
 
+void launch_bad_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
+                      const int32_t* order, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes, int grid,
+                      hipStream_t stream);
+
 // ---- spatial keypoint order (order.hip)
+float order_inv_cell(int32_t W, int32_t H);
 void launch_keypoint_order(const bd_keypoint* kps, int32_t n_kp, int32_t W, int32_t H, int32_t* order,
                            hipStream_t stream);
+void launch_keypoint_order_batch(const BatchImage* imgs, int32_t n_img, const bd_keypoint* kps, int32_t* order,
+                                 int grid, hipStream_t stream);
 
 // ---- HashSIFT (hashsift.hip)
 void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
                           const bd_keypoint* kps, int32_t n_kp, const int32_t* order, float* hist,
                           hipStream_t stream);
 void launch_hashsift_patch_features(const float* patches, int32_t n, float* hist, hipStream_t stream);
+void launch_hashsift_hist_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
+                                const int32_t* order, float* hist, int grid, hipStream_t stream);
 void launch_hashsift_project(int32_t precision, const float* hist, const bd_keypoint* kps, int32_t n_kp,
                              const float* B, const float* t, int32_t n_words, float margin, uint64_t* codes,
                              float* resp, uint32_t* recheck_count, hipStream_t stream);
@@ -102,5 +174,18 @@ struct KnnPlan {
 KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_cus);
 void launch_knn(const KnnPlan& p, const uint64_t* query, const uint64_t* train, int32_t* idx,
                 uint32_t* dist, void* workspace, hipStream_t stream);
+
+// Batched k-NN over BatchMatch problems sharing n_words (4 or 8) and k.
+struct KnnBatchPlan {
+    int32_t n_words, k;
+    int32_t qpl;             // queries per lane
+    int32_t rows_per_split;  // train rows per unit, <= 2^22
+    int32_t grid;            // blocks of the k-NN kernel (multiple of 8)
+    int32_t merge_units, merge_grid;
+};
+int knn_queries_per_wave(int qpl);
+void launch_knn_batch(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, const int32_t* pre,
+                      const int32_t* merge_pre, const uint64_t* codes, uint32_t* partial, int32_t* idx,
+                      uint32_t* dist, hipStream_t stream);
 
 }  // namespace bd

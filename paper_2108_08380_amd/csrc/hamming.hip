@@ -36,22 +36,15 @@ __device__ __forceinline__ void topk_insert(uint32_t (&best)[KK], uint32_t key)
     }
 }
 
+// One wavefront: queries q0 + p * 64 + lane (p < QPL) against train rows
+// [t0, t1).  Results go straight to (idx, dist) when `direct`, else as
+// packed keys to partial[split][query][k].
 template <int NW, int KK, int QPL>
-__global__ __launch_bounds__(256) void hamming_knn_kernel(const uint64_t* __restrict__ query, int32_t n_q,
-                                                          const uint64_t* __restrict__ train, int32_t n_t,
-                                                          int32_t rows_per_split,
-                                                          uint32_t* __restrict__ partial,
-                                                          int32_t* __restrict__ out_idx,
-                                                          uint32_t* __restrict__ out_dist, int direct)
+__device__ __forceinline__ void knn_wave_body(const uint64_t* __restrict__ query, int32_t n_q, int q0,
+                                              const uint64_t* __restrict__ train, int t0, int t1, int split,
+                                              uint32_t* __restrict__ partial, int32_t* __restrict__ out_idx,
+                                              uint32_t* __restrict__ out_dist, bool direct, int lane)
 {
-    const int lane = threadIdx.x % kWave;
-    const int qgroup = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    const int q0 = qgroup * kWave * QPL;
-    if (q0 >= n_q) return;
-    const int split = blockIdx.y;
-    const int t0 = split * rows_per_split;
-    const int t1 = min(n_t, t0 + rows_per_split);
-
     uint32_t ql[QPL][NW], qh[QPL][NW];
     uint32_t best[QPL][KK];
 #pragma unroll
@@ -109,6 +102,58 @@ __global__ __launch_bounds__(256) void hamming_knn_kernel(const uint64_t* __rest
     }
 }
 
+template <int NW, int KK, int QPL>
+__global__ __launch_bounds__(256) void hamming_knn_kernel(const uint64_t* __restrict__ query, int32_t n_q,
+                                                          const uint64_t* __restrict__ train, int32_t n_t,
+                                                          int32_t rows_per_split,
+                                                          uint32_t* __restrict__ partial,
+                                                          int32_t* __restrict__ out_idx,
+                                                          uint32_t* __restrict__ out_dist, int direct)
+{
+    const int lane = threadIdx.x % kWave;
+    const int qgroup = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int q0 = qgroup * kWave * QPL;
+    if (q0 >= n_q) return;
+    const int split = blockIdx.y;
+    const int t0 = split * rows_per_split;
+    const int t1 = min(n_t, t0 + rows_per_split);
+    knn_wave_body<NW, KK, QPL>(query, n_q, q0, train, t0, t1, split, partial, out_idx, out_dist, direct != 0, lane);
+}
+
+// Batch: units are (problem, split, query group) triples, one per wavefront,
+// problem-major and query group fastest, so consecutive units share a train
+// split.  The XCD ranges of xcd_units are cut at wavefront granularity.
+template <int NW, int KK, int QPL>
+__global__ __launch_bounds__(256) void hamming_knn_batch(const BatchMatch* __restrict__ m, int32_t n_m,
+                                                         const int32_t* __restrict__ pre,
+                                                         const uint64_t* __restrict__ codes,
+                                                         int32_t rows_per_split, uint32_t* __restrict__ partial,
+                                                         int32_t* __restrict__ out_idx,
+                                                         uint32_t* __restrict__ out_dist)
+{
+    const int lane = threadIdx.x % kWave;
+    const int total = pre[n_m];
+    const int x = (int)blockIdx.x % kXcds;
+    const int stride = (int)gridDim.x / kXcds * kWavesPerBlock;
+    // the wavefront index is uniform; readfirstlane lets the compiler keep
+    // the unit, its record and the train row pointer in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
+    const int first = (int)((int64_t)total * x / kXcds) + (int)blockIdx.x / kXcds * kWavesPerBlock + wave;
+    const int end = (int)((int64_t)total * (x + 1) / kXcds);
+    for (int u = first; u < end; u += stride) {
+        const int i = segment_of(pre, n_m, u);
+        const BatchMatch& b = m[i];
+        const int local = u - pre[i];
+        const int split = local / b.qgroups;
+        const int q0 = (local - split * b.qgroups) * kWave * QPL;
+        const int t0 = split * rows_per_split;
+        const int t1 = min(b.n_t, t0 + rows_per_split);
+        knn_wave_body<NW, KK, QPL>(codes + (int64_t)b.q_off * NW, b.n_q, q0, codes + (int64_t)b.t_off * NW, t0, t1,
+                                   split, partial + b.part_off, out_idx + (int64_t)b.out_off * KK,
+                                   out_dist + (int64_t)b.out_off * KK, b.splits == 1, lane);
+    }
+}
+
 // Merge of the per-split top-k: a block covers 64 queries, its four
 // wavefronts take every fourth split each (eight loads in flight per lane),
 // and the four partial results meet in LDS.  Keys become 64-bit (distance in
@@ -126,15 +171,15 @@ __device__ __forceinline__ void topk_insert64(uint64_t (&best)[KK], uint64_t k64
     }
 }
 
+// Block of four wavefronts: queries 64 * qb + lane of one problem.  Ends
+// with a barrier so a persistent block can reuse `part`.
 template <int KK>
-__global__ __launch_bounds__(256) void hamming_merge_kernel(const uint32_t* __restrict__ partial, int32_t n_q,
-                                                            int32_t splits, int32_t rows_per_split,
-                                                            int32_t* __restrict__ out_idx,
-                                                            uint32_t* __restrict__ out_dist)
+__device__ __forceinline__ void merge_block_body(const uint32_t* __restrict__ partial, int32_t n_q, int32_t splits,
+                                                 int32_t rows_per_split, int qb, int32_t* __restrict__ out_idx,
+                                                 uint32_t* __restrict__ out_dist, uint64_t (*part)[kWave][KK])
 {
-    __shared__ uint64_t part[4][kWave][KK];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int qi = blockIdx.x * kWave + lane;
+    const int qi = qb * kWave + lane;
     uint64_t best[KK];
 #pragma unroll
     for (int s = 0; s < KK; ++s) best[s] = ~0ull;
@@ -163,16 +208,47 @@ __global__ __launch_bounds__(256) void hamming_merge_kernel(const uint32_t* __re
 #pragma unroll
     for (int s = 0; s < KK; ++s) part[wave][lane][s] = best[s];
     __syncthreads();
-    if (wave != 0 || qi >= n_q) return;
+    if (wave == 0 && qi < n_q) {
 #pragma unroll
-    for (int w = 1; w < 4; ++w)
+        for (int w = 1; w < 4; ++w)
 #pragma unroll
-        for (int s = 0; s < KK; ++s) topk_insert64<KK>(best, part[w][lane][s]);
+            for (int s = 0; s < KK; ++s) topk_insert64<KK>(best, part[w][lane][s]);
 #pragma unroll
-    for (int s = 0; s < KK; ++s) {
-        const bool empty = best[s] == ~0ull;
-        out_idx[(int64_t)qi * KK + s] = empty ? -1 : (int32_t)(uint32_t)best[s];
-        out_dist[(int64_t)qi * KK + s] = empty ? kEmpty : (uint32_t)(best[s] >> 32);
+        for (int s = 0; s < KK; ++s) {
+            const bool empty = best[s] == ~0ull;
+            out_idx[(int64_t)qi * KK + s] = empty ? -1 : (int32_t)(uint32_t)best[s];
+            out_dist[(int64_t)qi * KK + s] = empty ? kEmpty : (uint32_t)(best[s] >> 32);
+        }
+    }
+    __syncthreads();
+}
+
+template <int KK>
+__global__ __launch_bounds__(256) void hamming_merge_kernel(const uint32_t* __restrict__ partial, int32_t n_q,
+                                                            int32_t splits, int32_t rows_per_split,
+                                                            int32_t* __restrict__ out_idx,
+                                                            uint32_t* __restrict__ out_dist)
+{
+    __shared__ uint64_t part[4][kWave][KK];
+    merge_block_body<KK>(partial, n_q, splits, rows_per_split, blockIdx.x, out_idx, out_dist, part);
+}
+
+// Batch merge: units are blocks of 64 queries of the problems with more
+// than one split (pre counts zero units for the others).
+template <int KK>
+__global__ __launch_bounds__(256) void hamming_merge_batch(const BatchMatch* __restrict__ m, int32_t n_m,
+                                                           const int32_t* __restrict__ pre, int32_t rows_per_split,
+                                                           const uint32_t* __restrict__ partial,
+                                                           int32_t* __restrict__ out_idx,
+                                                           uint32_t* __restrict__ out_dist)
+{
+    __shared__ uint64_t part[4][kWave][KK];
+    const UnitRange ur = xcd_units(pre[n_m]);
+    for (int u = ur.first; u < ur.end; u += ur.stride) {
+        const int i = segment_of(pre, n_m, u);
+        const BatchMatch& b = m[i];
+        merge_block_body<KK>(partial + b.part_off, b.n_q, b.splits, rows_per_split, u - pre[i],
+                             out_idx + (int64_t)b.out_off * KK, out_dist + (int64_t)b.out_off * KK, part);
     }
 }
 
@@ -214,7 +290,55 @@ void launch_nw(const KnnPlan& p, const uint64_t* query, const uint64_t* train, u
         launch_nw_k<NW, 2>(p, query, train, partial, idx, dist, stream);
 }
 
+template <int NW, int KK>
+void launch_batch_nw_k(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, const int32_t* pre,
+                       const int32_t* merge_pre, const uint64_t* codes, uint32_t* partial, int32_t* idx,
+                       uint32_t* dist, hipStream_t stream)
+{
+    const dim3 block(kWavesPerBlock * kWave);
+    switch (p.qpl) {
+        case 1:
+            hipLaunchKernelGGL((hamming_knn_batch<NW, KK, 1>), dim3(p.grid), block, 0, stream, m, n_m, pre, codes,
+                               p.rows_per_split, partial, idx, dist);
+            break;
+        case 2:
+            hipLaunchKernelGGL((hamming_knn_batch<NW, KK, 2>), dim3(p.grid), block, 0, stream, m, n_m, pre, codes,
+                               p.rows_per_split, partial, idx, dist);
+            break;
+        default:
+            hipLaunchKernelGGL((hamming_knn_batch<NW, KK, 4>), dim3(p.grid), block, 0, stream, m, n_m, pre, codes,
+                               p.rows_per_split, partial, idx, dist);
+            break;
+    }
+    if (p.merge_units > 0)
+        hipLaunchKernelGGL((hamming_merge_batch<KK>), dim3(p.merge_grid), block, 0, stream, m, n_m, merge_pre,
+                           p.rows_per_split, partial, idx, dist);
+}
+
+template <int NW>
+void launch_batch_nw(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, const int32_t* pre,
+                     const int32_t* merge_pre, const uint64_t* codes, uint32_t* partial, int32_t* idx,
+                     uint32_t* dist, hipStream_t stream)
+{
+    if (p.k == 1)
+        launch_batch_nw_k<NW, 1>(p, m, n_m, pre, merge_pre, codes, partial, idx, dist, stream);
+    else
+        launch_batch_nw_k<NW, 2>(p, m, n_m, pre, merge_pre, codes, partial, idx, dist, stream);
+}
+
 }  // namespace
+
+int knn_queries_per_wave(int qpl) { return kWave * qpl; }
+
+void launch_knn_batch(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, const int32_t* pre,
+                      const int32_t* merge_pre, const uint64_t* codes, uint32_t* partial, int32_t* idx,
+                      uint32_t* dist, hipStream_t stream)
+{
+    if (p.n_words == 4)
+        launch_batch_nw<4>(p, m, n_m, pre, merge_pre, codes, partial, idx, dist, stream);
+    else
+        launch_batch_nw<8>(p, m, n_m, pre, merge_pre, codes, partial, idx, dist, stream);
+}
 
 size_t KnnPlan::workspace_bytes() const
 {

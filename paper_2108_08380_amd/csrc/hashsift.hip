@@ -308,6 +308,34 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
     hist_one<DT>(img, W, H, pitch, kps[n], hist + (int64_t)n * 128, smem[wave], lane);
 }
 
+// Batch: units are blocks of four keypoints of every image in turn (pre is
+// the prefix of ceil(n_kp / 4)); order entries are image-local; features are
+// written to the flat array at the keypoint's global index.
+__global__ __launch_bounds__(256) void hashsift_hist_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
+                                                           const int32_t* __restrict__ pre,
+                                                           const bd_keypoint* __restrict__ kps,
+                                                           const int32_t* __restrict__ order, float* __restrict__ hist)
+{
+    __shared__ float smem[kHistWaves][kWaveLds];
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const UnitRange ur = xcd_units(pre[n_img]);
+    for (int u = ur.first; u < ur.end; u += ur.stride) {
+        const int im_i = segment_of(pre, n_img, u);
+        const BatchImage& im = imgs[im_i];
+        const int pos = (u - pre[im_i]) * kHistWaves + wave;
+        if (pos >= im.n_kp) continue;
+        const int n = order[im.kp_offset + pos];
+        if (n < 0 || n >= im.n_kp) continue;
+        const int g = im.kp_offset + n;
+        if (im.hs_dtype == BD_DTYPE_U8)
+            hist_one<BD_DTYPE_U8>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave], lane);
+        else
+            hist_one<BD_DTYPE_F32>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave],
+                                   lane);
+    }
+}
+
 // Features of 32x32 float32 patches: each patch is an image whose keypoint
 // sits at its centre (15.5, 15.5) with scale 1 and angle 0, so every sample
 // falls on a patch pixel (the apron clamps to the edge).
@@ -605,6 +633,13 @@ void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, 
     else
         hipLaunchKernelGGL(hashsift_hist_kernel<BD_DTYPE_F32>, dim3(blocks), dim3(kHistWaves * kWave), 0,
                            stream, p, W, H, img_pitch, kps, n_kp, order, hist);
+}
+
+void launch_hashsift_hist_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
+                                const int32_t* order, float* hist, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(hashsift_hist_batch, dim3(grid), dim3(kHistWaves * kWave), 0, stream, imgs, n_img, pre, kps,
+                       order, hist);
 }
 
 void launch_hashsift_patch_features(const float* patches, int32_t n, float* hist, hipStream_t stream)

@@ -113,15 +113,14 @@ __device__ __forceinline__ uint32_t wave_sum16(const uint32_t (&rs)[16], int lan
     return d;
 }
 
-__global__ __launch_bounds__(256) void integral_tile_sums(const uint8_t* __restrict__ img, int64_t pitch,
-                                                          int32_t W, int32_t H, int32_t strips,
-                                                          int32_t slabs, int64_t col_pitch, bool aligned,
-                                                          uint32_t* __restrict__ colsum,
-                                                          uint32_t* __restrict__ rowsum)
+// ---- bodies shared by the single-image and the batched kernels
+
+// One wavefront: the sums of tile `tile`.
+__device__ __forceinline__ void tile_sums_body(const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H,
+                                               int32_t slabs, int64_t col_pitch, bool aligned,
+                                               uint32_t* __restrict__ colsum, uint32_t* __restrict__ rowsum,
+                                               int tile, int lane)
 {
-    const int lane = threadIdx.x % kWave;
-    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (tile >= strips * slabs) return;
     const int s = tile / slabs, c = tile % slabs;
     const int y0 = s * kTileRows, x = c * kTileCols + 4 * lane;
     const int rows = min(kTileRows, H - y0);
@@ -144,58 +143,49 @@ __global__ __launch_bounds__(256) void integral_tile_sums(const uint8_t* __restr
     if (lane == 0) colsum[(int64_t)s * col_pitch + (int64_t)slabs * kTileCols + c] = tile_total;
 }
 
-// Blocks [0, col_blocks): exclusive scan down the strips for every column of
-// the column table (pixel columns and the tile-total columns), eight strips
-// loaded per round.  Remaining blocks: exclusive scan across the slabs for
-// every image row.
-__global__ __launch_bounds__(256) void integral_carry_scan(uint32_t* __restrict__ colsum,
-                                                           uint32_t* __restrict__ rowsum, int32_t H,
-                                                           int32_t strips, int32_t slabs,
-                                                           int64_t col_pitch, int32_t col_blocks)
+// One thread: exclusive scan down the strips of column x of the column table
+// (eight strips loaded per round).
+__device__ __forceinline__ void carry_col_body(uint32_t* __restrict__ colsum, int32_t strips, int64_t col_pitch,
+                                               int64_t x)
 {
     constexpr int kBatch = 8;
-    if ((int)blockIdx.x < col_blocks) {
-        const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (x >= col_pitch) return;
-        uint32_t acc = 0u;
-        for (int s0 = 0; s0 < strips; s0 += kBatch) {
-            uint32_t v[kBatch];
+    uint32_t acc = 0u;
+    for (int s0 = 0; s0 < strips; s0 += kBatch) {
+        uint32_t v[kBatch];
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k)
-                v[k] = s0 + k < strips ? colsum[(int64_t)(s0 + k) * col_pitch + x] : 0u;
+        for (int k = 0; k < kBatch; ++k) v[k] = s0 + k < strips ? colsum[(int64_t)(s0 + k) * col_pitch + x] : 0u;
 #pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                if (s0 + k < strips) colsum[(int64_t)(s0 + k) * col_pitch + x] = acc;
-                acc += v[k];
-            }
-        }
-    } else {
-        const int64_t y = (int64_t)(blockIdx.x - col_blocks) * blockDim.x + threadIdx.x;
-        if (y >= H) return;
-        uint32_t acc = 0u;
-        for (int c0 = 0; c0 < slabs; c0 += kBatch) {
-            uint32_t v[kBatch];
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) v[k] = c0 + k < slabs ? rowsum[y * slabs + c0 + k] : 0u;
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                if (c0 + k < slabs) rowsum[y * slabs + c0 + k] = acc;
-                acc += v[k];
-            }
+        for (int k = 0; k < kBatch; ++k) {
+            if (s0 + k < strips) colsum[(int64_t)(s0 + k) * col_pitch + x] = acc;
+            acc += v[k];
         }
     }
 }
 
-__global__ __launch_bounds__(256) void integral_tile_write(const uint8_t* __restrict__ img, int64_t pitch,
-                                                           int32_t W, int32_t H, int32_t strips,
-                                                           int32_t slabs, int64_t col_pitch, bool aligned,
-                                                           const uint32_t* __restrict__ colcarry,
-                                                           const uint32_t* __restrict__ rowcarry,
-                                                           uint32_t* __restrict__ ii, int64_t ii_pitch)
+// One thread: exclusive scan across the slabs of image row y.
+__device__ __forceinline__ void carry_row_body(uint32_t* __restrict__ rowsum, int32_t slabs, int64_t y)
 {
-    const int lane = threadIdx.x % kWave;
-    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (tile >= strips * slabs) return;
+    constexpr int kBatch = 8;
+    uint32_t acc = 0u;
+    for (int c0 = 0; c0 < slabs; c0 += kBatch) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) v[k] = c0 + k < slabs ? rowsum[y * slabs + c0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            if (c0 + k < slabs) rowsum[y * slabs + c0 + k] = acc;
+            acc += v[k];
+        }
+    }
+}
+
+// One wavefront: the integral-image entries of tile `tile`.
+__device__ __forceinline__ void tile_write_body(const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H,
+                                                int32_t slabs, int64_t col_pitch, bool aligned,
+                                                const uint32_t* __restrict__ colcarry,
+                                                const uint32_t* __restrict__ rowcarry, uint32_t* __restrict__ ii,
+                                                int64_t ii_pitch, int tile, int lane)
+{
     const int s = tile / slabs, c = tile % slabs;
     const int y0 = s * kTileRows, x0 = c * kTileCols, x = x0 + 4 * lane;
     const int rows = min(kTileRows, H - y0);
@@ -251,6 +241,97 @@ __global__ __launch_bounds__(256) void integral_tile_write(const uint8_t* __rest
     }
 }
 
+// ---- single-image kernels
+
+__global__ __launch_bounds__(256) void integral_tile_sums(const uint8_t* __restrict__ img, int64_t pitch,
+                                                          int32_t W, int32_t H, int32_t strips,
+                                                          int32_t slabs, int64_t col_pitch, bool aligned,
+                                                          uint32_t* __restrict__ colsum,
+                                                          uint32_t* __restrict__ rowsum)
+{
+    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile >= strips * slabs) return;
+    tile_sums_body(img, pitch, W, H, slabs, col_pitch, aligned, colsum, rowsum, tile, threadIdx.x % kWave);
+}
+
+// Blocks [0, col_blocks): column scans; remaining blocks: row scans.
+__global__ __launch_bounds__(256) void integral_carry_scan(uint32_t* __restrict__ colsum,
+                                                           uint32_t* __restrict__ rowsum, int32_t H,
+                                                           int32_t strips, int32_t slabs,
+                                                           int64_t col_pitch, int32_t col_blocks)
+{
+    if ((int)blockIdx.x < col_blocks) {
+        const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (x < col_pitch) carry_col_body(colsum, strips, col_pitch, x);
+    } else {
+        const int64_t y = (int64_t)(blockIdx.x - col_blocks) * blockDim.x + threadIdx.x;
+        if (y < H) carry_row_body(rowsum, slabs, y);
+    }
+}
+
+__global__ __launch_bounds__(256) void integral_tile_write(const uint8_t* __restrict__ img, int64_t pitch,
+                                                           int32_t W, int32_t H, int32_t strips,
+                                                           int32_t slabs, int64_t col_pitch, bool aligned,
+                                                           const uint32_t* __restrict__ colcarry,
+                                                           const uint32_t* __restrict__ rowcarry,
+                                                           uint32_t* __restrict__ ii, int64_t ii_pitch)
+{
+    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile >= strips * slabs) return;
+    tile_write_body(img, pitch, W, H, slabs, col_pitch, aligned, colcarry, rowcarry, ii, ii_pitch, tile,
+                    threadIdx.x % kWave);
+}
+
+// ---- persistent batch kernels: units are blocks of four tiles (tile passes)
+// or 256-column / 256-row blocks (carry scans) of every image in turn
+
+__global__ __launch_bounds__(256) void integral_tile_sums_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
+                                                                const int32_t* __restrict__ pre)
+{
+    const UnitRange ur = xcd_units(pre[n_img]);
+    for (int u = ur.first; u < ur.end; u += ur.stride) {
+        const int i = segment_of(pre, n_img, u);
+        const BatchImage& im = imgs[i];
+        const int tile = (u - pre[i]) * kWavesPerBlock + threadIdx.x / kWave;
+        if (tile < im.strips * im.slabs)
+            tile_sums_body(im.img_u8, im.pitch_u8, im.W, im.H, im.slabs, im.col_pitch, im.aligned != 0, im.colsum,
+                           im.rowsum, tile, threadIdx.x % kWave);
+    }
+}
+
+__global__ __launch_bounds__(256) void integral_carry_scan_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
+                                                                 const int32_t* __restrict__ pre)
+{
+    const UnitRange ur = xcd_units(pre[n_img]);
+    for (int u = ur.first; u < ur.end; u += ur.stride) {
+        const int i = segment_of(pre, n_img, u);
+        const BatchImage& im = imgs[i];
+        const int lb = u - pre[i];
+        const int col_blocks = (int)((im.col_pitch + 255) / 256);
+        if (lb < col_blocks) {
+            const int64_t x = (int64_t)lb * 256 + threadIdx.x;
+            if (x < im.col_pitch) carry_col_body(im.colsum, im.strips, im.col_pitch, x);
+        } else {
+            const int64_t y = (int64_t)(lb - col_blocks) * 256 + threadIdx.x;
+            if (y < im.H) carry_row_body(im.rowsum, im.slabs, y);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void integral_tile_write_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
+                                                                 const int32_t* __restrict__ pre)
+{
+    const UnitRange ur = xcd_units(pre[n_img]);
+    for (int u = ur.first; u < ur.end; u += ur.stride) {
+        const int i = segment_of(pre, n_img, u);
+        const BatchImage& im = imgs[i];
+        const int tile = (u - pre[i]) * kWavesPerBlock + threadIdx.x / kWave;
+        if (tile < im.strips * im.slabs)
+            tile_write_body(im.img_u8, im.pitch_u8, im.W, im.H, im.slabs, im.col_pitch, im.aligned != 0, im.colsum,
+                            im.rowsum, im.ii, im.ii_pitch, tile, threadIdx.x % kWave);
+    }
+}
+
 }  // namespace
 
 size_t IntegralPlan::workspace_bytes() const
@@ -287,6 +368,17 @@ void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitc
                        rowsum, p.H, p.strips, p.slabs, p.col_pitch, col_blocks);
     hipLaunchKernelGGL(integral_tile_write, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W,
                        p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, ii, ii_pitch);
+}
+
+int integral_tile_blocks(const IntegralPlan& p) { return (p.strips * p.slabs + kWavesPerBlock - 1) / kWavesPerBlock; }
+int integral_carry_blocks(const IntegralPlan& p) { return (int)((p.col_pitch + 255) / 256) + (p.H + 255) / 256; }
+
+void launch_integral_batch(const BatchImage* imgs, int32_t n_img, const int32_t* tile_pre, const int32_t* carry_pre,
+                           int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(integral_tile_sums_batch, dim3(grid), dim3(256), 0, stream, imgs, n_img, tile_pre);
+    hipLaunchKernelGGL(integral_carry_scan_batch, dim3(grid), dim3(256), 0, stream, imgs, n_img, carry_pre);
+    hipLaunchKernelGGL(integral_tile_write_batch, dim3(grid), dim3(256), 0, stream, imgs, n_img, tile_pre);
 }
 
 }  // namespace bd

@@ -36,11 +36,9 @@ __device__ __forceinline__ uint32_t cell_key(const bd_keypoint& k, float inv_cel
 
 // One workgroup: histogram of cell keys in LDS, exclusive scan, scatter.
 // Keypoints sharing a cell are placed in arbitrary order.
-__global__ __launch_bounds__(kThreads) void keypoint_order_kernel(const bd_keypoint* __restrict__ kps, int32_t n,
-                                                                 float inv_cell, int32_t* __restrict__ order)
+__device__ __forceinline__ void order_body(const bd_keypoint* __restrict__ kps, int32_t n, float inv_cell,
+                                           int32_t* __restrict__ order, uint32_t* bins, uint32_t* part)
 {
-    __shared__ uint32_t bins[kBins];
-    __shared__ uint32_t part[kThreads];
     const int t = threadIdx.x;
     for (int b = t; b < kBins; b += kThreads) bins[b] = 0u;
     __syncthreads();
@@ -67,16 +65,50 @@ __global__ __launch_bounds__(kThreads) void keypoint_order_kernel(const bd_keypo
     for (int k = 0; k < kPer; ++k) bins[t * kPer + k] = base + local[k];
     __syncthreads();
     for (int i = t; i < n; i += kThreads) order[atomicAdd(&bins[cell_key(kps[i], inv_cell)], 1u)] = i;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void keypoint_order_kernel(const bd_keypoint* __restrict__ kps, int32_t n,
+                                                                 float inv_cell, int32_t* __restrict__ order)
+{
+    __shared__ uint32_t bins[kBins];
+    __shared__ uint32_t part[kThreads];
+    order_body(kps, n, inv_cell, order, bins, part);
+}
+
+// Batch: one image per unit; order entries are indices local to the image.
+__global__ __launch_bounds__(kThreads) void keypoint_order_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
+                                                                const bd_keypoint* __restrict__ kps,
+                                                                int32_t* __restrict__ order)
+{
+    __shared__ uint32_t bins[kBins];
+    __shared__ uint32_t part[kThreads];
+    const UnitRange ur = xcd_units(n_img);
+    for (int i = ur.first; i < ur.end; i += ur.stride) {
+        const BatchImage& im = imgs[i];
+        order_body(kps + im.kp_offset, im.n_kp, im.inv_cell, order + im.kp_offset, bins, part);
+    }
 }
 
 }  // namespace
 
+float order_inv_cell(int32_t W, int32_t H)
+{
+    const int side = W > H ? W : H;
+    return 1.0f / (float)((side + 63) / 64 > 0 ? (side + 63) / 64 : 1);
+}
+
 void launch_keypoint_order(const bd_keypoint* kps, int32_t n_kp, int32_t W, int32_t H, int32_t* order,
                            hipStream_t stream)
 {
-    const int side = W > H ? W : H;
-    const float cell = (float)((side + 63) / 64 > 0 ? (side + 63) / 64 : 1);
-    hipLaunchKernelGGL(keypoint_order_kernel, dim3(1), dim3(kThreads), 0, stream, kps, n_kp, 1.0f / cell, order);
+    hipLaunchKernelGGL(keypoint_order_kernel, dim3(1), dim3(kThreads), 0, stream, kps, n_kp, order_inv_cell(W, H),
+                       order);
+}
+
+void launch_keypoint_order_batch(const BatchImage* imgs, int32_t n_img, const bd_keypoint* kps, int32_t* order,
+                                 int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(keypoint_order_batch, dim3(grid), dim3(kThreads), 0, stream, imgs, n_img, kps, order);
 }
 
 }  // namespace bd

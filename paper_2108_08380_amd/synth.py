@@ -65,9 +65,9 @@ def value_noise(rng: np.random.Generator, height: int, width: int,
         lat = rng.random((height // cell + 2, width // cell + 2))
         iy, sy = _smoothstep_axis(height, cell)
         ix, sx = _smoothstep_axis(width, cell)
-        top = lat[iy][:, ix] * (1.0 - sx) + lat[iy][:, ix + 1] * sx
-        bot = lat[iy + 1][:, ix] * (1.0 - sx) + lat[iy + 1][:, ix + 1] * sx
-        img += amp * (top * (1.0 - sy)[:, None] + bot * sy[:, None])
+        # blend along x on the lattice rows first, then gather rows and blend along y
+        lat_x = lat[:, ix] * (1.0 - sx) + lat[:, ix + 1] * sx
+        img += amp * (lat_x[iy] * (1.0 - sy)[:, None] + lat_x[iy + 1] * sy[:, None])
     lo, hi = img.min(), img.max()
     return (img - lo) * (255.0 / max(hi - lo, 1e-12))
 
@@ -223,6 +223,65 @@ def batched_sizes(rng: np.random.Generator, n_images: int = 64, w_range=(320, 40
     return out
 
 
+@dataclass
+class BatchedWorkload:
+    """Scenes of uneven sizes, each with a shifted noisy copy, for batched
+    describe-and-match.  images[2i] is scene i and images[2i+1] its copy;
+    kps[j] are image j's keypoints (the copy's are the scene's shifted by
+    the same (3, 2) px); matches pair each scene with its copy."""
+
+    images: list
+    kps: list
+    pairs: np.ndarray
+    B: np.ndarray
+    t: np.ndarray
+    matches: list
+    sizes: list
+
+    @property
+    def total_kp(self) -> int:
+        return int(sum(len(k) for k in self.kps))
+
+    def flat_keypoints(self) -> np.ndarray:
+        return np.concatenate(self.kps) if self.kps else np.empty(0, dtype=KEYPOINT_DTYPE)
+
+
+def _batched_scene(seed_seq: np.random.SeedSequence, width: int, height: int, n_kp: int):
+    r_img, r_kp, r_noise = [np.random.Generator(np.random.PCG64(s)) for s in seed_seq.spawn(3)]
+    img = quantize_u8(grey_image(r_img, width, height))
+    copy = shifted_noisy_copy(r_noise, img, 3, 2, 4.0)
+    border = min(32.0, 0.25 * min(width, height))
+    kp = keypoints(r_kp, n_kp, width, height, border, (1.0, 4.0))
+    return img, copy, kp, shift_keypoints(kp, 3, 2)
+
+
+def batched(seed: int = SEED_BASE + 2, n_images: int = 64, w_range=(320, 4000), kp_range=(500, 20000),
+            bad_bits: int = 512, hs_bits: int = 256, sizes=None, workers: int = 8) -> BatchedWorkload:
+    """Batched workload: n_images u8 scenes (W ~ U{w_range}, H = 0.75 W; the
+    generator of the BAD-256 workload), keypoint counts ~ U{kp_range}, each
+    scene with its shifted noisy copy; one BAD table and one HashSIFT
+    projection shared by all.  `sizes` overrides the drawn (W, H, n_kp)
+    list.  Scenes come from independent seed streams, so generating them
+    on `workers` threads gives the same images as generating them in turn."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    root = np.random.SeedSequence(seed)
+    r_sizes, r_par, r_proj = [np.random.Generator(np.random.PCG64(s)) for s in root.spawn(3)]
+    if sizes is None:
+        sizes = batched_sizes(r_sizes, n_images, w_range, kp_range)
+    scene_seeds = np.random.SeedSequence(seed + 1).spawn(len(sizes))
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as pool:
+        scenes = list(pool.map(lambda a: _batched_scene(*a),
+                               [(scene_seeds[i], w, h, n) for i, (w, h, n) in enumerate(sizes)]))
+    images, kps, matches = [], [], []
+    for i, (img, copy, kp, kp2) in enumerate(scenes):
+        images += [img, copy]
+        kps += [kp, kp2]
+        matches.append((2 * i, 2 * i + 1))
+    B, t = projection(r_proj, hs_bits)
+    return BatchedWorkload(images, kps, box_pairs(r_par, bad_bits), B, t, matches, list(sizes))
+
+
 # --------------------------------------------------------------------------- training triplets
 
 
@@ -237,8 +296,8 @@ class TripletBatch:
 
 def _resample_patches(img: np.ndarray, cx, cy, scale, angle) -> np.ndarray:
     """32x32 bilinear crops (scipy.ndimage.map_coordinates, edge-replicated) of img
-    around (cx, cy), one image pixel per `scale` patch pixels... i.e. patch offset
-    u maps to c + scale * Rot(angle) u, offsets (j - 15.5, i - 15.5)."""
+    around (cx, cy): the patch pixel at row i, column j has the offset
+    u = (j - 15.5, i - 15.5) and samples the image at c + scale * Rot(angle) u."""
     from scipy import ndimage
 
     n = len(cx)

@@ -136,3 +136,55 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(bd, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         bd.lib()
+
+
+def test_batch_validation(L):
+    p = 16  # never dereferenced: validation fails first or the context is null
+    imgs = (bd.BatchImageRec * 2)()
+    for i, (W, H, n) in enumerate(((64, 48, 10), (100, 75, 0))):
+        imgs[i].img, imgs[i].pitch, imgs[i].W, imgs[i].H, imgs[i].n_kp = p, W, W, H, n
+    m = (bd.BatchMatchRec * 1)()
+    m[0].query_image, m[0].train_image = 0, 1
+    out = ctypes.c_void_p(1)
+
+    def create(images=imgs, n_img=2, matches=m, n_m=1, bad=512, hs=256, prec=bd.BD_PREC_FP32, margin=1e-3, k=2):
+        return L.bd_batch_create(None, images, n_img, matches, n_m, bad, hs, prec, margin, k, ctypes.byref(out))
+
+    assert L.bd_batch_create(None, imgs, 2, m, 1, 512, 256, 0, 1e-3, 2, None) == bd.BD_EINVAL
+    assert create(n_img=0) == bd.BD_EINVAL and "at least one image" in err(L)
+    assert out.value is None  # cleared on error
+    assert create(bad=128) == bd.BD_EUNSUPPORTED
+    assert create(hs=1024) == bd.BD_EUNSUPPORTED
+    assert create(bad=0, hs=0) == bd.BD_EINVAL and "neither" in err(L)
+    assert create(prec=5) == bd.BD_EUNSUPPORTED
+    assert create(margin=float("inf")) == bd.BD_EINVAL
+    assert create(k=3) == bd.BD_EUNSUPPORTED
+    m[0].train_image = 2
+    assert create() == bd.BD_EINVAL and "names image" in err(L)
+    m[0].train_image = 1
+    imgs[1].pitch = 99
+    assert create() == bd.BD_EINVAL and "pitch" in err(L)
+    imgs[1].pitch = 100
+    imgs[0].n_kp = -1
+    assert create() == bd.BD_EINVAL
+    imgs[0].n_kp = 10
+    imgs[1].hs_img, imgs[1].hs_dtype, imgs[1].hs_pitch = p, bd.BD_DTYPE_F32, 398
+    assert create() == bd.BD_EINVAL and "HashSIFT pitch" in err(L)
+    imgs[1].hs_pitch = 400
+    imgs[0].W, imgs[0].H, imgs[0].pitch = 50000, 50000, 50000
+    assert create() == bd.BD_EINVAL and "32-bit" in err(L)
+    imgs[0].W, imgs[0].H, imgs[0].pitch = 64, 48, 64
+    assert create() == bd.BD_EINVAL and "null context" in err(L)
+
+
+def test_batch_tuning_and_run_validation(L):
+    tn = bd.BatchTuning()
+    assert L.bd_batch_default_tuning(ctypes.byref(tn)) == bd.BD_OK
+    assert tn.knn_rows[0] >= 256 and tn.knn_qpl[1] in (1, 2, 4)
+    assert L.bd_batch_default_tuning(None) == bd.BD_EINVAL
+    assert L.bd_batch_set_tuning(None, ctypes.byref(tn)) == bd.BD_EINVAL
+    assert L.bd_batch_get_tuning(None, ctypes.byref(tn)) == bd.BD_EINVAL
+    assert L.bd_batch_info(None, None, None) == bd.BD_EINVAL
+    assert L.bd_batch_run(None, *([None] * 10), 1, None) == bd.BD_EINVAL
+    assert L.bd_batch_autotune(None, *([None] * 10), 3, None) == bd.BD_EINVAL
+    assert L.bd_batch_destroy(None) == bd.BD_OK
