@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--stage-reps", type=int, default=50)
     p.add_argument("--cpu-sample", type=int, default=2500, help="keypoints per view for the CPU oracle sample")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-batched", action="store_true", help="skip the 128-image batched workload")
+    p.add_argument("--batched-only", action="store_true", help="run only the batched workload and print its JSON")
     p.add_argument("--only", default="", help="profile helper: run only this stage in the step loop")
     p.add_argument("--copy-calibration-mb", type=int, default=0,
                    help="run a plain device copy of this many MiB five times and exit (HBM counter calibration)")
@@ -244,6 +246,107 @@ def differentiation_step(dev, n=8192, reps=5):
     return out
 
 
+def mutual_matching(wl, reps=20):
+    """Mutual nearest neighbours + ratio 0.8 (two k-NN passes and the cross
+    check) on the step's BAD-256 and HashSIFT-512 codes of the two views:
+    time per call, matches kept and their true-correspondence rate."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+
+    out = {}
+    ar = torch.arange(N_KP, device=wl.bad[0].device, dtype=torch.int32)
+    for name, codes in (("bad256", wl.bad), ("hashsift512", wl.hs)):
+        match, dist, count = bd.match_mutual(codes[0], codes[1], 0.8, with_count=True)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            bd.match_mutual(codes[0], codes[1], 0.8)
+        e.record()
+        e.synchronize()
+        kept = match >= 0
+        out[name] = {"ms_per_call": round(s.elapsed_time(e) / reps, 4), "matches": int(count.cpu()[0]),
+                     "true_rate": round(float((match[kept] == ar[kept]).float().mean()), 4)}
+    return out
+
+
+def batched_step(dev, reps=5):
+    """The batching extension on its full workload: 64 u8 scenes of
+    320x240 .. 4000x3000 pixels with 500 .. 20000 keypoints, each with its
+    shifted noisy copy (128 images), BAD-512 + HashSIFT-256 and per-scene
+    Hamming 2-NN against the copy for both code types.  The batch is
+    autotuned, then replayed as one captured graph (HIP events around
+    `reps` replays) and compared, output for output, with the single-image
+    entry points run image by image on the same GPU (timed the same way)."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+    from paper_2108_08380_amd import synth
+
+    w = synth.batched(workers=16)
+    imgs = [torch.from_numpy(im).to(dev) for im in w.images]
+    kps = bd.keypoints_tensor(w.flat_keypoints(), dev)
+    pairs = bd.pairs_tensor(w.pairs, dev)
+    B, t = torch.from_numpy(w.B).to(dev), torch.from_numpy(w.t).to(dev)
+    n_kp = [len(k) for k in w.kps]
+    b = bd.Batch(imgs, n_kp, w.matches, bad_bits=512, hs_bits=256, k=2)
+    out = b.allocate_outputs()
+    t0 = time.perf_counter()
+    tuning = b.autotune(kps, pairs, B, t, out=out, reps=2)
+    tune_s = time.perf_counter() - t0
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        return s.elapsed_time(e) / reps
+
+    ms_batch = timed(lambda: b.run(kps, pairs, B, t, out=out, graph=True))
+
+    offs = np.concatenate([[0], np.cumsum(n_kp)])
+    kp_views = [kps[offs[j]:offs[j + 1]] for j in range(len(imgs))]
+    iis = [torch.empty((im.shape[0] + 1, im.shape[1] + 1), dtype=torch.uint32, device=dev) for im in imgs]
+    plain = {"bad": [torch.empty((n, 8), dtype=torch.uint64, device=dev) for n in n_kp],
+             "hs": [torch.empty((n, 4), dtype=torch.uint64, device=dev) for n in n_kp]}
+    pidx = {c: [torch.empty((n_kp[q], 2), dtype=torch.int32, device=dev) for q, _ in w.matches] for c in plain}
+    pdist = {c: [torch.empty((n_kp[q], 2), dtype=torch.uint32, device=dev) for q, _ in w.matches] for c in plain}
+
+    def plain_pass():
+        for j, im in enumerate(imgs):
+            bd.build_integral(im, out=iis[j])
+            bd.describe_bad(iis[j], kp_views[j], pairs, out=plain["bad"][j])
+            bd.describe_hashsift(im, kp_views[j], B, t, out=plain["hs"][j])
+        for c in plain:
+            for m, (q, tr) in enumerate(w.matches):
+                bd.match_hamming_knn(plain[c][q], plain[c][tr], k=2, idx=pidx[c][m], dist=pdist[c][m])
+
+    ms_plain = timed(plain_pass)
+    same = (torch.equal(out["bad_codes"], torch.cat(plain["bad"])) and torch.equal(out["hs_codes"], torch.cat(plain["hs"]))
+            and all(torch.equal(out[f"{c}_idx"], torch.cat(pidx[c])) and torch.equal(out[f"{c}_dist"], torch.cat(pdist[c]))
+                    for c in plain))
+    total = b.total_kp
+    pairs_n = float(sum(n_kp[q] * n_kp[tr] for q, tr in w.matches))
+    b.close()
+    return {
+        "workload": f"{len(imgs)} u8 images (64 scenes + shifted noisy copies), {total} keypoints, "
+                    f"{sum(im.numel() for im in imgs) / 1e6:.1f} Mpx, BAD-512 + HashSIFT-256, 2-NN per scene",
+        "ms_per_batch_graph": round(ms_batch, 3),
+        "keypoints_per_s": round(total / (ms_batch * 1e-3), 1),
+        "hamming_pairs_per_s": round(2 * pairs_n / (ms_batch * 1e-3), 1),
+        "ms_per_batch_single_image_calls": round(ms_plain, 3),
+        "speedup_vs_single_image_calls": round(ms_plain / ms_batch, 3),
+        "bit_identical_to_single_image_calls": bool(same),
+        "autotune_s": round(tune_s, 2),
+        "tuning": tuning,
+    }
+
+
 def cpu_baseline(sample: int):
     """The oracle on `sample` keypoints per view (full integral images), scaled to the full step."""
     import oracle
@@ -296,6 +399,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "reps": 5}))
+        return
+    if args.batched_only:
+        print(json.dumps({"batched_64_scenes": batched_step(dev)}))
         return
     wl = Workload(dev)
     torch.cuda.synchronize()
@@ -382,8 +488,11 @@ def main():
         "roofline": roofline,
     }
     if not args.only:
+        result["mutual_nn_ratio0.8"] = mutual_matching(wl)
         result["precision_projection_200k"] = precision_projection(wl)
         result["differentiation_8192_triplets"] = differentiation_step(dev)
+        if not args.no_batched:
+            result["batched_64_scenes"] = batched_step(dev)
     if not args.no_cpu and not args.only:
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(result))

@@ -188,6 +188,21 @@ int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q,
                          const uint64_t* train, int32_t n_t, int32_t n_words, int32_t k,
                          int32_t* idx, uint32_t* dist, void* stream);
 
+/* Mutual nearest neighbours with a distance-ratio filter: the Hamming MNN
+ * matcher of the paper's pipeline timing (Sec. IV, Table of the pipeline
+ * steps).  For query i, j is its nearest train code (smallest distance d1,
+ * ties: lowest index) and d2 the smallest distance to any other train code.
+ * i and j match when query i is also train j's nearest query (ties: lowest
+ * index) and, if max_ratio > 0, d1 < max_ratio * d2 (evaluated in double;
+ * always true when n_t < 2).  Outputs (device, n_q each): match[i] = j or
+ * -1, dist[i] = d1 (0xFFFFFFFF when n_t = 0), ratio[i] = d1 / d2 (1 when
+ * d2 = 0, 0 when n_t < 2; optional), *count = number of matches (optional
+ * device int32).  n_words 1..8; max_ratio finite, >= 0 (0: no filter).
+ * Uses the context workspace for both k-NN passes. */
+int bd_match_mutual(bd_context* ctx, const uint64_t* query, int32_t n_q, const uint64_t* train, int32_t n_t,
+                    int32_t n_words, float max_ratio, int32_t* match, uint32_t* dist, float* ratio, int32_t* count,
+                    void* stream);
+
 /* ------------------------------------------------------------------------
  * Differentiation extension (not proposed by the paper): relaxed descriptors
  * D = tanh(beta * rho) and the triplet ranking loss with in-batch hardest

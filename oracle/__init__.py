@@ -54,6 +54,8 @@ def lib():
         L.bdref_keypoint_valid.restype = i32
         L.bdref_match_knn.argtypes = [P, i32, P, i32, i32, i32, P, P]
         L.bdref_match_knn.restype = None
+        L.bdref_match_mutual.argtypes = [P, i32, P, i32, i32, ctypes.c_double, P, P, P]
+        L.bdref_match_mutual.restype = i32
         L.bdref_round_bf16.argtypes = [ctypes.c_float]
         L.bdref_round_bf16.restype = ctypes.c_float
         L.bdref_round_e4m3.argtypes = [ctypes.c_float]
@@ -174,6 +176,21 @@ def match_knn(query: np.ndarray, train: np.ndarray, k: int):
     dist = np.empty((q.shape[0], k), dtype=np.uint32)
     lib().bdref_match_knn(_ptr(q), q.shape[0], _ptr(t), t.shape[0], n_words, k, _ptr(idx), _ptr(dist))
     return idx, dist
+
+
+def match_mutual(query: np.ndarray, train: np.ndarray, max_ratio: float = 0.0):
+    """Mutual nearest neighbours with the distance-ratio filter.
+    Returns (match (n_q,) i32, dist (n_q,) u32, ratio (n_q,) f64, count)."""
+    q = np.ascontiguousarray(query, dtype=np.uint64)
+    t = np.ascontiguousarray(train, dtype=np.uint64)
+    n_words = q.shape[1]
+    assert t.shape[1] == n_words
+    match = np.empty(q.shape[0], dtype=np.int32)
+    dist = np.empty(q.shape[0], dtype=np.uint32)
+    ratio = np.empty(q.shape[0], dtype=np.float64)
+    count = lib().bdref_match_mutual(_ptr(q), q.shape[0], _ptr(t), t.shape[0], n_words, float(max_ratio),
+                                     _ptr(match), _ptr(dist), _ptr(ratio))
+    return match, dist, ratio, int(count)
 
 
 PRECISIONS = {"bf16": 1, "fp8": 2}

@@ -316,6 +316,62 @@ void bdref_match_knn(const uint64_t* query, int32_t n_q, const uint64_t* train, 
     }
 }
 
+static uint32_t hamming(const uint64_t* a, const uint64_t* b, int32_t n_words)
+{
+    uint32_t d = 0;
+    for (int32_t w = 0; w < n_words; ++w) d += popcount64(a[w] ^ b[w]);
+    return d;
+}
+
+int32_t bdref_match_mutual(const uint64_t* query, int32_t n_q, const uint64_t* train, int32_t n_t,
+                           int32_t n_words, double max_ratio, int32_t* match, uint32_t* dist, double* ratio)
+{
+    int32_t count = 0;
+    for (int32_t i = 0; i < n_q; ++i) {
+        const uint64_t* q = query + (int64_t)i * n_words;
+        /* nearest train code of query i, then the smallest distance among the others */
+        int32_t j1 = -1;
+        uint32_t d1 = 0xFFFFFFFFu;
+        for (int32_t j = 0; j < n_t; ++j) {
+            const uint32_t d = hamming(q, train + (int64_t)j * n_words, n_words);
+            if (j1 < 0 || d < d1) {
+                j1 = j;
+                d1 = d;
+            }
+        }
+        int have_d2 = 0;
+        uint32_t d2 = 0xFFFFFFFFu;
+        for (int32_t j = 0; j < n_t; ++j) {
+            if (j == j1) continue;
+            const uint32_t d = hamming(q, train + (int64_t)j * n_words, n_words);
+            if (!have_d2 || d < d2) {
+                have_d2 = 1;
+                d2 = d;
+            }
+        }
+        dist[i] = d1;
+        if (ratio) ratio[i] = !have_d2 ? 0.0 : (d2 == 0 ? 1.0 : (double)d1 / (double)d2);
+        match[i] = -1;
+        if (j1 < 0) continue;
+        /* nearest query of train j1 */
+        const uint64_t* t = train + (int64_t)j1 * n_words;
+        int32_t back = -1;
+        uint32_t db = 0xFFFFFFFFu;
+        for (int32_t r = 0; r < n_q; ++r) {
+            const uint32_t d = hamming(t, query + (int64_t)r * n_words, n_words);
+            if (back < 0 || d < db) {
+                back = r;
+                db = d;
+            }
+        }
+        if (back != i) continue;
+        if (max_ratio > 0.0 && have_d2 && !((double)d1 < max_ratio * (double)d2)) continue;
+        match[i] = j1;
+        ++count;
+    }
+    return count;
+}
+
 /* ------------------------------------------------------------------ reduced precision */
 
 float bdref_round_bf16(float x)

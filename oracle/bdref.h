@@ -129,6 +129,18 @@ int32_t bdref_keypoint_valid(const bdref_keypoint* kp);
 void bdref_match_knn(const uint64_t* query, int32_t n_q, const uint64_t* train, int32_t n_t,
                      int32_t n_words, int32_t k, int32_t* idx, uint32_t* dist);
 
+/* Mutual nearest neighbours with a distance-ratio filter (the Hamming MNN
+ * matcher of the Sec. IV pipeline timing, Table of pipeline steps).  For
+ * query i let j = the train index of the smallest distance d1 (ties: lowest
+ * index) and d2 the second smallest distance over the other train codes.
+ * i and j match when i is also the nearest query of train j (ties: lowest
+ * index) and, if max_ratio > 0, d1 < max_ratio * d2 in double precision
+ * (always true when n_t < 2).  match[i] = j or -1; dist[i] = d1
+ * (0xFFFFFFFF when n_t = 0); ratio[i] = d1 / d2 (1 when d2 = 0, 0 when
+ * n_t < 2), may be NULL.  Returns the number of matches. */
+int32_t bdref_match_mutual(const uint64_t* query, int32_t n_q, const uint64_t* train, int32_t n_t,
+                           int32_t n_words, double max_ratio, int32_t* match, uint32_t* dist, double* ratio);
+
 #ifdef __cplusplus
 }
 #endif

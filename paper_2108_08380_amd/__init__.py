@@ -47,6 +47,7 @@ SIGNATURES = {
     "bd_hashsift_features": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P], ctypes.c_int),
     "bd_hashsift_project": ([_P, _P, _P, _I32, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_match_hamming_knn": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
+    "bd_match_mutual": ([_P, _P, _I32, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P, _P], ctypes.c_int),
     "bd_hashsift_patch_features": ([_P, _P, _I32, _P, _P], ctypes.c_int),
     "bd_relaxed_bad_fwd": ([_P, _P, _I32, _P, _P, _P, _P, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_relaxed_bad_bwd": ([_P, _P, _P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
@@ -377,6 +378,35 @@ def match_hamming_knn(query, train, k: int = 1, idx=None, dist=None):
     _check(lib().bd_match_hamming_knn(context(dev), query.data_ptr(), n_q, train.data_ptr(), train.shape[0],
                                       n_words, k, idx.data_ptr(), dist.data_ptr(), stream))
     return idx, dist
+
+
+def match_mutual(query, train, max_ratio: float = 0.0, with_ratio: bool = False, with_count: bool = False):
+    """Mutual nearest neighbours with the distance-ratio filter (bd_match_mutual).
+    Returns (match int32 (n_q,), dist uint32 (n_q,)) plus ratio float32 (n_q,) and
+    count int32 (1,) when requested."""
+    torch = _torch()
+    _require(query, torch.uint64, 2, "query")
+    _require(train, torch.uint64, 2, "train")
+    _contig(query, "query")
+    _contig(train, "train")
+    if query.shape[1] != train.shape[1]:
+        raise ValueError("query and train codes differ in length")
+    n_q, n_words = query.shape
+    match = torch.empty((n_q,), dtype=torch.int32, device=query.device)
+    dist = torch.empty((n_q,), dtype=torch.uint32, device=query.device)
+    ratio = torch.empty((n_q,), dtype=torch.float32, device=query.device) if with_ratio else None
+    count = torch.empty((1,), dtype=torch.int32, device=query.device) if with_count else None
+    dev, stream = _device_and_stream(query, train)
+    _check(lib().bd_match_mutual(context(dev), query.data_ptr(), n_q, train.data_ptr(), train.shape[0], n_words,
+                                 max_ratio, match.data_ptr(), dist.data_ptr(),
+                                 ratio.data_ptr() if ratio is not None else None,
+                                 count.data_ptr() if count is not None else None, stream))
+    out = (match, dist)
+    if with_ratio:
+        out += (ratio,)
+    if with_count:
+        out += (count,)
+    return out
 
 
 # --------------------------------------------------------------------------- differentiation extension

@@ -175,6 +175,17 @@ KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_c
 void launch_knn(const KnnPlan& p, const uint64_t* query, const uint64_t* train, int32_t* idx,
                 uint32_t* dist, void* workspace, hipStream_t stream);
 
+// ---- mutual nearest neighbours + ratio filter (mutual.hip)
+struct MutualPlan {
+    int32_t n_q, n_t;
+    KnnPlan qt, tq;  // query -> train (k = 2), train -> query (k = 1)
+    size_t workspace_bytes() const;
+};
+MutualPlan plan_mutual(int32_t n_q, int32_t n_t, int32_t n_words, int num_cus);
+void launch_mutual(const MutualPlan& p, const uint64_t* query, const uint64_t* train, float max_ratio,
+                   int32_t* match, uint32_t* dist, float* ratio, int32_t* count, void* workspace,
+                   hipStream_t stream);
+
 // Batched k-NN over BatchMatch problems sharing n_words (4 or 8) and k.
 struct KnnBatchPlan {
     int32_t n_words, k;

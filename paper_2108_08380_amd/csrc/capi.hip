@@ -278,6 +278,26 @@ int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q, co
     return check_launch(fn);
 }
 
+int bd_match_mutual(bd_context* ctx, const uint64_t* query, int32_t n_q, const uint64_t* train, int32_t n_t,
+                    int32_t n_words, float max_ratio, int32_t* match, uint32_t* dist, float* ratio, int32_t* count,
+                    void* stream)
+{
+    const char* fn = "bd_match_mutual";
+    if (n_words < 1 || n_words > 8) return fail(BD_EUNSUPPORTED, "%s: n_words %d (1..8)", fn, n_words);
+    if (n_q < 0 || n_t < 0) return fail(BD_EINVAL, "%s: negative count", fn);
+    if (!(max_ratio >= 0.0f) || max_ratio > 1e30f) return fail(BD_EINVAL, "%s: max_ratio must be finite and >= 0", fn);
+    if (n_q > 0 && (!query || !match || !dist)) return fail(BD_EINVAL, "%s: null query or output pointer", fn);
+    if (n_q > 0 && n_t > 0 && !train) return fail(BD_EINVAL, "%s: null train pointer", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n_q == 0 && !count) return BD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const MutualPlan plan = plan_mutual(n_q, n_t, n_words, ctx->num_cus);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, plan.workspace_bytes(), s, &ws)) return rc;
+    launch_mutual(plan, query, train, max_ratio, match, dist, ratio, count, ws, s);
+    return check_launch(fn);
+}
+
 int bd_hashsift_patch_features(bd_context* ctx, const float* patches, int32_t n, float* hist, void* stream)
 {
     const char* fn = "bd_hashsift_patch_features";

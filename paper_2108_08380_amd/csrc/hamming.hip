@@ -355,7 +355,8 @@ KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_c
     // Aim for ~16 wavefronts per CU while keeping every split at >= 64 rows.
     const int64_t target_waves = 16ll * (num_cus > 0 ? num_cus : 256);
     p.qpl = n_q >= 64 * 2 * target_waves ? 4 : (n_q >= 64 * target_waves ? 2 : 1);
-    const int64_t qgroups = ((int64_t)n_q + 64 * p.qpl - 1) / (64 * p.qpl);
+    int64_t qgroups = ((int64_t)n_q + 64 * p.qpl - 1) / (64 * p.qpl);
+    if (qgroups < 1) qgroups = 1;  // an empty query set still gets a valid plan
     int64_t splits = (target_waves + qgroups - 1) / qgroups;
     const int64_t max_splits = (n_t + 63) / 64;
     if (splits > max_splits) splits = max_splits;

@@ -188,3 +188,16 @@ def test_batch_tuning_and_run_validation(L):
     assert L.bd_batch_run(None, *([None] * 10), 1, None) == bd.BD_EINVAL
     assert L.bd_batch_autotune(None, *([None] * 10), 3, None) == bd.BD_EINVAL
     assert L.bd_batch_destroy(None) == bd.BD_OK
+
+
+def test_match_mutual_validation(L):
+    p = ctypes.c_void_p(16)
+    assert L.bd_match_mutual(None, p, 4, p, 4, 9, 0.8, p, p, None, None, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_match_mutual(None, p, -1, p, 4, 4, 0.8, p, p, None, None, None) == bd.BD_EINVAL
+    assert L.bd_match_mutual(None, p, 4, p, 4, 4, -0.5, p, p, None, None, None) == bd.BD_EINVAL
+    assert "max_ratio" in err(L)
+    assert L.bd_match_mutual(None, p, 4, p, 4, 4, float("nan"), p, p, None, None, None) == bd.BD_EINVAL
+    assert L.bd_match_mutual(None, p, 4, p, 4, 4, 0.8, None, p, None, None, None) == bd.BD_EINVAL
+    assert L.bd_match_mutual(None, p, 4, None, 4, 4, 0.8, p, p, None, None, None) == bd.BD_EINVAL
+    assert L.bd_match_mutual(None, p, 4, None, 0, 4, 0.8, p, p, None, None, None) == bd.BD_EINVAL
+    assert "null context" in err(L)

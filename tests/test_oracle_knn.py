@@ -107,3 +107,92 @@ def test_popcount_against_bit_loop(ref):
             c += v & 1
             v >>= 1
         assert dist[i, 0] == c
+
+
+# ---------------------------------------------------------------- mutual nearest neighbours + ratio filter
+
+
+def distance_matrix(q, t):
+    """All pairwise Hamming distances by unpacking bits (independent of the oracle's popcount loop)."""
+    qb = np.unpackbits(q.view(np.uint8), axis=1).astype(np.int32)
+    tb = np.unpackbits(t.view(np.uint8), axis=1).astype(np.int32)
+    return (qb[:, None, :] != tb[None, :, :]).sum(axis=2)
+
+
+def mutual_by_matrix(q, t, max_ratio):
+    D = distance_matrix(q, t)
+    n_q, n_t = D.shape
+    match = np.full(n_q, -1, np.int32)
+    for i in range(n_q):
+        if n_t == 0:
+            continue
+        j = int(np.argmin(D[i]))  # first minimum: lowest index among ties
+        if int(np.argmin(D[:, j])) != i:
+            continue
+        others = np.delete(D[i], j)
+        if max_ratio > 0 and len(others) and not (float(D[i, j]) < max_ratio * float(others.min())):
+            continue
+        match[i] = j
+    return match
+
+
+def test_mutual_matches_by_brute_force_distance_matrix(ref):
+    rng = np.random.default_rng(70)
+    for n_q, n_t, nw in ((30, 40, 1), (57, 23, 2), (64, 64, 4)):
+        base = rng.integers(0, 2**63, (max(n_q, n_t), nw), dtype=np.uint64)
+        q = base[:n_q].copy()
+        t = base[rng.permutation(len(base))[:n_t]].copy()
+        t ^= (rng.random(t.shape) < 0.05).astype(np.uint64) << rng.integers(0, 64, t.shape).astype(np.uint64)
+        t[:3] = t[3]  # duplicates: ties in both directions
+        for r in (0.0, 0.8, 0.95):
+            m, d, ratio, c = ref.match_mutual(q, t, r)
+            np.testing.assert_array_equal(m, mutual_by_matrix(q, t, r))
+            assert c == int((m >= 0).sum())
+            D = distance_matrix(q, t)
+            np.testing.assert_array_equal(d, D.min(axis=1))
+
+
+def test_mutual_recovers_a_permutation(ref):
+    rng = np.random.default_rng(71)
+    q = rng.integers(0, 2**63, (200, 8), dtype=np.uint64)
+    perm = rng.permutation(200)
+    t = q[perm]
+    m, d, ratio, c = ref.match_mutual(q, t, 0.8)
+    assert c == 200
+    np.testing.assert_array_equal(perm[m], np.arange(200))
+    assert (d == 0).all() and (ratio == 0).all()
+
+
+def test_mutual_is_symmetric_without_ratio(ref):
+    rng = np.random.default_rng(72)
+    q = rng.integers(0, 2**63, (80, 2), dtype=np.uint64)
+    t = q[:60] ^ (np.uint64(1) << rng.integers(0, 64, (60, 2)).astype(np.uint64))
+    t = np.concatenate([t, rng.integers(0, 2**63, (25, 2), dtype=np.uint64)])
+    m_qt, *_ = ref.match_mutual(q, t, 0.0)
+    m_tq, *_ = ref.match_mutual(t, q, 0.0)
+    pairs_qt = {(i, int(j)) for i, j in enumerate(m_qt) if j >= 0}
+    pairs_tq = {(int(i), j) for j, i in enumerate(m_tq) if i >= 0}
+    assert pairs_qt == pairs_tq and len(pairs_qt) >= 55
+
+
+def test_ratio_filter_edge_cases(ref):
+    q = np.array([[0b1011]], dtype=np.uint64)
+    # one train code: no second neighbour, ratio 0, accepted
+    m, d, ratio, c = ref.match_mutual(q, np.array([[0b0011]], dtype=np.uint64), 0.5)
+    assert m[0] == 0 and d[0] == 1 and ratio[0] == 0.0 and c == 1
+    # two equally near train codes: d1 = d2, rejected by any ratio <= 1, kept without the filter
+    t = np.array([[0b0011], [0b1001]], dtype=np.uint64)
+    m, d, ratio, _ = ref.match_mutual(q, t, 0.99)
+    assert m[0] == -1 and ratio[0] == 1.0
+    m, _, _, _ = ref.match_mutual(q, t, 0.0)
+    assert m[0] == 0
+    # d1 = d2 = 0: ratio reported as 1
+    _, _, ratio, _ = ref.match_mutual(q, np.array([[0b1011], [0b1011]], dtype=np.uint64), 0.8)
+    assert ratio[0] == 1.0
+    # 1 < 0.5 * 3 passes, 2 < 0.5 * 3 does not
+    t = np.array([[0b1010], [0b0100]], dtype=np.uint64)  # distances 1 and 4
+    assert ref.match_mutual(q, t, 0.3)[0][0] == 0
+    assert ref.match_mutual(q, t, 0.25)[0][0] == -1  # 1 < 1.0 fails
+    # empty train set
+    m, d, ratio, c = ref.match_mutual(q, np.zeros((0, 1), dtype=np.uint64), 0.8)
+    assert m[0] == -1 and d[0] == 0xFFFFFFFF and c == 0
