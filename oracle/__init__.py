@@ -56,6 +56,10 @@ def lib():
         L.bdref_match_knn.restype = None
         L.bdref_match_mutual.argtypes = [P, i32, P, i32, i32, ctypes.c_double, P, P, P]
         L.bdref_match_mutual.restype = i32
+        L.bdref_threshold_bin.argtypes = [P, P]
+        L.bdref_threshold_bin.restype = i32
+        L.bdref_find_threshold.argtypes = [P, i32, P, P, ctypes.c_double, P, i32, P, P]
+        L.bdref_find_threshold.restype = None
         L.bdref_round_bf16.argtypes = [ctypes.c_float]
         L.bdref_round_bf16.restype = ctypes.c_float
         L.bdref_round_e4m3.argtypes = [ctypes.c_float]
@@ -274,3 +278,30 @@ def hashsift_patch_features(patches):
     f = np.zeros((pt.shape[0], 128))
     lib().bdref_hashsift_patch_features(_ptr(pt), pt.shape[0], _ptr(f))
     return f
+
+
+THRESHOLD_BINS = 5110
+
+
+def threshold_bin(patch: np.ndarray, cand) -> int:
+    """Bin q = floor((f + 255) * 10) of one candidate feature on one u8 32x32 patch."""
+    p = np.ascontiguousarray(patch, dtype=np.uint8).reshape(32, 32)
+    c = _as_pairs(np.atleast_1d(cand))
+    return int(lib().bdref_threshold_bin(_ptr(p), _ptr(c)))
+
+
+def find_threshold(patches: np.ndarray, s_ap, s_an, tau: float, cands):
+    """Alg. 2 for each candidate over the triplets (patches (3n, 32, 32) u8, a/p/n
+    interleaved).  Returns (best_bin (J,) int32, best_loss (J,) float64)."""
+    p = np.ascontiguousarray(patches, dtype=np.uint8)
+    n = p.shape[0] // 3
+    assert p.shape[0] == 3 * n and p[0].size == 1024
+    sap = np.ascontiguousarray(s_ap, dtype=np.int32)
+    san = np.ascontiguousarray(s_an, dtype=np.int32)
+    assert sap.shape == (n,) and san.shape == (n,)
+    c = _as_pairs(cands)
+    best_bin = np.empty(len(c), dtype=np.int32)
+    best_loss = np.empty(len(c), dtype=np.float64)
+    lib().bdref_find_threshold(_ptr(p), n, _ptr(sap), _ptr(san), float(tau), _ptr(c), len(c), _ptr(best_bin),
+                               _ptr(best_loss))
+    return best_bin, best_loss

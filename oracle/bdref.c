@@ -12,6 +12,7 @@
 #include "bdref.h"
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 /* ------------------------------------------------------------------ integral image */
@@ -577,4 +578,77 @@ void bdref_hashsift_patch_features(const float* patches, int32_t n, double* f)
     bdref_keypoint kp = {15.5f, 15.5f, 1.0f, 0.0f};
     for (int32_t i = 0; i < n; ++i)
         bdref_hashsift_hist(patches + (int64_t)i * 1024, 1, 32, 32, 128, &kp, 1, f + (int64_t)i * 128);
+}
+
+/* ------------------------------------------------------------------ feature selection */
+
+/* Sum of the (2r+1)^2 box centred at 16 + u, clamped into the patch. */
+static int64_t patch_box_sum_u8(const uint8_t* patch, int ux, int uy, int r)
+{
+    const int cx = clampi(16 + ux, r, 31 - r), cy = clampi(16 + uy, r, 31 - r);
+    int64_t sum = 0;
+    for (int y = cy - r; y <= cy + r; ++y)
+        for (int x = cx - r; x <= cx + r; ++x) sum += patch[y * 32 + x];
+    return sum;
+}
+
+int32_t bdref_threshold_bin(const uint8_t* patch, const bdref_box_pair* cand)
+{
+    const int r = cand->radius > 15 ? 15 : cand->radius;
+    const int64_t area = (int64_t)(2 * r + 1) * (2 * r + 1);
+    const int64_t s1 = patch_box_sum_u8(patch, cand->x1, cand->y1, r);
+    const int64_t s2 = patch_box_sum_u8(patch, cand->x2, cand->y2, r);
+    /* (f + 255) * 10 = (10 (s1 - s2) + 2550 area) / area >= 0: exact floor */
+    return (int32_t)((10 * (s1 - s2) + 2550 * area) / area);
+}
+
+static double trl_term(double tau, int32_t s_ap, int32_t s_an, int ha, int hp, int hn)
+{
+    const double v = tau - (double)s_ap - (double)(ha * hp) + (double)s_an + (double)(ha * hn);
+    return v > 0.0 ? v : 0.0;
+}
+
+void bdref_find_threshold(const uint8_t* patches, int32_t n_triplets, const int32_t* s_ap, const int32_t* s_an,
+                          double tau, const bdref_box_pair* cands, int32_t n_cands, int32_t* best_bin,
+                          double* best_loss)
+{
+    double* delta = (double*)calloc(BDREF_THRESHOLD_BINS, sizeof(double));
+    /* loss with the threshold below every value: every stump is -1 */
+    double base = 0.0;
+    for (int32_t i = 0; i < n_triplets; ++i) base += trl_term(tau, s_ap[i], s_an[i], -1, -1, -1);
+    for (int32_t c = 0; c < n_cands; ++c) {
+        memset(delta, 0, BDREF_THRESHOLD_BINS * sizeof(double));
+        for (int32_t i = 0; i < n_triplets; ++i) {
+            int32_t q[3];
+            for (int m = 0; m < 3; ++m) q[m] = bdref_threshold_bin(patches + (int64_t)(3 * i + m) * 1024, &cands[c]);
+            /* raise the threshold past the triplet's patches one at a time, in
+             * the order of (bin, position in the triplet) */
+            int h[3] = {-1, -1, -1};
+            int done[3] = {0, 0, 0};
+            double prev = trl_term(tau, s_ap[i], s_an[i], h[0], h[1], h[2]);
+            for (int step = 0; step < 3; ++step) {
+                int next = -1;
+                for (int m = 0; m < 3; ++m)
+                    if (!done[m] && (next < 0 || q[m] < q[next])) next = m;
+                done[next] = 1;
+                h[next] = 1;
+                const double cur = trl_term(tau, s_ap[i], s_an[i], h[0], h[1], h[2]);
+                delta[q[next]] += cur - prev;
+                prev = cur;
+            }
+        }
+        /* cumulative sum over the bins in ascending order; first minimum */
+        double sum = base, best = INFINITY;
+        int32_t bb = -1;
+        for (int32_t b = 0; b < BDREF_THRESHOLD_BINS; ++b) {
+            sum += delta[b];
+            if (sum < best) {
+                best = sum;
+                bb = b;
+            }
+        }
+        best_bin[c] = bb;
+        best_loss[c] = best;
+    }
+    free(delta);
 }

@@ -141,6 +141,28 @@ void bdref_match_knn(const uint64_t* query, int32_t n_q, const uint64_t* train, 
 int32_t bdref_match_mutual(const uint64_t* query, int32_t n_q, const uint64_t* train, int32_t n_t,
                            int32_t n_words, double max_ratio, int32_t* match, uint32_t* dist, double* ratio);
 
+/* ------------------------------------------------------------------ feature selection */
+
+/* Threshold search of a candidate BAD feature over a triplet set (Sec. III-A,
+ * Alg. 2 with the integer-sorting speed-up).  patches: 3 n_triplets u8
+ * 32x32 patches, triplet i = (anchor 3i, positive 3i+1, negative 3i+2).  The
+ * candidate's feature on a patch is f = mean(box 1) - mean(box 2), boxes of
+ * side 2r+1 (r <= 15) centred at 16 + (x, y) clamped to [r, 31 - r]; its
+ * bin is q = floor((f + 255) * 10) in [0, 5100] of BDREF_THRESHOLD_BINS =
+ * 5110 (precision 0.1 over [-255, 255]).  A threshold after bin b gives the
+ * stump h(x) = +1 if q(x) <= b, else -1, and the loss of Eq. 3,
+ *   L(b) = sum_i [tau - s_ap[i] - h(a_i) h(p_i) + s_an[i] + h(a_i) h(n_i)]_+,
+ * with s_ap, s_an the similarities of the previously selected bits.  Per
+ * candidate: best_bin = the lowest b with the smallest L(b), best_loss =
+ * L(best_bin).  Per-triplet loss changes are attributed to the triplet's
+ * three patches in the order of (bin, position in the triplet), so tied
+ * values flip together exactly. */
+#define BDREF_THRESHOLD_BINS 5110
+int32_t bdref_threshold_bin(const uint8_t* patch, const bdref_box_pair* cand);
+void bdref_find_threshold(const uint8_t* patches, int32_t n_triplets, const int32_t* s_ap, const int32_t* s_an,
+                          double tau, const bdref_box_pair* cands, int32_t n_cands, int32_t* best_bin,
+                          double* best_loss);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,130 @@
+"""Pins for the oracle's threshold search (Sec. III-A, Alg. 2 with integer
+sorting into m bins).
+
+* The bin count is the paper's m = 5110 (tests/golden/threshold_search.txt).
+* Bins are pinned by exact rational arithmetic on box sums computed with
+  numpy slicing, including clamped boxes and the extreme features +-255.
+* The whole search is pinned by brute force: the loss of Eq. 3 evaluated
+  directly at every one of the 5110 thresholds (the O(P^2)-type search the
+  paper contrasts with), on sets with tied feature values inside triplets.
+* A one-triplet closed form: the best stump separates the negative from the
+  identical anchor and positive, loss 0."""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2108_08380_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "threshold_search.txt")
+
+
+def golden():
+    out = {}
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            out[k] = float(v)
+    return out
+
+
+def cand(x1, y1, x2, y2, r):
+    c = np.zeros(1, dtype=synth.BOX_PAIR_DTYPE)
+    c[0]["x1"], c[0]["y1"], c[0]["x2"], c[0]["y2"], c[0]["radius"] = x1, y1, x2, y2, r
+    return c
+
+
+def box_sum(patch, ux, uy, r):
+    r = min(int(r), 15)
+    cx = min(max(16 + int(ux), r), 31 - r)
+    cy = min(max(16 + int(uy), r), 31 - r)
+    return int(patch[cy - r:cy + r + 1, cx - r:cx + r + 1].astype(np.int64).sum()), (2 * r + 1) ** 2
+
+
+def bin_exact(patch, c):
+    s1, a = box_sum(patch, c["x1"], c["y1"], c["radius"])
+    s2, _ = box_sum(patch, c["x2"], c["y2"], c["radius"])
+    return math.floor((Fraction(s1 - s2, a) + 255) * 10)
+
+
+def test_bin_count_is_the_papers_m(ref):
+    g = golden()
+    assert ref.THRESHOLD_BINS == int(g["m"]) == round((g["search_max"] - g["search_min"] + 1) / g["precision"])
+
+
+def test_bins_by_exact_rationals(ref):
+    rng = np.random.default_rng(80)
+    patches = rng.integers(0, 256, (40, 32, 32), dtype=np.uint8)
+    cands = synth.box_pairs(rng, 60, max_offset=16, radius_range=(0, 15))
+    for p in patches[:10]:
+        for c in cands:
+            assert ref.threshold_bin(p, c) == bin_exact(p, c)
+    # extremes: +-255 and 0
+    p = np.zeros((32, 32), dtype=np.uint8)
+    p[:, :16] = 255
+    assert ref.threshold_bin(p, cand(-8, 0, 8, 0, 3)) == 5100
+    assert ref.threshold_bin(p, cand(8, 0, -8, 0, 3)) == 0
+    assert ref.threshold_bin(p, cand(-8, 0, -8, 5, 3)) == 2550
+    # fractional features: six ones in a 3x3 box give f = 2/3, bin floor(2556.67) = 2556;
+    # the reverse gives f = -2/3, bin floor(2543.33) = 2543
+    q = np.zeros((32, 32), dtype=np.uint8)
+    q[14:17, 2:4] = 1  # columns 2, 3 of the box centred at (3, 15)
+    assert ref.threshold_bin(q, cand(-13, -1, 10, 10, 1)) == 2556
+    assert ref.threshold_bin(q, cand(10, 10, -13, -1, 1)) == 2543
+
+
+def brute_force(patches, s_ap, s_an, tau, cands):
+    n = len(s_ap)
+    best_bin, best_loss = [], []
+    for c in cands:
+        q = np.array([bin_exact(patches[k], c) for k in range(3 * n)]).reshape(n, 3)
+        b = np.arange(5110)[:, None]
+        h = np.where(q[None, :, :] <= b[:, :, None], 1, -1)  # (bins, n, 3)
+        terms = tau - s_ap[None] - h[:, :, 0] * h[:, :, 1] + s_an[None] + h[:, :, 0] * h[:, :, 2]
+        L = np.maximum(terms, 0).sum(axis=1)
+        bb = int(np.argmin(L))  # first minimum
+        best_bin.append(bb)
+        best_loss.append(float(L[bb]))
+    return np.array(best_bin), np.array(best_loss)
+
+
+@pytest.mark.parametrize("tau", [0.5, 1.0, 2.5])
+def test_search_equals_brute_force(ref, tau):
+    rng = np.random.default_rng(81 + int(tau * 2))
+    n = 40
+    base = rng.integers(0, 256, (n, 32, 32), dtype=np.uint8)
+    patches = np.empty((3 * n, 32, 32), dtype=np.uint8)
+    patches[0::3] = base
+    patches[1::3] = np.clip(base.astype(int) + rng.integers(-30, 31, base.shape), 0, 255)
+    patches[2::3] = rng.integers(0, 256, (n, 32, 32), dtype=np.uint8)
+    patches[3] = patches[4]            # tied anchor/positive values
+    patches[7] = patches[8]            # tied positive/negative values
+    patches[9:12] = 100                # a constant triplet: every feature 0
+    s_ap = rng.integers(-8, 9, n).astype(np.int32)
+    s_an = rng.integers(-8, 9, n).astype(np.int32)
+    cands = synth.box_pairs(rng, 12, radius_range=(0, 6))
+    got_bin, got_loss = ref.find_threshold(patches, s_ap, s_an, tau, cands)
+    exp_bin, exp_loss = brute_force(patches, s_ap, s_an, tau, cands)
+    np.testing.assert_array_equal(got_bin, exp_bin)
+    np.testing.assert_array_equal(got_loss, exp_loss)
+
+
+def test_one_triplet_closed_form(ref):
+    """Anchor = positive, negative brighter in box 1: tau = 1, s = 0.  At the
+    lowest threshold every stump is -1 and the loss is [1 - 1 + 1]_+ = 1; the
+    best stump puts anchor and positive on one side and the negative on the
+    other, loss [1 - 1 - 1]_+ = 0, first reached at the anchor's bin."""
+    a = np.full((32, 32), 50, dtype=np.uint8)
+    n_ = a.copy()
+    n_[:, :16] = 200
+    patches = np.stack([a, a, n_])
+    c = cand(-8, 0, 8, 0, 2)
+    qa, qn = bin_exact(a, c[0]), bin_exact(n_, c[0])
+    assert qa < qn
+    b, loss = ref.find_threshold(patches, np.zeros(1, np.int32), np.zeros(1, np.int32), 1.0, c)
+    assert b[0] == qa and loss[0] == 0.0
+    # with the negative darker the stump flips it alone first
+    b, loss = ref.find_threshold(np.stack([n_, n_, a]), np.zeros(1, np.int32), np.zeros(1, np.int32), 1.0, c)
+    assert b[0] == qa and loss[0] == 0.0
