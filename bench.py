@@ -271,6 +271,36 @@ def mutual_matching(wl, reps=20):
     return out
 
 
+def threshold_search(dev, n=16384, J=1000, reps=5):
+    """Alg. 2 (threshold search) for J = 1000 candidate BAD features, the
+    paper's per-round candidate count, over n triplets of u8 32x32 patches:
+    time per call and candidate-patch features per second."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+    from paper_2108_08380_amd import synth
+
+    b = synth.triplets(synth.SEED_BASE + 4, n=n)
+    p = np.empty((3 * n, 32, 32), dtype=np.float32)
+    p[0::3], p[1::3], p[2::3] = b.anchor, b.positive, b.negative
+    patches = torch.from_numpy(np.clip(np.rint(p * 255.0), 0, 255).astype(np.uint8)).to(dev)
+    rng = np.random.default_rng(7)
+    s_ap = torch.from_numpy(rng.integers(-64, 65, n).astype(np.int32)).to(dev)
+    s_an = torch.from_numpy(rng.integers(-64, 65, n).astype(np.int32)).to(dev)
+    cands = bd.pairs_tensor(synth.box_pairs(rng, J, radius_range=(0, 7)), dev)
+    bd.find_threshold(patches, s_ap, s_an, 1.0, cands)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        bd.find_threshold(patches, s_ap, s_an, 1.0, cands)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    return {"triplets": n, "candidates": J, "bins": 5110, "ms_per_call": round(ms, 3),
+            "candidate_patch_features_per_s": round(3.0 * n * J / (ms * 1e-3), 1)}
+
+
 def batched_step(dev, reps=5):
     """The batching extension on its full workload: 64 u8 scenes of
     320x240 .. 4000x3000 pixels with 500 .. 20000 keypoints, each with its
@@ -490,6 +520,7 @@ def main():
     if not args.only:
         result["mutual_nn_ratio0.8"] = mutual_matching(wl)
         result["precision_projection_200k"] = precision_projection(wl)
+        result["threshold_search_alg2"] = threshold_search(dev)
         result["differentiation_8192_triplets"] = differentiation_step(dev)
         if not args.no_batched:
             result["batched_64_scenes"] = batched_step(dev)

@@ -203,6 +203,26 @@ int bd_match_mutual(bd_context* ctx, const uint64_t* query, int32_t n_q, const u
                     int32_t n_words, float max_ratio, int32_t* match, uint32_t* dist, float* ratio, int32_t* count,
                     void* stream);
 
+/* Threshold search for candidate BAD features (Sec. III-A, Alg. 2 with the
+ * integer sorting the paper proposes for it).  patches: 3 n_triplets u8
+ * 32x32 patches (1024 bytes each, row-major), triplet i = (anchor 3i,
+ * positive 3i+1, negative 3i+2); s_ap, s_an (n_triplets int32): the
+ * similarities h^T h of each triplet's (anchor, positive) and (anchor,
+ * negative) under the features selected so far; cands: n_cands box pairs
+ * (threshold field ignored).  A candidate's feature on a patch is
+ * f = mean(box 1) - mean(box 2), boxes of side 2r+1 (r <= 15) centred at
+ * 16 + (x, y) clamped to [r, 31 - r]; its bin is q = floor((f + 255) * 10),
+ * one of m = 5110 bins (precision 0.1 over [-255, 255]).  The stump after
+ * bin b is h(x) = +1 if q(x) <= b, else -1, with the loss of Eq. 3
+ *   L(b) = sum_i [tau - s_ap - h(a)h(p) + s_an + h(a)h(n)]_+.
+ * Outputs per candidate (device): best_bin = the lowest b of smallest L(b),
+ * best_theta = (best_bin + 1 - 2550) / 10 (so h = +1 iff f < best_theta;
+ * optional), best_loss = L(best_bin) (optional).  tau must be a multiple of
+ * 1/2 (all loss values are then exact).  Workspace: 5110 x n_cands int32. */
+int bd_find_threshold(bd_context* ctx, const uint8_t* patches, int32_t n_triplets, const int32_t* s_ap,
+                      const int32_t* s_an, float tau, const bd_box_pair* cands, int32_t n_cands, int32_t* best_bin,
+                      float* best_theta, double* best_loss, void* stream);
+
 /* ------------------------------------------------------------------------
  * Differentiation extension (not proposed by the paper): relaxed descriptors
  * D = tanh(beta * rho) and the triplet ranking loss with in-batch hardest

@@ -48,6 +48,7 @@ SIGNATURES = {
     "bd_hashsift_project": ([_P, _P, _P, _I32, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_match_hamming_knn": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
     "bd_match_mutual": ([_P, _P, _I32, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P, _P], ctypes.c_int),
+    "bd_find_threshold": ([_P, _P, _I32, _P, _P, ctypes.c_float, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "bd_hashsift_patch_features": ([_P, _P, _I32, _P, _P], ctypes.c_int),
     "bd_relaxed_bad_fwd": ([_P, _P, _I32, _P, _P, _P, _P, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_relaxed_bad_bwd": ([_P, _P, _P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
@@ -407,6 +408,31 @@ def match_mutual(query, train, max_ratio: float = 0.0, with_ratio: bool = False,
     if with_count:
         out += (count,)
     return out
+
+
+def find_threshold(patches, s_ap, s_an, tau: float, cands):
+    """Alg. 2 threshold search for each candidate box pair (bd_find_threshold).
+    patches (3n, 32, 32) uint8 (anchor, positive, negative interleaved), s_ap / s_an
+    (n,) int32, cands (J, 12) uint8 box-pair records.  Returns (best_bin int32 (J,),
+    best_theta float32 (J,), best_loss float64 (J,))."""
+    torch = _torch()
+    if patches.dtype != torch.uint8 or not patches.is_contiguous() or patches.numel() % 3072 != 0:
+        raise ValueError("patches must be a contiguous (3n, 32, 32) uint8 tensor")
+    n = patches.numel() // 3072
+    for v, name in ((s_ap, "s_ap"), (s_an, "s_an")):
+        if v.dtype != torch.int32 or tuple(v.shape) != (n,) or not v.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous ({n},) int32 tensor")
+    _contig(cands, "cands")
+    J = cands.shape[0]
+    dev = patches.device
+    best_bin = torch.empty((J,), dtype=torch.int32, device=dev)
+    best_theta = torch.empty((J,), dtype=torch.float32, device=dev)
+    best_loss = torch.empty((J,), dtype=torch.float64, device=dev)
+    d, stream = _device_and_stream(patches, s_ap, s_an, cands)
+    _check(lib().bd_find_threshold(context(d), patches.data_ptr(), n, s_ap.data_ptr(), s_an.data_ptr(), tau,
+                                   cands.data_ptr(), J, best_bin.data_ptr(), best_theta.data_ptr(),
+                                   best_loss.data_ptr(), stream))
+    return best_bin, best_theta, best_loss
 
 
 # --------------------------------------------------------------------------- differentiation extension

@@ -186,6 +186,12 @@ void launch_mutual(const MutualPlan& p, const uint64_t* query, const uint64_t* t
                    int32_t* match, uint32_t* dist, float* ratio, int32_t* count, void* workspace,
                    hipStream_t stream);
 
+// ---- BAD feature selection: threshold search (select.hip)
+size_t select_workspace(int32_t n_cands);
+void launch_find_threshold(const uint8_t* patches, int32_t n, const int32_t* s_ap, const int32_t* s_an, int tau2,
+                           const bd_box_pair* cands, int32_t n_cands, int32_t* best_bin, float* best_theta,
+                           double* best_loss, void* workspace, int num_cus, hipStream_t stream);
+
 // Batched k-NN over BatchMatch problems sharing n_words (4 or 8) and k.
 struct KnnBatchPlan {
     int32_t n_words, k;

@@ -4,6 +4,7 @@
 // the HIP runtime, so argument errors are reported identically with or
 // without a GPU.  Nothing here synchronizes except workspace growth and
 // context destruction.
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -295,6 +296,29 @@ int bd_match_mutual(bd_context* ctx, const uint64_t* query, int32_t n_q, const u
     void* ws = nullptr;
     if (int rc = reserve_workspace(ctx, plan.workspace_bytes(), s, &ws)) return rc;
     launch_mutual(plan, query, train, max_ratio, match, dist, ratio, count, ws, s);
+    return check_launch(fn);
+}
+
+int bd_find_threshold(bd_context* ctx, const uint8_t* patches, int32_t n_triplets, const int32_t* s_ap,
+                      const int32_t* s_an, float tau, const bd_box_pair* cands, int32_t n_cands, int32_t* best_bin,
+                      float* best_theta, double* best_loss, void* stream)
+{
+    const char* fn = "bd_find_threshold";
+    if (n_triplets < 0 || n_cands < 0) return fail(BD_EINVAL, "%s: negative count", fn);
+    if (n_triplets > (1 << 24)) return fail(BD_EINVAL, "%s: more than 2^24 triplets", fn);
+    const float tau2 = 2.0f * tau;
+    if (!(tau2 == tau2) || tau2 != (float)(int)tau2 || fabsf(tau) > 65536.0f)
+        return fail(BD_EINVAL, "%s: tau must be a multiple of 1/2 with |tau| <= 65536", fn);
+    if (n_cands > 0 && (!cands || !best_bin)) return fail(BD_EINVAL, "%s: null candidate or output pointer", fn);
+    if (n_cands > 0 && n_triplets > 0 && (!patches || !s_ap || !s_an))
+        return fail(BD_EINVAL, "%s: null triplet input", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n_cands == 0) return BD_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, select_workspace(n_cands), s, &ws)) return rc;
+    launch_find_threshold(patches, n_triplets, s_ap, s_an, (int)tau2, cands, n_cands, best_bin, best_theta,
+                          best_loss, ws, ctx->num_cus, s);
     return check_launch(fn);
 }
 

@@ -201,3 +201,15 @@ def test_match_mutual_validation(L):
     assert L.bd_match_mutual(None, p, 4, None, 4, 4, 0.8, p, p, None, None, None) == bd.BD_EINVAL
     assert L.bd_match_mutual(None, p, 4, None, 0, 4, 0.8, p, p, None, None, None) == bd.BD_EINVAL
     assert "null context" in err(L)
+
+
+def test_find_threshold_validation(L):
+    p = ctypes.c_void_p(16)
+    assert L.bd_find_threshold(None, p, -1, p, p, 0.5, p, 4, p, None, None, None) == bd.BD_EINVAL
+    assert L.bd_find_threshold(None, p, 10, p, p, 0.3, p, 4, p, None, None, None) == bd.BD_EINVAL
+    assert "multiple of 1/2" in err(L)
+    assert L.bd_find_threshold(None, p, 10, p, p, float("nan"), p, 4, p, None, None, None) == bd.BD_EINVAL
+    assert L.bd_find_threshold(None, p, 10, p, p, 0.5, None, 4, p, None, None, None) == bd.BD_EINVAL
+    assert L.bd_find_threshold(None, None, 10, p, p, 0.5, p, 4, p, None, None, None) == bd.BD_EINVAL
+    assert L.bd_find_threshold(None, p, 10, p, p, 1.5, p, 4, p, None, None, None) == bd.BD_EINVAL
+    assert "null context" in err(L)
