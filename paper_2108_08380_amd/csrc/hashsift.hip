@@ -354,8 +354,11 @@ __global__ __launch_bounds__(256) void hashsift_patch_kernel(const float* __rest
 
 // ---------------------------------------------------------------- projection
 
-constexpr int kProjKp = 16;      // keypoints per block (one MFMA row tile)
-constexpr int kProjChunks = 4;   // 64-bit chunks per block, one per wavefront
+constexpr int kProjRows = 16;                 // keypoints per wavefront tile (one MFMA row tile)
+constexpr int kProjWaves = 4;                 // wavefronts per block
+constexpr int kProjTile = kProjRows * kProjWaves;  // keypoints per block tile
+constexpr int kProjStride = 132;              // LDS row stride in floats (128 + 4)
+constexpr int kProjBlocksPerCu = 2;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -398,224 +401,238 @@ __device__ __forceinline__ bf16x8 pack_bf16(const float (&v)[32], int s)
     return r;
 }
 
-// Wavefront-cooperative FP32 re-check of one (keypoint, bit) response from
-// the unrounded operands: lane l multiplies elements 2l and 2l+1, and the 64
-// partial sums are added by a fixed xor tree.  When that FP32 value is within
-// 1e-6 of the threshold the same sum is redone in FP64.  Called by the whole
-// wavefront with uniform arguments; every lane returns the response.
-__device__ __forceinline__ float wave_dot_tree(float v)
+// 32 consecutive floats of an LDS row.
+__device__ __forceinline__ void lds_row32(const float* src, float (&v)[32])
 {
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
-__device__ __forceinline__ double wave_dot_tree64(double v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
-
-template <int N>
-__device__ __forceinline__ void recheck_batch(const float* __restrict__ hist, const float* __restrict__ B,
-                                              const float* __restrict__ t, const int (&kp)[N], const int (&bit)[N],
-                                              int lane, float (&r)[N])
-{
-    float2 fv[N], bv[N];
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-        fv[c] = reinterpret_cast<const float2*>(hist + (int64_t)kp[c] * 128)[lane];
-        bv[c] = reinterpret_cast<const float2*>(B + (int64_t)bit[c] * 128)[lane];
-    }
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-        r[c] = wave_dot_tree(fmaf(fv[c].y, bv[c].y, fv[c].x * bv[c].x)) - t[bit[c]];
-        if (fabsf(r[c]) < 1e-6f) {
-            const double p = (double)fv[c].x * (double)bv[c].x + (double)fv[c].y * (double)bv[c].y;
-            r[c] = (float)(wave_dot_tree64(p) - (double)t[bit[c]]);
-        }
+    for (int q = 0; q < 8; ++q) {
+        const float4 f = reinterpret_cast<const float4*>(src)[q];
+        v[4 * q] = f.x;
+        v[4 * q + 1] = f.y;
+        v[4 * q + 2] = f.z;
+        v[4 * q + 3] = f.w;
     }
 }
 
-// grid = (ceil(n_kp / 16), ceil(n_words / 4)); wavefront w of a block computes
-// the 64 responses of chunk blockIdx.y*4 + w for the block's 16 keypoints.
-// Operands come straight from L2 (B is 128 or 256 KiB and shared by every
-// block); lane (g, m) holds features 32g..32g+31 of keypoint row m and of
-// B row m of each 16-bit subtile, so the k order of the MFMA chain is a
-// permutation applied identically to both operands.
+// Persistent, B-stationary projection.  Block b works on XCD b % 8 for the
+// chunk of 64 bits (b / 8) % n_words over that XCD's contiguous range of
+// 64-keypoint tiles, so the n_words blocks that need one tile run on the
+// same XCD and share its rows through L2.  The block keeps its chunk of B in
+// LDS as FP32 (64 rows) and in registers as the MFMA operand of the chosen
+// precision; each wavefront streams 16-keypoint tiles through its own LDS
+// slice, the next tile's rows in flight (registers) while the current one is
+// multiplied.  Lane (g, m) holds elements 32g..32g+31 of keypoint row m and
+// of B row m of each 16-bit subtile, so the k order of the MFMA chain is one
+// permutation applied to both operands.
 //   PREC = FP32: v_mfma_f32_16x16x4_f32, 32 steps per subtile.
 //   PREC = BF16: operands rounded to bfloat16, v_mfma_f32_16x16x32_bf16.
 //   PREC = FP8:  operands scaled per row (max|row| / 448) and rounded to
 //                OCP e4m3, v_mfma_f32_16x16x32_fp8_fp8, response rescaled.
 // With BF16/FP8 every response within `margin` of its threshold is
-// recomputed from the unrounded operands (recheck_response) and counted.
+// recomputed by its own lane in FP32 from the unrounded rows in LDS (in FP64
+// when that result is within 1e-6 of the threshold) and counted.
 template <int PREC>
-__global__ __launch_bounds__(256) void hashsift_project_kernel(const float* __restrict__ hist,
-                                                              const bd_keypoint* __restrict__ kps, int32_t n_kp,
-                                                              const float* __restrict__ B,
-                                                              const float* __restrict__ t, int32_t n_words,
-                                                              float margin, uint64_t* __restrict__ codes,
-                                                              float* __restrict__ resp,
-                                                              uint32_t* __restrict__ recheck_count)
+__global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* __restrict__ hist,
+                                                                 const bd_keypoint* __restrict__ kps, int32_t n_kp,
+                                                                 const float* __restrict__ B,
+                                                                 const float* __restrict__ t, int32_t n_words,
+                                                                 float margin, uint64_t* __restrict__ codes,
+                                                                 float* __restrict__ resp,
+                                                                 uint32_t* __restrict__ recheck_count)
 {
-    const int lane = threadIdx.x % kWave;
-    const int chunk = blockIdx.y * kProjChunks + threadIdx.x / kWave;
-    if (chunk >= n_words) return;
+    __shared__ __align__(16) float Bs[64 * kProjStride];
+    __shared__ __align__(16) float As[kProjWaves][kProjRows * kProjStride];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int g = lane >> 4, m = lane & 15;
-    const int kp0 = blockIdx.x * kProjKp;
+    const int x = (int)blockIdx.x % kXcds, r = (int)blockIdx.x / kXcds;
+    const int chunk = r % n_words, grp = r / n_words;
+    const int n_groups = (int)gridDim.x / kXcds / n_words;
+    const int n_tiles = (n_kp + kProjTile - 1) / kProjTile;
+    const int tile_end = (int)((int64_t)n_tiles * (x + 1) / kXcds);
+    const int tile_first = (int)((int64_t)n_tiles * x / kXcds) + grp;
+    if (tile_first >= tile_end) return;  // uniform per block
     const int n_bits = n_words * 64;
 
-    float a[32];
-    {
-        const int row = kp0 + m;
-        if (row < n_kp) {
-            const float4* src = reinterpret_cast<const float4*>(hist + (int64_t)row * 128 + 32 * g);
+    // B chunk to LDS: 64 rows x 128 floats, 8 float4 per thread
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const float4 v = src[q];
-                a[4 * q] = v.x;
-                a[4 * q + 1] = v.y;
-                a[4 * q + 2] = v.z;
-                a[4 * q + 3] = v.w;
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 32; ++q) a[q] = 0.0f;
-        }
+    for (int q = 0; q < 8; ++q) {
+        const int e = (q * 256 + (int)threadIdx.x) * 4;  // float index in the chunk
+        const int row = e >> 7, col = e & 127;
+        *reinterpret_cast<float4*>(&Bs[row * kProjStride + col]) =
+            *reinterpret_cast<const float4*>(B + (int64_t)(chunk * 64 + row) * 128 + col);
     }
-    float b[4][32];
+    __syncthreads();
+
+    // the MFMA operand of B in registers
+    float bf[4][32];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) lds_row32(&Bs[(16 * nt + m) * kProjStride + 32 * g], bf[nt]);
+    float tv[4], sb[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        const float4* brow = reinterpret_cast<const float4*>(B + (int64_t)(chunk * 64 + 16 * nt + m) * 128 + 32 * g);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float4 v = brow[q];
-            b[nt][4 * q] = v.x;
-            b[nt][4 * q + 1] = v.y;
-            b[nt][4 * q + 2] = v.z;
-            b[nt][4 * q + 3] = v.w;
-        }
+        tv[nt] = t[chunk * 64 + 16 * nt + m];
+        sb[nt] = 1.0f;
     }
-
-    floatx4 acc[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    float scale[4][4];  // per (subtile, register): factor applied to the accumulator
-    if constexpr (PREC == BD_PREC_FP32) {
-#pragma unroll
-        for (int k = 0; k < 32; ++k)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], b[nt][k], acc[nt], 0, 0, 0);
+    bf16x8 bb[4][4];
+    long bq[4][4];
+    if constexpr (PREC == BD_PREC_BF16) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) scale[nt][i] = 1.0f;
-    } else if constexpr (PREC == BD_PREC_BF16) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const bf16x8 av = pack_bf16(a, s);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, pack_bf16(b[nt], s), acc[nt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) scale[nt][i] = 1.0f;
-    } else {
-        const float sa = e4m3_scale(row_maxabs(a));  // scale of keypoint row m
-        float sb[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) sb[nt] = e4m3_scale(row_maxabs(b[nt]));  // scale of B row 16nt + m
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const long av = pack_e4m3(a, s, sa);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, pack_e4m3(b[nt], s, sb[nt]), acc[nt], 0, 0, 0);
-        }
-        // the accumulator of register i belongs to keypoint row 4g + i, whose
-        // scale lane 4g + i computed
-        float sk[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sk[i] = __shfl(sa, 4 * g + i, kWave);
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) scale[nt][i] = sk[i] * sb[nt];
-    }
-
-    // lane holds D[kp = 4g + i][bit = m] of each 16-bit subtile nt
-    float rv[4][4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const float tv = t[chunk * 64 + 16 * nt + m];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) rv[nt][i] = acc[nt][i] * scale[nt][i] - tv;
-    }
-    if constexpr (PREC != BD_PREC_FP32) {
-        // responses within the margin: the wavefront recomputes them one after
-        // another (four candidates' operands in flight at a time)
-        uint32_t rechecked = 0;
+            for (int s = 0; s < 4; ++s) bb[nt][s] = pack_bf16(bf[nt], s);
+    } else if constexpr (PREC == BD_PREC_FP8) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
+            sb[nt] = e4m3_scale(row_maxabs(bf[nt]));  // scale of B row 16nt + m
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const bool need = fabsf(rv[nt][i]) < margin && kp0 + 4 * g + i < n_kp;
-                uint64_t cand = __ballot(need);
-                rechecked += (uint32_t)__popcll(cand);
-                while (cand) {
-                    constexpr int kB = 4;
-                    int ln[kB], kp[kB], bit[kB];
-                    int cnt = 0;
+            for (int s = 0; s < 4; ++s) bq[nt][s] = pack_e4m3(bf[nt], s, sb[nt]);
+        }
+    }
+
+    float* A = As[wave];
+    // tile rows for this wavefront: 16 rows x 128 floats, lane l loads row l / 4, floats 32 (l % 4) ..
+    const int lrow = lane >> 2, lcol = (lane & 3) * 32;
+    float4 pre[8];
+    auto load_tile = [&](int tile) {
+        const int row = tile * kProjTile + wave * kProjRows + lrow;
+        if (row < n_kp) {
+            const float4* src = reinterpret_cast<const float4*>(hist + (int64_t)row * 128 + lcol);
 #pragma unroll
-                    for (int c = 0; c < kB; ++c) {
-                        const int L = cand ? (int)__builtin_ctzll(cand) : -1;
-                        if (cand) cand &= cand - 1;
-                        ln[c] = L;
-                        const int Ls = L >= 0 ? L : ln[0];
-                        kp[c] = kp0 + 4 * (Ls >> 4) + i;
-                        bit[c] = chunk * 64 + 16 * nt + (Ls & 15);
-                        cnt += L >= 0;
+            for (int q = 0; q < 8; ++q) pre[q] = src[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) pre[q] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    };
+    load_tile(tile_first);
+    uint32_t rechecked = 0;
+
+    for (int tile = tile_first; tile < tile_end; tile += n_groups) {
+        wave_sync();  // the previous tile's LDS reads are done
+#pragma unroll
+        for (int q = 0; q < 8; ++q) *reinterpret_cast<float4*>(&A[lrow * kProjStride + lcol + 4 * q]) = pre[q];
+        wave_sync();
+        if (tile + n_groups < tile_end) load_tile(tile + n_groups);
+        const int kp0 = tile * kProjTile + wave * kProjRows;
+
+        float a[32];
+        lds_row32(&A[m * kProjStride + 32 * g], a);
+        floatx4 acc[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        float sk[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+        if constexpr (PREC == BD_PREC_FP32) {
+#pragma unroll
+            for (int k = 0; k < 32; ++k)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bf[nt][k], acc[nt], 0, 0, 0);
+        } else if constexpr (PREC == BD_PREC_BF16) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bf16x8 av = pack_bf16(a, s);
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bb[nt][s], acc[nt], 0, 0, 0);
+            }
+        } else {
+            const float sa = e4m3_scale(row_maxabs(a));  // scale of keypoint row m
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const long av = pack_e4m3(a, s, sa);
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bq[nt][s], acc[nt], 0, 0, 0);
+            }
+            // the accumulator of register i belongs to keypoint row 4g + i,
+            // whose scale lane 4g + i computed
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sk[i] = __shfl(sa, 4 * g + i, kWave);
+        }
+
+        // lane holds D[kp = 4g + i][bit = 16nt + m]
+        float rv[4][4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) rv[nt][i] = acc[nt][i] * (sk[i] * sb[nt]) - tv[nt];
+
+        if constexpr (PREC != BD_PREC_FP32) {
+            uint32_t pending = 0;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (fabsf(rv[nt][i]) < margin && kp0 + 4 * g + i < n_kp) pending |= 1u << (4 * nt + i);
+            rechecked += __popc(pending);
+            // each lane re-checks its own responses, one per pass
+            while (__ballot(pending != 0u)) {
+                if (pending) {
+                    const int slot = __builtin_ctz(pending);
+                    pending &= pending - 1u;
+                    const int nt = slot >> 2, i = slot & 3;
+                    const float* arow = &A[(4 * g + i) * kProjStride];
+                    const float* brow = &Bs[(16 * nt + m) * kProjStride];
+                    float dot = 0.0f;
+#pragma unroll 8
+                    for (int q = 0; q < 32; ++q) {
+                        const float4 av = reinterpret_cast<const float4*>(arow)[q];
+                        const float4 bv = reinterpret_cast<const float4*>(brow)[q];
+                        dot = fmaf(av.x, bv.x, dot);
+                        dot = fmaf(av.y, bv.y, dot);
+                        dot = fmaf(av.z, bv.z, dot);
+                        dot = fmaf(av.w, bv.w, dot);
                     }
-                    float r[kB];
-                    recheck_batch<kB>(hist, B, t, kp, bit, lane, r);
+                    float res = dot - tv[nt];
+                    if (fabsf(res) < 1e-6f) {
+                        double d = 0.0;
+                        for (int k = 0; k < 128; ++k) d = fma((double)arow[k], (double)brow[k], d);
+                        res = (float)(d - (double)tv[nt]);
+                    }
+                    // write back to the slot without dynamic register indexing
 #pragma unroll
-                    for (int c = 0; c < kB; ++c)
-                        if (c < cnt && lane == ln[c]) rv[nt][i] = r[c];
+                    for (int s2 = 0; s2 < 16; ++s2)
+                        if (s2 == slot) rv[s2 >> 2][s2 & 3] = res;
                 }
             }
         }
+
+        uint64_t mask[4][4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int bit = chunk * 64 + 16 * nt + m;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kp = kp0 + 4 * g + i;
+                if (resp && kp < n_kp) resp[(int64_t)kp * n_bits + bit] = rv[nt][i];
+                mask[nt][i] = __ballot(rv[nt][i] > 0.0f);
+            }
+        }
+        if (lane < 16) {
+            const int kp = kp0 + lane;
+            if (kp < n_kp) {
+                bool valid = true;
+                if (kps) {
+                    const bd_keypoint k = kps[kp];
+                    valid = finite_f(k.x) && finite_f(k.y) && finite_f(k.scale) && finite_f(k.angle) &&
+                            k.scale > 0.0f;
+                }
+                const int gq = lane >> 2, iq = lane & 3;
+                uint64_t word = 0ull;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const uint64_t mk =
+                        iq == 0 ? mask[nt][0] : iq == 1 ? mask[nt][1] : iq == 2 ? mask[nt][2] : mask[nt][3];
+                    word |= ((mk >> (16 * gq)) & 0xffffull) << (16 * nt);
+                }
+                codes[(int64_t)kp * n_words + chunk] = valid ? word : 0ull;
+            }
+        }
+    }
+    if constexpr (PREC != BD_PREC_FP32) {
+        // one atomic per wavefront
+        for (int d = 32; d >= 1; d >>= 1) rechecked += __shfl_xor(rechecked, d, kWave);
         if (recheck_count && lane == 0 && rechecked) atomicAdd(recheck_count, rechecked);
-    }
-    uint64_t mask[4][4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const int bit = chunk * 64 + 16 * nt + m;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int kp = kp0 + 4 * g + i;
-            if (resp && kp < n_kp) resp[(int64_t)kp * n_bits + bit] = rv[nt][i];
-            mask[nt][i] = __ballot(rv[nt][i] > 0.0f);
-        }
-    }
-    if (lane < 16) {
-        const int kp = kp0 + lane;
-        if (kp < n_kp) {
-            bool valid = true;
-            if (kps) {
-                const bd_keypoint k = kps[kp];
-                valid = finite_f(k.x) && finite_f(k.y) && finite_f(k.scale) && finite_f(k.angle) && k.scale > 0.0f;
-            }
-            const int gq = lane >> 2, iq = lane & 3;
-            uint64_t word = 0ull;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const uint64_t mk = iq == 0 ? mask[nt][0] : iq == 1 ? mask[nt][1] : iq == 2 ? mask[nt][2] : mask[nt][3];
-                word |= ((mk >> (16 * gq)) & 0xffffull) << (16 * nt);
-            }
-            codes[(int64_t)kp * n_words + chunk] = valid ? word : 0ull;
-        }
     }
 }
 
@@ -652,8 +669,15 @@ void launch_hashsift_project(int32_t precision, const float* hist, const bd_keyp
                              const float* B, const float* t, int32_t n_words, float margin, uint64_t* codes,
                              float* resp, uint32_t* recheck_count, hipStream_t stream)
 {
-    const dim3 grid((n_kp + kProjKp - 1) / kProjKp, (n_words + kProjChunks - 1) / kProjChunks);
-    const dim3 block(kProjChunks * kWave);
+    // groups of n_words blocks per XCD: enough to cover the XCD's tiles, at
+    // most what two resident blocks per CU allow
+    const int n_tiles = (n_kp + kProjTile - 1) / kProjTile;
+    const int tiles_per_xcd = (n_tiles + kXcds - 1) / kXcds;
+    int groups = (kProjBlocksPerCu * 256 / kXcds) / n_words;
+    if (groups > tiles_per_xcd) groups = tiles_per_xcd;
+    if (groups < 1) groups = 1;
+    const dim3 grid(kXcds * n_words * groups);
+    const dim3 block(kProjWaves * kWave);
     if (precision == BD_PREC_BF16)
         hipLaunchKernelGGL(hashsift_project_kernel<BD_PREC_BF16>, grid, block, 0, stream, hist, kps, n_kp, B, t,
                            n_words, margin, codes, resp, recheck_count);
