@@ -60,6 +60,10 @@ def lib():
         L.bdref_threshold_bin.restype = i32
         L.bdref_find_threshold.argtypes = [P, i32, P, P, ctypes.c_double, P, i32, P, P]
         L.bdref_find_threshold.restype = None
+        L.bdref_hnm_codes.argtypes = [P, P, i32, i32, P, P, P]
+        L.bdref_hnm_codes.restype = None
+        L.bdref_select_features.argtypes = [P, i32, P, i32, P, i32, i32, ctypes.c_double, P, P, P, P, P]
+        L.bdref_select_features.restype = None
         L.bdref_round_bf16.argtypes = [ctypes.c_float]
         L.bdref_round_bf16.restype = ctypes.c_float
         L.bdref_round_e4m3.argtypes = [ctypes.c_float]
@@ -305,3 +309,36 @@ def find_threshold(patches: np.ndarray, s_ap, s_an, tau: float, cands):
     lib().bdref_find_threshold(_ptr(p), n, _ptr(sap), _ptr(san), float(tau), _ptr(c), len(c), _ptr(best_bin),
                                _ptr(best_loss))
     return best_bin, best_loss
+
+
+def hnm_codes(a_codes: np.ndarray, p_codes: np.ndarray):
+    """In-batch hardest negatives with anchor swap.  Returns (neg, dist_neg, dist_pos), int32 (n,)."""
+    a = np.ascontiguousarray(a_codes, dtype=np.uint64)
+    p = np.ascontiguousarray(p_codes, dtype=np.uint64)
+    n, w = a.shape
+    neg = np.empty(n, np.int32)
+    dn = np.empty(n, np.int32)
+    dp = np.empty(n, np.int32)
+    lib().bdref_hnm_codes(_ptr(a), _ptr(p), n, w, _ptr(neg), _ptr(dn), _ptr(dp))
+    return neg, dn, dp
+
+
+def select_features(pool: np.ndarray, samples: np.ndarray, cands: np.ndarray, tau: float):
+    """Alg. 1: pool (2P, 32, 32) u8 (anchor, positive interleaved), samples (K, N) int32 pair
+    indices, cands (K, J) box pairs.  Returns (table (K,) box pairs, chosen (K,), chosen_bin (K,),
+    round_loss (K,), pool_codes (2P, ceil(K/64)) u64)."""
+    pl = np.ascontiguousarray(pool, dtype=np.uint8)
+    n_pairs = pl.shape[0] // 2
+    smp = np.ascontiguousarray(samples, dtype=np.int32)
+    K, N = smp.shape
+    c = _as_pairs(cands)
+    assert c.shape[0] == K
+    J = c.shape[1]
+    table = np.zeros(K, dtype=c.dtype)
+    chosen = np.empty(K, np.int32)
+    chosen_bin = np.empty(K, np.int32)
+    loss = np.empty(K, np.float64)
+    codes = np.zeros((2 * n_pairs, (K + 63) // 64), np.uint64)
+    lib().bdref_select_features(_ptr(pl), n_pairs, _ptr(smp), N, _ptr(c), J, K, float(tau), _ptr(table),
+                                _ptr(chosen), _ptr(chosen_bin), _ptr(loss), _ptr(codes))
+    return table, chosen, chosen_bin, loss, codes

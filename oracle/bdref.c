@@ -652,3 +652,109 @@ void bdref_find_threshold(const uint8_t* patches, int32_t n_triplets, const int3
     }
     free(delta);
 }
+
+void bdref_hnm_codes(const uint64_t* a_codes, const uint64_t* p_codes, int32_t n, int32_t n_words, int32_t* neg,
+                     int32_t* dist_neg, int32_t* dist_pos)
+{
+    for (int32_t s = 0; s < n; ++s) {
+        const uint64_t* as = a_codes + (int64_t)s * n_words;
+        const uint64_t* ps = p_codes + (int64_t)s * n_words;
+        int32_t jr = -1, jc = -1;
+        uint32_t dr = 0, dc = 0;
+        for (int32_t j = 0; j < n; ++j) {
+            if (j == s) continue;
+            const uint32_t d1 = hamming(as, p_codes + (int64_t)j * n_words, n_words);
+            if (jr < 0 || d1 < dr) {
+                jr = j;
+                dr = d1;
+            }
+            const uint32_t d2 = hamming(ps, a_codes + (int64_t)j * n_words, n_words);
+            if (jc < 0 || d2 < dc) {
+                jc = j;
+                dc = d2;
+            }
+        }
+        if (dr <= dc) {
+            neg[s] = jr;
+            dist_neg[s] = (int32_t)dr;
+        } else {
+            neg[s] = -1 - jc;
+            dist_neg[s] = (int32_t)dc;
+        }
+        dist_pos[s] = (int32_t)hamming(as, ps, n_words);
+    }
+}
+
+void bdref_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t* samples, int32_t n_sample,
+                           const bdref_box_pair* cands, int32_t n_cands, int32_t n_bits, double tau,
+                           bdref_box_pair* table, int32_t* chosen, int32_t* chosen_bin, double* round_loss,
+                           uint64_t* pool_codes)
+{
+    const int32_t W = (n_bits + 63) / 64;
+    const int32_t n = n_sample;
+    uint64_t* codes = (uint64_t*)calloc((size_t)2 * n_pairs * W, sizeof(uint64_t));
+    uint64_t* ac = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n * W);
+    uint64_t* pc = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n * W);
+    int32_t* neg = (int32_t*)malloc(sizeof(int32_t) * n);
+    int32_t* dneg = (int32_t*)malloc(sizeof(int32_t) * n);
+    int32_t* dpos = (int32_t*)malloc(sizeof(int32_t) * n);
+    int32_t* s_ap = (int32_t*)malloc(sizeof(int32_t) * n);
+    int32_t* s_an = (int32_t*)malloc(sizeof(int32_t) * n);
+    uint8_t* trip = (uint8_t*)malloc((size_t)3 * n * 1024);
+    int32_t* bins = (int32_t*)malloc(sizeof(int32_t) * n_cands);
+    double* losses = (double*)malloc(sizeof(double) * n_cands);
+    for (int32_t k = 0; k < n_bits; ++k) {
+        const int32_t* smp = samples + (int64_t)k * n;
+        /* 1. triplets of the sampled pairs by hardest negatives with anchor swap */
+        for (int32_t s = 0; s < n; ++s) {
+            memcpy(ac + (int64_t)s * W, codes + (int64_t)(2 * smp[s]) * W, sizeof(uint64_t) * W);
+            memcpy(pc + (int64_t)s * W, codes + (int64_t)(2 * smp[s] + 1) * W, sizeof(uint64_t) * W);
+        }
+        bdref_hnm_codes(ac, pc, n, W, neg, dneg, dpos);
+        for (int32_t s = 0; s < n; ++s) {
+            int32_t anc, pos, ngp;
+            if (neg[s] >= 0) {
+                anc = 2 * smp[s];
+                pos = 2 * smp[s] + 1;
+                ngp = 2 * smp[neg[s]] + 1;
+            } else {
+                anc = 2 * smp[s] + 1;
+                pos = 2 * smp[s];
+                ngp = 2 * smp[-1 - neg[s]];
+            }
+            memcpy(trip + (int64_t)(3 * s) * 1024, pool + (int64_t)anc * 1024, 1024);
+            memcpy(trip + (int64_t)(3 * s + 1) * 1024, pool + (int64_t)pos * 1024, 1024);
+            memcpy(trip + (int64_t)(3 * s + 2) * 1024, pool + (int64_t)ngp * 1024, 1024);
+            s_ap[s] = k - 2 * dpos[s];
+            s_an[s] = k - 2 * dneg[s];
+        }
+        /* 2. the best threshold of every candidate, then the best candidate */
+        const bdref_box_pair* ck = cands + (int64_t)k * n_cands;
+        bdref_find_threshold(trip, n, s_ap, s_an, tau, ck, n_cands, bins, losses);
+        int32_t best = 0;
+        for (int32_t c = 1; c < n_cands; ++c)
+            if (losses[c] < losses[best]) best = c;
+        const int r = ck[best].radius > 15 ? 15 : ck[best].radius;
+        table[k] = ck[best];
+        table[k].threshold = (float)((double)(bins[best] + 1 - 2550) / 10.0 - 1.0 / (20.0 * (2 * r + 1) * (2 * r + 1)));
+        if (chosen) chosen[k] = best;
+        if (chosen_bin) chosen_bin[k] = bins[best];
+        if (round_loss) round_loss[k] = losses[best];
+        /* 3. the new stump becomes bit k of every pool patch */
+        for (int32_t x = 0; x < 2 * n_pairs; ++x)
+            if (bdref_threshold_bin(pool + (int64_t)x * 1024, &ck[best]) <= bins[best])
+                codes[(int64_t)x * W + k / 64] |= 1ull << (k % 64);
+    }
+    if (pool_codes) memcpy(pool_codes, codes, sizeof(uint64_t) * (size_t)2 * n_pairs * W);
+    free(codes);
+    free(ac);
+    free(pc);
+    free(neg);
+    free(dneg);
+    free(dpos);
+    free(s_ap);
+    free(s_an);
+    free(trip);
+    free(bins);
+    free(losses);
+}

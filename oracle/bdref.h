@@ -163,6 +163,34 @@ void bdref_find_threshold(const uint8_t* patches, int32_t n_triplets, const int3
                           double tau, const bdref_box_pair* cands, int32_t n_cands, int32_t* best_bin,
                           double* best_loss);
 
+/* In-batch hardest negatives with anchor swap for n (anchor, positive) code
+ * pairs of n_words words: for pair s the row candidate is the positive p_j
+ * (j != s) nearest to a_s and the column candidate the anchor a_j (j != s)
+ * nearest to p_s (Hamming distance, ties: lowest j).  The row candidate wins
+ * ties between the two.  neg[s] = j for a row candidate, -1 - j for a column
+ * candidate; dist_neg[s] = its distance, dist_pos[s] = d(a_s, p_s).  n >= 2. */
+void bdref_hnm_codes(const uint64_t* a_codes, const uint64_t* p_codes, int32_t n, int32_t n_words, int32_t* neg,
+                     int32_t* dist_neg, int32_t* dist_pos);
+
+/* Greedy BAD feature selection (Sec. III-A, Alg. 1).  pool: 2 n_pairs u8
+ * 32x32 patches, pair i = (anchor 2i, positive 2i+1), each pair its own 3D
+ * point.  Round k (0 <= k < n_bits) samples the pairs samples[k * n_sample ..]
+ * (n_sample >= 2), forms triplets with bdref_hnm_codes on the codes of the k
+ * bits selected so far (a column candidate swaps anchor and positive: the
+ * triplet is (p_s, a_s, a_j)), sets s_ap = k - 2 d(anchor, positive) and
+ * s_an = k - 2 d(anchor, negative), runs bdref_find_threshold for the
+ * candidates cands[k * n_cands ..] and keeps the first candidate of lowest
+ * loss.  Its stump (+1 iff bin <= best bin) becomes bit k of every pool
+ * patch.  Outputs: table[k] = the chosen pair with threshold
+ * (bin + 1 - 2550) / 10 - 1 / (20 area) (so that f <= threshold iff
+ * bin <= best bin), chosen[k], chosen_bin[k], round_loss[k] (each optional
+ * except table), pool_codes (2 n_pairs x ceil(n_bits / 64) words, optional;
+ * bit j of a patch in word j / 64 at position j % 64). */
+void bdref_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t* samples, int32_t n_sample,
+                           const bdref_box_pair* cands, int32_t n_cands, int32_t n_bits, double tau,
+                           bdref_box_pair* table, int32_t* chosen, int32_t* chosen_bin, double* round_loss,
+                           uint64_t* pool_codes);
+
 #ifdef __cplusplus
 }
 #endif

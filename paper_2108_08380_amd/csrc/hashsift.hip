@@ -573,17 +573,18 @@ __global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* _
                     const int nt = slot >> 2, i = slot & 3;
                     const float* arow = &A[(4 * g + i) * kProjStride];
                     const float* brow = &Bs[(16 * nt + m) * kProjStride];
-                    float dot = 0.0f;
+                    // four independent chains (elements k mod 4), then a fixed tree
+                    float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, d3 = 0.0f;
 #pragma unroll 8
                     for (int q = 0; q < 32; ++q) {
                         const float4 av = reinterpret_cast<const float4*>(arow)[q];
                         const float4 bv = reinterpret_cast<const float4*>(brow)[q];
-                        dot = fmaf(av.x, bv.x, dot);
-                        dot = fmaf(av.y, bv.y, dot);
-                        dot = fmaf(av.z, bv.z, dot);
-                        dot = fmaf(av.w, bv.w, dot);
+                        d0 = fmaf(av.x, bv.x, d0);
+                        d1 = fmaf(av.y, bv.y, d1);
+                        d2 = fmaf(av.z, bv.z, d2);
+                        d3 = fmaf(av.w, bv.w, d3);
                     }
-                    float res = dot - tv[nt];
+                    float res = ((d0 + d1) + (d2 + d3)) - tv[nt];
                     if (fabsf(res) < 1e-6f) {
                         double d = 0.0;
                         for (int k = 0; k < 128; ++k) d = fma((double)arow[k], (double)brow[k], d);

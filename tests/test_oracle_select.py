@@ -128,3 +128,104 @@ def test_one_triplet_closed_form(ref):
     # with the negative darker the stump flips it alone first
     b, loss = ref.find_threshold(np.stack([n_, n_, a]), np.zeros(1, np.int32), np.zeros(1, np.int32), 1.0, c)
     assert b[0] == qa and loss[0] == 0.0
+
+
+# ---------------------------------------------------------------- Alg. 1: greedy selection
+
+
+def hamming_matrix(x, y):
+    xb = np.unpackbits(x.view(np.uint8), axis=1).astype(np.int32)
+    yb = np.unpackbits(y.view(np.uint8), axis=1).astype(np.int32)
+    return (xb[:, None, :] != yb[None, :, :]).sum(axis=2)
+
+
+def hnm_by_matrix(a, p):
+    n = len(a)
+    Dap = hamming_matrix(a, p)  # row candidates: d(a_s, p_j)
+    Dpa = hamming_matrix(p, a)  # column candidates: d(p_s, a_j)
+    neg, dn = [], []
+    for s in range(n):
+        r = np.where(np.arange(n) == s, 10**9, Dap[s])
+        c = np.where(np.arange(n) == s, 10**9, Dpa[s])
+        jr, jc = int(np.argmin(r)), int(np.argmin(c))
+        if r[jr] <= c[jc]:
+            neg.append(jr)
+            dn.append(r[jr])
+        else:
+            neg.append(-1 - jc)
+            dn.append(c[jc])
+    return np.array(neg), np.array(dn), np.diag(Dap)
+
+
+def test_hardest_negatives_by_distance_matrix(ref):
+    rng = np.random.default_rng(90)
+    for n, w in ((2, 1), (9, 1), (33, 2), (40, 4)):
+        a = rng.integers(0, 2**63, (n, w), dtype=np.uint64)
+        p = a ^ (rng.random((n, w)) < 0.3).astype(np.uint64) * rng.integers(0, 2**63, (n, w), dtype=np.uint64)
+        if n > 4:
+            p[2] = a[0]  # ties and exact duplicates
+            a[3] = p[1]
+        neg, dn, dp = ref.hnm_codes(a, p)
+        en, ed, ep = hnm_by_matrix(a, p)
+        np.testing.assert_array_equal(neg, en)
+        np.testing.assert_array_equal(dn, ed)
+        np.testing.assert_array_equal(dp, ep)
+    # all codes equal (the first round: no bits yet): the row candidate with the lowest index
+    z = np.zeros((5, 1), dtype=np.uint64)
+    neg, dn, _ = ref.hnm_codes(z, z)
+    np.testing.assert_array_equal(neg, [1, 0, 0, 0, 0])
+    assert (dn == 0).all()
+
+
+def select_by_brute_force(pool, samples, cands, tau):
+    """Alg. 1 written out with numpy: exact bins, HNM by distance matrices and the
+    loss of Eq. 3 at all 5110 thresholds."""
+    K, N = samples.shape
+    P2 = len(pool)
+    bits = np.zeros((P2, K), dtype=np.int64)  # 1 where the stump is +1
+    out = []
+    for k in range(K):
+        sm = samples[k]
+        def codes_of(rows):
+            b = np.zeros((len(rows), 64), dtype=np.uint8)
+            b[:, :k] = bits[rows][:, :k]
+            return np.packbits(b, axis=1, bitorder="little").view(np.uint64)
+        a, p = codes_of(2 * sm), codes_of(2 * sm + 1)
+        neg, dn, dp = hnm_by_matrix(a, p)
+        trip = []
+        for s in range(N):
+            if neg[s] >= 0:
+                trip += [2 * sm[s], 2 * sm[s] + 1, 2 * sm[neg[s]] + 1]
+            else:
+                trip += [2 * sm[s] + 1, 2 * sm[s], 2 * sm[-1 - neg[s]]]
+        s_ap = k - 2 * dp
+        s_an = k - 2 * dn
+        bb, bl = brute_force(pool[trip], s_ap, s_an, tau, cands[k])
+        c = int(np.argmin(bl))
+        out.append((c, int(bb[c]), float(bl[c])))
+        for x in range(P2):
+            bits[x, k] = int(bin_exact(pool[x], cands[k][c]) <= bb[c])
+    return out, bits
+
+
+def test_greedy_selection_by_brute_force(ref):
+    rng = np.random.default_rng(91)
+    P, N, J, K = 14, 9, 5, 4
+    b = synth.triplets(synth.SEED_BASE + 91, n=P)
+    pool = np.empty((2 * P, 32, 32), dtype=np.uint8)
+    pool[0::2] = np.clip(np.rint(b.anchor * 255), 0, 255)
+    pool[1::2] = np.clip(np.rint(b.positive * 255), 0, 255)
+    samples = np.stack([rng.permutation(P)[:N] for _ in range(K)]).astype(np.int32)
+    cands = np.stack([synth.box_pairs(rng, J, radius_range=(0, 5)) for _ in range(K)])
+    table, chosen, cbin, loss, codes = ref.select_features(pool, samples, cands, 1.0)
+    exp, bits = select_by_brute_force(pool, samples, cands, 1.0)
+    assert [(int(c), int(q), float(l)) for c, q, l in zip(chosen, cbin, loss)] == exp
+    got_bits = np.unpackbits(codes.view(np.uint8), axis=1, bitorder="little")[:, :K]
+    np.testing.assert_array_equal(got_bits, bits)
+    # the table's thresholds reproduce the stumps with the BAD convention f <= theta
+    for k in range(K):
+        c = table[k]
+        for x in range(2 * P):
+            s1, a = box_sum(pool[x], c["x1"], c["y1"], c["radius"])
+            s2, _ = box_sum(pool[x], c["x2"], c["y2"], c["radius"])
+            assert (Fraction(s1 - s2, a) <= Fraction(float(c["threshold"]))) == bool(bits[x, k])
