@@ -301,6 +301,41 @@ def threshold_search(dev, n=16384, J=1000, reps=5):
             "candidate_patch_features_per_s": round(3.0 * n * J / (ms * 1e-3), 1)}
 
 
+def greedy_selection(dev, P=16384, N=8192, J=1000, K=256):
+    """Alg. 1: learning a BAD-256 table by greedy selection on a pool of P
+    matched u8 patch pairs, each of the K = 256 rounds with N sampled pairs
+    (in-batch hardest negatives with anchor swap on the bits so far) and
+    J = 1000 random candidate box pairs (the paper's J).  One run, timed with
+    HIP events; loss of the first and last rounds."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+    from paper_2108_08380_amd import synth
+
+    b = synth.triplets(synth.SEED_BASE + 5, n=P)
+    pool = np.empty((2 * P, 32, 32), dtype=np.uint8)
+    pool[0::2] = np.clip(np.rint(b.anchor * 255), 0, 255)
+    pool[1::2] = np.clip(np.rint(b.positive * 255), 0, 255)
+    rng = np.random.default_rng(11)
+    samples = np.stack([rng.permutation(P)[:N] for _ in range(K)]).astype(np.int32)
+    cands = synth.box_pairs(rng, K * J, radius_range=(0, 7)).view(np.uint8).reshape(K, J, 12)
+    pool_t = torch.from_numpy(pool).to(dev)
+    samples_t = torch.from_numpy(samples).to(dev)
+    cands_t = torch.from_numpy(cands).to(dev)
+    bd.select_features(pool_t, samples_t[:2].contiguous(), cands_t[:2].contiguous())  # warm-up, workspace
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    table, chosen, cbin, loss, codes = bd.select_features(pool_t, samples_t, cands_t)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e)
+    loss = loss.cpu().numpy()
+    return {"pool_pairs": P, "sampled_pairs_per_round": N, "candidates_per_round": J, "rounds": K,
+            "ms_total": round(ms, 2), "ms_per_round": round(ms / K, 3),
+            "loss_first_round": float(loss[0]), "loss_last_round": float(loss[-1])}
+
+
 def batched_step(dev, reps=5):
     """The batching extension on its full workload: 64 u8 scenes of
     320x240 .. 4000x3000 pixels with 500 .. 20000 keypoints, each with its
@@ -521,6 +556,7 @@ def main():
         result["mutual_nn_ratio0.8"] = mutual_matching(wl)
         result["precision_projection_200k"] = precision_projection(wl)
         result["threshold_search_alg2"] = threshold_search(dev)
+        result["greedy_selection_alg1"] = greedy_selection(dev)
         result["differentiation_8192_triplets"] = differentiation_step(dev)
         if not args.no_batched:
             result["batched_64_scenes"] = batched_step(dev)

@@ -223,6 +223,29 @@ int bd_find_threshold(bd_context* ctx, const uint8_t* patches, int32_t n_triplet
                       const int32_t* s_an, float tau, const bd_box_pair* cands, int32_t n_cands, int32_t* best_bin,
                       float* best_theta, double* best_loss, void* stream);
 
+/* Greedy BAD feature selection (Sec. III-A, Alg. 1), all rounds on the
+ * device.  pool: 2 n_pairs u8 32x32 patches (16-byte aligned), pair i =
+ * (anchor 2i, positive 2i+1), each pair its own 3D point.  Round k
+ * (0 <= k < n_bits) takes the n_sample pairs samples[k n_sample ..] (indices
+ * in [0, n_pairs); out-of-range values are clamped), forms triplets by
+ * in-batch hardest negatives on the codes of the k bits selected so far,
+ * with anchor swap (for pair s the nearest positive p_j of a_s, j != s, and
+ * the nearest anchor a_j of p_s; ties: lowest j, then the positive; an
+ * anchor winner makes the triplet (p_s, a_s, a_j)), runs the threshold
+ * search of bd_find_threshold with s_ap = k - 2 d(anchor, positive),
+ * s_an = k - 2 d(anchor, negative) over the n_cands candidates
+ * cands[k n_cands ..], and keeps the first candidate of lowest loss; its
+ * stump becomes bit k of every pool patch.  Outputs (device): table[k] =
+ * the chosen pair, threshold (bin + 1 - 2550) / 10 - 1 / (20 area) so that
+ * the BAD stump f <= threshold equals bin <= chosen bin; chosen[k],
+ * chosen_bin[k], round_loss[k] and pool_codes (2 n_pairs x ceil(n_bits/64)
+ * u64) are optional.  n_bits 1..512, 2 <= n_sample <= n_pairs, tau a
+ * multiple of 1/2.  Uses the context workspace. */
+int bd_select_features(bd_context* ctx, const uint8_t* pool, int32_t n_pairs, const int32_t* samples,
+                       int32_t n_sample, const bd_box_pair* cands, int32_t n_cands, int32_t n_bits, float tau,
+                       bd_box_pair* table, int32_t* chosen, int32_t* chosen_bin, double* round_loss,
+                       uint64_t* pool_codes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Differentiation extension (not proposed by the paper): relaxed descriptors
  * D = tanh(beta * rho) and the triplet ranking loss with in-batch hardest

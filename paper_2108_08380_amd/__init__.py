@@ -49,6 +49,8 @@ SIGNATURES = {
     "bd_match_hamming_knn": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
     "bd_match_mutual": ([_P, _P, _I32, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P, _P], ctypes.c_int),
     "bd_find_threshold": ([_P, _P, _I32, _P, _P, ctypes.c_float, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
+    "bd_select_features": ([_P, _P, _I32, _P, _I32, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P, _P, _P],
+                           ctypes.c_int),
     "bd_hashsift_patch_features": ([_P, _P, _I32, _P, _P], ctypes.c_int),
     "bd_relaxed_bad_fwd": ([_P, _P, _I32, _P, _P, _P, _P, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_relaxed_bad_bwd": ([_P, _P, _P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
@@ -433,6 +435,36 @@ def find_threshold(patches, s_ap, s_an, tau: float, cands):
                                    cands.data_ptr(), J, best_bin.data_ptr(), best_theta.data_ptr(),
                                    best_loss.data_ptr(), stream))
     return best_bin, best_theta, best_loss
+
+
+def select_features(pool, samples, cands, tau: float = 1.0):
+    """Greedy BAD feature selection, Alg. 1 (bd_select_features).
+    pool (2P, 32, 32) uint8 (anchor, positive interleaved), samples (K, N) int32 pair
+    indices, cands (K, J, 12) uint8 box-pair records.  Returns (table (K, 12) uint8
+    box pairs with thresholds, chosen (K,) int32, chosen_bin (K,) int32, round_loss
+    (K,) float64, pool_codes (2P, ceil(K/64)) uint64)."""
+    torch = _torch()
+    if pool.dtype != torch.uint8 or not pool.is_contiguous() or pool.numel() % 2048 != 0:
+        raise ValueError("pool must be a contiguous (2P, 32, 32) uint8 tensor")
+    n_pairs = pool.numel() // 2048
+    if samples.dtype != torch.int32 or samples.dim() != 2 or not samples.is_contiguous():
+        raise ValueError("samples must be a contiguous (K, N) int32 tensor")
+    K, N = samples.shape
+    if cands.dtype != torch.uint8 or cands.dim() != 3 or cands.shape[0] != K or cands.shape[2] != 12:
+        raise ValueError("cands must be a (K, J, 12) uint8 tensor")
+    _contig(cands, "cands")
+    J = cands.shape[1]
+    dev = pool.device
+    table = torch.empty((K, 12), dtype=torch.uint8, device=dev)
+    chosen = torch.empty((K,), dtype=torch.int32, device=dev)
+    chosen_bin = torch.empty((K,), dtype=torch.int32, device=dev)
+    loss = torch.empty((K,), dtype=torch.float64, device=dev)
+    codes = torch.empty((2 * n_pairs, (K + 63) // 64), dtype=torch.uint64, device=dev)
+    d, stream = _device_and_stream(pool, samples, cands)
+    _check(lib().bd_select_features(context(d), pool.data_ptr(), n_pairs, samples.data_ptr(), N, cands.data_ptr(),
+                                    J, K, tau, table.data_ptr(), chosen.data_ptr(), chosen_bin.data_ptr(),
+                                    loss.data_ptr(), codes.data_ptr(), stream))
+    return table, chosen, chosen_bin, loss, codes
 
 
 # --------------------------------------------------------------------------- differentiation extension

@@ -188,9 +188,15 @@ void launch_mutual(const MutualPlan& p, const uint64_t* query, const uint64_t* t
 
 // ---- BAD feature selection: threshold search (select.hip)
 size_t select_workspace(int32_t n_cands);
-void launch_find_threshold(const uint8_t* patches, int32_t n, const int32_t* s_ap, const int32_t* s_an, int tau2,
-                           const bd_box_pair* cands, int32_t n_cands, int32_t* best_bin, float* best_theta,
-                           double* best_loss, void* workspace, int num_cus, hipStream_t stream);
+void launch_find_threshold(const uint8_t* patches, const int32_t* patch_index, int32_t n, const int32_t* s_ap,
+                           const int32_t* s_an, int tau2, const bd_box_pair* cands, int32_t n_cands,
+                           int32_t* best_bin, float* best_theta, double* best_loss, void* workspace, int num_cus,
+                           hipStream_t stream);
+size_t select_features_workspace(int32_t n_pairs, int32_t n_sample, int32_t n_cands, int32_t n_bits, int num_cus);
+void launch_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t* samples, int32_t n_sample,
+                            const bd_box_pair* cands, int32_t n_cands, int32_t n_bits, int tau2,
+                            bd_box_pair* table, int32_t* chosen, int32_t* chosen_bin, double* round_loss,
+                            uint64_t* pool_codes_out, void* workspace, int num_cus, hipStream_t stream);
 
 // Batched k-NN over BatchMatch problems sharing n_words (4 or 8) and k.
 struct KnnBatchPlan {

@@ -317,8 +317,34 @@ int bd_find_threshold(bd_context* ctx, const uint8_t* patches, int32_t n_triplet
     hipStream_t s = static_cast<hipStream_t>(stream);
     void* ws = nullptr;
     if (int rc = reserve_workspace(ctx, select_workspace(n_cands), s, &ws)) return rc;
-    launch_find_threshold(patches, n_triplets, s_ap, s_an, (int)tau2, cands, n_cands, best_bin, best_theta,
-                          best_loss, ws, ctx->num_cus, s);
+    launch_find_threshold(patches, nullptr, n_triplets, s_ap, s_an, (int)tau2, cands, n_cands, best_bin,
+                          best_theta, best_loss, ws, ctx->num_cus, s);
+    return check_launch(fn);
+}
+
+int bd_select_features(bd_context* ctx, const uint8_t* pool, int32_t n_pairs, const int32_t* samples,
+                       int32_t n_sample, const bd_box_pair* cands, int32_t n_cands, int32_t n_bits, float tau,
+                       bd_box_pair* table, int32_t* chosen, int32_t* chosen_bin, double* round_loss,
+                       uint64_t* pool_codes, void* stream)
+{
+    const char* fn = "bd_select_features";
+    if (n_bits < 1 || n_bits > 512) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (1..512)", fn, n_bits);
+    if (n_pairs < 2 || n_sample < 2 || n_sample > n_pairs)
+        return fail(BD_EINVAL, "%s: need 2 <= n_sample <= n_pairs (got %d, %d)", fn, n_sample, n_pairs);
+    if (n_pairs > (1 << 22) || n_sample > (1 << 22)) return fail(BD_EINVAL, "%s: more than 2^22 pairs", fn);
+    if (n_cands < 1) return fail(BD_EINVAL, "%s: n_cands %d < 1", fn, n_cands);
+    const float tau2 = 2.0f * tau;
+    if (!(tau2 == tau2) || tau2 != (float)(int)tau2 || fabsf(tau) > 65536.0f)
+        return fail(BD_EINVAL, "%s: tau must be a multiple of 1/2 with |tau| <= 65536", fn);
+    if (!pool || !samples || !cands || !table) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, select_features_workspace(n_pairs, n_sample, n_cands, n_bits, ctx->num_cus),
+                                   s, &ws))
+        return rc;
+    launch_select_features(pool, n_pairs, samples, n_sample, cands, n_cands, n_bits, (int)tau2, table, chosen,
+                           chosen_bin, round_loss, pool_codes, ws, ctx->num_cus, s);
     return check_launch(fn);
 }
 

@@ -99,7 +99,8 @@ __global__ __launch_bounds__(1024) void select_base_kernel(const int32_t* __rest
     if (threadIdx.x == 0) *base2 = part[0];
 }
 
-__global__ __launch_bounds__(kThreads) void select_hist_kernel(const uint8_t* __restrict__ patches, int32_t n,
+__global__ __launch_bounds__(kThreads) void select_hist_kernel(const uint8_t* __restrict__ patches,
+                                                               const int32_t* __restrict__ patch_index, int32_t n,
                                                                const int32_t* __restrict__ s_ap,
                                                                const int32_t* __restrict__ s_an, int tau2,
                                                                const bd_box_pair* __restrict__ cands,
@@ -121,7 +122,8 @@ __global__ __launch_bounds__(kThreads) void select_hist_kernel(const uint8_t* __
             uint32_t* dst = ii[p] + (y + 1) * kIIPitch;
             dst[0] = 0u;
             if (p < 3 * n_here) {
-                const uint8_t* src = patches + ((int64_t)(3 * tri0 + p) * 32 + y) * 32;
+                const int64_t pid = patch_index ? patch_index[3 * tri0 + p] : 3 * tri0 + p;
+                const uint8_t* src = patches + (pid * 32 + y) * 32;
                 uint32_t acc = 0;
 #pragma unroll 8
                 for (int xx = 0; xx < 32; ++xx) {
@@ -241,13 +243,224 @@ __global__ __launch_bounds__(1024) void select_scan_kernel(const int32_t* __rest
     }
 }
 
+// ---- Alg. 1 (greedy selection) steps
+
+__global__ __launch_bounds__(kThreads) void sel_zero_u64_kernel(uint64_t* __restrict__ p, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+__device__ __forceinline__ int sample_pair(const int32_t* samples, int s, int32_t n_pairs)
+{
+    return clampi(samples[s], 0, n_pairs - 1);  // out-of-range indices are clamped, never dereferenced
+}
+
+// Codes of the sampled anchors and positives (pair i: pool patches 2i, 2i+1).
+__global__ __launch_bounds__(kThreads) void sel_gather_codes_kernel(const uint64_t* __restrict__ pool_codes,
+                                                                    int32_t W, const int32_t* __restrict__ samples,
+                                                                    int32_t n, int32_t n_pairs,
+                                                                    uint64_t* __restrict__ ac,
+                                                                    uint64_t* __restrict__ pc)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * W) return;
+    const int s = e / W, w = e - s * W;
+    const int i = sample_pair(samples, s, n_pairs);
+    ac[e] = pool_codes[(int64_t)(2 * i) * W + w];
+    pc[e] = pool_codes[(int64_t)(2 * i + 1) * W + w];
+}
+
+// Hardest in-batch negative with anchor swap from the two 2-NN results
+// (a -> p and p -> a): the first neighbour other than s in each direction;
+// the row candidate (a positive) wins ties.  Writes the triplet's pool patch
+// indices and the similarities k - 2 d of (anchor, positive) and (anchor,
+// negative) under the k bits selected so far.
+__global__ __launch_bounds__(kThreads) void sel_hnm_kernel(const int32_t* __restrict__ idx_ap,
+                                                           const uint32_t* __restrict__ dist_ap,
+                                                           const int32_t* __restrict__ idx_pa,
+                                                           const uint32_t* __restrict__ dist_pa,
+                                                           const uint64_t* __restrict__ ac,
+                                                           const uint64_t* __restrict__ pc, int32_t n, int32_t W,
+                                                           int32_t k, const int32_t* __restrict__ samples,
+                                                           int32_t n_pairs, int32_t* __restrict__ patch_index,
+                                                           int32_t* __restrict__ s_ap, int32_t* __restrict__ s_an)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int slot_r = idx_ap[2 * s] == s ? 1 : 0;
+    const int slot_c = idx_pa[2 * s] == s ? 1 : 0;
+    const int jr = idx_ap[2 * s + slot_r], jc = idx_pa[2 * s + slot_c];
+    const uint32_t dr = dist_ap[2 * s + slot_r], dc = dist_pa[2 * s + slot_c];
+    uint32_t dp = 0;
+    for (int w = 0; w < W; ++w) dp += __popcll(ac[(int64_t)s * W + w] ^ pc[(int64_t)s * W + w]);
+    const int i = sample_pair(samples, s, n_pairs);
+    const bool row = dr <= dc;
+    const int j = sample_pair(samples, clampi(row ? jr : jc, 0, n - 1), n_pairs);
+    patch_index[3 * s] = row ? 2 * i : 2 * i + 1;
+    patch_index[3 * s + 1] = row ? 2 * i + 1 : 2 * i;
+    patch_index[3 * s + 2] = row ? 2 * j + 1 : 2 * j;
+    s_ap[s] = k - 2 * (int)dp;
+    s_an[s] = k - 2 * (int)(row ? dr : dc);
+}
+
+// First candidate of lowest loss; writes the table entry and the round's
+// outputs, and keeps (candidate, bin) for the bit update.
+__global__ __launch_bounds__(1024) void sel_best_kernel(const int32_t* __restrict__ best_bin,
+                                                        const double* __restrict__ best_loss, int32_t n_cands,
+                                                        const bd_box_pair* __restrict__ cands, int32_t k,
+                                                        bd_box_pair* __restrict__ table, int32_t* __restrict__ chosen,
+                                                        int32_t* __restrict__ chosen_bin,
+                                                        double* __restrict__ round_loss, int2* __restrict__ state)
+{
+    __shared__ double lv[1024];
+    __shared__ int32_t li[1024];
+    const int t = threadIdx.x;
+    double bv = INFINITY;
+    int bi = INT32_MAX;
+    for (int c = t; c < n_cands; c += blockDim.x)
+        if (best_loss[c] < bv) {  // ascending c per thread: the first minimum
+            bv = best_loss[c];
+            bi = c;
+        }
+    lv[t] = bv;
+    li[t] = bi;
+    __syncthreads();
+    for (int d = 512; d >= 1; d >>= 1) {
+        if (t < d && (lv[t + d] < lv[t] || (lv[t + d] == lv[t] && li[t + d] < li[t]))) {
+            lv[t] = lv[t + d];
+            li[t] = li[t + d];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const int c = li[0];
+        const int b = best_bin[c];
+        bd_box_pair e = cands[c];
+        const int r = e.radius > 15 ? 15 : e.radius;
+        const double area = (double)((2 * r + 1) * (2 * r + 1));
+        e.threshold = (float)((double)(b + 1 - 2550) / 10.0 - 1.0 / (20.0 * area));
+        table[k] = e;
+        if (chosen) chosen[k] = c;
+        if (chosen_bin) chosen_bin[k] = b;
+        if (round_loss) round_loss[k] = lv[0];
+        *state = int2{c, b};
+    }
+}
+
+// Bit k of every pool patch from the chosen stump: one wavefront per patch
+// (16 bytes per lane cover the 32 x 32 patch), box sums by a wavefront sum.
+__global__ __launch_bounds__(kThreads) void sel_update_kernel(const uint8_t* __restrict__ pool, int32_t n_patches,
+                                                              const bd_box_pair* __restrict__ cands,
+                                                              const int2* __restrict__ state,
+                                                              uint64_t* __restrict__ pool_codes, int32_t W,
+                                                              int32_t k)
+{
+    const int lane = threadIdx.x % kWave;
+    const int x = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    if (x >= n_patches) return;
+    const int2 st = *state;
+    const CandGeom g = geometry(cands[st.x]);
+    const uint4 v = reinterpret_cast<const uint4*>(pool + (int64_t)x * 1024)[lane];
+    const int y = lane >> 1, x0 = (lane & 1) * 16;  // this lane: row y, columns x0 .. x0+15
+    const uint32_t words[4] = {v.x, v.y, v.z, v.w};
+    int d = 0;
+    const bool row1 = y >= g.cy1 - g.r && y <= g.cy1 + g.r;
+    const bool row2 = y >= g.cy2 - g.r && y <= g.cy2 + g.r;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int px = (int)((words[e >> 2] >> (8 * (e & 3))) & 0xffu);
+        const int xx = x0 + e;
+        if (row1 && xx >= g.cx1 - g.r && xx <= g.cx1 + g.r) d += px;
+        if (row2 && xx >= g.cx2 - g.r && xx <= g.cx2 + g.r) d -= px;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o, kWave);
+    if (lane == 0) {
+        const int num = 10 * d + 2550 * g.area;
+        const int q = num / g.area;  // num >= 0
+        if (q <= st.y) pool_codes[(int64_t)x * W + k / 64] |= 1ull << (k % 64);
+    }
+}
+
+size_t align_up256(size_t v) { return (v + 255) / 256 * 256; }
+
 }  // namespace
+
+size_t select_features_workspace(int32_t n_pairs, int32_t n_sample, int32_t n_cands, int32_t n_bits, int num_cus)
+{
+    const size_t W = (size_t)(n_bits + 63) / 64, N = (size_t)n_sample;
+    const KnnPlan kp = plan_knn(n_sample, n_sample, (int32_t)W, 2, num_cus);
+    return align_up256(sizeof(uint64_t) * 2 * (size_t)n_pairs * W) + 2 * align_up256(sizeof(uint64_t) * N * W) +
+           4 * align_up256(sizeof(int32_t) * 2 * N) + align_up256(kp.workspace_bytes()) +
+           2 * align_up256(sizeof(int32_t) * N) + align_up256(sizeof(int32_t) * 3 * N) +
+           align_up256(select_workspace(n_cands)) + align_up256(sizeof(int32_t) * n_cands) +
+           align_up256(sizeof(double) * n_cands) + 256;
+}
+
+void launch_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t* samples, int32_t n_sample,
+                            const bd_box_pair* cands, int32_t n_cands, int32_t n_bits, int tau2,
+                            bd_box_pair* table, int32_t* chosen, int32_t* chosen_bin, double* round_loss,
+                            uint64_t* pool_codes_out, void* workspace, int num_cus, hipStream_t stream)
+{
+    const int32_t W = (n_bits + 63) / 64, N = n_sample;
+    char* ws = static_cast<char*>(workspace);
+    auto take = [&](size_t bytes) {
+        void* p = ws;
+        ws += align_up256(bytes);
+        return p;
+    };
+    uint64_t* codes = static_cast<uint64_t*>(take(sizeof(uint64_t) * 2 * (size_t)n_pairs * W));
+    uint64_t* ac = static_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)N * W));
+    uint64_t* pc = static_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)N * W));
+    int32_t* idx_ap = static_cast<int32_t*>(take(sizeof(int32_t) * 2 * (size_t)N));
+    uint32_t* dist_ap = static_cast<uint32_t*>(take(sizeof(int32_t) * 2 * (size_t)N));
+    int32_t* idx_pa = static_cast<int32_t*>(take(sizeof(int32_t) * 2 * (size_t)N));
+    uint32_t* dist_pa = static_cast<uint32_t*>(take(sizeof(int32_t) * 2 * (size_t)N));
+    const KnnPlan kp = plan_knn(N, N, W, 2, num_cus);
+    void* knn_ws = take(kp.workspace_bytes());
+    int32_t* s_ap = static_cast<int32_t*>(take(sizeof(int32_t) * (size_t)N));
+    int32_t* s_an = static_cast<int32_t*>(take(sizeof(int32_t) * (size_t)N));
+    int32_t* patch_index = static_cast<int32_t*>(take(sizeof(int32_t) * 3 * (size_t)N));
+    void* thr_ws = take(select_workspace(n_cands));
+    int32_t* bins = static_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n_cands));
+    double* losses = static_cast<double*>(take(sizeof(double) * (size_t)n_cands));
+    int2* state = static_cast<int2*>(take(sizeof(int2)));
+
+    const int64_t n_codes = 2 * (int64_t)n_pairs * W;
+    hipLaunchKernelGGL(sel_zero_u64_kernel, dim3((int)((n_codes + kThreads - 1) / kThreads < 4096 ? (n_codes + kThreads - 1) / kThreads : 4096)),
+                       dim3(kThreads), 0, stream, codes, n_codes);
+    const int nb = (N + kThreads - 1) / kThreads;
+    const int nbw = (N * W + kThreads - 1) / kThreads;
+    const int n_patches = 2 * n_pairs;
+    const int ub = (n_patches + kThreads / kWave - 1) / (kThreads / kWave);
+    for (int32_t k = 0; k < n_bits; ++k) {
+        const int32_t* smp = samples + (int64_t)k * N;
+        const bd_box_pair* ck = cands + (int64_t)k * n_cands;
+        hipLaunchKernelGGL(sel_gather_codes_kernel, dim3(nbw), dim3(kThreads), 0, stream, codes, W, smp, N, n_pairs,
+                           ac, pc);
+        launch_knn(kp, ac, pc, idx_ap, dist_ap, knn_ws, stream);
+        launch_knn(kp, pc, ac, idx_pa, dist_pa, knn_ws, stream);
+        hipLaunchKernelGGL(sel_hnm_kernel, dim3(nb), dim3(kThreads), 0, stream, idx_ap, dist_ap, idx_pa, dist_pa,
+                           ac, pc, N, W, k, smp, n_pairs, patch_index, s_ap, s_an);
+        launch_find_threshold(pool, patch_index, N, s_ap, s_an, tau2, ck, n_cands, bins, nullptr, losses, thr_ws,
+                              num_cus, stream);
+        hipLaunchKernelGGL(sel_best_kernel, dim3(1), dim3(1024), 0, stream, bins, losses, n_cands, ck, k, table,
+                           chosen, chosen_bin, round_loss, state);
+        hipLaunchKernelGGL(sel_update_kernel, dim3(ub), dim3(kThreads), 0, stream, pool, n_patches, ck, state, codes,
+                           W, k);
+    }
+    if (pool_codes_out)
+        (void)hipMemcpyAsync(pool_codes_out, codes, sizeof(uint64_t) * (size_t)n_codes, hipMemcpyDeviceToDevice,
+                             stream);
+}
 
 size_t select_workspace(int32_t n_cands) { return 256 + sizeof(int32_t) * (size_t)kBins * (size_t)n_cands; }
 
-void launch_find_threshold(const uint8_t* patches, int32_t n, const int32_t* s_ap, const int32_t* s_an, int tau2,
-                           const bd_box_pair* cands, int32_t n_cands, int32_t* best_bin, float* best_theta,
-                           double* best_loss, void* workspace, int num_cus, hipStream_t stream)
+void launch_find_threshold(const uint8_t* patches, const int32_t* patch_index, int32_t n, const int32_t* s_ap,
+                           const int32_t* s_an, int tau2, const bd_box_pair* cands, int32_t n_cands,
+                           int32_t* best_bin, float* best_theta, double* best_loss, void* workspace, int num_cus,
+                           hipStream_t stream)
 {
     int64_t* base2 = static_cast<int64_t*>(workspace);
     int32_t* hist = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 256);
@@ -260,8 +473,8 @@ void launch_find_threshold(const uint8_t* patches, int32_t n, const int32_t* s_a
         // three blocks per CU of an XCD's 32 CUs, at most one per tile
         const int per_xcd_cap = 3 * (num_cus > 0 ? num_cus : 256) / kXcds;
         const int per_xcd = n_tiles < per_xcd_cap ? n_tiles : per_xcd_cap;
-        hipLaunchKernelGGL(select_hist_kernel, dim3(kXcds * per_xcd), dim3(kThreads), 0, stream, patches, n, s_ap,
-                           s_an, tau2, cands, n_cands, hist);
+        hipLaunchKernelGGL(select_hist_kernel, dim3(kXcds * per_xcd), dim3(kThreads), 0, stream, patches,
+                           patch_index, n, s_ap, s_an, tau2, cands, n_cands, hist);
     }
     hipLaunchKernelGGL(select_scan_kernel, dim3(n_cands), dim3(1024), 0, stream, hist, base2, best_bin, best_theta,
                        best_loss);

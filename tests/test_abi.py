@@ -213,3 +213,16 @@ def test_find_threshold_validation(L):
     assert L.bd_find_threshold(None, None, 10, p, p, 0.5, p, 4, p, None, None, None) == bd.BD_EINVAL
     assert L.bd_find_threshold(None, p, 10, p, p, 1.5, p, 4, p, None, None, None) == bd.BD_EINVAL
     assert "null context" in err(L)
+
+
+def test_select_features_validation(L):
+    p = ctypes.c_void_p(16)
+    call = lambda **kw: L.bd_select_features(None, p, kw.get("P", 100), p, kw.get("N", 50), p, kw.get("J", 10),
+                                             kw.get("K", 64), kw.get("tau", 1.0), p, None, None, None, None, None)
+    assert call(K=0) == bd.BD_EUNSUPPORTED
+    assert call(K=513) == bd.BD_EUNSUPPORTED
+    assert call(N=1) == bd.BD_EINVAL
+    assert call(N=101) == bd.BD_EINVAL
+    assert call(J=0) == bd.BD_EINVAL
+    assert call(tau=0.7) == bd.BD_EINVAL
+    assert call() == bd.BD_EINVAL and "null context" in err(L)
