@@ -64,6 +64,8 @@ def lib():
         L.bdref_hnm_codes.restype = None
         L.bdref_select_features.argtypes = [P, i32, P, i32, P, i32, i32, ctypes.c_double, P, P, P, P, P]
         L.bdref_select_features.restype = None
+        L.bdref_augment_patches.argtypes = [P, i32, P, P, P]
+        L.bdref_augment_patches.restype = None
         L.bdref_round_bf16.argtypes = [ctypes.c_float]
         L.bdref_round_bf16.restype = ctypes.c_float
         L.bdref_round_e4m3.argtypes = [ctypes.c_float]
@@ -342,3 +344,58 @@ def select_features(pool: np.ndarray, samples: np.ndarray, cands: np.ndarray, ta
     lib().bdref_select_features(_ptr(pl), n_pairs, _ptr(smp), N, _ptr(c), J, K, float(tau), _ptr(table),
                                 _ptr(chosen), _ptr(chosen_bin), _ptr(loss), _ptr(codes))
     return table, chosen, chosen_bin, loss, codes
+
+
+# ---------------------------------------------------------------- HashSIFT training (Sec. III-B)
+
+
+def augment_patches(src: np.ndarray, params: np.ndarray, noise: np.ndarray) -> np.ndarray:
+    """Rotation/scale, blur, illumination and noise of (n, 32, 32) float patches;
+    params (n, 5) = (angle, scale, gain, bias, sigma), noise (n, 32, 32)."""
+    sp = np.ascontiguousarray(src, dtype=np.float32).reshape(-1, 1024)
+    n = sp.shape[0]
+    pr = np.ascontiguousarray(params, dtype=np.float64).reshape(n, 5)
+    nz = np.ascontiguousarray(noise, dtype=np.float32).reshape(n, 1024)
+    out = np.empty((n, 1024), dtype=np.float32)
+    lib().bdref_augment_patches(_ptr(sp), n, _ptr(pr), _ptr(nz), _ptr(out))
+    return out.reshape(n, 32, 32)
+
+
+def adam_step(param, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8):
+    """One Adam update (Kingma and Ba) of FP64 arrays, in place; step counts from 1."""
+    m *= beta1
+    m += (1.0 - beta1) * grad
+    v *= beta2
+    v += (1.0 - beta2) * grad * grad
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    param -= lr * m_hat / (np.sqrt(v_hat) + eps)
+
+
+def hashsift_train_step(pool, batch, params, noise, B, t, state, lr=2e-4, tau=0.5, beta=1.0,
+                        beta1=0.9, beta2=0.999, eps=1e-8):
+    """One training iteration of the HashSIFT projection (Sec. III-B, Eq. 4):
+    pair s of the batch is pool pair batch[s] (anchor 2 batch[s], positive
+    2 batch[s] + 1), augmented with params / noise rows 2s (anchor) and 2s + 1
+    (positive); relaxed descriptors tanh(beta (B f - t)); triplet loss with
+    in-batch hardest negatives and anchor swap; Adam on B and t.  B, t and
+    state = {"mB", "vB", "mt", "vt", "step"} are updated in place.  Returns
+    (loss, gB, gt)."""
+    pool = np.asarray(pool).reshape(-1, 32, 32)
+    idx = np.asarray(batch, dtype=np.int64)
+    n = len(idx)
+    src = np.empty((2 * n, 32, 32), dtype=np.float32)
+    src[0::2], src[1::2] = pool[2 * idx], pool[2 * idx + 1]
+    aug = augment_patches(src, params, noise)
+    fa, fp = hashsift_patch_features(aug[0::2]), hashsift_patch_features(aug[1::2])
+    _, Da = relaxed_hashsift(fa, B, t, beta)
+    _, Dp = relaxed_hashsift(fp, B, t, beta)
+    loss, _, gA, gP = trl_hnm(Da, Dp, tau)
+    gBa, gta = relaxed_hashsift_grad(gA, Da, fa, beta)
+    gBp, gtp = relaxed_hashsift_grad(gP, Dp, fp, beta)
+    gB, gt = gBa + gBp, gta + gtp
+    state["step"] += 1
+    adam_step(B, gB, state["mB"], state["vB"], state["step"], lr, beta1, beta2, eps)
+    adam_step(t, gt, state["mt"], state["vt"], state["step"], lr, beta1, beta2, eps)
+    return loss, gB, gt

@@ -758,3 +758,62 @@ void bdref_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t* 
     free(bins);
     free(losses);
 }
+
+/* ------------------------------------------------------------------ training augmentation */
+
+static double patch_at(const float* p, int x, int y)
+{
+    x = clampi(x, 0, 31);
+    y = clampi(y, 0, 31);
+    return (double)p[y * 32 + x];
+}
+
+void bdref_augment_patches(const float* src, int32_t n, const double* params, const float* noise, float* dst)
+{
+    double warp[1024], tmp[1024];
+    for (int32_t k = 0; k < n; ++k) {
+        const float* s = src + (int64_t)k * 1024;
+        const double* pr = params + (int64_t)k * 5;
+        const double ca = cos(pr[0]), sa = sin(pr[0]), sc = pr[1];
+        /* 1. rotation and scale about the patch centre, bilinear */
+        for (int i = 0; i < 32; ++i)
+            for (int j = 0; j < 32; ++j) {
+                const double ux = j - 15.5, uy = i - 15.5;
+                const double px = 15.5 + sc * (ca * ux - sa * uy);
+                const double py = 15.5 + sc * (sa * ux + ca * uy);
+                const double x0 = floor(px), y0 = floor(py);
+                const double fx = px - x0, fy = py - y0;
+                const int xi = (int)x0, yi = (int)y0;
+                const double top = patch_at(s, xi, yi) + fx * (patch_at(s, xi + 1, yi) - patch_at(s, xi, yi));
+                const double bot =
+                    patch_at(s, xi, yi + 1) + fx * (patch_at(s, xi + 1, yi + 1) - patch_at(s, xi, yi + 1));
+                warp[i * 32 + j] = top + fy * (bot - top);
+            }
+        /* 2. separable Gaussian blur */
+        const double sigma = pr[4];
+        if (sigma > 0.0) {
+            const int R = (int)ceil(3.0 * sigma);
+            double w[64], wsum = 0.0;
+            for (int d = -R; d <= R; ++d) wsum += (w[d + R] = exp(-(double)(d * d) / (2.0 * sigma * sigma)));
+            for (int d = 0; d <= 2 * R; ++d) w[d] /= wsum;
+            for (int i = 0; i < 32; ++i)
+                for (int j = 0; j < 32; ++j) {
+                    double acc = 0.0;
+                    for (int d = -R; d <= R; ++d) acc += w[d + R] * warp[i * 32 + clampi(j + d, 0, 31)];
+                    tmp[i * 32 + j] = acc;
+                }
+            for (int i = 0; i < 32; ++i)
+                for (int j = 0; j < 32; ++j) {
+                    double acc = 0.0;
+                    for (int d = -R; d <= R; ++d) acc += w[d + R] * tmp[clampi(i + d, 0, 31) * 32 + j];
+                    warp[i * 32 + j] = acc;
+                }
+        }
+        /* 3-5. illumination, noise, clipping */
+        for (int e = 0; e < 1024; ++e) {
+            double v = pr[2] * warp[e] + pr[3] + (double)noise[(int64_t)k * 1024 + e];
+            v = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+            dst[(int64_t)k * 1024 + e] = (float)v;
+        }
+    }
+}

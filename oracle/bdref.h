@@ -191,6 +191,19 @@ void bdref_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t* 
                            bdref_box_pair* table, int32_t* chosen, int32_t* chosen_bin, double* round_loss,
                            uint64_t* pool_codes);
 
+/* Data augmentation of 32x32 float patches for HashSIFT training (Sec.
+ * III-B: small random rotation, scale, illumination change, blurring and
+ * pixel Gaussian noise; the random draws are inputs).  params: n x 5
+ * (angle, scale, gain, bias, sigma) per patch.  Output pixel (i, j) takes
+ *   1. the bilinear sample (clamp-to-edge) of the source at
+ *      (15.5, 15.5) + scale * Rot(angle) (j - 15.5, i - 15.5),
+ *   2. a separable Gaussian blur of standard deviation sigma (weights
+ *      exp(-d^2 / (2 sigma^2)) for |d| <= ceil(3 sigma), normalised,
+ *      clamp-to-edge; none when sigma <= 0),
+ *   3. gain * v + bias, 4. + noise[i][j], 5. clipped to [0, 1].
+ * FP64 throughout, result rounded to float. */
+void bdref_augment_patches(const float* src, int32_t n, const double* params, const float* noise, float* dst);
+
 #ifdef __cplusplus
 }
 #endif
