@@ -336,6 +336,45 @@ def greedy_selection(dev, P=16384, N=8192, J=1000, K=256):
             "loss_first_round": float(loss[0]), "loss_last_round": float(loss[-1])}
 
 
+def hashsift_training(dev, P=16384, n=8192, K=512, iters=50):
+    """HashSIFT training (Sec. III-B): Adam (lr 2e-4) on a 512 x 128 projection
+    from N(0, 0.25), batches of 8192 augmented pairs (the differentiation
+    workload's batch size) with in-batch hardest negatives; time per
+    iteration (augment, features, relaxed descriptors, loss, backward,
+    update) and the loss trend."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+    from paper_2108_08380_amd import synth
+
+    b = synth.triplets(synth.SEED_BASE + 6, n=P)
+    pool = np.empty((2 * P, 32, 32), np.float32)
+    pool[0::2], pool[1::2] = b.anchor, b.positive
+    pool = torch.from_numpy(pool).to(dev)
+    rng = np.random.default_rng(12)
+    batches, params, noise = [], [], []
+    for _ in range(4):  # a few pre-drawn batches, reused in turn
+        batches.append(torch.from_numpy(rng.permutation(P)[:n].astype(np.int32)).to(dev))
+        params.append(torch.from_numpy(np.stack([rng.uniform(-0.17, 0.17, 2 * n), rng.uniform(0.9, 1.1, 2 * n),
+                                                 rng.uniform(0.8, 1.2, 2 * n), rng.uniform(-0.1, 0.1, 2 * n),
+                                                 rng.uniform(0.0, 1.0, 2 * n)], axis=1).astype(np.float32)).to(dev))
+        noise.append(torch.from_numpy(rng.normal(0, 0.02, (2 * n, 32, 32)).astype(np.float32)).to(dev))
+    tr = bd.HashSIFTTrainer(K, dev, seed=1)
+    first = float(tr.train_step(pool, batches[0], params[0], noise[0]).cpu()[0])
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for it in range(iters):
+        j = it % 4
+        loss = tr.train_step(pool, batches[j], params[j], noise[j])
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / iters
+    return {"batch_pairs": n, "n_bits": K, "iterations": iters + 1, "ms_per_iteration": round(ms, 3),
+            "pairs_per_s": round(n / (ms * 1e-3), 1), "loss_first": round(first, 5),
+            "loss_last": round(float(loss.cpu()[0]), 5)}
+
+
 def batched_step(dev, reps=5):
     """The batching extension on its full workload: 64 u8 scenes of
     320x240 .. 4000x3000 pixels with 500 .. 20000 keypoints, each with its
@@ -557,6 +596,7 @@ def main():
         result["precision_projection_200k"] = precision_projection(wl)
         result["threshold_search_alg2"] = threshold_search(dev)
         result["greedy_selection_alg1"] = greedy_selection(dev)
+        result["hashsift_training"] = hashsift_training(dev)
         result["differentiation_8192_triplets"] = differentiation_step(dev)
         if not args.no_batched:
             result["batched_64_scenes"] = batched_step(dev)

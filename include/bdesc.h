@@ -395,6 +395,38 @@ int bd_batch_set_tuning(bd_batch* b, const bd_batch_tuning* t);
 /* Total keypoints and total match rows of the batch (either pointer may be NULL). */
 int bd_batch_info(const bd_batch* b, int64_t* total_kp, int32_t* match_rows);
 
+/* ------------------------------------------------------------------------
+ * HashSIFT training (Sec. III-B, Eq. 4): Adam on B and t for the relaxed
+ * descriptors tanh(beta (B f - t)) under the triplet ranking loss with
+ * in-batch hardest negatives and anchor swap (bd_trl_hnm_fwd), every patch
+ * augmented.  pool: 2 n_pairs float32 32x32 patches, pair i = (anchor 2i,
+ * positive 2i+1); batch: n pair indices (clamped into range).
+ * ---------------------------------------------------------------------- */
+
+/* Augmentation of the batch's 2n patches into out (2n x 1024 floats: the n
+ * anchors, then the n positives).  params and noise rows 2s (anchor of pair
+ * s) and 2s+1 (its positive): params = (angle, scale, gain, bias, sigma),
+ * noise = 1024 floats.  Output pixel (i, j): the bilinear sample
+ * (clamp-to-edge) at (15.5, 15.5) + scale Rot(angle) (j - 15.5, i - 15.5),
+ * blurred by a separable Gaussian of standard deviation sigma (clamped to
+ * 4; weights exp(-d^2 / 2 sigma^2), |d| <= ceil(3 sigma), clamp-to-edge;
+ * none for sigma <= 0), then gain v + bias + noise, clipped to [0, 1]. */
+int bd_augment_patches(bd_context* ctx, const float* pool, int32_t n_pairs, const int32_t* batch, int32_t n,
+                       const float* params, const float* noise, float* out, void* stream);
+
+/* One training iteration: augment (as bd_augment_patches), HashSIFT
+ * features of the 2n patches, relaxed descriptors, hardest-negative triplet
+ * loss (*loss, device) with margin tau, its gradient with respect to B
+ * (n_bits x 128) and t (n_bits), and one Adam step (beta1 0.9, beta2 0.999,
+ * eps 1e-8, learning rate lr, bias correction for `step`, counted from 1)
+ * applied to B and t in place.  adam_state: 2 n_bits 128 + 2 n_bits floats
+ * (first and second moments of B, then of t), zero before step 1.  n_bits 256
+ * or 512; n >= 2.  Uses the context workspace. */
+int bd_hashsift_train_step(bd_context* ctx, const float* pool, int32_t n_pairs, const int32_t* batch, int32_t n,
+                           const float* params, const float* noise, float* B, float* t, int32_t n_bits,
+                           float* adam_state, int32_t step, float lr, float tau, float beta, float* loss,
+                           void* stream);
+
 #ifdef __cplusplus
 }
 #endif

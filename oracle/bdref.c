@@ -790,7 +790,7 @@ void bdref_augment_patches(const float* src, int32_t n, const double* params, co
                 warp[i * 32 + j] = top + fy * (bot - top);
             }
         /* 2. separable Gaussian blur */
-        const double sigma = pr[4];
+        const double sigma = pr[4] > 4.0 ? 4.0 : pr[4];
         if (sigma > 0.0) {
             const int R = (int)ceil(3.0 * sigma);
             double w[64], wsum = 0.0;

@@ -197,7 +197,7 @@ void bdref_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t* 
  * (angle, scale, gain, bias, sigma) per patch.  Output pixel (i, j) takes
  *   1. the bilinear sample (clamp-to-edge) of the source at
  *      (15.5, 15.5) + scale * Rot(angle) (j - 15.5, i - 15.5),
- *   2. a separable Gaussian blur of standard deviation sigma (weights
+ *   2. a separable Gaussian blur of standard deviation sigma (at most 4; weights
  *      exp(-d^2 / (2 sigma^2)) for |d| <= ceil(3 sigma), normalised,
  *      clamp-to-edge; none when sigma <= 0),
  *   3. gain * v + bias, 4. + noise[i][j], 5. clipped to [0, 1].

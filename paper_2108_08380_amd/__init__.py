@@ -58,6 +58,9 @@ SIGNATURES = {
     "bd_relaxed_hashsift_bwd": ([_P, _P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P], ctypes.c_int),
     "bd_trl_hnm_fwd": ([_P, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_trl_hnm_bwd": ([_P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "bd_augment_patches": ([_P, _P, _I32, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
+    "bd_hashsift_train_step": ([_P, _P, _I32, _P, _I32, _P, _P, _P, _P, _I32, _P, _I32, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, _P, _P], ctypes.c_int),
     "bd_batch_create": ([_P, _P, _I32, _P, _I32, _I32, _I32, _I32, ctypes.c_float, _I32,
                          ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "bd_batch_destroy": ([_P], ctypes.c_int),
@@ -720,3 +723,71 @@ def default_batch_tuning() -> dict:
     tn = BatchTuning()
     _check(lib().bd_batch_default_tuning(ctypes.byref(tn)))
     return tn.as_dict()
+
+
+# --------------------------------------------------------------------------- HashSIFT training
+
+
+def _pool_pairs(pool):
+    torch = _torch()
+    if pool.dtype != torch.float32 or not pool.is_contiguous() or pool.numel() % 2048 != 0:
+        raise ValueError("pool must be a contiguous (2P, 32, 32) float32 tensor")
+    return pool.numel() // 2048
+
+
+def augment_patches(pool, batch, params, noise, out=None):
+    """(2n, 32, 32) augmented patches of the batch's pairs (bd_augment_patches):
+    anchors first, then positives; params (2n, 5), noise (2n, 32, 32) float32."""
+    torch = _torch()
+    n_pairs = _pool_pairs(pool)
+    n = batch.shape[0]
+    if batch.dtype != torch.int32 or not batch.is_contiguous():
+        raise ValueError("batch must be a contiguous int32 tensor")
+    _f32_contig(params, "params", (2 * n, 5))
+    _f32_contig(noise, "noise")
+    if noise.numel() != 2 * n * 1024:
+        raise ValueError("noise must hold 2n x 1024 floats")
+    if out is None:
+        out = torch.empty((2 * n, 32, 32), dtype=torch.float32, device=pool.device)
+    d, stream = _device_and_stream(pool, batch, params, noise, out)
+    _check(lib().bd_augment_patches(context(d), pool.data_ptr(), n_pairs, batch.data_ptr(), n, params.data_ptr(),
+                                    noise.data_ptr(), out.data_ptr(), stream))
+    return out
+
+
+class HashSIFTTrainer:
+    """Adam training of the HashSIFT projection (Sec. III-B) through
+    bd_hashsift_train_step.  B (K, 128) starts from N(0, 0.25) unless given,
+    t from zeros; lr 2e-4 as in the paper."""
+
+    def __init__(self, n_bits: int = 512, device="cuda", B=None, t=None, lr: float = 2e-4, tau: float = 0.5,
+                 beta: float = 1.0, seed: int = 0):
+        torch = _torch()
+        dev = torch.device(device)
+        if B is None:
+            g = torch.Generator().manual_seed(seed)
+            B = torch.randn((n_bits, 128), generator=g, dtype=torch.float32) * 0.5  # variance 0.25
+        self.B = B.to(dev).contiguous()
+        self.t = (torch.zeros(n_bits) if t is None else t).to(dev, torch.float32).contiguous()
+        self.state = torch.zeros(2 * n_bits * 128 + 2 * n_bits, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.n_bits, self.lr, self.tau, self.beta, self.step = n_bits, lr, tau, beta, 0
+
+    def train_step(self, pool, batch, params, noise):
+        """One iteration on the batch; returns the loss as a (1,) device tensor."""
+        torch = _torch()
+        n_pairs = _pool_pairs(pool)
+        n = batch.shape[0]
+        if batch.dtype != torch.int32 or not batch.is_contiguous():
+            raise ValueError("batch must be a contiguous int32 tensor")
+        _f32_contig(params, "params", (2 * n, 5))
+        _f32_contig(noise, "noise")
+        if noise.numel() != 2 * n * 1024:
+            raise ValueError("noise must hold 2n x 1024 floats")
+        self.step += 1
+        d, stream = _device_and_stream(pool, batch, params, noise, self.B)
+        _check(lib().bd_hashsift_train_step(context(d), pool.data_ptr(), n_pairs, batch.data_ptr(), n,
+                                            params.data_ptr(), noise.data_ptr(), self.B.data_ptr(),
+                                            self.t.data_ptr(), self.n_bits, self.state.data_ptr(), self.step,
+                                            self.lr, self.tau, self.beta, self.loss.data_ptr(), stream))
+        return self.loss

@@ -198,6 +198,14 @@ void launch_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t*
                             bd_box_pair* table, int32_t* chosen, int32_t* chosen_bin, double* round_loss,
                             uint64_t* pool_codes_out, void* workspace, int num_cus, hipStream_t stream);
 
+// ---- HashSIFT training (train.hip)
+size_t train_step_workspace(int32_t n, int32_t n_bits);
+void launch_train_step(const float* pool, int32_t n_pairs, const int32_t* batch, int32_t n, const float* params,
+                       const float* noise, float* B, float* t, int32_t n_bits, float* adam_state, int32_t step,
+                       float lr, float tau, float beta, float* loss, void* workspace, hipStream_t stream);
+void launch_augment(const float* pool, int32_t n_pairs, const int32_t* batch, int32_t n, const float* params,
+                    const float* noise, float* out, hipStream_t stream);
+
 // Batched k-NN over BatchMatch problems sharing n_words (4 or 8) and k.
 struct KnnBatchPlan {
     int32_t n_words, k;

@@ -466,4 +466,38 @@ int bd_trl_hnm_bwd(bd_context* ctx, const float* A, const float* P, int32_t n, i
     return check_launch(fn);
 }
 
+int bd_augment_patches(bd_context* ctx, const float* pool, int32_t n_pairs, const int32_t* batch, int32_t n,
+                       const float* params, const float* noise, float* out, void* stream)
+{
+    const char* fn = "bd_augment_patches";
+    if (n_pairs < 1 || n < 1) return fail(BD_EINVAL, "%s: need n_pairs >= 1 and n >= 1", fn);
+    if (!pool || !batch || !params || !noise || !out) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    launch_augment(pool, n_pairs, batch, n, params, noise, out, static_cast<hipStream_t>(stream));
+    return check_launch(fn);
+}
+
+int bd_hashsift_train_step(bd_context* ctx, const float* pool, int32_t n_pairs, const int32_t* batch, int32_t n,
+                           const float* params, const float* noise, float* B, float* t, int32_t n_bits,
+                           float* adam_state, int32_t step, float lr, float tau, float beta, float* loss,
+                           void* stream)
+{
+    const char* fn = "bd_hashsift_train_step";
+    if (n_bits != 256 && n_bits != 512) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (256 or 512)", fn, n_bits);
+    if (n_pairs < 2 || n < 2) return fail(BD_EINVAL, "%s: need n_pairs >= 2 and n >= 2", fn);
+    if (n > (1 << 20)) return fail(BD_EINVAL, "%s: batch of %d pairs exceeds 2^20", fn, n);
+    if (step < 1) return fail(BD_EINVAL, "%s: step %d (counts from 1)", fn, step);
+    if (!(lr > 0.0f) || lr > 1e30f || !(beta > 0.0f) || beta > 1e30f || !(tau == tau) || fabsf(tau) > 1e30f)
+        return fail(BD_EINVAL, "%s: lr and beta must be finite and > 0, tau finite", fn);
+    if (!pool || !batch || !params || !noise || !B || !t || !adam_state || !loss)
+        return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, train_step_workspace(n, n_bits), s, &ws)) return rc;
+    launch_train_step(pool, n_pairs, batch, n, params, noise, B, t, n_bits, adam_state, step, lr, tau, beta, loss,
+                      ws, s);
+    return check_launch(fn);
+}
+
 }  // extern "C"

@@ -226,3 +226,21 @@ def test_select_features_validation(L):
     assert call(J=0) == bd.BD_EINVAL
     assert call(tau=0.7) == bd.BD_EINVAL
     assert call() == bd.BD_EINVAL and "null context" in err(L)
+
+
+def test_training_validation(L):
+    p = ctypes.c_void_p(16)
+    assert L.bd_augment_patches(None, p, 0, p, 4, p, p, p, None) == bd.BD_EINVAL
+    assert L.bd_augment_patches(None, p, 10, None, 4, p, p, p, None) == bd.BD_EINVAL
+    assert L.bd_augment_patches(None, p, 10, p, 4, p, p, p, None) == bd.BD_EINVAL and "null context" in err(L)
+
+    def step(**kw):
+        return L.bd_hashsift_train_step(None, p, kw.get("P", 10), p, kw.get("n", 4), p, p, p, p, kw.get("K", 256), p,
+                                        kw.get("step", 1), kw.get("lr", 2e-4), kw.get("tau", 0.5),
+                                        kw.get("beta", 1.0), p, None)
+    assert step(K=128) == bd.BD_EUNSUPPORTED
+    assert step(n=1) == bd.BD_EINVAL
+    assert step(step=0) == bd.BD_EINVAL
+    assert step(lr=0.0) == bd.BD_EINVAL
+    assert step(beta=float("inf")) == bd.BD_EINVAL
+    assert step() == bd.BD_EINVAL and "null context" in err(L)

@@ -187,7 +187,7 @@ def test_full_batch_8192_triplets(dev):
             p.grad = None
         loss = ag.bad_triplet_loss(an, po, w1, w2, th, pairs, BETA, TAU)
         loss.backward()
-        grads.append([to_np(p.grad) for p in (w1, w2, th)] + [float(loss)])
+        grads.append([to_np(p.grad) for p in (w1, w2, th)] + [float(loss.detach())])
     for a, c in zip(grads[0], grads[1]):
         np.testing.assert_array_equal(a, c)
     # sampled check of the hardest negatives against FP64 similarities
