@@ -661,8 +661,9 @@ void bdref_hnm_codes(const uint64_t* a_codes, const uint64_t* p_codes, int32_t n
         const uint64_t* ps = p_codes + (int64_t)s * n_words;
         int32_t jr = -1, jc = -1;
         uint32_t dr = 0, dc = 0;
-        for (int32_t j = 0; j < n; ++j) {
-            if (j == s) continue;
+        /* candidates in cyclic order from s + 1: equal distances keep the first */
+        for (int32_t step = 1; step < n; ++step) {
+            const int32_t j = (s + step) % n;
             const uint32_t d1 = hamming(as, p_codes + (int64_t)j * n_words, n_words);
             if (jr < 0 || d1 < dr) {
                 jr = j;

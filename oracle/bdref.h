@@ -166,8 +166,9 @@ void bdref_find_threshold(const uint8_t* patches, int32_t n_triplets, const int3
 /* In-batch hardest negatives with anchor swap for n (anchor, positive) code
  * pairs of n_words words: for pair s the row candidate is the positive p_j
  * (j != s) nearest to a_s and the column candidate the anchor a_j (j != s)
- * nearest to p_s (Hamming distance, ties: lowest j).  The row candidate wins
- * ties between the two.  neg[s] = j for a row candidate, -1 - j for a column
+ * nearest to p_s (Hamming distance; among equal distances the first j in the
+ * cyclic order s+1, s+2, ..., s-1 mod n).  The row candidate wins ties
+ * between the two.  neg[s] = j for a row candidate, -1 - j for a column
  * candidate; dist_neg[s] = its distance, dist_pos[s] = d(a_s, p_s).  n >= 2. */
 void bdref_hnm_codes(const uint64_t* a_codes, const uint64_t* p_codes, int32_t n, int32_t n_words, int32_t* neg,
                      int32_t* dist_neg, int32_t* dist_pos);

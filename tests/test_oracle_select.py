@@ -145,9 +145,10 @@ def hnm_by_matrix(a, p):
     Dpa = hamming_matrix(p, a)  # column candidates: d(p_s, a_j)
     neg, dn = [], []
     for s in range(n):
-        r = np.where(np.arange(n) == s, 10**9, Dap[s])
-        c = np.where(np.arange(n) == s, 10**9, Dpa[s])
-        jr, jc = int(np.argmin(r)), int(np.argmin(c))
+        order = (s + 1 + np.arange(n - 1)) % n  # cyclic from s + 1: argmin keeps the first
+        r, c = Dap[s][order], Dpa[s][order]
+        jr, jc = int(order[np.argmin(r)]), int(order[np.argmin(c)])
+        r, c = Dap[s], Dpa[s]
         if r[jr] <= c[jc]:
             neg.append(jr)
             dn.append(r[jr])
@@ -170,10 +171,10 @@ def test_hardest_negatives_by_distance_matrix(ref):
         np.testing.assert_array_equal(neg, en)
         np.testing.assert_array_equal(dn, ed)
         np.testing.assert_array_equal(dp, ep)
-    # all codes equal (the first round: no bits yet): the row candidate with the lowest index
+    # all codes equal (the first round: no bits yet): the next pair's positive
     z = np.zeros((5, 1), dtype=np.uint64)
     neg, dn, _ = ref.hnm_codes(z, z)
-    np.testing.assert_array_equal(neg, [1, 0, 0, 0, 0])
+    np.testing.assert_array_equal(neg, [1, 2, 3, 4, 0])
     assert (dn == 0).all()
 
 
