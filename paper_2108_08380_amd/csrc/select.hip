@@ -271,15 +271,52 @@ __global__ __launch_bounds__(kThreads) void sel_gather_codes_kernel(const uint64
     pc[e] = pool_codes[(int64_t)(2 * i + 1) * W + w];
 }
 
-// Hardest in-batch negative with anchor swap from the two 2-NN results
-// (a -> p and p -> a): the first neighbour other than s in each direction;
-// the row candidate (a positive) wins ties.  Writes the triplet's pool patch
-// indices and the similarities k - 2 d of (anchor, positive) and (anchor,
-// negative) under the k bits selected so far.
-__global__ __launch_bounds__(kThreads) void sel_hnm_kernel(const int32_t* __restrict__ idx_ap,
-                                                           const uint32_t* __restrict__ dist_ap,
-                                                           const int32_t* __restrict__ idx_pa,
-                                                           const uint32_t* __restrict__ dist_pa,
+__global__ __launch_bounds__(kThreads) void sel_fill_keys_kernel(uint32_t* __restrict__ keys, int32_t count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) keys[i] = 0xffffffffu;
+}
+
+// In-batch nearest other code with a cyclic tie-break.  Lane = query s
+// (codes in VGPRs), train rows j of this split wave-uniform (scalar loads);
+// the key (d << 22) | ((j - s - 1) mod n) orders candidates by distance, then
+// cyclically from s + 1, and j = s (rank n - 1) is skipped.  Per-split
+// minima meet through atomicMin, whose result does not depend on the order.
+// grid = (ceil(n / 256), splits), direction y: 0 = anchors vs positives,
+// 1 = positives vs anchors.
+template <int W>
+__global__ __launch_bounds__(kThreads) void sel_hnm_dist_kernel(const uint64_t* __restrict__ ac,
+                                                                const uint64_t* __restrict__ pc, int32_t n,
+                                                                int32_t rows_per_split, uint32_t* __restrict__ keys)
+{
+    const int dir = blockIdx.z;
+    const uint64_t* query = dir == 0 ? ac : pc;
+    const uint64_t* train = dir == 0 ? pc : ac;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j0 = blockIdx.y * rows_per_split;
+    const int j1 = min(n, j0 + rows_per_split);
+    if (blockIdx.x * blockDim.x >= (unsigned)n) return;
+    uint64_t q[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) q[w] = s < n ? query[(int64_t)s * W + w] : 0ull;
+    uint32_t best = 0xffffffffu;
+    for (int j = j0; j < j1; ++j) {
+        uint32_t d = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) d += __popcll(q[w] ^ train[(int64_t)j * W + w]);
+        int c = j - s - 1;
+        c += c < 0 ? n : 0;
+        const uint32_t key = (d << 22) | (uint32_t)c;
+        if (j != s) best = min(best, key);
+    }
+    if (s < n) atomicMin(&keys[dir * n + s], best);
+}
+
+// Hardest in-batch negative with anchor swap from the two nearest-other
+// keys: the row candidate (a positive) wins ties.  Writes the triplet's pool
+// patch indices and the similarities k - 2 d of (anchor, positive) and
+// (anchor, negative) under the k bits selected so far.
+__global__ __launch_bounds__(kThreads) void sel_hnm_kernel(const uint32_t* __restrict__ keys,
                                                            const uint64_t* __restrict__ ac,
                                                            const uint64_t* __restrict__ pc, int32_t n, int32_t W,
                                                            int32_t k, const int32_t* __restrict__ samples,
@@ -288,10 +325,11 @@ __global__ __launch_bounds__(kThreads) void sel_hnm_kernel(const int32_t* __rest
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const int slot_r = idx_ap[2 * s] == s ? 1 : 0;
-    const int slot_c = idx_pa[2 * s] == s ? 1 : 0;
-    const int jr = idx_ap[2 * s + slot_r], jc = idx_pa[2 * s + slot_c];
-    const uint32_t dr = dist_ap[2 * s + slot_r], dc = dist_pa[2 * s + slot_c];
+    const uint32_t kr = keys[s], kc = keys[n + s];
+    const uint32_t dr = kr >> 22, dc = kc >> 22;
+    int jr = s + 1 + (int)(kr & 0x3fffffu), jc = s + 1 + (int)(kc & 0x3fffffu);
+    jr -= jr >= n ? n : 0;
+    jc -= jc >= n ? n : 0;
     uint32_t dp = 0;
     for (int w = 0; w < W; ++w) dp += __popcll(ac[(int64_t)s * W + w] ^ pc[(int64_t)s * W + w]);
     const int i = sample_pair(samples, s, n_pairs);
@@ -387,13 +425,46 @@ size_t align_up256(size_t v) { return (v + 255) / 256 * 256; }
 
 }  // namespace
 
+template <int W>
+void launch_hnm_dist_w(const uint64_t* ac, const uint64_t* pc, int32_t n, int32_t rows, int32_t splits,
+                       uint32_t* keys, hipStream_t stream)
+{
+    hipLaunchKernelGGL((sel_hnm_dist_kernel<W>), dim3((n + kThreads - 1) / kThreads, splits, 2), dim3(kThreads), 0,
+                       stream, ac, pc, n, rows, keys);
+}
+
+void launch_hnm_dist(const uint64_t* ac, const uint64_t* pc, int32_t n, int32_t W, uint32_t* keys, int num_cus,
+                     hipStream_t stream)
+{
+    // splits of the train rows so that about 8 wavefronts per CU are busy
+    const int qblocks = (n + kThreads - 1) / kThreads;
+    const int want = 2 * (num_cus > 0 ? num_cus : 256);
+    int splits = (want + 2 * qblocks - 1) / (2 * qblocks);
+    const int max_splits = (n + 63) / 64;
+    splits = splits < 1 ? 1 : (splits > max_splits ? max_splits : splits);
+    const int rows = (n + splits - 1) / splits;
+    splits = (n + rows - 1) / rows;
+    hipLaunchKernelGGL(sel_fill_keys_kernel, dim3((2 * n + kThreads - 1) / kThreads), dim3(kThreads), 0, stream, keys,
+                       2 * n);
+    switch (W) {
+        case 1: launch_hnm_dist_w<1>(ac, pc, n, rows, splits, keys, stream); break;
+        case 2: launch_hnm_dist_w<2>(ac, pc, n, rows, splits, keys, stream); break;
+        case 3: launch_hnm_dist_w<3>(ac, pc, n, rows, splits, keys, stream); break;
+        case 4: launch_hnm_dist_w<4>(ac, pc, n, rows, splits, keys, stream); break;
+        case 5: launch_hnm_dist_w<5>(ac, pc, n, rows, splits, keys, stream); break;
+        case 6: launch_hnm_dist_w<6>(ac, pc, n, rows, splits, keys, stream); break;
+        case 7: launch_hnm_dist_w<7>(ac, pc, n, rows, splits, keys, stream); break;
+        default: launch_hnm_dist_w<8>(ac, pc, n, rows, splits, keys, stream); break;
+    }
+}
+
 size_t select_features_workspace(int32_t n_pairs, int32_t n_sample, int32_t n_cands, int32_t n_bits, int num_cus)
 {
+    (void)num_cus;
     const size_t W = (size_t)(n_bits + 63) / 64, N = (size_t)n_sample;
-    const KnnPlan kp = plan_knn(n_sample, n_sample, (int32_t)W, 2, num_cus);
     return align_up256(sizeof(uint64_t) * 2 * (size_t)n_pairs * W) + 2 * align_up256(sizeof(uint64_t) * N * W) +
-           4 * align_up256(sizeof(int32_t) * 2 * N) + align_up256(kp.workspace_bytes()) +
-           2 * align_up256(sizeof(int32_t) * N) + align_up256(sizeof(int32_t) * 3 * N) +
+           align_up256(sizeof(uint32_t) * 2 * N) + 2 * align_up256(sizeof(int32_t) * N) +
+           align_up256(sizeof(int32_t) * 3 * N) +
            align_up256(select_workspace(n_cands)) + align_up256(sizeof(int32_t) * n_cands) +
            align_up256(sizeof(double) * n_cands) + 256;
 }
@@ -413,12 +484,7 @@ void launch_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t*
     uint64_t* codes = static_cast<uint64_t*>(take(sizeof(uint64_t) * 2 * (size_t)n_pairs * W));
     uint64_t* ac = static_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)N * W));
     uint64_t* pc = static_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)N * W));
-    int32_t* idx_ap = static_cast<int32_t*>(take(sizeof(int32_t) * 2 * (size_t)N));
-    uint32_t* dist_ap = static_cast<uint32_t*>(take(sizeof(int32_t) * 2 * (size_t)N));
-    int32_t* idx_pa = static_cast<int32_t*>(take(sizeof(int32_t) * 2 * (size_t)N));
-    uint32_t* dist_pa = static_cast<uint32_t*>(take(sizeof(int32_t) * 2 * (size_t)N));
-    const KnnPlan kp = plan_knn(N, N, W, 2, num_cus);
-    void* knn_ws = take(kp.workspace_bytes());
+    uint32_t* keys = static_cast<uint32_t*>(take(sizeof(uint32_t) * 2 * (size_t)N));
     int32_t* s_ap = static_cast<int32_t*>(take(sizeof(int32_t) * (size_t)N));
     int32_t* s_an = static_cast<int32_t*>(take(sizeof(int32_t) * (size_t)N));
     int32_t* patch_index = static_cast<int32_t*>(take(sizeof(int32_t) * 3 * (size_t)N));
@@ -439,10 +505,9 @@ void launch_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t*
         const bd_box_pair* ck = cands + (int64_t)k * n_cands;
         hipLaunchKernelGGL(sel_gather_codes_kernel, dim3(nbw), dim3(kThreads), 0, stream, codes, W, smp, N, n_pairs,
                            ac, pc);
-        launch_knn(kp, ac, pc, idx_ap, dist_ap, knn_ws, stream);
-        launch_knn(kp, pc, ac, idx_pa, dist_pa, knn_ws, stream);
-        hipLaunchKernelGGL(sel_hnm_kernel, dim3(nb), dim3(kThreads), 0, stream, idx_ap, dist_ap, idx_pa, dist_pa,
-                           ac, pc, N, W, k, smp, n_pairs, patch_index, s_ap, s_an);
+        launch_hnm_dist(ac, pc, N, W, keys, num_cus, stream);
+        hipLaunchKernelGGL(sel_hnm_kernel, dim3(nb), dim3(kThreads), 0, stream, keys, ac, pc, N, W, k, smp, n_pairs,
+                           patch_index, s_ap, s_an);
         launch_find_threshold(pool, patch_index, N, s_ap, s_an, tau2, ck, n_cands, bins, nullptr, losses, thr_ws,
                               num_cus, stream);
         hipLaunchKernelGGL(sel_best_kernel, dim3(1), dim3(1024), 0, stream, bins, losses, n_cands, ck, k, table,
