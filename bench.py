@@ -47,6 +47,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-batched", action="store_true", help="skip the 128-image batched workload")
     p.add_argument("--batched-only", action="store_true", help="run only the batched workload and print its JSON")
+    p.add_argument("--step-only", action="store_true", help="only the step, its stage timings and the checks")
     p.add_argument("--only", default="", help="profile helper: run only this stage in the step loop")
     p.add_argument("--copy-calibration-mb", type=int, default=0,
                    help="run a plain device copy of this many MiB five times and exit (HBM counter calibration)")
@@ -93,10 +94,43 @@ class Workload:
             "match_hashsift512": lambda: bd.match_hamming_knn(s.hs[0], s.hs[1], K, s.idx[1], s.dist[1]),
         }
 
+    def describe(self, v):
+        import paper_2108_08380_amd as bd
+
+        s = self
+        bd.keypoint_order(s.kps[v], W, H, out=s.order[v])
+        bd.build_integral(s.u8[v], out=s.ii[v])
+        bd.describe_bad(s.ii[v], s.kps[v], s.pairs, out=s.bad[v], order=s.order[v])
+        bd.hashsift_features(s.f32[v], s.kps[v], out=s.hist[v], order=s.order[v])
+        bd.hashsift_project(s.hist[v], s.B, s.t, s.kps[v], out=s.hs[v])
+
     def step(self, only=""):
-        for name, fn in self.stages().items():
-            if not only or name == only:
-                fn()
+        """One step.  The two views are described on two streams (view 1 on a
+        side stream forked from the current one), then the two code types
+        are matched on the two streams; each stream has its own library
+        context.  Inside graph capture the fork becomes two graph branches."""
+        import torch
+
+        import paper_2108_08380_amd as bd
+
+        if only:
+            for name, fn in self.stages().items():
+                if name == only:
+                    fn()
+            return
+        cur = torch.cuda.current_stream()
+        if not hasattr(self, "side"):
+            self.side = torch.cuda.Stream()
+        self.side.wait_stream(cur)
+        with torch.cuda.stream(self.side):
+            self.describe(1)
+        self.describe(0)
+        cur.wait_stream(self.side)
+        self.side.wait_stream(cur)
+        with torch.cuda.stream(self.side):
+            bd.match_hamming_knn(self.hs[0], self.hs[1], K, self.idx[1], self.dist[1])
+        bd.match_hamming_knn(self.bad[0], self.bad[1], K, self.idx[0], self.dist[0])
+        cur.wait_stream(self.side)
 
 
 # algorithmic work per launch of each stage's main kernel (definitions in DESIGN.md)
@@ -591,7 +625,7 @@ def main():
         "checks": check,
         "roofline": roofline,
     }
-    if not args.only:
+    if not args.only and not args.step_only:
         result["mutual_nn_ratio0.8"] = mutual_matching(wl)
         result["precision_projection_200k"] = precision_projection(wl)
         result["threshold_search_alg2"] = threshold_search(dev)
@@ -600,7 +634,7 @@ def main():
         result["differentiation_8192_triplets"] = differentiation_step(dev)
         if not args.no_batched:
             result["batched_64_scenes"] = batched_step(dev)
-    if not args.no_cpu and not args.only:
+    if not args.no_cpu and not args.only and not args.step_only:
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(result))
 

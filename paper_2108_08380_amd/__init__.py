@@ -111,7 +111,7 @@ class BDError(RuntimeError):
 
 _lib = None
 _lock = threading.Lock()
-_contexts: dict[int, int] = {}
+_contexts: dict = {}
 
 
 def lib() -> ctypes.CDLL:
@@ -140,17 +140,20 @@ def _check(rc: int) -> None:
         raise BDError(rc, last_error())
 
 
-def context(device: int) -> int:
-    """The per-process library context of a device (created on first use)."""
-    ctx = _contexts.get(device)
+def context(device: int, stream=None) -> int:
+    """The library context of (device, stream), created on first use.  Each
+    stream gets its own context, hence its own workspace, so work enqueued on
+    different streams never shares scratch memory."""
+    key = (device, stream)
+    ctx = _contexts.get(key)
     if ctx is None:
         with _lock:
-            ctx = _contexts.get(device)
+            ctx = _contexts.get(key)
             if ctx is None:
                 out = ctypes.c_void_p()
                 _check(lib().bd_context_create(ctypes.byref(out), device))
                 ctx = out.value
-                _contexts[device] = ctx
+                _contexts[key] = ctx
     return ctx
 
 
@@ -217,7 +220,7 @@ def build_integral(img, out=None):
         out = torch.empty((H + 1, W + 1), dtype=torch.uint32, device=img.device)
     _require(out, torch.uint32, 2, "out")
     dev, stream = _device_and_stream(img, out)
-    _check(lib().bd_build_integral(context(dev), img.data_ptr(), W, H, img.stride(0), out.data_ptr(),
+    _check(lib().bd_build_integral(context(dev, stream), img.data_ptr(), W, H, img.stride(0), out.data_ptr(),
                                    out.stride(0), stream))
     return out
 
@@ -240,7 +243,7 @@ def keypoint_order(kps, width: int, height: int, out=None):
     if out is None:
         out = torch.empty((n,), dtype=torch.int32, device=kps.device)
     dev, stream = _device_and_stream(kps, out)
-    _check(lib().bd_keypoint_order(context(dev), kps.data_ptr(), n, width, height, out.data_ptr(), stream))
+    _check(lib().bd_keypoint_order(context(dev, stream), kps.data_ptr(), n, width, height, out.data_ptr(), stream))
     return out
 
 
@@ -262,7 +265,7 @@ def describe_bad(ii, kps, pairs, n_bits: int | None = None, out=None, order=None
         out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=ii.device)
     _contig(out, "out")
     dev, stream = _device_and_stream(ii, kps, pairs, out, order)
-    _check(lib().bd_describe_bad(context(dev), ii.data_ptr(), W, H, ii.stride(0), kps.data_ptr(), n,
+    _check(lib().bd_describe_bad(context(dev, stream), ii.data_ptr(), W, H, ii.stride(0), kps.data_ptr(), n,
                                  _order_arg(order, n), pairs.data_ptr(), n_bits, out.data_ptr(), stream))
     return out
 
@@ -292,7 +295,7 @@ def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool =
     hist = torch.empty((n, 128), dtype=torch.float32, device=img.device) if with_hist else None
     resp = torch.empty((n, n_bits), dtype=torch.float32, device=img.device) if with_resp else None
     dev, stream = _device_and_stream(img, kps, B, t, out, hist, resp, order, recheck_count)
-    _check(lib().bd_describe_hashsift(context(dev), img.data_ptr(), dtype, W, H, img.stride(0) * img.element_size(),
+    _check(lib().bd_describe_hashsift(context(dev, stream), img.data_ptr(), dtype, W, H, img.stride(0) * img.element_size(),
                                       kps.data_ptr(), n, _order_arg(order, n), B.data_ptr(), t.data_ptr(), n_bits,
                                       _PRECISIONS[precision], margin, out.data_ptr(),
                                       hist.data_ptr() if hist is not None else None,
@@ -334,7 +337,7 @@ def hashsift_features(img, kps, out=None, order=None):
         out = torch.empty((n, 128), dtype=torch.float32, device=img.device)
     _contig(out, "out")
     dev, stream = _device_and_stream(img, kps, out, order)
-    _check(lib().bd_hashsift_features(context(dev), img.data_ptr(), dtype, W, H, img.stride(0) * img.element_size(),
+    _check(lib().bd_hashsift_features(context(dev, stream), img.data_ptr(), dtype, W, H, img.stride(0) * img.element_size(),
                                       kps.data_ptr(), n, _order_arg(order, n), out.data_ptr(), stream))
     return out
 
@@ -359,7 +362,7 @@ def hashsift_project(hist, B, t, kps=None, precision: str = "fp32", with_resp: b
         out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=hist.device)
     resp = torch.empty((n, n_bits), dtype=torch.float32, device=hist.device) if with_resp else None
     dev, stream = _device_and_stream(hist, B, t, out, kps, resp, recheck_count)
-    _check(lib().bd_hashsift_project(context(dev), hist.data_ptr(), kps.data_ptr() if kps is not None else None, n,
+    _check(lib().bd_hashsift_project(context(dev, stream), hist.data_ptr(), kps.data_ptr() if kps is not None else None, n,
                                      B.data_ptr(), t.data_ptr(), n_bits, _PRECISIONS[precision], margin,
                                      out.data_ptr(), resp.data_ptr() if resp is not None else None,
                                      _counter_arg(recheck_count), stream))
@@ -381,7 +384,7 @@ def match_hamming_knn(query, train, k: int = 1, idx=None, dist=None):
     if dist is None:
         dist = torch.empty((n_q, k), dtype=torch.uint32, device=query.device)
     dev, stream = _device_and_stream(query, train, idx, dist)
-    _check(lib().bd_match_hamming_knn(context(dev), query.data_ptr(), n_q, train.data_ptr(), train.shape[0],
+    _check(lib().bd_match_hamming_knn(context(dev, stream), query.data_ptr(), n_q, train.data_ptr(), train.shape[0],
                                       n_words, k, idx.data_ptr(), dist.data_ptr(), stream))
     return idx, dist
 
@@ -403,7 +406,7 @@ def match_mutual(query, train, max_ratio: float = 0.0, with_ratio: bool = False,
     ratio = torch.empty((n_q,), dtype=torch.float32, device=query.device) if with_ratio else None
     count = torch.empty((1,), dtype=torch.int32, device=query.device) if with_count else None
     dev, stream = _device_and_stream(query, train)
-    _check(lib().bd_match_mutual(context(dev), query.data_ptr(), n_q, train.data_ptr(), train.shape[0], n_words,
+    _check(lib().bd_match_mutual(context(dev, stream), query.data_ptr(), n_q, train.data_ptr(), train.shape[0], n_words,
                                  max_ratio, match.data_ptr(), dist.data_ptr(),
                                  ratio.data_ptr() if ratio is not None else None,
                                  count.data_ptr() if count is not None else None, stream))
@@ -434,7 +437,7 @@ def find_threshold(patches, s_ap, s_an, tau: float, cands):
     best_theta = torch.empty((J,), dtype=torch.float32, device=dev)
     best_loss = torch.empty((J,), dtype=torch.float64, device=dev)
     d, stream = _device_and_stream(patches, s_ap, s_an, cands)
-    _check(lib().bd_find_threshold(context(d), patches.data_ptr(), n, s_ap.data_ptr(), s_an.data_ptr(), tau,
+    _check(lib().bd_find_threshold(context(d, stream), patches.data_ptr(), n, s_ap.data_ptr(), s_an.data_ptr(), tau,
                                    cands.data_ptr(), J, best_bin.data_ptr(), best_theta.data_ptr(),
                                    best_loss.data_ptr(), stream))
     return best_bin, best_theta, best_loss
@@ -464,7 +467,7 @@ def select_features(pool, samples, cands, tau: float = 1.0):
     loss = torch.empty((K,), dtype=torch.float64, device=dev)
     codes = torch.empty((2 * n_pairs, (K + 63) // 64), dtype=torch.uint64, device=dev)
     d, stream = _device_and_stream(pool, samples, cands)
-    _check(lib().bd_select_features(context(d), pool.data_ptr(), n_pairs, samples.data_ptr(), N, cands.data_ptr(),
+    _check(lib().bd_select_features(context(d, stream), pool.data_ptr(), n_pairs, samples.data_ptr(), N, cands.data_ptr(),
                                     J, K, tau, table.data_ptr(), chosen.data_ptr(), chosen_bin.data_ptr(),
                                     loss.data_ptr(), codes.data_ptr(), stream))
     return table, chosen, chosen_bin, loss, codes
@@ -492,7 +495,7 @@ def hashsift_patch_features(patches, out=None):
     if out is None:
         out = torch.empty((n, 128), dtype=torch.float32, device=patches.device)
     dev, stream = _device_and_stream(patches, out)
-    _check(lib().bd_hashsift_patch_features(context(dev), patches.data_ptr(), n, out.data_ptr(), stream))
+    _check(lib().bd_hashsift_patch_features(context(dev, stream), patches.data_ptr(), n, out.data_ptr(), stream))
     return out
 
 
@@ -506,7 +509,7 @@ def relaxed_bad_fwd(patches, pairs, w1, w2, theta, beta: float):
     D = torch.empty((n, K), dtype=torch.float32, device=patches.device)
     m1, m2 = torch.empty_like(D), torch.empty_like(D)
     dev, stream = _device_and_stream(patches, pairs, w1, w2, theta)
-    _check(lib().bd_relaxed_bad_fwd(context(dev), patches.data_ptr(), n, pairs.data_ptr(), w1.data_ptr(),
+    _check(lib().bd_relaxed_bad_fwd(context(dev, stream), patches.data_ptr(), n, pairs.data_ptr(), w1.data_ptr(),
                                     w2.data_ptr(), theta.data_ptr(), K, beta, D.data_ptr(), m1.data_ptr(),
                                     m2.data_ptr(), stream))
     return D, m1, m2
@@ -520,7 +523,7 @@ def relaxed_bad_bwd(gD, D, m1, m2, beta: float):
         _f32_contig(v, name, (n, K))
     g = [torch.empty((K,), dtype=torch.float32, device=D.device) for _ in range(3)]
     dev, stream = _device_and_stream(gD, D, m1, m2)
-    _check(lib().bd_relaxed_bad_bwd(context(dev), gD.data_ptr(), D.data_ptr(), m1.data_ptr(), m2.data_ptr(), n, K,
+    _check(lib().bd_relaxed_bad_bwd(context(dev, stream), gD.data_ptr(), D.data_ptr(), m1.data_ptr(), m2.data_ptr(), n, K,
                                     beta, g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(), stream))
     return tuple(g)
 
@@ -535,7 +538,7 @@ def relaxed_hashsift_fwd(f, B, t, beta: float):
     rho = torch.empty((n, K), dtype=torch.float32, device=f.device)
     D = torch.empty_like(rho)
     dev, stream = _device_and_stream(f, B, t)
-    _check(lib().bd_relaxed_hashsift_fwd(context(dev), f.data_ptr(), n, B.data_ptr(), t.data_ptr(), K, beta,
+    _check(lib().bd_relaxed_hashsift_fwd(context(dev, stream), f.data_ptr(), n, B.data_ptr(), t.data_ptr(), K, beta,
                                          rho.data_ptr(), D.data_ptr(), stream))
     return rho, D
 
@@ -550,7 +553,7 @@ def relaxed_hashsift_bwd(gD, D, f, beta: float):
     gB = torch.empty((K, 128), dtype=torch.float32, device=D.device)
     gt = torch.empty((K,), dtype=torch.float32, device=D.device)
     dev, stream = _device_and_stream(gD, D, f)
-    _check(lib().bd_relaxed_hashsift_bwd(context(dev), gD.data_ptr(), D.data_ptr(), f.data_ptr(), n, K, beta,
+    _check(lib().bd_relaxed_hashsift_bwd(context(dev, stream), gD.data_ptr(), D.data_ptr(), f.data_ptr(), n, K, beta,
                                          gB.data_ptr(), gt.data_ptr(), stream))
     return gB, gt
 
@@ -565,7 +568,7 @@ def trl_hnm_fwd(A, P, tau: float):
     neg = torch.empty((n,), dtype=torch.int32, device=A.device)
     hinge = torch.empty((n,), dtype=torch.float32, device=A.device)
     dev, stream = _device_and_stream(A, P)
-    _check(lib().bd_trl_hnm_fwd(context(dev), A.data_ptr(), P.data_ptr(), n, K, tau, loss.data_ptr(), neg.data_ptr(),
+    _check(lib().bd_trl_hnm_fwd(context(dev, stream), A.data_ptr(), P.data_ptr(), n, K, tau, loss.data_ptr(), neg.data_ptr(),
                                 hinge.data_ptr(), stream))
     return loss, neg, hinge
 
@@ -577,7 +580,7 @@ def trl_hnm_bwd(A, P, neg, hinge, grad_loss):
     gA, gP = torch.empty_like(A), torch.empty_like(P)
     grad_loss = _f32_contig(grad_loss.reshape(1).contiguous(), "grad_loss")
     dev, stream = _device_and_stream(A, P, neg, hinge, grad_loss)
-    _check(lib().bd_trl_hnm_bwd(context(dev), A.data_ptr(), P.data_ptr(), n, K, neg.data_ptr(), hinge.data_ptr(),
+    _check(lib().bd_trl_hnm_bwd(context(dev, stream), A.data_ptr(), P.data_ptr(), n, K, neg.data_ptr(), hinge.data_ptr(),
                                 grad_loss.data_ptr(), gA.data_ptr(), gP.data_ptr(), stream))
     return gA, gP
 
@@ -750,7 +753,7 @@ def augment_patches(pool, batch, params, noise, out=None):
     if out is None:
         out = torch.empty((2 * n, 32, 32), dtype=torch.float32, device=pool.device)
     d, stream = _device_and_stream(pool, batch, params, noise, out)
-    _check(lib().bd_augment_patches(context(d), pool.data_ptr(), n_pairs, batch.data_ptr(), n, params.data_ptr(),
+    _check(lib().bd_augment_patches(context(d, stream), pool.data_ptr(), n_pairs, batch.data_ptr(), n, params.data_ptr(),
                                     noise.data_ptr(), out.data_ptr(), stream))
     return out
 
@@ -786,7 +789,7 @@ class HashSIFTTrainer:
             raise ValueError("noise must hold 2n x 1024 floats")
         self.step += 1
         d, stream = _device_and_stream(pool, batch, params, noise, self.B)
-        _check(lib().bd_hashsift_train_step(context(d), pool.data_ptr(), n_pairs, batch.data_ptr(), n,
+        _check(lib().bd_hashsift_train_step(context(d, stream), pool.data_ptr(), n_pairs, batch.data_ptr(), n,
                                             params.data_ptr(), noise.data_ptr(), self.B.data_ptr(),
                                             self.t.data_ptr(), self.n_bits, self.state.data_ptr(), self.step,
                                             self.lr, self.tau, self.beta, self.loss.data_ptr(), stream))
