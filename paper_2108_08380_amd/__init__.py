@@ -40,6 +40,9 @@ SIGNATURES = {
     "bd_last_error": ([], ctypes.c_char_p),
     "bd_version": ([], ctypes.c_char_p),
     "bd_build_integral": ([_P, _P, _I32, _I32, _I64, _P, _I64, _P], ctypes.c_int),
+    "bd_bad_table_create": ([_P, _P, _I32, ctypes.POINTER(ctypes.c_void_p), _P], ctypes.c_int),
+    "bd_bad_table_destroy": ([_P], ctypes.c_int),
+    "bd_describe_bad_table": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "bd_keypoint_order": ([_P, _P, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "bd_describe_bad": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _P, _I32, _P, _P], ctypes.c_int),
     "bd_describe_hashsift": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P, _I32, _I32, ctypes.c_float,
@@ -247,12 +250,23 @@ def keypoint_order(kps, width: int, height: int, out=None):
     return out
 
 
-def describe_bad(ii, kps, pairs, n_bits: int | None = None, out=None, order=None):
-    """BAD codes from an integral image (bd_describe_bad)."""
+def describe_bad(ii, kps, pairs=None, n_bits: int | None = None, out=None, order=None, table=None):
+    """BAD codes from an integral image (bd_describe_bad, or bd_describe_bad_table
+    when a compiled BadTable is given instead of pairs)."""
     torch = _torch()
     _require(ii, torch.uint32, 2, "ii")
     _require(kps, torch.float32, 2, "kps")
     _contig(kps, "kps")
+    if table is not None:
+        H, W = ii.shape[0] - 1, ii.shape[1] - 1
+        n = kps.shape[0]
+        if out is None:
+            out = torch.empty((n, table.n_bits // 64), dtype=torch.uint64, device=ii.device)
+        _contig(out, "out")
+        dev, stream = _device_and_stream(ii, kps, out, order)
+        _check(lib().bd_describe_bad_table(context(dev, stream), ii.data_ptr(), W, H, ii.stride(0), kps.data_ptr(), n,
+                                           _order_arg(order, n), table._h, out.data_ptr(), stream))
+        return out
     _contig(pairs, "pairs")
     if pairs.dtype != torch.uint8 or pairs.dim() != 2 or pairs.shape[1] != 12:
         raise TypeError("pairs must be an (n_bits, 12) uint8 tensor")
@@ -268,6 +282,37 @@ def describe_bad(ii, kps, pairs, n_bits: int | None = None, out=None, order=None
     _check(lib().bd_describe_bad(context(dev, stream), ii.data_ptr(), W, H, ii.stride(0), kps.data_ptr(), n,
                                  _order_arg(order, n), pairs.data_ptr(), n_bits, out.data_ptr(), stream))
     return out
+
+
+class BadTable:
+    """A compiled BAD table (bd_bad_table_create): the pairs' distinct boxes in
+    spatial order.  Use with describe_bad(..., table=...)."""
+
+    def __init__(self, pairs, n_bits: int | None = None):
+        torch = _torch()
+        _contig(pairs, "pairs")
+        if pairs.dtype != torch.uint8 or pairs.dim() != 2 or pairs.shape[1] != 12:
+            raise TypeError("pairs must be an (n_bits, 12) uint8 tensor")
+        self.n_bits = pairs.shape[0] if n_bits is None else n_bits
+        if pairs.shape[0] < self.n_bits:
+            raise ValueError("fewer box pairs than n_bits")
+        dev, stream = _device_and_stream(pairs)
+        self.device = dev
+        out = ctypes.c_void_p()
+        _check(lib().bd_bad_table_create(context(dev, stream), pairs.data_ptr(), self.n_bits, ctypes.byref(out),
+                                         stream))
+        self._h = out.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().bd_bad_table_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool = False,

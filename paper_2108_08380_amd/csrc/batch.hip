@@ -72,6 +72,7 @@ struct bd_batch {
     int32_t* d_kpb_pre = nullptr;
     int32_t* d_order = nullptr;
     float* d_hist = nullptr;
+    uint8_t* d_bad_table = nullptr;  // compiled BAD table, rebuilt at every run
     int32_t tile_units = 0, carry_units = 0, kpb_units = 0;
 
     Matcher bad_m, hs_m;
@@ -224,9 +225,12 @@ void launch_stage(bd_batch* b, int stage, const RunArgs& a, hipStream_t s)
                                       s);
             break;
         case kBad:
-            if (b->bad_bits)
-                launch_bad_batch(b->d_images, b->n_img, b->d_kpb_pre, a.kps, b->d_order, a.pairs, b->bad_bits / 64,
-                                 a.bad_codes, grid_for(b->kpb_units, b->tune.bad_blocks_per_cu, cus), s);
+            if (b->bad_bits) {
+                launch_bad_compile(a.pairs, b->bad_bits, b->d_bad_table, s);
+                launch_bad_compiled_batch(b->d_images, b->n_img, b->d_kpb_pre, a.kps, b->d_order, b->d_bad_table,
+                                          b->bad_bits / 64, a.bad_codes,
+                                          grid_for(b->kpb_units, b->tune.bad_blocks_per_cu, cus), s);
+            }
             break;
         case kHist:
             if (b->hs_bits)
@@ -457,6 +461,8 @@ int bd_batch_create(bd_context* ctx, const bd_batch_image* images, int32_t n_ima
     bytes = align_up(bytes + sizeof(int32_t) * (size_t)std::max<int64_t>(total_kp, 1));
     const size_t hist_at = bytes;
     if (hs_bits) bytes = align_up(bytes + sizeof(float) * 128 * (size_t)total_kp);
+    const size_t table_at = bytes;
+    if (bad_bits) bytes = align_up(bytes + bad_table_bytes(bad_bits));
     const size_t images_at = bytes;
     bytes = align_up(bytes + sizeof(BatchImage) * n_images);
     const size_t pre_at = bytes;
@@ -501,6 +507,7 @@ int bd_batch_create(bd_context* ctx, const bd_batch_image* images, int32_t n_ima
     b->images = ims;
     b->d_order = reinterpret_cast<int32_t*>(base + order_at);
     b->d_hist = hs_bits ? reinterpret_cast<float*>(base + hist_at) : nullptr;
+    b->d_bad_table = bad_bits ? reinterpret_cast<uint8_t*>(base + table_at) : nullptr;
     b->d_images = reinterpret_cast<BatchImage*>(base + images_at);
     b->d_tile_pre = reinterpret_cast<int32_t*>(base + pre_at);
     b->d_carry_pre = b->d_tile_pre + (n_images + 1);

@@ -123,6 +123,14 @@ void launch_bad(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch, cons
                 int32_t n_kp, const int32_t* order, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes,
                 hipStream_t stream);
 
+size_t bad_table_bytes(int32_t n_bits);
+void launch_bad_compile(const bd_box_pair* pairs, int32_t n_bits, uint8_t* table, hipStream_t stream);
+void launch_bad_compiled(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch, const bd_keypoint* kps,
+                         int32_t n_kp, const int32_t* order, const uint8_t* table, int32_t n_words, uint64_t* codes,
+                         hipStream_t stream);
+void launch_bad_compiled_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
+                               const int32_t* order, const uint8_t* table, int32_t n_words, uint64_t* codes, int grid,
+                               hipStream_t stream);
 void launch_bad_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
                       const int32_t* order, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes, int grid,
                       hipStream_t stream);

@@ -188,6 +188,78 @@ int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, i
     return check_launch(fn);
 }
 
+}  // extern "C"
+
+struct bd_bad_table {
+    int device = 0;
+    int32_t n_bits = 0;
+    uint8_t* data = nullptr;  // device, bad_table_bytes(n_bits)
+};
+
+extern "C" {
+
+int bd_bad_table_create(bd_context* ctx, const bd_box_pair* pairs, int32_t n_bits, bd_bad_table** out, void* stream)
+{
+    const char* fn = "bd_bad_table_create";
+    if (!out) return fail(BD_EINVAL, "%s: null output pointer", fn);
+    *out = nullptr;
+    if (!is_supported_bits(n_bits)) return fail(BD_EUNSUPPORTED, "%s: n_bits %d (256 or 512)", fn, n_bits);
+    if (!pairs) return fail(BD_EINVAL, "%s: null pairs", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    bd_bad_table* t = new (std::nothrow) bd_bad_table();
+    if (!t) return fail(BD_ENOMEM, "%s: out of host memory", fn);
+    t->device = ctx->device;
+    t->n_bits = n_bits;
+    DeviceGuard guard(ctx->device);
+    hipError_t e = guard.err;
+    if (e == hipSuccess) e = hipMalloc((void**)&t->data, bad_table_bytes(n_bits));
+    if (e != hipSuccess) {
+        delete t;
+        return fail(BD_ENOMEM, "%s: allocation failed: %s", fn, hipGetErrorString(e));
+    }
+    launch_bad_compile(pairs, n_bits, t->data, static_cast<hipStream_t>(stream));
+    if (int rc = check_launch(fn)) {
+        (void)hipFree(t->data);
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return BD_OK;
+}
+
+int bd_bad_table_destroy(bd_bad_table* t)
+{
+    if (!t) return BD_OK;
+    int rc = BD_OK;
+    {
+        DeviceGuard guard(t->device);
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) rc = fail(BD_EDEVICE, "bd_bad_table_destroy: %s", hipGetErrorString(e));
+        (void)hipFree(t->data);
+    }
+    delete t;
+    return rc;
+}
+
+int bd_describe_bad_table(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch,
+                          const bd_keypoint* kps, int32_t n_kp, const int32_t* order, const bd_bad_table* table,
+                          uint64_t* codes, void* stream)
+{
+    const char* fn = "bd_describe_bad_table";
+    if (!table) return fail(BD_EINVAL, "%s: null table", fn);
+    if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
+    if (ii_pitch < (int64_t)W + 1) return fail(BD_EINVAL, "%s: ii_pitch %lld < W+1", fn, (long long)ii_pitch);
+    if (((int64_t)H + 1) * ii_pitch >= (int64_t)1 << 31) return fail(BD_EINVAL, "%s: integral image exceeds 2^31 elements", fn);
+    if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
+    if (n_kp > 0 && (!ii || !kps || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (table->device != ctx->device) return fail(BD_EINVAL, "%s: table belongs to device %d", fn, table->device);
+    if (n_kp == 0) return BD_OK;
+    launch_bad_compiled(ii, W, H, ii_pitch, kps, n_kp, order, table->data, table->n_bits / 64, codes,
+                        static_cast<hipStream_t>(stream));
+    return check_launch(fn);
+}
+
 int check_image(const char* fn, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch)
 {
     if (dtype != BD_DTYPE_U8 && dtype != BD_DTYPE_F32) return fail(BD_EUNSUPPORTED, "%s: dtype %d", fn, dtype);

@@ -244,3 +244,16 @@ def test_training_validation(L):
     assert step(lr=0.0) == bd.BD_EINVAL
     assert step(beta=float("inf")) == bd.BD_EINVAL
     assert step() == bd.BD_EINVAL and "null context" in err(L)
+
+
+def test_bad_table_validation(L):
+    p = ctypes.c_void_p(16)
+    out = ctypes.c_void_p(1)
+    assert L.bd_bad_table_create(None, p, 256, None, None) == bd.BD_EINVAL
+    assert L.bd_bad_table_create(None, p, 128, ctypes.byref(out), None) == bd.BD_EUNSUPPORTED
+    assert out.value is None
+    assert L.bd_bad_table_create(None, None, 256, ctypes.byref(out), None) == bd.BD_EINVAL
+    assert L.bd_bad_table_create(None, p, 256, ctypes.byref(out), None) == bd.BD_EINVAL and "null context" in err(L)
+    assert L.bd_bad_table_destroy(None) == bd.BD_OK
+    assert L.bd_describe_bad_table(None, p, 10, 10, 11, p, 4, None, None, p, None) == bd.BD_EINVAL
+    assert "null table" in err(L)

@@ -153,3 +153,54 @@ def test_order_entries_out_of_range_are_skipped(dev):
     named[bad_order[(bad_order >= 0) & (bad_order < n)]] = True
     np.testing.assert_array_equal(got[named], good[named])
     assert not got[~named].any()
+
+
+# ---------------------------------------------------------------- compiled tables
+
+
+def compiled_vs_direct(dev, img, kp, pairs, order=True):
+    ii = bd.build_integral(img)
+    pt = bd.pairs_tensor(pairs, dev)
+    o = bd.keypoint_order(kp, img.shape[1], img.shape[0]) if order else None
+    direct = bd.describe_bad(ii, kp, pt, order=o)
+    table = bd.BadTable(pt)
+    compiled = bd.describe_bad(ii, kp, order=o, table=table)
+    np.testing.assert_array_equal(to_np(compiled), to_np(direct))
+    table.close()
+    return to_np(direct)
+
+
+@pytest.mark.parametrize("n_bits", [256, 512])
+def test_compiled_table_equals_direct(ref, dev, n_bits):
+    w = synth.hashsift512_pair(synth.SEED_BASE + 20, 1920, 1080, 3000, with_bad_bits=n_bits)
+    img = torch.from_numpy(w.extra["image1_u8"]).to(dev)
+    kp = w.kp1.copy()
+    kp["scale"][:10] = 40.0            # boxes clamped to the image
+    kp["x"][10] = np.float32(np.nan)   # invalid keypoint: zero code
+    kpt = bd.keypoints_tensor(kp, dev)
+    codes = compiled_vs_direct(dev, img, kpt, w.pairs)
+    compiled_vs_direct(dev, img, kpt, w.pairs, order=False)
+    # and the oracle on a sample
+    sel = np.arange(0, 3000, 97)
+    exp, _ = ref.describe_bad(ref.build_integral(w.extra["image1_u8"]), kp[sel], w.pairs)
+    np.testing.assert_array_equal(codes[sel], exp)
+
+
+def test_compiled_table_duplicates_and_extremes(dev):
+    rng = np.random.default_rng(30)
+    pairs = synth.box_pairs(rng, 512)
+    pairs[1] = pairs[0]                                  # a repeated pair
+    pairs[2]["x1"], pairs[2]["y1"] = pairs[3]["x2"], pairs[3]["y2"]
+    pairs[2]["radius"] = pairs[3]["radius"]              # a box shared by two pairs
+    pairs[4]["x1"], pairs[4]["y1"], pairs[4]["x2"], pairs[4]["y2"] = -128, 127, 127, -128
+    pairs[5]["radius"] = 255
+    pairs[6]["x1"] = pairs[6]["x2"]
+    pairs[6]["y1"] = pairs[6]["y2"]                      # both boxes equal: f = 0
+    pairs[7:64]["x1"], pairs[7:64]["y1"], pairs[7:64]["radius"] = 0, 0, 1   # many identical boxes
+    img = torch.from_numpy(synth.quantize_u8(synth.grey_image(rng, 333, 251))).to(dev)
+    kp = bd.keypoints_tensor(synth.keypoints(rng, 777, 333, 251, 8.0, (0.5, 6.0)), dev)
+    compiled_vs_direct(dev, img, kp, pairs)
+    # a tiny image where every box is clamped
+    tiny = torch.from_numpy(rng.integers(0, 256, (9, 13), dtype=np.uint8)).to(dev)
+    kp2 = bd.keypoints_tensor(synth.keypoints(rng, 50, 13, 9, 0.0, (1.0, 3.0)), dev)
+    compiled_vs_direct(dev, tiny, kp2, pairs)
