@@ -32,7 +32,11 @@ namespace {
 
 constexpr int kApron = 34;                 // 32 + one-pixel apron on each side
 constexpr int kSamples = kApron * kApron;  // 1156
-constexpr int kWaveLds = 24 * kWave;       // floats per wavefront (reduction needs 24 x 64)
+// Per-lane partial histograms: entry e = slot * 8 + o (24 entries) of lane
+// (half, column j) at e * kHistStride + half * 40 + 4 + j; four zero columns
+// pad each side of a half so the cell-column sums need no bounds checks.
+constexpr int kHistStride = 80;
+constexpr int kWaveLds = 24 * kHistStride;  // floats per wavefront
 static_assert(kWaveLds >= kSamples, "patch must fit the per-wave LDS slice");
 constexpr int kHistWaves = 4;
 
@@ -87,6 +91,21 @@ struct RowTable {
     }
 };
 __constant__ RowTable kRow = RowTable();
+
+// Horizontal cell weight of column 8 cx - 4 + t for cell column cx:
+// max(0, 1 - |(t + 0.5) / 8 - 1|), the same for every cx.
+struct ColTable {
+    float v[16];
+    constexpr ColTable() : v{}
+    {
+        for (int t = 0; t < 16; ++t) {
+            const double d = (t + 0.5) / 8.0 - 1.0;
+            const double w = 1.0 - (d < 0 ? -d : d);
+            v[t] = (float)(w > 0.0 ? w : 0.0);
+        }
+    }
+};
+constexpr ColTable kCol = ColTable();
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -217,13 +236,14 @@ __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_
     }
     wave_sync();
 
-    // 2. gradients and votes
+    // 2. gradients and votes.  Pixel k of lane (half, j) is patch row
+    // i = k (half 0) or 31 - k (half 1), column j.
     const int j = lane & 31, half = lane >> 5;
     float acc[3][8];
 #pragma unroll
-    for (int s = 0; s < 3; ++s)
+    for (int sl = 0; sl < 3; ++sl)
 #pragma unroll
-        for (int o = 0; o < 8; ++o) acc[s][o] = 0.0f;
+        for (int o = 0; o < 8; ++o) acc[sl][o] = 0.0f;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int i = half ? 31 - k : k;
@@ -237,24 +257,35 @@ __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_
         for (int o = 0; o < 8; ++o) tri[o] = fmaxf(0.0f, 1.0f - fabsf(bo - (float)o));
         tri[0] += fmaxf(0.0f, 1.0f - fabsf(bo - 8.0f));
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            if (slot_active(k, s)) {
-                const float w = m * kRow.v[k][s];
+        for (int sl = 0; sl < 3; ++sl) {
+            if (slot_active(k, sl)) {
+                const float w = m * kRow.v[k][sl];
 #pragma unroll
-                for (int o = 0; o < 8; ++o) acc[s][o] += w * tri[o];
+                for (int o = 0; o < 8; ++o) acc[sl][o] += w * tri[o];
             }
         }
     }
-    wave_sync();
+    wave_sync();  // the patch is dead; its LDS now holds the lane histograms
 
-    // 3. cross-lane reduction through LDS: element e = slot*8 + o of lane l at e*64 + l
+    // lane histograms (times the column's Gaussian weight) into the padded
+    // layout; lanes 0..23 of each half also zero the four pad columns on
+    // each side of entry `lane`
     const float gxj = kGauss.v[j];
+    float* Hl = P + half * 40 + 4 + j;
 #pragma unroll
-    for (int s = 0; s < 3; ++s)
+    for (int sl = 0; sl < 3; ++sl)
 #pragma unroll
-        for (int o = 0; o < 8; ++o) P[(s * 8 + o) * kWave + lane] = acc[s][o] * gxj;
+        for (int o = 0; o < 8; ++o) Hl[(sl * 8 + o) * kHistStride] = acc[sl][o] * gxj;
+    if (j < 24) {
+        float* pad = P + j * kHistStride + half * 40;
+        *reinterpret_cast<float4*>(pad) = float4{0.0f, 0.0f, 0.0f, 0.0f};
+        *reinterpret_cast<float4*>(pad + 36) = float4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
     wave_sync();
 
+    // 3. bin b = (cy, cx, o) of the 4x4x8 histogram: cell row cy is slot cy
+    // of the top half and slot 3 - cy of the bottom half; cell column cx sums
+    // columns 8 cx - 4 .. 8 cx + 11 (padding where outside) with kCol
     float h[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -264,15 +295,11 @@ __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             const int slot = hh ? 3 - cy : cy;
-            if (slot > 2) continue;
-            const float* src = P + (slot * 8 + o) * kWave + hh * 32;
+            const float* src = P + ((slot > 2 ? 2 : slot) * 8 + o) * kHistStride + hh * 40 + 8 * cx;
+            float part = 0.0f;
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const int jj = 8 * cx - 4 + t;
-                if (jj < 0 || jj > 31) continue;
-                const float wx = fmaxf(0.0f, 1.0f - fabsf(((float)jj + 0.5f) * 0.125f - 0.5f - (float)cx));
-                sum += wx * src[jj];
-            }
+            for (int t = 0; t < 16; ++t) part = fmaf(kCol.v[t], src[t], part);
+            sum += slot > 2 ? 0.0f : part;
         }
         h[q] = sum;
     }
