@@ -35,16 +35,29 @@ __device__ __forceinline__ uint32_t cell_key(const bd_keypoint& k, float inv_cel
 }
 
 // One workgroup: histogram of cell keys in LDS, exclusive scan, scatter.
-// Keypoints sharing a cell are placed in arbitrary order.
+// Keypoints sharing a cell are placed in arbitrary order.  The first 8192
+// keypoints keep their cell keys in registers between the histogram and the
+// scatter; the scan is four bins per thread, a wavefront scan by shuffles
+// and a scan of the 16 wavefront totals.
 __device__ __forceinline__ void order_body(const bd_keypoint* __restrict__ kps, int32_t n, float inv_cell,
                                            int32_t* __restrict__ order, uint32_t* bins, uint32_t* part)
 {
-    const int t = threadIdx.x;
-    for (int b = t; b < kBins; b += kThreads) bins[b] = 0u;
+    constexpr int kKeep = 8;
+    const int t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+    for (int b = t; b < kBins; b += kThreads) bins[b] = 0;
     __syncthreads();
-    for (int i = t; i < n; i += kThreads) atomicAdd(&bins[cell_key(kps[i], inv_cell)], 1u);
+    uint32_t keys[kKeep];
+#pragma unroll
+    for (int r = 0; r < kKeep; ++r) {
+        const int i = t + r * kThreads;
+        keys[r] = i < n ? cell_key(kps[i], inv_cell) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kKeep; ++r)
+        if (t + r * kThreads < n) atomicAdd(&bins[keys[r]], 1u);
+    for (int i = t + kKeep * kThreads; i < n; i += kThreads) atomicAdd(&bins[cell_key(kps[i], inv_cell)], 1u);
     __syncthreads();
-    // exclusive scan of 4096 bins: 4 consecutive bins per thread, then the 1024 thread sums
+    // exclusive scan of the 4096 bins
     constexpr int kPer = kBins / kThreads;
     uint32_t local[kPer], sum = 0u;
 #pragma unroll
@@ -52,19 +65,35 @@ __device__ __forceinline__ void order_body(const bd_keypoint* __restrict__ kps, 
         local[k] = sum;
         sum += bins[t * kPer + k];
     }
-    part[t] = sum;
-    __syncthreads();
-    for (int d = 1; d < kThreads; d <<= 1) {
-        const uint32_t v = t >= d ? part[t - d] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    uint32_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += v;
     }
-    const uint32_t base = part[t] - sum;
+    if (lane == kWave - 1) part[wave] = incl;
+    __syncthreads();
+    if (t < kWave) {
+        constexpr int kWaves = kThreads / kWave;  // 16
+        uint32_t w = t < kWaves ? part[t] : 0u;
+#pragma unroll
+        for (int d = 1; d < kWaves; d <<= 1) {
+            const uint32_t v = __shfl_up(w, d, kWave);
+            if (t >= d) w += v;
+        }
+        if (t < kWaves) part[kWaves + t] = w;  // inclusive totals
+    }
+    __syncthreads();
+    const uint32_t base = (wave > 0 ? part[kThreads / kWave + wave - 1] : 0u) + incl - sum;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) bins[t * kPer + k] = base + local[k];
     __syncthreads();
-    for (int i = t; i < n; i += kThreads) order[atomicAdd(&bins[cell_key(kps[i], inv_cell)], 1u)] = i;
+#pragma unroll
+    for (int r = 0; r < kKeep; ++r) {
+        const int i = t + r * kThreads;
+        if (i < n) order[atomicAdd(&bins[keys[r]], 1u)] = i;
+    }
+    for (int i = t + kKeep * kThreads; i < n; i += kThreads) order[atomicAdd(&bins[cell_key(kps[i], inv_cell)], 1u)] = i;
     __syncthreads();
 }
 
