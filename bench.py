@@ -315,6 +315,35 @@ def differentiation_step(dev, n=8192, reps=5):
     return out
 
 
+def pair_via_batch(wl, reps=200):
+    """The same step (both views, both descriptors, both matchers) through the
+    batched entry point: one launch per stage for the two views, captured as
+    one graph.  Outputs are compared with the single-image step's."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+
+    kps = torch.cat(wl.kps).contiguous()
+    b = bd.Batch(wl.u8, [N_KP, N_KP], [(0, 1)], bad_bits=BAD_BITS, hs_bits=HS_BITS, k=K, hs_images=wl.f32)
+    out = b.allocate_outputs()
+    tuning = b.autotune(kps, wl.pairs, wl.B, wl.t, out=out, reps=5)
+    b.run(kps, wl.pairs, wl.B, wl.t, out=out, graph=True)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.run(kps, wl.pairs, wl.B, wl.t, out=out, graph=True)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    same = (torch.equal(out["bad_codes"], torch.cat(wl.bad)) and torch.equal(out["hs_codes"], torch.cat(wl.hs))
+            and torch.equal(out["bad_idx"], wl.idx[0]) and torch.equal(out["bad_dist"], wl.dist[0])
+            and torch.equal(out["hs_idx"], wl.idx[1]) and torch.equal(out["hs_dist"], wl.dist[1]))
+    b.close()
+    return {"ms_per_step": round(ms, 4), "keypoints_per_s": round(2 * N_KP / (ms * 1e-3), 1),
+            "bit_identical_to_single_image_step": bool(same), "tuning": tuning}
+
+
 def mutual_matching(wl, reps=20):
     """Mutual nearest neighbours + ratio 0.8 (two k-NN passes and the cross
     check) on the step's BAD-256 and HashSIFT-512 codes of the two views:
@@ -662,6 +691,8 @@ def main():
         "checks": check,
         "roofline": roofline,
     }
+    if not args.only:
+        result["same_step_via_batched_entry_point"] = pair_via_batch(wl)
     if not args.only and not args.step_only:
         result["mutual_nn_ratio0.8"] = mutual_matching(wl)
         result["precision_projection_200k"] = precision_projection(wl)
