@@ -62,3 +62,24 @@ def test_integral_deterministic(dev):
     a = to_np(bd.build_integral(img))
     b = to_np(bd.build_integral(img))
     np.testing.assert_array_equal(a, b)
+
+
+def test_integral_near_the_index_limit(ref, dev):
+    """32767 x 32768 (1.07e9 integral elements, the largest power-of-two width
+    under the 2^31-element limit of bd_build_integral): sampled rows and the
+    last row against the oracle, total sum modulo 2^32."""
+    H, W = 32767, 32768
+    rng = np.random.default_rng(77)
+    img = np.full((H, W), 200, dtype=np.uint8)
+    img[rng.integers(0, H, 4096), :] = rng.integers(0, 256, (4096, W), dtype=np.uint8)
+    d_img = torch.from_numpy(img).to(dev)
+    ii = bd.build_integral(d_img)
+    del d_img
+    exp = ref.build_integral(img)
+    iv = ii.view(torch.int32)  # torch indexes no uint32 device tensors; same bits
+    rows = [0, 1, 17, 4096, H // 2, H - 1, H]
+    got_rows = iv[rows].cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(got_rows, exp[rows])
+    cols = torch.from_numpy(rng.integers(0, W + 1, 64)).to(dev)
+    np.testing.assert_array_equal(iv[:, cols].cpu().numpy().view(np.uint32), exp[:, cols.cpu().numpy()])
+    assert int(got_rows[-1, -1]) == int(img.sum(dtype=np.uint64) % (1 << 32))

@@ -87,3 +87,26 @@ def test_deterministic(dev):
     b = [to_np(x) for x in bd.match_hamming_knn(q, t, 2)]
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_train_set_beyond_packed_row_range(ref, dev):
+    """More than 2^22 train codes: the row index no longer fits the 22 bits of
+    a packed key, so the set is split and merged with global indices.  Exact
+    duplicates of the queries are planted on both sides of row 2^22 (ties
+    resolved to the lower index) and near-duplicates beyond it."""
+    rng = np.random.default_rng(78)
+    n_t = (1 << 22) + 3000
+    q = rng.integers(0, 2**63, (100, 1), dtype=np.uint64)
+    t = rng.integers(0, 2**63, (n_t, 1), dtype=np.uint64)
+    t[(1 << 22) + 5] = q[0]
+    t[(1 << 22) - 7] = q[0]
+    t[(1 << 22) + 100] = q[1]
+    t[n_t - 1] = q[2] ^ np.uint64(1)
+    t[(1 << 22) + 200] = q[3]
+    t[17] = q[3] ^ np.uint64(3)
+    for k in (1, 2):
+        idx, dist = bd.match_hamming_knn(torch.from_numpy(q).to(dev), torch.from_numpy(t).to(dev), k=k)
+        ei, ed = ref.match_knn(q, t, k)
+        np.testing.assert_array_equal(to_np(idx), ei)
+        np.testing.assert_array_equal(to_np(dist), ed)
+    assert ei[0, 0] == (1 << 22) - 7 and ei[1, 0] == (1 << 22) + 100 and ei[2, 0] == n_t - 1
