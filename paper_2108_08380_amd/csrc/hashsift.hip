@@ -12,19 +12,22 @@
 //   2. Lane (h, j) owns patch column j and 16 rows (rows 0..15 top-down for
 //      h = 0, rows 31..16 bottom-up for h = 1).  With the bottom-up order the
 //      vertical cell weights and Gaussian row weights of step k are the same
-//      compile-time constants for both halves, so each pixel's vote is 18
-//      triangular orientation weights and 16 FMAs into 3 cell rows x 8
+//      compile-time constants for both halves, so each pixel's vote is 9
+//      triangular orientation weights and 8 or 16 FMAs into 3 cell rows x 8
 //      orientations held in registers.  No atomics: the order of every sum is
 //      fixed, so the result is deterministic.
-//   3. The per-lane partial histograms go through LDS and each lane forms
-//      two of the 128 bins by a fixed-order weighted sum over the columns of
-//      its cell (horizontal cell weight times the column's Gaussian weight).
+//   3. The per-lane partial histograms (times the column's Gaussian weight)
+//      go to LDS with four zero columns padding each side, and each lane
+//      forms two of the 128 bins by a fixed-order sum over the 16 columns of
+//      its cell's support with compile-time horizontal weights, no bounds
+//      checks needed.
 //   4. L2 normalization by a wavefront reduction.
 //
-// hashsift_project: responses r = B f - t on MFMA (FP32, or BF16 / FP8 with
-// FP32 accumulation and an FP32 re-check near the threshold), 16 keypoints x
-// 64 bits per wavefront, operands read from L2; the signs are packed into
-// code words with 16 ballots.
+// hashsift_project: persistent and B-stationary: a block keeps one 64-bit
+// chunk of B (FP32 in LDS for the re-check, the MFMA operand in registers)
+// and streams 16-keypoint tiles per wavefront; responses r = B f - t on
+// MFMA (FP32, or BF16 / FP8 with FP32 accumulation and an FP32 re-check of
+// responses near the threshold); the signs are packed with 16 ballots.
 #include "bd_internal.hpp"
 
 namespace bd {
