@@ -167,8 +167,8 @@ PMC_TRAFFIC = {
     "keypoint_order": ("order.hip", "b9c2afd100b6dde1", 89654 + 20000),
     "integral": ("integral.hip", "ace12b3b1e8860be", 5677659 + 9591264),
     "bad_describe": ("bad.hip", "884a2f98d19ec233", 18584155 + 164541),
-    "hashsift_features": ("hashsift.hip", "6d7dc603ce02fac2", 18979337 + 2560000),
-    "hashsift_project": ("hashsift.hip", "6d7dc603ce02fac2", 4844421 + 325058),
+    "hashsift_features": ("hashsift.hip", "8a3f21a5096ee430", 18979337 + 2560000),
+    "hashsift_project": ("hashsift.hip", "8a3f21a5096ee430", 4844421 + 325058),
     "match_bad256": ("hamming.hip", "908e86d0e6e30368", 2914249 + 2080000 + 2420736 + 80000),
     "match_hashsift512": ("hamming.hip", "908e86d0e6e30368", 5790445 + 2080000 + 2420736 + 80000),
 }
