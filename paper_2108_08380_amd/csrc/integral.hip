@@ -27,12 +27,23 @@ constexpr int kTileCols = 256;  // 64 lanes x 4 columns
 constexpr int kWavesPerBlock = 4;
 
 // Four pixels of row `y` starting at column x, packed little-endian into one
-// u32 (a byte per pixel); columns >= W read as zero.
+// u32 (a byte per pixel); columns >= W read as zero.  When the row is not
+// 4-byte aligned, the two aligned dwords around the four bytes are loaded
+// and shifted into place (v_alignbyte); each of them holds at least one
+// byte of the row, so neither crosses into memory the image does not own.
 __device__ __forceinline__ uint32_t load_quad(const uint8_t* __restrict__ img, int64_t pitch, int32_t y,
                                               int32_t x, int32_t W, bool aligned)
 {
     const uint8_t* row = img + (int64_t)y * pitch;
-    if (aligned && x + 3 < W) return *reinterpret_cast<const uint32_t*>(row + x);
+    if (x + 3 < W) {
+        if (aligned) return *reinterpret_cast<const uint32_t*>(row + x);
+        const uintptr_t addr = reinterpret_cast<uintptr_t>(row + x);
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(addr & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(addr & 3u);
+        const uint32_t lo = p[0];
+        const uint32_t hi = sh ? p[1] : 0u;
+        return __builtin_amdgcn_alignbyte(hi, lo, sh);
+    }
     uint32_t w = 0u;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
