@@ -59,6 +59,7 @@ struct bd_batch {
     bd_context* ctx = nullptr;
     int32_t n_img = 0, n_match = 0;
     int32_t bad_bits = 0, hs_bits = 0, precision = 0, k = 1;
+    int32_t hs_dtypes = 0;  // bit (1 << dtype) for every HashSIFT source dtype present
     float margin = 0.0f;
     int64_t total_kp = 0;
     std::vector<BatchImage> images;
@@ -234,7 +235,7 @@ void launch_stage(bd_batch* b, int stage, const RunArgs& a, hipStream_t s)
             break;
         case kHist:
             if (b->hs_bits)
-                launch_hashsift_hist_batch(b->d_images, b->n_img, b->d_kpb_pre, a.kps, b->d_order, b->d_hist,
+                launch_hashsift_hist_batch(b->d_images, b->n_img, b->hs_dtypes, b->d_kpb_pre, a.kps, b->d_order, b->d_hist,
                                            grid_for(b->kpb_units, b->tune.hist_blocks_per_cu, cus), s);
             break;
         case kProject:
@@ -399,6 +400,8 @@ int bd_batch_create(bd_context* ctx, const bd_batch_image* images, int32_t n_ima
             b.pitch_hs = s.pitch;
             b.hs_dtype = BD_DTYPE_U8;
         }
+        if (hs_bits && !hashsift_image_fits(b.pitch_hs, s.H))
+            return fail(BD_EINVAL, "%s: image %d HashSIFT image needs pitch < 2^24, H < 2^24, pitch * H <= 2^32", fn, i);
         b.W = s.W;
         b.H = s.H;
         b.kp_offset = (int32_t)total_kp;
@@ -424,6 +427,7 @@ int bd_batch_create(bd_context* ctx, const bd_batch_image* images, int32_t n_ima
     if (!b) return fail(BD_ENOMEM, "%s: out of host memory", fn);
     b->ctx = ctx;
     b->n_img = n_images;
+    for (const BatchImage& im : ims) b->hs_dtypes |= 1 << im.hs_dtype;
     b->n_match = n_matches;
     b->bad_bits = bad_bits;
     b->hs_bits = hs_bits;

@@ -143,12 +143,20 @@ void launch_keypoint_order_batch(const BatchImage* imgs, int32_t n_img, const bd
                                  int grid, hipStream_t stream);
 
 // ---- HashSIFT (hashsift.hip)
+// Images the HashSIFT sampler addresses with 32-bit offsets and 24-bit row
+// multiplies: pitch < 2^24 bytes, H < 2^24 and pitch * H <= 2^32.
+inline bool hashsift_image_fits(int64_t pitch, int32_t H)
+{
+    return pitch < ((int64_t)1 << 24) && H < (1 << 24) && pitch * (int64_t)H <= ((int64_t)1 << 32);
+}
 void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
                           const bd_keypoint* kps, int32_t n_kp, const int32_t* order, float* hist,
                           hipStream_t stream);
 void launch_hashsift_patch_features(const float* patches, int32_t n, float* hist, hipStream_t stream);
-void launch_hashsift_hist_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
-                                const int32_t* order, float* hist, int grid, hipStream_t stream);
+// dtypes: bit (1 << dtype) set for every dtype among the images.
+void launch_hashsift_hist_batch(const BatchImage* imgs, int32_t n_img, int32_t dtypes, const int32_t* pre,
+                                const bd_keypoint* kps, const int32_t* order, float* hist, int grid,
+                                hipStream_t stream);
 void launch_hashsift_project(int32_t precision, const float* hist, const bd_keypoint* kps, int32_t n_kp,
                              const float* B, const float* t, int32_t n_words, float margin, uint64_t* codes,
                              float* resp, uint32_t* recheck_count, hipStream_t stream);

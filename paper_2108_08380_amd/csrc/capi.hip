@@ -267,6 +267,8 @@ int check_image(const char* fn, int32_t dtype, int32_t W, int32_t H, int64_t img
     const int64_t elem = dtype == BD_DTYPE_U8 ? 1 : 4;
     if (img_pitch < W * elem) return fail(BD_EINVAL, "%s: img_pitch %lld < row bytes", fn, (long long)img_pitch);
     if (dtype == BD_DTYPE_F32 && img_pitch % 4 != 0) return fail(BD_EINVAL, "%s: f32 img_pitch must be a multiple of 4", fn);
+    if (!hashsift_image_fits(img_pitch, H))
+        return fail(BD_EINVAL, "%s: image needs img_pitch < 2^24, H < 2^24 and img_pitch * H <= 2^32", fn);
     return BD_OK;
 }
 

@@ -4,11 +4,16 @@
 // hashsift_hist: one wavefront per keypoint, in the caller's spatial order
 // (optional) with an XCD-aware block mapping so an XCD's samples stay within
 // one image region.
-//   1. 34x34 bilinear samples of the rotated, scaled patch (positions in
-//      FP64, clamp-to-edge, nested linear interpolation so flat regions give
-//      exactly zero gradients) go to LDS, stored relative to the pixel under
-//      the keypoint so small gradients in near-flat patches keep their
-//      relative precision in FP32.
+//   1. 34x34 bilinear samples of the rotated, scaled patch (clamp-to-edge,
+//      nested linear interpolation so flat regions give exactly zero
+//      gradients) go to LDS, stored relative to the pixel under the keypoint
+//      so small gradients in near-flat patches keep their relative precision
+//      in FP32.  Positions are 32.32 fixed point: lane (h, c) walks patch
+//      column c + 1 down rows 1 + h, 3 + h, ... with one uniform 64-bit
+//      step, so a sample costs two 64-bit adds instead of FP64 arithmetic;
+//      two more steps take the apron rows and columns (the four apron
+//      corners are never read).  Keypoints whose patch may reach beyond
+//      2^30 pixels take the FP64 position path.
 //   2. Lane (h, j) owns patch column j and 16 rows (rows 0..15 top-down for
 //      h = 0, rows 31..16 bottom-up for h = 1).  With the bottom-up order the
 //      vertical cell weights and Gaussian row weights of step k are the same
@@ -173,32 +178,103 @@ __device__ __forceinline__ float wave_sum_f(float v)
     return v;
 }
 
-// The histogram of one keypoint, computed by one wavefront with a
-// kWaveLds-float LDS slice P; writes the 128 features to out.
+// Bilinear value at a sample from its four corner pixels, relative to the
+// reference level.  For u8 the corner differences are exact integers, so
+// (v01 - base) - (v00 - base) is formed directly as v01 - v00.
 template <int DT>
-__device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_t W, int32_t H, int64_t pitch,
-                                         const bd_keypoint kp, float* __restrict__ out, float* P, int lane)
+__device__ __forceinline__ float bilinear(const float (&v)[4], float fx, float fy, float base)
 {
-    if (!(finite_f(kp.x) && finite_f(kp.y) && finite_f(kp.scale) && finite_f(kp.angle) && kp.scale > 0.0f)) {
-        out[lane] = 0.0f;
-        out[lane + kWave] = 0.0f;
-        return;
+    float top, bot;
+    if constexpr (DT == BD_DTYPE_U8) {
+        top = fmaf(fx, v[1] - v[0], v[0] - base);
+        bot = fmaf(fx, v[3] - v[2], v[2] - base);
+    } else {
+        const float v00 = v[0] - base, v01 = v[1] - base, v10 = v[2] - base, v11 = v[3] - base;
+        top = v00 + fx * (v01 - v00);
+        bot = v10 + fx * (v11 - v10);
     }
-    double sn, cs;
-    sincos((double)kp.angle, &sn, &cs);
-    const double sa = (double)kp.scale * cs, sb = (double)kp.scale * sn;
-    const double kx = kp.x, ky = kp.y;
+    return top + fy * (bot - top);
+}
 
-    // reference level: the pixel under the keypoint (clamped)
-    const int bx = (int)fmin(fmax(rint(kx), 0.0), (double)(W - 1));
-    const int by = (int)fmin(fmax(rint(ky), 0.0), (double)(H - 1));
-    const float base = pixel<DT>(img, pitch, bx, by);
+// v clamped to [0, hi] (hi >= 0) in one instruction (the compiler forms
+// v_med3_i32 only for constant bounds).
+__device__ __forceinline__ int clampi(int v, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(v), "v"(hi));
+    return r;
+}
 
-    // 1. resample the 34x34 patch.  Sample s = (i+1)*34 + (j+1) sits at patch
-    // offset (j - 15.5, i - 15.5); its image position is the row origin
-    // (kx - sb*uy, ky + sa*uy) plus (sa, sb) * ux, two FP64 FMAs per axis.
-    // Three samples per lane are in flight at a time.
-    const uint32_t upitch = (uint32_t)pitch;
+// 32.32 fixed point of v (|v| < 2^31).
+__device__ __forceinline__ int64_t to_fixed(double v) { return (int64_t)rint(v * 4294967296.0); }
+
+// The four corner pixels and weights of the sample at fixed-point image
+// position (X, Y).  Row offsets use 24-bit multiplies: the host admits only
+// images with pitch < 2^24, H < 2^24 and pitch * H <= 2^32.
+template <int DT>
+__device__ __forceinline__ void fetch_fixed(const uint8_t* __restrict__ img, int wm1, int hm1, uint32_t upitch,
+                                            int64_t X, int64_t Y, float (&v)[4], float& fx, float& fy)
+{
+    const int xi = (int)(X >> 32), yi = (int)(Y >> 32);
+    fx = (float)(uint32_t)X * 0x1p-32f;
+    fy = (float)(uint32_t)Y * 0x1p-32f;
+    const int xa = clampi(xi, wm1), xb = clampi(xi + 1, wm1);
+    const uint32_t ra = __umul24((uint32_t)clampi(yi, hm1), upitch);
+    const uint32_t rb = __umul24((uint32_t)clampi(yi + 1, hm1), upitch);
+    v[0] = pixel_at<DT>(img, ra, xa);
+    v[1] = pixel_at<DT>(img, ra, xb);
+    v[2] = pixel_at<DT>(img, rb, xa);
+    v[3] = pixel_at<DT>(img, rb, xb);
+}
+
+// Resampling with fixed-point positions (every sample within 2^30 pixels of
+// the origin).  Core: 16 steps over the 32x32 interior, lane (h, c) at
+// sample (1 + h + 2t, 1 + c), four steps' loads in flight at a time; then
+// the apron rows 0 and 33 (columns 1..32) and columns 0 and 33 (rows 1..32).
+template <int DT>
+__device__ __forceinline__ void resample_fixed(const uint8_t* __restrict__ img, int32_t W, int32_t H,
+                                               uint32_t upitch, double kx, double ky, double sa, double sb,
+                                               float base, float* P, int lane)
+{
+    const int wm1 = W - 1, hm1 = H - 1;
+    const int h = lane >> 5, c = lane & 31;
+    const double ux = (double)c - 15.5, uy = (double)h - 15.5;
+    int64_t X = to_fixed(fma(sa, ux, fma(-sb, uy, kx)));
+    int64_t Y = to_fixed(fma(sb, ux, fma(sa, uy, ky)));
+    const int64_t dX = to_fixed(-2.0 * sb), dY = to_fixed(2.0 * sa);
+    float* dst = P + (1 + h) * kApron + 1 + c;
+    constexpr int kStep = 4;
+#pragma unroll 1
+    for (int t0 = 0; t0 < 16; t0 += kStep) {
+        float v[kStep][4], fx[kStep], fy[kStep];
+#pragma unroll
+        for (int g = 0; g < kStep; ++g) {
+            fetch_fixed<DT>(img, wm1, hm1, upitch, X, Y, v[g], fx[g], fy[g]);
+            X += dX;
+            Y += dY;
+        }
+#pragma unroll
+        for (int g = 0; g < kStep; ++g) dst[(t0 + g) * 2 * kApron] = bilinear<DT>(v[g], fx[g], fy[g], base);
+    }
+    // apron: rows 0 / 33 at column 1 + c, then columns 0 / 33 at row 1 + c
+    const double ar = h ? 16.5 : -16.5, ac = (double)c - 15.5;
+    float v[2][4], fx[2], fy[2];
+    fetch_fixed<DT>(img, wm1, hm1, upitch, to_fixed(fma(sa, ac, fma(-sb, ar, kx))),
+                    to_fixed(fma(sb, ac, fma(sa, ar, ky))), v[0], fx[0], fy[0]);
+    fetch_fixed<DT>(img, wm1, hm1, upitch, to_fixed(fma(sa, ar, fma(-sb, ac, kx))),
+                    to_fixed(fma(sb, ar, fma(sa, ac, ky))), v[1], fx[1], fy[1]);
+    P[(h ? 33 : 0) * kApron + 1 + c] = bilinear<DT>(v[0], fx[0], fy[0], base);
+    P[(1 + c) * kApron + (h ? 33 : 0)] = bilinear<DT>(v[1], fx[1], fy[1], base);
+}
+
+// Resampling with FP64 positions, for keypoints far outside any image (or
+// with huge scales): sample s = lane + 64 it of the 1156, three per lane in
+// flight at a time.
+template <int DT>
+__device__ __forceinline__ void resample_f64(const uint8_t* __restrict__ img, int32_t W, int32_t H, uint32_t upitch,
+                                             double kx, double ky, double sa, double sb, float base, float* P,
+                                             int lane)
+{
     const int wm1 = W - 1, hm1 = H - 1;
     constexpr int kIters = (kSamples + kWave - 1) / kWave;  // 19
     constexpr int kGroup = 3;
@@ -220,23 +296,48 @@ __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_
             fys[g] = (float)(py - y0);
             // keep the conversion in range for far-off keypoints; clamping follows
             const int xi = (int)fmin(fmax(x0, -1.0e9), 1.0e9), yi = (int)fmin(fmax(y0, -1.0e9), 1.0e9);
-            const int xa = min(max(xi, 0), wm1), xb = min(max(xi + 1, 0), wm1);
-            const uint32_t ra = (uint32_t)min(max(yi, 0), hm1) * upitch;
-            const uint32_t rb = (uint32_t)min(max(yi + 1, 0), hm1) * upitch;
+            const int xa = clampi(xi, wm1), xb = clampi(xi + 1, wm1);
+            const uint32_t ra = __umul24((uint32_t)clampi(yi, hm1), upitch);
+            const uint32_t rb = __umul24((uint32_t)clampi(yi + 1, hm1), upitch);
             v[g][0] = pixel_at<DT>(img, ra, xa);
             v[g][1] = pixel_at<DT>(img, ra, xb);
             v[g][2] = pixel_at<DT>(img, rb, xa);
             v[g][3] = pixel_at<DT>(img, rb, xb);
         }
 #pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
-            const float v00 = v[g][0] - base, v01 = v[g][1] - base;
-            const float v10 = v[g][2] - base, v11 = v[g][3] - base;
-            const float top = v00 + fxs[g] * (v01 - v00);
-            const float bot = v10 + fxs[g] * (v11 - v10);
-            if (sidx[g] < kSamples) P[sidx[g]] = top + fys[g] * (bot - top);
-        }
+        for (int g = 0; g < kGroup; ++g)
+            if (sidx[g] < kSamples) P[sidx[g]] = bilinear<DT>(v[g], fxs[g], fys[g], base);
     }
+}
+
+// The histogram of one keypoint, computed by one wavefront with a
+// kWaveLds-float LDS slice P; writes the 128 features to out.
+template <int DT>
+__device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_t W, int32_t H, int64_t pitch,
+                                         const bd_keypoint kp, float* __restrict__ out, float* P, int lane)
+{
+    if (!(finite_f(kp.x) && finite_f(kp.y) && finite_f(kp.scale) && finite_f(kp.angle) && kp.scale > 0.0f)) {
+        out[lane] = 0.0f;
+        out[lane + kWave] = 0.0f;
+        return;
+    }
+    double sn, cs;
+    sincos((double)kp.angle, &sn, &cs);
+    const double sa = (double)kp.scale * cs, sb = (double)kp.scale * sn;
+    const double kx = kp.x, ky = kp.y;
+
+    // reference level: the pixel under the keypoint (clamped)
+    const int bx = (int)fmin(fmax(rint(kx), 0.0), (double)(W - 1));
+    const int by = (int)fmin(fmax(rint(ky), 0.0), (double)(H - 1));
+    const float base = pixel<DT>(img, pitch, bx, by);
+
+    // 1. resample the 34x34 patch.  Sample (i, j) sits at patch offset
+    // (j - 16.5, i - 16.5); its image position is (kx, ky) plus that offset
+    // rotated and scaled by (sa, sb).
+    if (fabs((double)kp.x) + 24.0 * kp.scale < 1073741824.0 && fabs((double)kp.y) + 24.0 * kp.scale < 1073741824.0)
+        resample_fixed<DT>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
+    else
+        resample_f64<DT>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
     wave_sync();
 
     // 2. gradients and votes.  Pixel k of lane (half, j) is patch row
@@ -255,10 +356,13 @@ __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_
         const float gy = P[c + kApron] - P[c - kApron];
         const float m = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);
         const float bo = orientation_bin(gx, gy);
+        // triangular weights max(0, 1 - |bo - o|), bin 0 also taking bo near 8:
+        // for bo in [0, 8] that sum is max(0, |bo - 4| - 3).  Both forms are
+        // at most 1, so a clamp to [0, 1] gives the max.
         float tri[8];
+        tri[0] = __builtin_amdgcn_fmed3f(fabsf(bo - 4.0f) - 3.0f, 0.0f, 1.0f);
 #pragma unroll
-        for (int o = 0; o < 8; ++o) tri[o] = fmaxf(0.0f, 1.0f - fabsf(bo - (float)o));
-        tri[0] += fmaxf(0.0f, 1.0f - fabsf(bo - 8.0f));
+        for (int o = 1; o < 8; ++o) tri[o] = __builtin_amdgcn_fmed3f(1.0f - fabsf(bo - (float)o), 0.0f, 1.0f);
 #pragma unroll
         for (int sl = 0; sl < 3; ++sl) {
             if (slot_active(k, sl)) {
@@ -340,14 +444,19 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
 
 // Batch: units are blocks of four keypoints of every image in turn (pre is
 // the prefix of ceil(n_kp / 4)); order entries are image-local; features are
-// written to the flat array at the keypoint's global index.
-__global__ __launch_bounds__(256) void hashsift_hist_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
-                                                           const int32_t* __restrict__ pre,
-                                                           const bd_keypoint* __restrict__ kps,
-                                                           const int32_t* __restrict__ order, float* __restrict__ hist)
+// written to the flat array at the keypoint's global index.  DT is the
+// dtype of every image's HashSIFT source, or kMixedDtypes.  The u8 form runs
+// at 5 waves per SIMD, as LDS allows; the others need more registers (4).
+constexpr int kMixedDtypes = -1;
+
+template <int DT>
+__global__ __launch_bounds__(256, DT == BD_DTYPE_U8 ? 5 : 4) void hashsift_hist_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
+                                                              const int32_t* __restrict__ pre,
+                                                              const bd_keypoint* __restrict__ kps,
+                                                              const int32_t* __restrict__ order,
+                                                              float* __restrict__ hist)
 {
     __shared__ float smem[kHistWaves][kWaveLds];
-    const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     const UnitRange ur = xcd_units(pre[n_img]);
     for (int u = ur.first; u < ur.end; u += ur.stride) {
@@ -358,11 +467,19 @@ __global__ __launch_bounds__(256) void hashsift_hist_batch(const BatchImage* __r
         const int n = order[im.kp_offset + pos];
         if (n < 0 || n >= im.n_kp) continue;
         const int g = im.kp_offset + n;
-        if (im.hs_dtype == BD_DTYPE_U8)
-            hist_one<BD_DTYPE_U8>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave], lane);
-        else
+        // lane is opaque to the compiler inside each unit, so per-lane
+        // addresses are not hoisted out of the loop and kept live throughout
+        int lane = threadIdx.x % kWave;
+        asm volatile("" : "+v"(lane));
+        if constexpr (DT != kMixedDtypes) {
+            hist_one<DT>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave], lane);
+        } else if (im.hs_dtype == BD_DTYPE_U8) {
+            hist_one<BD_DTYPE_U8>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave],
+                                  lane);
+        } else {
             hist_one<BD_DTYPE_F32>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave],
                                    lane);
+        }
     }
 }
 
@@ -683,11 +800,19 @@ void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, 
                            stream, p, W, H, img_pitch, kps, n_kp, order, hist);
 }
 
-void launch_hashsift_hist_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
-                                const int32_t* order, float* hist, int grid, hipStream_t stream)
+void launch_hashsift_hist_batch(const BatchImage* imgs, int32_t n_img, int32_t dtypes, const int32_t* pre,
+                                const bd_keypoint* kps, const int32_t* order, float* hist, int grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL(hashsift_hist_batch, dim3(grid), dim3(kHistWaves * kWave), 0, stream, imgs, n_img, pre, kps,
-                       order, hist);
+    const dim3 block(kHistWaves * kWave);
+    if (dtypes == (1 << BD_DTYPE_U8))
+        hipLaunchKernelGGL(hashsift_hist_batch<BD_DTYPE_U8>, dim3(grid), block, 0, stream, imgs, n_img, pre, kps,
+                           order, hist);
+    else if (dtypes == (1 << BD_DTYPE_F32))
+        hipLaunchKernelGGL(hashsift_hist_batch<BD_DTYPE_F32>, dim3(grid), block, 0, stream, imgs, n_img, pre, kps,
+                           order, hist);
+    else
+        hipLaunchKernelGGL(hashsift_hist_batch<kMixedDtypes>, dim3(grid), block, 0, stream, imgs, n_img, pre, kps,
+                           order, hist);
 }
 
 void launch_hashsift_patch_features(const float* patches, int32_t n, float* hist, hipStream_t stream)

@@ -124,3 +124,48 @@ def test_ordered_features_equal_unordered(dev):
     c2 = to_np(bd.describe_hashsift(img, kps, B, t, order=order))
     np.testing.assert_array_equal(c1, c2)
     np.testing.assert_array_equal(c1, to_np(bd.hashsift_project(torch.from_numpy(b).to(dev), B, t, kps)))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
+def test_far_keypoints_and_huge_scales(ref, dev, dtype):
+    """Sample positions are 32.32 fixed point while every sample of the patch
+    stays within 2^30 pixels of the origin, FP64 otherwise: keypoints on both
+    sides of that bound (far off the image, or with scales up to 5e7) all
+    clamp to the image edges like the oracle's."""
+    rng = np.random.default_rng(11)
+    img = rng.random((37, 41)).astype(np.float32)
+    if dtype == "u8":
+        img = (img * 255).astype(np.uint8)
+    kps = np.zeros(10, dtype=synth.KEYPOINT_DTYPE)
+    kps[:] = [(1.0e9, 20.0, 1.0, 0.5),        # fixed point, positions near 1e9
+              (-1.0e9, 30.0, 2.0, 2.5),       # fixed point, negative
+              (20.0, 18.0, 4.0e7, 0.2),       # fixed point, |offsets| up to 9.3e8
+              (1.2e9, 20.0, 1.0, 0.5),        # FP64 path
+              (20.0, -3.0e9, 3.0, 2.0),       # FP64 path
+              (20.0, 18.0, 5.0e7, 0.2),       # FP64 path: scale reaches past 2^30
+              (-2.0e9, -3.0e9, 3.0, 4.0),     # FP64 path, far corner
+              (20.0, 18.0, 1.0e30, 1.0),      # FP64 path, absurd scale
+              (40.5, 36.5, 1.0, 0.0),         # ordinary keypoints beside them
+              (10.25, 30.75, 0.5, -1.0)]
+    B, t = synth.projection(rng, 256)
+    compare(ref, dev, img, kps, B, t, f"far-{dtype}")
+
+
+def test_hashsift_image_size_limits(ref, dev):
+    """Images whose row offsets do not fit the sampler's 24-bit multiplies and
+    32-bit offsets are rejected before any launch; the tallest admitted image
+    (2^24 - 1 rows) samples correctly at its far end."""
+    B, t = synth.projection(np.random.default_rng(2), 256)
+    Bd, td = torch.from_numpy(B).to(dev), torch.from_numpy(t).to(dev)
+    kps = bd.keypoints_tensor(np.zeros(1, dtype=synth.KEYPOINT_DTYPE), dev)
+    wide = torch.zeros((2, (1 << 24) + 64), dtype=torch.uint8, device=dev)[:, :100]  # pitch 2^24 + 64
+    with pytest.raises(bd.BDError, match="2\\^24"):
+        bd.describe_hashsift(wide, kps, Bd, td)
+    tall = torch.zeros((1 << 24, 1), dtype=torch.uint8, device=dev)  # H = 2^24
+    with pytest.raises(bd.BDError, match="2\\^24"):
+        bd.hashsift_features(tall, kps)
+    rng = np.random.default_rng(12)
+    tall_ok = rng.integers(0, 256, size=((1 << 24) - 1, 3), dtype=np.uint8)
+    kp = np.zeros(2, dtype=synth.KEYPOINT_DTYPE)
+    kp[:] = [(1.0, 16777000.0, 2.0, 0.3), (1.5, 16777210.0, 1.0, 1.3)]
+    compare(ref, dev, tall_ok, kp, B, t, "tall")
