@@ -71,7 +71,7 @@ class Workload:
         self.table = bd.BadTable(self.pairs)  # compiled once, like a plan
         self.B, self.t = T(w.B), T(w.t)
         self.order = [torch.empty((N_KP,), dtype=torch.int32, device=dev) for _ in range(2)]
-        self.ii = [torch.empty((H + 1, W + 1), dtype=torch.uint32, device=dev) for _ in range(2)]
+        self.ii = [bd.integral_buffer(H, W, dev) for _ in range(2)]
         self.bad = [torch.empty((N_KP, BAD_BITS // 64), dtype=torch.uint64, device=dev) for _ in range(2)]
         self.hist = [torch.empty((N_KP, 128), dtype=torch.float32, device=dev) for _ in range(2)]
         self.hs = [torch.empty((N_KP, HS_BITS // 64), dtype=torch.uint64, device=dev) for _ in range(2)]
@@ -515,7 +515,7 @@ def batched_step(dev, reps=5):
 
     offs = np.concatenate([[0], np.cumsum(n_kp)])
     kp_views = [kps[offs[j]:offs[j + 1]] for j in range(len(imgs))]
-    iis = [torch.empty((im.shape[0] + 1, im.shape[1] + 1), dtype=torch.uint32, device=dev) for im in imgs]
+    iis = [bd.integral_buffer(im.shape[0], im.shape[1], dev) for im in imgs]
     plain = {"bad": [torch.empty((n, 8), dtype=torch.uint64, device=dev) for n in n_kp],
              "hs": [torch.empty((n, 4), dtype=torch.uint64, device=dev) for n in n_kp]}
     pidx = {c: [torch.empty((n_kp[q], 2), dtype=torch.int32, device=dev) for q, _ in w.matches] for c in plain}

@@ -214,13 +214,23 @@ def pairs_tensor(pairs: np.ndarray, device="cuda"):
 # --------------------------------------------------------------------------- entry points
 
 
+def integral_buffer(H, W, device):
+    """An (H+1, W+1) uint32 view whose rows start 16-byte aligned (row stride
+    W+1 rounded up to a multiple of 4), the layout the integral-image kernel
+    writes with full-width stores."""
+    torch = _torch()
+    pitch = (W + 1 + 3) // 4 * 4
+    return torch.empty((H + 1, pitch), dtype=torch.uint32, device=device)[:, :W + 1]
+
+
 def build_integral(img, out=None):
-    """(H, W) uint8 image -> (H+1, W+1) uint32 integral image (bd_build_integral)."""
+    """(H, W) uint8 image -> (H+1, W+1) uint32 integral image (bd_build_integral).
+    Without `out`, the result is an integral_buffer view (padded rows)."""
     torch = _torch()
     _require(img, torch.uint8, 2, "img")
     H, W = img.shape
     if out is None:
-        out = torch.empty((H + 1, W + 1), dtype=torch.uint32, device=img.device)
+        out = integral_buffer(H, W, img.device)
     _require(out, torch.uint32, 2, "out")
     dev, stream = _device_and_stream(img, out)
     _check(lib().bd_build_integral(context(dev, stream), img.data_ptr(), W, H, img.stride(0), out.data_ptr(),

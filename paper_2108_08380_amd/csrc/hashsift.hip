@@ -229,13 +229,17 @@ __device__ __forceinline__ void fetch_fixed(const uint8_t* __restrict__ img, int
 
 // Resampling with fixed-point positions (every sample within 2^30 pixels of
 // the origin).  Core: 16 steps over the 32x32 interior, lane (h, c) at
-// sample (1 + h + 2t, 1 + c), four steps' loads in flight at a time; then
-// the apron rows 0 and 33 (columns 1..32) and columns 0 and 33 (rows 1..32).
-template <int DT>
+// sample (1 + h + 2t, 1 + c); apron: rows 0 and 33 (columns 1..32) and
+// columns 0 and 33 (rows 1..32), fetched with the last round.  Every load
+// of a round of R steps is in flight before any is used: R = 8 (two round
+// trips) where a launch holds about one keypoint per wavefront and so is
+// bound by these round trips, R = 4 (fewer registers) for persistent loops.
+template <int DT, int R>
 __device__ __forceinline__ void resample_fixed(const uint8_t* __restrict__ img, int32_t W, int32_t H,
                                                uint32_t upitch, double kx, double ky, double sa, double sb,
                                                float base, float* P, int lane)
 {
+    static_assert(16 % R == 0, "rounds must tile the 16 core steps");
     const int wm1 = W - 1, hm1 = H - 1;
     const int h = lane >> 5, c = lane & 31;
     const double ux = (double)c - 15.5, uy = (double)h - 15.5;
@@ -243,28 +247,36 @@ __device__ __forceinline__ void resample_fixed(const uint8_t* __restrict__ img, 
     int64_t Y = to_fixed(fma(sb, ux, fma(sa, uy, ky)));
     const int64_t dX = to_fixed(-2.0 * sb), dY = to_fixed(2.0 * sa);
     float* dst = P + (1 + h) * kApron + 1 + c;
-    constexpr int kStep = 4;
 #pragma unroll 1
-    for (int t0 = 0; t0 < 16; t0 += kStep) {
-        float v[kStep][4], fx[kStep], fy[kStep];
+    for (int t0 = 0; t0 < 16 - R; t0 += R) {
+        float v[R][4], fx[R], fy[R];
 #pragma unroll
-        for (int g = 0; g < kStep; ++g) {
+        for (int g = 0; g < R; ++g) {
             fetch_fixed<DT>(img, wm1, hm1, upitch, X, Y, v[g], fx[g], fy[g]);
             X += dX;
             Y += dY;
         }
 #pragma unroll
-        for (int g = 0; g < kStep; ++g) dst[(t0 + g) * 2 * kApron] = bilinear<DT>(v[g], fx[g], fy[g], base);
+        for (int g = 0; g < R; ++g) dst[(t0 + g) * 2 * kApron] = bilinear<DT>(v[g], fx[g], fy[g], base);
     }
-    // apron: rows 0 / 33 at column 1 + c, then columns 0 / 33 at row 1 + c
+    // last round: core steps 16 - R .. 15, then rows 0 / 33 at column 1 + c
+    // and columns 0 / 33 at row 1 + c
+    float v[R + 2][4], fx[R + 2], fy[R + 2];
+#pragma unroll
+    for (int g = 0; g < R; ++g) {
+        fetch_fixed<DT>(img, wm1, hm1, upitch, X, Y, v[g], fx[g], fy[g]);
+        X += dX;
+        Y += dY;
+    }
     const double ar = h ? 16.5 : -16.5, ac = (double)c - 15.5;
-    float v[2][4], fx[2], fy[2];
     fetch_fixed<DT>(img, wm1, hm1, upitch, to_fixed(fma(sa, ac, fma(-sb, ar, kx))),
-                    to_fixed(fma(sb, ac, fma(sa, ar, ky))), v[0], fx[0], fy[0]);
+                    to_fixed(fma(sb, ac, fma(sa, ar, ky))), v[R], fx[R], fy[R]);
     fetch_fixed<DT>(img, wm1, hm1, upitch, to_fixed(fma(sa, ar, fma(-sb, ac, kx))),
-                    to_fixed(fma(sb, ar, fma(sa, ac, ky))), v[1], fx[1], fy[1]);
-    P[(h ? 33 : 0) * kApron + 1 + c] = bilinear<DT>(v[0], fx[0], fy[0], base);
-    P[(1 + c) * kApron + (h ? 33 : 0)] = bilinear<DT>(v[1], fx[1], fy[1], base);
+                    to_fixed(fma(sb, ar, fma(sa, ac, ky))), v[R + 1], fx[R + 1], fy[R + 1]);
+#pragma unroll
+    for (int g = 0; g < R; ++g) dst[(16 - R + g) * 2 * kApron] = bilinear<DT>(v[g], fx[g], fy[g], base);
+    P[(h ? 33 : 0) * kApron + 1 + c] = bilinear<DT>(v[R], fx[R], fy[R], base);
+    P[(1 + c) * kApron + (h ? 33 : 0)] = bilinear<DT>(v[R + 1], fx[R + 1], fy[R + 1], base);
 }
 
 // Resampling with FP64 positions, for keypoints far outside any image (or
@@ -312,7 +324,7 @@ __device__ __forceinline__ void resample_f64(const uint8_t* __restrict__ img, in
 
 // The histogram of one keypoint, computed by one wavefront with a
 // kWaveLds-float LDS slice P; writes the 128 features to out.
-template <int DT>
+template <int DT, int R>
 __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_t W, int32_t H, int64_t pitch,
                                          const bd_keypoint kp, float* __restrict__ out, float* P, int lane)
 {
@@ -335,7 +347,7 @@ __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_
     // (j - 16.5, i - 16.5); its image position is (kx, ky) plus that offset
     // rotated and scaled by (sa, sb).
     if (fabs((double)kp.x) + 24.0 * kp.scale < 1073741824.0 && fabs((double)kp.y) + 24.0 * kp.scale < 1073741824.0)
-        resample_fixed<DT>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
+        resample_fixed<DT, R>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
     else
         resample_f64<DT>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
     wave_sync();
@@ -439,7 +451,7 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
     if (pos >= n_kp) return;
     const int n = order ? order[pos] : pos;
     if (n < 0 || n >= n_kp) return;  // malformed order entries are skipped
-    hist_one<DT>(img, W, H, pitch, kps[n], hist + (int64_t)n * 128, smem[wave], lane);
+    hist_one<DT, 8>(img, W, H, pitch, kps[n], hist + (int64_t)n * 128, smem[wave], lane);
 }
 
 // Batch: units are blocks of four keypoints of every image in turn (pre is
@@ -472,12 +484,12 @@ __global__ __launch_bounds__(256, DT == BD_DTYPE_U8 ? 5 : 4) void hashsift_hist_
         int lane = threadIdx.x % kWave;
         asm volatile("" : "+v"(lane));
         if constexpr (DT != kMixedDtypes) {
-            hist_one<DT>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave], lane);
+            hist_one<DT, 4>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave], lane);
         } else if (im.hs_dtype == BD_DTYPE_U8) {
-            hist_one<BD_DTYPE_U8>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave],
+            hist_one<BD_DTYPE_U8, 4>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave],
                                   lane);
         } else {
-            hist_one<BD_DTYPE_F32>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave],
+            hist_one<BD_DTYPE_F32, 4>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave],
                                    lane);
         }
     }
@@ -495,7 +507,7 @@ __global__ __launch_bounds__(256) void hashsift_patch_kernel(const float* __rest
     const int i = blockIdx.x * kHistWaves + wave;
     if (i >= n) return;
     const bd_keypoint kp{15.5f, 15.5f, 1.0f, 0.0f};
-    hist_one<BD_DTYPE_F32>(reinterpret_cast<const uint8_t*>(patches + (int64_t)i * 1024), 32, 32, 128, kp,
+    hist_one<BD_DTYPE_F32, 4>(reinterpret_cast<const uint8_t*>(patches + (int64_t)i * 1024), 32, 32, 128, kp,
                            hist + (int64_t)i * 128, smem[wave], lane);
 }
 

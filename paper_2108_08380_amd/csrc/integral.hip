@@ -27,28 +27,51 @@ constexpr int kTileCols = 256;  // 64 lanes x 4 columns
 constexpr int kWavesPerBlock = 4;
 
 // Four pixels of row `y` starting at column x, packed little-endian into one
-// u32 (a byte per pixel); columns >= W read as zero.  When the row is not
-// 4-byte aligned, the two aligned dwords around the four bytes are loaded
-// and shifted into place (v_alignbyte); each of them holds at least one
-// byte of the row, so neither crosses into memory the image does not own.
+// u32 (a byte per pixel); columns >= W read as zero.  Only for tiles that
+// cross the right image edge (per-lane bounds checks).
 __device__ __forceinline__ uint32_t load_quad(const uint8_t* __restrict__ img, int64_t pitch, int32_t y,
                                               int32_t x, int32_t W, bool aligned)
 {
     const uint8_t* row = img + (int64_t)y * pitch;
-    if (x + 3 < W) {
-        if (aligned) return *reinterpret_cast<const uint32_t*>(row + x);
-        const uintptr_t addr = reinterpret_cast<uintptr_t>(row + x);
-        const uint32_t* p = reinterpret_cast<const uint32_t*>(addr & ~(uintptr_t)3);
-        const uint32_t sh = (uint32_t)(addr & 3u);
-        const uint32_t lo = p[0];
-        const uint32_t hi = sh ? p[1] : 0u;
-        return __builtin_amdgcn_alignbyte(hi, lo, sh);
-    }
+    if (aligned && x + 3 < W) return *reinterpret_cast<const uint32_t*>(row + x);
     uint32_t w = 0u;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         if (x + k < W) w |= (uint32_t)row[x + k] << (8 * k);
     return w;
+}
+
+// The 16 row quads of a tile at rows y0.. and column x of this lane.  A
+// tile wholly inside the image (a wave-uniform test) issues all 16 loads
+// back to back, with no branch between them; edge tiles check rows and
+// columns.  Unaligned rows: the aligned dwords holding the first and the
+// last of the four bytes (the same dword when the row happens to be
+// aligned) shifted into place with v_alignbyte; each holds a byte of the
+// row, so neither reaches memory the image does not own.
+__device__ __forceinline__ void load_tile(const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t y0,
+                                          int32_t rows, int32_t x0, int32_t x, bool aligned, uint32_t (&q)[16])
+{
+    if (rows == 16 && x0 + 256 <= W) {
+        const uint8_t* p = img + (int64_t)y0 * pitch + x;
+        if (aligned) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) q[r] = *reinterpret_cast<const uint32_t*>(p + r * pitch);
+        } else {
+            uint32_t lo[16], hi[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uintptr_t a = reinterpret_cast<uintptr_t>(p + r * pitch);
+                lo[r] = *reinterpret_cast<const uint32_t*>(a & ~(uintptr_t)3);
+                hi[r] = *reinterpret_cast<const uint32_t*>((a + 3) & ~(uintptr_t)3);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                q[r] = __builtin_amdgcn_alignbyte(hi[r], lo[r], (uint32_t)(reinterpret_cast<uintptr_t>(p + r * pitch) & 3u));
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) q[r] = r < rows ? load_quad(img, pitch, y0 + r, x, W, aligned) : 0u;
+    }
 }
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t w, int k) { return (w >> (8 * k)) & 0xffu; }
@@ -136,8 +159,7 @@ __device__ __forceinline__ void tile_sums_body(const uint8_t* __restrict__ img, 
     const int y0 = s * kTileRows, x = c * kTileCols + 4 * lane;
     const int rows = min(kTileRows, H - y0);
     uint32_t q[kTileRows];
-#pragma unroll
-    for (int r = 0; r < kTileRows; ++r) q[r] = r < rows ? load_quad(img, pitch, y0 + r, x, W, aligned) : 0u;
+    load_tile(img, pitch, W, y0, rows, c * kTileCols, x, aligned, q);
     uint32_t col[4] = {0u, 0u, 0u, 0u};
     uint32_t rs[kTileRows];
 #pragma unroll
@@ -154,20 +176,33 @@ __device__ __forceinline__ void tile_sums_body(const uint8_t* __restrict__ img, 
     if (lane == 0) colsum[(int64_t)s * col_pitch + (int64_t)slabs * kTileCols + c] = tile_total;
 }
 
-// One thread: exclusive scan down the strips of column x of the column table
-// (eight strips loaded per round).
+// One thread: exclusive scan down the strips of column x of the column table.
+// The scan is a chain of load round trips, so 32 strips are loaded per
+// round, unconditionally for whole rounds.
 __device__ __forceinline__ void carry_col_body(uint32_t* __restrict__ colsum, int32_t strips, int64_t col_pitch,
                                                int64_t x)
 {
-    constexpr int kBatch = 8;
+    constexpr int kBatch = 32;
     uint32_t acc = 0u;
-    for (int s0 = 0; s0 < strips; s0 += kBatch) {
+    uint32_t* col = colsum + x;
+    int s0 = 0;
+    for (; s0 + kBatch <= strips; s0 += kBatch) {
         uint32_t v[kBatch];
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) v[k] = s0 + k < strips ? colsum[(int64_t)(s0 + k) * col_pitch + x] : 0u;
+        for (int k = 0; k < kBatch; ++k) v[k] = col[(int64_t)(s0 + k) * col_pitch];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
-            if (s0 + k < strips) colsum[(int64_t)(s0 + k) * col_pitch + x] = acc;
+            col[(int64_t)(s0 + k) * col_pitch] = acc;
+            acc += v[k];
+        }
+    }
+    if (s0 < strips) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) v[k] = s0 + k < strips ? col[(int64_t)(s0 + k) * col_pitch] : 0u;
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            if (s0 + k < strips) col[(int64_t)(s0 + k) * col_pitch] = acc;
             acc += v[k];
         }
     }
@@ -203,10 +238,13 @@ __device__ __forceinline__ void tile_write_body(const uint8_t* __restrict__ img,
 
     // every load of the tile is issued before any arithmetic
     uint32_t q[kTileRows], rc[kTileRows];
+    load_tile(img, pitch, W, y0, rows, x0, x, aligned, q);
+    if (rows == kTileRows) {
 #pragma unroll
-    for (int r = 0; r < kTileRows; ++r) {
-        q[r] = r < rows ? load_quad(img, pitch, y0 + r, x, W, aligned) : 0u;
-        rc[r] = r < rows ? rowcarry[(int64_t)(y0 + r) * slabs + c] : 0u;
+        for (int r = 0; r < kTileRows; ++r) rc[r] = rowcarry[(int64_t)(y0 + r) * slabs + c];
+    } else {
+#pragma unroll
+        for (int r = 0; r < kTileRows; ++r) rc[r] = r < rows ? rowcarry[(int64_t)(y0 + r) * slabs + c] : 0u;
     }
     const uint32_t* strip_row = colcarry + (int64_t)s * col_pitch;
     const uint4 cv = *reinterpret_cast<const uint4*>(strip_row + x);
@@ -224,10 +262,28 @@ __device__ __forceinline__ void tile_write_body(const uint8_t* __restrict__ img,
 #pragma unroll
     for (int k = 0; k < 4; ++k) above[k] += above_off;
 
+    // Stores.  With 16-byte aligned output rows, a tile wholly inside the
+    // image writes output columns x0 .. x0 + 255 as one aligned 16-byte
+    // store per lane: lane l takes the last value of lane l - 1 (a DPP
+    // wavefront shift), lane 0 the boundary column x0 = corner + left, and
+    // the rightmost tile also writes column W.  Otherwise each lane writes
+    // its columns x + 1 .. x + 4 one by one; next to an aligned tile it also
+    // writes the boundary column x0 the tile on its left leaves out.
+    const bool rows_aligned = ((reinterpret_cast<uintptr_t>(ii) | (uintptr_t)ii_pitch * 4u) & 15u) == 0;
+    const bool wide = rows_aligned && x0 + kTileCols <= W;
+    const bool last_col = x0 + kTileCols == W && lane == kWave - 1;
+    const bool boundary = rows_aligned && !wide && c > 0 && lane == 0;
+
     if (s == 0) {  // zero first row of the integral image
-        for (int k = 0; k < 4; ++k)
-            if (x + k < W) ii[x + k + 1] = 0u;
-        if (c == 0 && lane == 0) ii[0] = 0u;
+        if (wide) {
+            *reinterpret_cast<uint4*>(ii + x0 + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
+            if (last_col) ii[W] = 0u;
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (x + k < W) ii[x + k + 1] = 0u;
+            if (c == 0 && lane == 0) ii[0] = 0u;
+            if (boundary) ii[x0] = 0u;
+        }
     }
 
     uint32_t acc[4] = {0u, 0u, 0u, 0u};
@@ -242,13 +298,26 @@ __device__ __forceinline__ void tile_write_body(const uint8_t* __restrict__ img,
         p[2] = p[1] + byte_of(q[r], 2);
         p[3] = p[2] + byte_of(q[r], 3);
         const uint32_t off = wave_exclusive_scan(p[3], lane);
-        uint32_t* out = ii + (int64_t)(y0 + r + 1) * ii_pitch;
+        uint32_t v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             acc[k] += p[k] + off;
-            if (x + k < W) out[x + k + 1] = above[k] + left + acc[k];
+            v[k] = above[k] + left + acc[k];
         }
-        if (c == 0 && lane == 0) out[0] = 0u;
+        uint32_t* out = ii + (int64_t)(y0 + r + 1) * ii_pitch;
+        if (wide) {
+            // wave_shr:1; lane 0 keeps `old`, the boundary column
+            const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int)(corner + left), (int)v[3], 0x138, 0xf,
+                                                                        0xf, false);
+            *reinterpret_cast<uint4*>(out + x0 + 4 * lane) = make_uint4(prev, v[0], v[1], v[2]);
+            if (last_col) out[W] = v[3];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (x + k < W) out[x + k + 1] = v[k];
+            if (c == 0 && lane == 0) out[0] = 0u;
+            if (boundary) out[x0] = corner + left;
+        }
     }
 }
 

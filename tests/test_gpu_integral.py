@@ -83,3 +83,29 @@ def test_integral_near_the_index_limit(ref, dev):
     cols = torch.from_numpy(rng.integers(0, W + 1, 64)).to(dev)
     np.testing.assert_array_equal(iv[:, cols].cpu().numpy().view(np.uint32), exp[:, cols.cpu().numpy()])
     assert int(got_rows[-1, -1]) == int(img.sum(dtype=np.uint64) % (1 << 32))
+
+
+@pytest.mark.parametrize("W", [255, 256, 257, 512, 700, 1023, 1024])
+@pytest.mark.parametrize("aligned_rows", [True, False])
+def test_integral_row_alignment(ref, dev, W, aligned_rows):
+    """16-byte aligned output rows (row stride a multiple of 4) take the
+    full-width store path, with the boundary column shared by neighbouring
+    tiles and column W written by the rightmost tile; other strides store
+    per column.  Both equal the oracle and leave the row padding untouched."""
+    H = 37
+    rng = np.random.default_rng(W * 3 + aligned_rows)
+    img = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    pitch = (W + 1 + 3) // 4 * 4 + 4 if aligned_rows else (W + 1) | 1
+    if not aligned_rows and pitch % 4 == 0:
+        pitch += 1
+    parent = torch.full((H + 1, pitch), 7, dtype=torch.uint32, device=dev)
+    out = parent[:, : W + 1]
+    bd.build_integral(torch.from_numpy(img).to(dev), out=out)
+    got = to_np(parent)
+    np.testing.assert_array_equal(got[:, : W + 1], ref.build_integral(img))
+    assert (got[:, W + 1:] == 7).all(), "wrote outside the output rows"
+
+
+def test_integral_default_buffer_is_aligned(dev):
+    ii = bd.build_integral(torch.zeros((5, 300), dtype=torch.uint8, device=dev))
+    assert ii.shape == (6, 301) and ii.stride(0) % 4 == 0 and ii.data_ptr() % 16 == 0
