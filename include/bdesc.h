@@ -199,6 +199,10 @@ int bd_hashsift_project(bd_context* ctx, const float* hist, const bd_keypoint* k
  * For each query the k smallest (distance, train index) pairs in
  * lexicographic order (equal distances: lower index first).  Slots beyond
  * n_t get idx = -1 and dist = 0xFFFFFFFF.  n_words in 1..8, k in 1..2.
+ * Codes of 4 and 8 words (256 and 512 bits) run on the int8 MFMA units as
+ * the inner product of -+1 query bytes with 0/1 train bytes (exact); other
+ * widths on a lane-per-query XOR/popcount kernel.  Codes must be 8-byte
+ * aligned.
  */
 int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q,
                          const uint64_t* train, int32_t n_t, int32_t n_words, int32_t k,
@@ -350,8 +354,11 @@ typedef struct bd_batch_match {
 
 /* Schedule knobs.  Grids are blocks_per_cu x CUs (capped by the stage's
  * work units, rounded to a multiple of the 8 XCDs).  knn_*[0] set the BAD
- * matcher, knn_*[1] the HashSIFT matcher: queries per lane (1, 2, 4) and
- * train rows per work unit (BD_BATCH_MIN_ROWS .. BD_BATCH_MAX_ROWS). */
+ * matcher, knn_*[1] the HashSIFT matcher: the engine, knn_qpl = 0 for the
+ * int8 MFMA engine (blocks of 256 queries) or 1, 2, 4 queries per lane of
+ * the lane-per-query kernel, and train rows per work unit
+ * (BD_BATCH_MIN_ROWS .. BD_BATCH_MAX_ROWS, a multiple of 16 for the MFMA
+ * engine).  Results do not depend on the knobs. */
 typedef struct bd_batch_tuning {
     int32_t order_blocks_per_cu;
     int32_t integral_blocks_per_cu;

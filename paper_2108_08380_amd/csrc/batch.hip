@@ -129,7 +129,7 @@ void plan_matcher(const bd_batch* b, Matcher& m, int32_t qpl, int32_t rows, std:
     recs.assign(b->n_match, BatchMatch{});
     pre.assign(b->n_match + 1, 0);
     mpre.assign(b->n_match + 1, 0);
-    const int qpw = knn_queries_per_wave(qpl);
+    const int qpw = knn_queries_per_unit(qpl);
     int64_t part = 0;
     for (int i = 0; i < b->n_match; ++i) {
         const BatchImage& q = b->images[b->matches[i].query_image];
@@ -166,8 +166,8 @@ int apply_matcher(bd_batch* b, Matcher& m, int32_t qpl, int32_t rows, int32_t bl
     plan_matcher(b, m, qpl, rows, recs, pre, mpre);
     if (m.partial_elems > b->partial_cap) return fail(BD_EINVAL, "%s: partial buffer too small for %d rows per unit", fn, rows);
     const int num_cus = b->ctx->num_cus;
-    // the matcher counts units per wavefront, four wavefronts per block
-    m.plan.grid = grid_for((m.units + 3) / 4, blocks_per_cu, num_cus);
+    // lane-per-query units are wavefronts (four per block), MFMA units blocks
+    m.plan.grid = grid_for(qpl == 0 ? m.units : (m.units + 3) / 4, blocks_per_cu, num_cus);
     m.plan.merge_grid = grid_for(m.plan.merge_units, 4, num_cus);
     hipError_t e = hipMemcpy(m.d_match, recs.data(), sizeof(BatchMatch) * recs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m.d_pre, pre.data(), sizeof(int32_t) * pre.size(), hipMemcpyHostToDevice);
@@ -197,11 +197,13 @@ int check_tuning(const bd_batch_tuning& t)
     for (const int32_t* v : bpc)
         if (*v < 1 || *v > 64) return fail(BD_EINVAL, "%s: blocks per CU %d outside [1, 64]", fn, *v);
     for (int i = 0; i < 2; ++i) {
-        if (t.knn_qpl[i] != 1 && t.knn_qpl[i] != 2 && t.knn_qpl[i] != 4)
-            return fail(BD_EINVAL, "%s: queries per lane %d (1, 2 or 4)", fn, t.knn_qpl[i]);
+        if (t.knn_qpl[i] != 0 && t.knn_qpl[i] != 1 && t.knn_qpl[i] != 2 && t.knn_qpl[i] != 4)
+            return fail(BD_EINVAL, "%s: queries per lane %d (0 for the MFMA engine, 1, 2 or 4)", fn, t.knn_qpl[i]);
         if (t.knn_rows[i] < BD_BATCH_MIN_ROWS || t.knn_rows[i] > BD_BATCH_MAX_ROWS)
             return fail(BD_EINVAL, "%s: rows per unit %d outside [%d, %d]", fn, t.knn_rows[i], BD_BATCH_MIN_ROWS,
                         BD_BATCH_MAX_ROWS);
+        if (t.knn_qpl[i] == 0 && t.knn_rows[i] % 16 != 0)
+            return fail(BD_EINVAL, "%s: rows per unit %d of the MFMA engine not a multiple of 16", fn, t.knn_rows[i]);
     }
     return BD_OK;
 }
@@ -344,9 +346,9 @@ int bd_batch_default_tuning(bd_batch_tuning* out)
     t.bad_blocks_per_cu = 8;
     t.hist_blocks_per_cu = 4;
     for (int i = 0; i < 2; ++i) {
-        t.knn_qpl[i] = 1;
+        t.knn_qpl[i] = 0;
         t.knn_rows[i] = 1024;
-        t.knn_blocks_per_cu[i] = 4;
+        t.knn_blocks_per_cu[i] = 2;
     }
     *out = t;
     return BD_OK;
@@ -664,7 +666,7 @@ int bd_batch_autotune(bd_batch* b, const bd_keypoint* kps, const bd_box_pair* pa
         best.*kn.field = best_v;
     }
 
-    static const int kQpl[] = {1, 2, 4};
+    static const int kQpl[] = {0, 1, 2, 4};
     static const int kRows[] = {256, 512, 1024, 2048, 4096};
     static const int kKnnGrid[] = {2, 4, 8};
     for (int j = 0; j < 2 && rc == BD_OK && b->n_match > 0; ++j) {

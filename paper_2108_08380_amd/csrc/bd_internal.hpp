@@ -182,7 +182,8 @@ void launch_trl_bwd(const float* A, const float* P, int32_t n, int32_t K, const 
 // ---- Hamming k-NN (hamming.hip)
 struct KnnPlan {
     int32_t n_q, n_t, n_words, k;
-    int32_t qpl;             // queries per lane
+    int32_t mfma;            // 1: int8 MFMA engine (4 or 8 words), 0: lane-per-query kernel
+    int32_t qpl;             // queries per lane (lane-per-query kernel)
     int32_t splits;          // train-set splits (grid.y)
     int32_t rows_per_split;  // <= 2^22 so a (distance, local row) key fits 32 bits
     size_t workspace_bytes() const;
@@ -225,12 +226,14 @@ void launch_augment(const float* pool, int32_t n_pairs, const int32_t* batch, in
 // Batched k-NN over BatchMatch problems sharing n_words (4 or 8) and k.
 struct KnnBatchPlan {
     int32_t n_words, k;
-    int32_t qpl;             // queries per lane
+    int32_t qpl;             // 0: int8 MFMA engine; 1, 2, 4: queries per lane of the lane-per-query kernel
     int32_t rows_per_split;  // train rows per unit, <= 2^22
     int32_t grid;            // blocks of the k-NN kernel (multiple of 8)
     int32_t merge_units, merge_grid;
 };
-int knn_queries_per_wave(int qpl);
+// Queries per unit of the batch k-NN: a wavefront of the lane-per-query
+// kernel (qpl 1, 2, 4) or a block of the MFMA engine (qpl 0).
+int knn_queries_per_unit(int qpl);
 void launch_knn_batch(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, const int32_t* pre,
                       const int32_t* merge_pre, const uint64_t* codes, uint32_t* partial, int32_t* idx,
                       uint32_t* dist, hipStream_t stream);

@@ -180,7 +180,7 @@ def test_batch_validation(L):
 def test_batch_tuning_and_run_validation(L):
     tn = bd.BatchTuning()
     assert L.bd_batch_default_tuning(ctypes.byref(tn)) == bd.BD_OK
-    assert tn.knn_rows[0] >= 256 and tn.knn_qpl[1] in (1, 2, 4)
+    assert tn.knn_rows[0] >= 256 and tn.knn_qpl[1] in (0, 1, 2, 4)
     assert L.bd_batch_default_tuning(None) == bd.BD_EINVAL
     assert L.bd_batch_set_tuning(None, ctypes.byref(tn)) == bd.BD_EINVAL
     assert L.bd_batch_get_tuning(None, ctypes.byref(tn)) == bd.BD_EINVAL

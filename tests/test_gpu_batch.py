@@ -122,6 +122,9 @@ def test_batch_outputs_do_not_depend_on_tuning(dev):
         dict(integral_blocks_per_cu=16, bad_blocks_per_cu=16, hist_blocks_per_cu=8,
              knn_qpl=[2, 4], knn_rows=[4096, 512], knn_blocks_per_cu=[8, 2]),
         dict(knn_qpl=[4, 2], knn_rows=[1 << 22, 300], knn_blocks_per_cu=[16, 16]),
+        # the MFMA engine: one-unit splits, several per problem, one for all
+        dict(knn_qpl=[0, 0], knn_rows=[256, 272], knn_blocks_per_cu=[1, 3]),
+        dict(knn_qpl=[0, 1], knn_rows=[1 << 22, 1024], knn_blocks_per_cu=[2, 4]),
     ]
     for tn in tunings:
         b.tuning = tn
@@ -152,7 +155,7 @@ def test_batch_autotune_keeps_results(dev):
     ref = b.run(kps, pairs, B, t, graph=False)
     out = b.allocate_outputs()
     tn = b.autotune(kps, pairs, B, t, out=out, reps=1)
-    assert tn["knn_qpl"][0] in (1, 2, 4) and tn["knn_rows"][0] >= 256
+    assert tn["knn_qpl"][0] in (0, 1, 2, 4) and tn["knn_rows"][0] >= 256
     assert_same(out, ref, "autotune outputs")
     assert_same(b.run(kps, pairs, B, t), ref, "after autotune")
 
@@ -189,6 +192,8 @@ def test_batch_validation_errors(dev):
         b.tuning = dict(knn_rows=[100, 1024])
     with pytest.raises(bd.BDError, match="queries per lane"):
         b.tuning = dict(knn_qpl=[3, 1])
+    with pytest.raises(bd.BDError, match="multiple of 16"):
+        b.tuning = dict(knn_qpl=[0, 1], knn_rows=[300, 1024])
     # a rejected tuning leaves the batch usable
     assert_same(b.run(kps, pairs, B, t), single_image_outputs(w, imgs, hs, kps, pairs, B, t))
 

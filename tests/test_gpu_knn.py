@@ -110,3 +110,42 @@ def test_train_set_beyond_packed_row_range(ref, dev):
         np.testing.assert_array_equal(to_np(idx), ei)
         np.testing.assert_array_equal(to_np(dist), ed)
     assert ei[0, 0] == (1 << 22) - 7 and ei[1, 0] == (1 << 22) + 100 and ei[2, 0] == n_t - 1
+
+
+@pytest.mark.parametrize("n_words", [4, 8])
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("n_q,n_t", [(15, 63), (16, 64), (17, 65), (255, 129), (256, 300), (257, 1031)])
+def test_mfma_tile_and_chunk_boundaries(ref, dev, n_words, k, n_q, n_t):
+    """Codes of 4 and 8 words run on the int8 MFMA engine (16-query x 16-row
+    tiles, 64-row LDS chunks, 256 queries per block): query and train counts
+    around those sizes, with equal codes planted across tiles and chunks so
+    ties must resolve to the lower index, and a partial last chunk."""
+    rng = np.random.default_rng(n_q * 7 + n_t * 3 + n_words + k)
+    t = synth.random_codes(rng, n_t, n_words)
+    q = synth.random_codes(rng, n_q, n_words)
+    for j, r in enumerate(sorted({0, 15, 16, 63, 64, n_t - 1} & set(range(n_t)))):
+        t[r] = q[j % n_q]                      # exact matches in different tiles and chunks
+    t[n_t - 1] = t[min(15, n_t - 1)]          # a tie between the first and the last chunk
+    q[n_q - 1] = t[n_t // 2] ^ np.uint64(1)    # a near match in the middle
+    gi, gd, ei, ed = both(ref, dev, q, t, k)
+    np.testing.assert_array_equal(gd, ed)
+    np.testing.assert_array_equal(gi, ei)
+
+
+def test_mfma_train_set_beyond_packed_row_range(ref, dev):
+    """4-word codes (MFMA engine) with more than 2^22 train codes: splits and
+    the merge restore global indices; duplicates on both sides of 2^22."""
+    rng = np.random.default_rng(79)
+    n_t = (1 << 22) + 1000
+    q = synth.random_codes(rng, 8, 4)
+    t = synth.random_codes(rng, n_t, 4)
+    t[(1 << 22) + 5] = q[0]
+    t[(1 << 22) - 7] = q[0]
+    t[(1 << 22) + 100] = q[1]
+    t[n_t - 1] = q[2] ^ np.uint64(1)
+    for k in (1, 2):
+        idx, dist = bd.match_hamming_knn(torch.from_numpy(q).to(dev), torch.from_numpy(t).to(dev), k=k)
+        ei, ed = ref.match_knn(q, t, k)
+        np.testing.assert_array_equal(to_np(dist), ed)
+        np.testing.assert_array_equal(to_np(idx), ei)
+    assert ei[0, 0] == (1 << 22) - 7 and ei[1, 0] == (1 << 22) + 100 and ei[2, 0] == n_t - 1
