@@ -129,7 +129,7 @@ void plan_matcher(const bd_batch* b, Matcher& m, int32_t qpl, int32_t rows, std:
     recs.assign(b->n_match, BatchMatch{});
     pre.assign(b->n_match + 1, 0);
     mpre.assign(b->n_match + 1, 0);
-    const int qpw = knn_queries_per_unit(qpl);
+    const int qpw = knn_queries_per_unit(qpl, m.n_words);
     int64_t part = 0;
     for (int i = 0; i < b->n_match; ++i) {
         const BatchImage& q = b->images[b->matches[i].query_image];

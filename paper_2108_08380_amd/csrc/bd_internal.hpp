@@ -233,7 +233,7 @@ struct KnnBatchPlan {
 };
 // Queries per unit of the batch k-NN: a wavefront of the lane-per-query
 // kernel (qpl 1, 2, 4) or a block of the MFMA engine (qpl 0).
-int knn_queries_per_unit(int qpl);
+int knn_queries_per_unit(int qpl, int n_words);
 void launch_knn_batch(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, const int32_t* pre,
                       const int32_t* merge_pre, const uint64_t* codes, uint32_t* partial, int32_t* idx,
                       uint32_t* dist, hipStream_t stream);

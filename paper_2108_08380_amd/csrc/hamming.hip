@@ -280,7 +280,10 @@ typedef int int32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaWaves = 4;
 constexpr int kMfmaChunk = 64;  // train rows per LDS stage: four 16-row tiles
-constexpr int kMfmaQM = 4;      // query tiles of 16 per wavefront
+// query tiles of 16 per wavefront: every B operand read from LDS feeds QM
+// MFMAs; the A operands take 4 QM NW VGPRs
+template <int NW>
+constexpr int mfma_qm() { return 4; }
 
 __device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c)
 {
@@ -343,7 +346,26 @@ __device__ __forceinline__ void mfma_tables(MfmaShared<NW>& sh)
     sh.bits_pm[v] = make_uint2(plo, phi);
 }
 
-// One block (256 threads): queries 256 qb .. of one problem against train
+// Distances of the wavefront's 16 QM queries to the 16 rows of tile tau of
+// an LDS chunk: D[qm] = |q| + sum over the NW words of the MFMA products.
+template <int NW, int QM>
+__device__ __forceinline__ void mfma_tile(const int32x4* chunk, int tau, int lane, const int32x4 (&A)[QM][NW],
+                                          const int32x4 (&pa)[QM], int32x4 (&D)[QM])
+{
+    {
+        const int32x4 b = chunk[(tau * NW) * kWave + lane];
+#pragma unroll
+        for (int qm = 0; qm < QM; ++qm) D[qm] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qm][0], b, pa[qm], 0, 0, 0);
+    }
+#pragma unroll
+    for (int kc = 1; kc < NW; ++kc) {
+        const int32x4 b = chunk[(tau * NW + kc) * kWave + lane];
+#pragma unroll
+        for (int qm = 0; qm < QM; ++qm) D[qm] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qm][kc], b, D[qm], 0, 0, 0);
+    }
+}
+
+// One block (256 threads): queries 64 QM qb .. of one problem against train
 // split `split` (splits start on 16-row tiles: rows_per_split is a multiple
 // of 16).  Every thread of the block calls it with the same arguments.
 template <int NW, int KK>
@@ -353,7 +375,7 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
                                                 uint32_t* __restrict__ partial, int32_t* __restrict__ out_idx,
                                                 uint32_t* __restrict__ out_dist, bool direct, MfmaShared<NW>& sh)
 {
-    constexpr int QM = kMfmaQM;
+    constexpr int QM = mfma_qm<NW>();
     auto& tiles = sh.tiles;
     const uint2* bits01 = sh.bits01;
     const uint2* bits_pm = sh.bits_pm;
@@ -426,36 +448,36 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
         const bool more = c0 + kMfmaChunk < t1;
         if (more) load_chunk(c0 + kMfmaChunk);
         const bool full = c0 + kMfmaChunk <= t1;
+        const uint32_t row0 = (uint32_t)(c0 - t0 + m);
+        if (NW == 4 && full) {
+            // software pipeline over the four tiles: the MFMAs of tile tau + 1
+            // run while tile tau's distances are inserted (8-word operands
+            // leave no registers for the second accumulator set)
+            int32x4 D[2][QM];
+            mfma_tile<NW, QM>(tiles[buf], 0, lane, A, pa, D[0]);
 #pragma unroll
-        for (int tau = 0; tau < 4; ++tau) {
-            if (!full && c0 + 16 * tau >= t1) break;  // tiles past the split end
-            int32x4 D[QM];
-            {
-                const int32x4 b = tiles[buf][(tau * NW) * kWave + lane];
-#pragma unroll
-                for (int qm = 0; qm < QM; ++qm) D[qm] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qm][0], b, pa[qm], 0, 0, 0);
-            }
-#pragma unroll
-            for (int kc = 1; kc < NW; ++kc) {
-                const int32x4 b = tiles[buf][(tau * NW + kc) * kWave + lane];
-#pragma unroll
-                for (int qm = 0; qm < QM; ++qm)
-                    D[qm] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qm][kc], b, D[qm], 0, 0, 0);
-            }
-            const uint32_t row = (uint32_t)(c0 - t0 + 16 * tau + m);
-            if (full || c0 + 16 * tau + 16 <= t1) {
+            for (int tau = 0; tau < 4; ++tau) {
+                if (tau < 3) mfma_tile<NW, QM>(tiles[buf], tau + 1, lane, A, pa, D[(tau + 1) & 1]);
 #pragma unroll
                 for (int qm = 0; qm < QM; ++qm)
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        topk_insert_med3<KK>(best[qm][i], ((uint32_t)D[qm][i] << kRowBits) | row);
-            } else {
-                const bool valid = c0 + 16 * tau + m < t1;
+                        topk_insert_med3<KK>(best[qm][i], ((uint32_t)D[tau & 1][qm][i] << kRowBits) | (row0 + 16 * tau));
+            }
+        } else {
+            // 8-word codes, and partial chunks: one tile at a time
+#pragma unroll
+            for (int tau = 0; tau < 4; ++tau) {
+                if (!full && c0 + 16 * tau >= t1) break;  // tiles past the split end
+                int32x4 D[QM];
+                mfma_tile<NW, QM>(tiles[buf], tau, lane, A, pa, D);
+                const bool valid = full || c0 + 16 * tau + m < t1;
 #pragma unroll
                 for (int qm = 0; qm < QM; ++qm)
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        topk_insert_med3<KK>(best[qm][i], valid ? ((uint32_t)D[qm][i] << kRowBits) | row : kEmpty);
+                        topk_insert_med3<KK>(best[qm][i],
+                                             valid ? ((uint32_t)D[qm][i] << kRowBits) | (row0 + 16 * tau) : kEmpty);
             }
         }
         if (more) store_chunk(buf ^ 1);
@@ -534,7 +556,7 @@ void launch_mfma_nw_k(const KnnPlan& p, const uint64_t* query, const uint64_t* t
                       uint32_t* dist, hipStream_t stream)
 {
     const int direct = p.splits == 1;
-    const int per_block = kMfmaWaves * 16 * kMfmaQM;
+    const int per_block = kMfmaWaves * 16 * mfma_qm<NW>();
     const dim3 grid((p.n_q + per_block - 1) / per_block, p.splits);
     hipLaunchKernelGGL((hamming_mfma_kernel<NW, KK>), grid, dim3(kMfmaWaves * kWave), 0, stream, query, p.n_q, train,
                        p.n_t, p.rows_per_split, partial, idx, dist, direct);
@@ -632,7 +654,10 @@ void launch_batch_nw(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, co
 
 }  // namespace
 
-int knn_queries_per_unit(int qpl) { return qpl == 0 ? kMfmaWaves * 16 * kMfmaQM : kWave * qpl; }
+int knn_queries_per_unit(int qpl, int n_words)
+{
+    return qpl == 0 ? kMfmaWaves * 16 * (n_words == 4 ? mfma_qm<4>() : mfma_qm<8>()) : kWave * qpl;
+}
 
 void launch_knn_batch(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, const int32_t* pre,
                       const int32_t* merge_pre, const uint64_t* codes, uint32_t* partial, int32_t* idx,
@@ -657,11 +682,12 @@ KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_c
     p.n_words = n_words;
     p.k = k;
     if (n_words == 4 || n_words == 8) {
-        // MFMA engine: blocks of 256 queries, two per CU; as many splits as
+        // MFMA engine: blocks of 64 QM queries, two per CU; as many splits as
         // fill one round of blocks, each of at least one 64-row chunk
         p.mfma = 1;
         p.qpl = 0;
-        const int64_t qblocks = n_q > 0 ? ((int64_t)n_q + 255) / 256 : 1;
+        const int64_t per_block = knn_queries_per_unit(0, n_words);
+        const int64_t qblocks = n_q > 0 ? ((int64_t)n_q + per_block - 1) / per_block : 1;
         const int64_t target = 2ll * (num_cus > 0 ? num_cus : 256);
         int64_t splits = target / qblocks;
         const int64_t max_splits = (n_t + 63) / 64;
