@@ -300,13 +300,15 @@ __device__ __forceinline__ void topk_insert_med3(uint32_t (&best)[KK], uint32_t 
     best[0] = min(best[0], key);
 }
 
-// Merge the top-k list of lane ^ d (a disjoint set of train rows).
-template <int KK>
-__device__ __forceinline__ void topk_merge_xor(uint32_t (&best)[KK], int d)
+// Merge the top-k list of the lane CTRL (a DPP row rotation) away inside
+// the lane's row of 16: after rotations by 8, 4, 2 and 1 every lane of the
+// row has merged the 16 disjoint lists of the row.
+template <int KK, int CTRL>
+__device__ __forceinline__ void topk_merge_ror(uint32_t (&best)[KK])
 {
-    const uint32_t p0 = (uint32_t)__shfl_xor((int)best[0], d, kWave);
+    const uint32_t p0 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best[0], CTRL, 0xf, 0xf, false);
     if constexpr (KK == 2) {
-        const uint32_t p1 = (uint32_t)__shfl_xor((int)best[1], d, kWave);
+        const uint32_t p1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best[1], CTRL, 0xf, 0xf, false);
         best[1] = min(max(best[0], p0), min(best[1], p1));
     }
     best[0] = min(best[0], p0);
@@ -415,23 +417,39 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
         }
     };
 
+    // the wavefront's query codes (rows past n_q read as zero codes; a zero
+    // code yields zero operands below), loaded before the table barrier
+    uint32_t qcode[QM][NW];  // bits 16g..16g+15 of each word
+    uint32_t pc[QM];         // |q| of query row m
+    {
+        const bool all_in = (qt0 + QM) * 16 <= n_q;
+#pragma unroll
+        for (int qm = 0; qm < QM; ++qm) {
+            const int qi = (qt0 + qm) * 16 + m;
+            const bool in = all_in || qi < n_q;
+            pc[qm] = 0u;
+#pragma unroll
+            for (int kc = 0; kc < NW; ++kc) {
+                const uint64_t v = in ? query[(int64_t)qi * NW + kc] : 0ull;
+                pc[qm] += (uint32_t)__popcll(v);
+                qcode[qm][kc] = (uint32_t)(v >> (16 * g)) & 0xffffu;
+            }
+        }
+    }
     load_chunk(t0);
     __syncthreads();  // tables; the previous unit's reads of the buffers
 
-    // queries as -+1 operands; |q| of the rows this lane receives in D
+    // queries as -+1 operands (zero for rows past n_q); |q| of the rows this
+    // lane receives in D
     int32x4 A[QM][NW], pa[QM];
 #pragma unroll
     for (int qm = 0; qm < QM; ++qm) {
-        const int qi = (qt0 + qm) * 16 + m;
-        uint32_t pc = 0u;
+        const bool in = (qt0 + qm) * 16 + m < n_q;
 #pragma unroll
-        for (int kc = 0; kc < NW; ++kc) {
-            const uint64_t v = qi < n_q ? query[(int64_t)qi * NW + kc] : 0ull;
-            pc += (uint32_t)__popcll(v);
-            A[qm][kc] = qi < n_q ? expand16(bits_pm, (uint32_t)(v >> (16 * g)) & 0xffffu) : int32x4{0, 0, 0, 0};
-        }
+        for (int kc = 0; kc < NW; ++kc)
+            A[qm][kc] = in ? expand16(bits_pm, qcode[qm][kc]) : int32x4{0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) pa[qm][i] = __shfl((int)pc, 4 * g + i, kWave);
+        for (int i = 0; i < 4; ++i) pa[qm][i] = __shfl((int)pc[qm], 4 * g + i, kWave);
     }
     uint32_t best[QM][4][KK];
 #pragma unroll
@@ -485,13 +503,17 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
         buf ^= 1;
     }
 
-    // merge over the 16 lanes of each query row, then lane m == 0 writes
+    // merge over the 16 lanes of each query row (DPP row_ror:8, 4, 2, 1),
+    // then lane m == 0 writes
 #pragma unroll
     for (int qm = 0; qm < QM; ++qm)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int d = 1; d < 16; d <<= 1) topk_merge_xor<KK>(best[qm][i], d);
+        for (int i = 0; i < 4; ++i) {
+            topk_merge_ror<KK, 0x128>(best[qm][i]);
+            topk_merge_ror<KK, 0x124>(best[qm][i]);
+            topk_merge_ror<KK, 0x122>(best[qm][i]);
+            topk_merge_ror<KK, 0x121>(best[qm][i]);
+        }
     if (m != 0) return;
 #pragma unroll
     for (int qm = 0; qm < QM; ++qm)
