@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 64 lanes x 2.4 GHz: one 32-bit VALU op per lane per clock (not packed)
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 FP32_MFMA_PEAK_TFLOPS = 157.3
+INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 MFMA, 5.0 POP/s
 
 W, H, N_KP = 1920, 1080, 5000
 BAD_BITS, HS_BITS, K = 256, 512, 2
@@ -148,9 +149,9 @@ def stage_work():
         "hashsift_features": ("alu", (1156 * 14 + 1024 * 50) * N_KP, "TOP/s"),
         # projection: 2 * n_bits * 128 flops per keypoint on FP32 MFMA
         "hashsift_project": ("mfma", 2.0 * HS_BITS * 128 * N_KP, "TFLOP/s"),
-        # Hamming: per pair 4 ops per 64-bit word (2 xor + 2 popcount) + 4 for the top-2 key update
-        "match_bad256": ("alu", (4 * BAD_BITS / 64 + 4) * float(N_KP) * N_KP, "TOP/s"),
-        "match_hashsift512": ("alu", (4 * HS_BITS / 64 + 4) * float(N_KP) * N_KP, "TOP/s"),
+        # Hamming on int8 MFMA: per pair one multiply-add per code bit (2 ops)
+        "match_bad256": ("mfma", 2.0 * BAD_BITS * float(N_KP) * N_KP, "TOP/s", INT8_MFMA_PEAK_TOPS),
+        "match_hashsift512": ("mfma", 2.0 * HS_BITS * float(N_KP) * N_KP, "TOP/s", INT8_MFMA_PEAK_TOPS),
     }
 
 
@@ -160,17 +161,15 @@ def stage_work():
 # scaled by the same counters on a plain 256 MiB device copy (FETCH_SIZE
 # reads half the copied bytes: x2.000; WRITE_SIZE exact: x1.000).  A value
 # is reported only while the stage's source file still has the recorded
-# SHA-256 prefix: any change to the kernels invalidates the counters.  (The
-# projection's numbers come from an earlier run of the same projection code,
-# before the histogram kernel in the same file changed.)
+# SHA-256 prefix: any change to the kernels invalidates the counters.
 PMC_TRAFFIC = {
-    "keypoint_order": ("order.hip", "b9c2afd100b6dde1", 89654 + 20000),
-    "integral": ("integral.hip", "ace12b3b1e8860be", 5677659 + 9591264),
-    "bad_describe": ("bad.hip", "884a2f98d19ec233", 18584155 + 164541),
-    "hashsift_features": ("hashsift.hip", "8a3f21a5096ee430", 18979337 + 2560000),
-    "hashsift_project": ("hashsift.hip", "8a3f21a5096ee430", 4844421 + 325058),
-    "match_bad256": ("hamming.hip", "908e86d0e6e30368", 2914249 + 2080000 + 2420736 + 80000),
-    "match_hashsift512": ("hamming.hip", "908e86d0e6e30368", 5790445 + 2080000 + 2420736 + 80000),
+    "keypoint_order": ("order.hip", "b9c2afd100b6dde1", 89637 + 20000),
+    "integral": ("integral.hip", "64d461e94933cbb9", 2164929 + 749657 + 2840902 + 630528 + 593792 + 8354530),
+    "bad_describe": ("bad.hip", "884a2f98d19ec233", 18582403 + 163696),
+    "hashsift_features": ("hashsift.hip", "46a4763e3e99df95", 18959425 + 2560000),
+    "hashsift_project": ("hashsift.hip", "46a4763e3e99df95", 4846378 + 320000),
+    "match_bad256": ("hamming.hip", "81d2cc4f7dd5f9a6", 1847914 + 1199111 + 1000000 + 80000),
+    "match_hashsift512": ("hamming.hip", "81d2cc4f7dd5f9a6", 3471596 + 1199111 + 1000000 + 80000),
 }
 
 
@@ -191,6 +190,8 @@ def pmc_traffic(stage):
 
 
 def peak_of(bound):
+    """Default peak of a bound: HBM bandwidth, VALU lane-ops, FP32 MFMA (a
+    stage of another MFMA type names its own peak in stage_work)."""
     return {"hbm": HBM_PEAK_GBS, "alu": ALU_PEAK_TOPS, "mfma": FP32_MFMA_PEAK_TFLOPS}[bound]
 
 
@@ -659,16 +660,17 @@ def main():
     work = stage_work()
     stages = {}
     for name, ms in stage_ms.items():
-        bound, units, unit = work[name]
+        bound, units, unit = work[name][:3]
+        peak = work[name][3] if len(work[name]) > 3 else peak_of(bound)
         achieved = units / (ms * 1e-3) / 1e9 if bound == "hbm" else units / (ms * 1e-3) / 1e12
         stages[name] = {"ms_per_launch": round(ms, 5), "bound": bound, "achieved": round(achieved, 2),
-                        "unit": unit, "frac": round(achieved / peak_of(bound), 4),
+                        "unit": unit, "peak": peak, "frac": round(achieved / peak, 4),
                         "traffic_bytes_per_launch": pmc_traffic(name)}
     roofline = None
     if stages:
         dom = max(stages, key=lambda n: stages[n]["ms_per_launch"])
         d = stages[dom]
-        roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": peak_of(d["bound"]),
+        roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
                     "unit": d["unit"], "frac": d["frac"], "traffic": d["traffic_bytes_per_launch"],
                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
 
@@ -683,7 +685,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8/u32 integer (integral, BAD, Hamming); f32 (HashSIFT, FP32 MFMA projection)",
+        "dtype": "u8/u32 integer (integral, BAD); int8 MFMA with int32 sums (Hamming); f32 (HashSIFT, FP32 MFMA "
+                 "projection)",
         "data": "synthetic",
         "config": {"workload": f"describe-and-match, {W}x{H} image pair, {N_KP} keypoints per view, BAD-256 + "
                                f"HashSIFT-512, Hamming 2-NN {N_KP}x{N_KP} per code type",
