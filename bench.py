@@ -173,11 +173,23 @@ PMC_TRAFFIC = {
 }
 
 
-def pmc_traffic(stage):
-    """Measured HBM bytes per launch of a stage, or None once its source changed."""
+# Vector-L1 (TCP) cache accesses per launch, from rocprofv3 --pmc
+# TCP_TOTAL_CACHE_ACCESSES_sum on the same launch (a gather instruction counts
+# one access per lane).  The L1 of a CU serves one access per clock, so
+# accesses / (duration x 256 CUs x 2.4 GHz) is the kernel's fraction of that
+# limit; the histogram's bilinear gathers run at it.
+PMC_L1_ACCESSES = {
+    "hashsift_features": ("hashsift.hip", "46a4763e3e99df95", 22956186),
+}
+L1_ACCESS_PEAK_PER_S = 256 * 2.4e9
+
+
+def pmc_traffic(stage, table=None):
+    """Measured HBM bytes (or another counter of `table`) per launch of a
+    stage, or None once its source changed."""
     import hashlib
 
-    entry = PMC_TRAFFIC.get(stage)
+    entry = (PMC_TRAFFIC if table is None else table).get(stage)
     if entry is None:
         return None
     fname, digest, nbytes = entry
@@ -666,11 +678,16 @@ def main():
         stages[name] = {"ms_per_launch": round(ms, 5), "bound": bound, "achieved": round(achieved, 2),
                         "unit": unit, "peak": peak, "frac": round(achieved / peak, 4),
                         "traffic_bytes_per_launch": pmc_traffic(name)}
+        l1 = pmc_traffic(name, PMC_L1_ACCESSES)
+        if l1 is not None:
+            stages[name]["vector_l1_accesses_per_launch"] = l1
+            stages[name]["vector_l1_access_frac"] = round(l1 / (ms * 1e-3) / L1_ACCESS_PEAK_PER_S, 4)
     roofline = None
     if stages:
         dom = max(stages, key=lambda n: stages[n]["ms_per_launch"])
         d = stages[dom]
         roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+                    **({"vector_l1_access_frac": d["vector_l1_access_frac"]} if "vector_l1_access_frac" in d else {}),
                     "unit": d["unit"], "frac": d["frac"], "traffic": d["traffic_bytes_per_launch"],
                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
 
