@@ -710,7 +710,7 @@ KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_c
         p.qpl = 0;
         const int64_t per_block = knn_queries_per_unit(0, n_words);
         const int64_t qblocks = n_q > 0 ? ((int64_t)n_q + per_block - 1) / per_block : 1;
-        const int64_t target = 2ll * (num_cus > 0 ? num_cus : 256);
+        const int64_t target = 1ll * (num_cus > 0 ? num_cus : 256);
         int64_t splits = target / qblocks;
         const int64_t max_splits = (n_t + 63) / 64;
         if (splits > max_splits) splits = max_splits;
