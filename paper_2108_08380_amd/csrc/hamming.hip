@@ -704,14 +704,18 @@ KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_c
     p.n_words = n_words;
     p.k = k;
     if (n_words == 4 || n_words == 8) {
-        // MFMA engine: blocks of 64 QM queries, two per CU; as many splits as
-        // fill one round of blocks, each of at least one 64-row chunk
+        // MFMA engine: blocks of 64 QM queries; as many splits as fill one
+        // round of one block per CU (a small problem then leaves room for a
+        // concurrent one on another stream), or of two blocks per CU when
+        // splits would exceed 1024 rows (a wavefront alone on its SIMD does
+        // not keep the matrix pipe busy); splits of at least one 64-row chunk
         p.mfma = 1;
         p.qpl = 0;
         const int64_t per_block = knn_queries_per_unit(0, n_words);
         const int64_t qblocks = n_q > 0 ? ((int64_t)n_q + per_block - 1) / per_block : 1;
-        const int64_t target = 1ll * (num_cus > 0 ? num_cus : 256);
-        int64_t splits = target / qblocks;
+        const int64_t cus = num_cus > 0 ? num_cus : 256;
+        int64_t splits = cus / qblocks;
+        if (splits >= 1 && ((int64_t)n_t + splits - 1) / splits > 1024) splits = 2 * cus / qblocks;
         const int64_t max_splits = (n_t + 63) / 64;
         if (splits > max_splits) splits = max_splits;
         const int64_t min_splits = ((int64_t)n_t + kRowMask) / (kRowMask + 1);
