@@ -652,7 +652,8 @@ class Batch:
               keypoints first, then image 1's, ...
     matches:  list of (query_image, train_image) index pairs
     hs_images: optional list of (H, W) uint8 or float32 tensors for HashSIFT
-    The image tensors are kept alive by the batch."""
+    (an entry of None: that image's u8 tensor); sources of both dtypes may be
+    mixed.  The image tensors are kept alive by the batch."""
 
     def __init__(self, images, n_kp, matches=(), bad_bits: int = 512, hs_bits: int = 256,
                  precision: str = "fp32", margin: float = DEFAULT_MARGIN, k: int = 2, hs_images=None):
@@ -668,7 +669,7 @@ class Batch:
             _require(img, torch.uint8, 2, f"images[{i}]")
             H, W = img.shape
             recs[i].img, recs[i].pitch, recs[i].W, recs[i].H, recs[i].n_kp = img.data_ptr(), img.stride(0), W, H, int(n_kp[i])
-            if hs_images is not None:
+            if hs_images is not None and hs_images[i] is not None:
                 h = hs_images[i]
                 if tuple(h.shape) != (H, W):
                     raise ValueError(f"hs_images[{i}] must match images[{i}] in shape")

@@ -102,6 +102,21 @@ def test_batch_with_float_hashsift_images_and_k1(dev):
     assert_same(got, single_image_outputs(w, imgs, hs, kps, pairs, B, t, k=1))
 
 
+def test_batch_mixed_hashsift_sources(dev):
+    """Float32 HashSIFT sources for some images, the u8 images (given, or
+    None) for the others: the batch's mixed-dtype histogram path, equal to
+    the single-image calls on each image's own source."""
+    w = small_workload(seed=synth.SEED_BASE + 58)
+    imgs, _, kps, pairs, B, t = upload(w, dev)
+    hs = [(im.float() / 255.0).contiguous() if j % 2 == 0 else (im if j % 4 == 1 else None)
+          for j, im in enumerate(imgs)]
+    b = make_batch(w, imgs, hs=hs)
+    got = b.run(kps, pairs, B, t)
+    ref_hs = [h if h is not None else im for h, im in zip(hs, imgs)]
+    assert_same(got, single_image_outputs(w, imgs, ref_hs, kps, pairs, B, t), "mixed")
+    b.close()
+
+
 @pytest.mark.parametrize("precision", ["bf16", "fp8"])
 def test_batch_reduced_precision_equals_single_image(dev, precision):
     w = small_workload(seed=synth.SEED_BASE + 52)
