@@ -357,8 +357,9 @@ typedef struct bd_batch_match {
  * matcher, knn_*[1] the HashSIFT matcher: the engine, knn_qpl = 0 for the
  * int8 MFMA engine (blocks of 256 queries) or 1, 2, 4 queries per lane of
  * the lane-per-query kernel, and train rows per work unit
- * (BD_BATCH_MIN_ROWS .. BD_BATCH_MAX_ROWS, a multiple of 16 for the MFMA
- * engine).  Results do not depend on the knobs. */
+ * (BD_BATCH_MIN_ROWS .. BD_BATCH_MAX_ROWS; for the MFMA engine a multiple of
+ * 16 and at most BD_BATCH_MFMA_MAX_ROWS).  Results do not depend on the
+ * knobs. */
 typedef struct bd_batch_tuning {
     int32_t order_blocks_per_cu;
     int32_t integral_blocks_per_cu;
@@ -371,6 +372,7 @@ typedef struct bd_batch_tuning {
 
 #define BD_BATCH_MIN_ROWS 256
 #define BD_BATCH_MAX_ROWS (1 << 22)
+#define BD_BATCH_MFMA_MAX_ROWS 2048
 
 typedef struct bd_batch bd_batch;
 

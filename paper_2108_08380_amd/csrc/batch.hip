@@ -161,6 +161,10 @@ void plan_matcher(const bd_batch* b, Matcher& m, int32_t qpl, int32_t rows, std:
 int apply_matcher(bd_batch* b, Matcher& m, int32_t qpl, int32_t rows, int32_t blocks_per_cu)
 {
     const char* fn = "bd_batch";
+    // the MFMA engine's keys number at most 64 tiles of 32 rows per unit
+    if (qpl == 0 && (rows % 16 != 0 || rows > BD_BATCH_MFMA_MAX_ROWS))
+        return fail(BD_EINVAL, "%s: rows per unit %d of the MFMA engine not a multiple of 16 up to %d", fn, rows,
+                    BD_BATCH_MFMA_MAX_ROWS);
     std::vector<BatchMatch> recs;
     std::vector<int32_t> pre, mpre;
     plan_matcher(b, m, qpl, rows, recs, pre, mpre);
@@ -202,8 +206,9 @@ int check_tuning(const bd_batch_tuning& t)
         if (t.knn_rows[i] < BD_BATCH_MIN_ROWS || t.knn_rows[i] > BD_BATCH_MAX_ROWS)
             return fail(BD_EINVAL, "%s: rows per unit %d outside [%d, %d]", fn, t.knn_rows[i], BD_BATCH_MIN_ROWS,
                         BD_BATCH_MAX_ROWS);
-        if (t.knn_qpl[i] == 0 && t.knn_rows[i] % 16 != 0)
-            return fail(BD_EINVAL, "%s: rows per unit %d of the MFMA engine not a multiple of 16", fn, t.knn_rows[i]);
+        if (t.knn_qpl[i] == 0 && (t.knn_rows[i] % 16 != 0 || t.knn_rows[i] > BD_BATCH_MFMA_MAX_ROWS))
+            return fail(BD_EINVAL, "%s: rows per unit %d of the MFMA engine not a multiple of 16 up to %d", fn,
+                        t.knn_rows[i], BD_BATCH_MFMA_MAX_ROWS);
     }
     return BD_OK;
 }
@@ -677,6 +682,7 @@ int bd_batch_autotune(bd_batch* b, const bd_keypoint* kps, const bd_box_pair* pa
         int32_t bq = best.knn_qpl[j], br = best.knn_rows[j], bg = best.knn_blocks_per_cu[j];
         for (int q : kQpl) {
             for (int r : kRows) {
+                if (q == 0 && r > BD_BATCH_MFMA_MAX_ROWS) continue;
                 if ((rc = apply_matcher(b, m, q, r, bg))) break;
                 float ms = 0.0f;
                 if ((rc = time_stage(b, stage, a, s, e0, e1, reps, &ms))) break;

@@ -231,8 +231,8 @@ struct KnnBatchPlan {
     int32_t grid;            // blocks of the k-NN kernel (multiple of 8)
     int32_t merge_units, merge_grid;
 };
-// Queries per unit of the batch k-NN: a wavefront of the lane-per-query
-// kernel (qpl 1, 2, 4) or a block of the MFMA engine (qpl 0).
+// Queries per unit of the k-NN: a wavefront of the lane-per-query kernel
+// (qpl 1, 2, 4) or a block of the MFMA engine (qpl 0).
 int knn_queries_per_unit(int qpl, int n_words);
 void launch_knn_batch(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, const int32_t* pre,
                       const int32_t* merge_pre, const uint64_t* codes, uint32_t* partial, int32_t* idx,

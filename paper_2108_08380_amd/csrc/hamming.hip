@@ -254,64 +254,91 @@ __global__ __launch_bounds__(256) void hamming_merge_batch(const BatchMatch* __r
 
 // ---- MFMA engine (codes of 4 or 8 words)
 //
-// The Hamming distance as a dense contraction.  With the query bits
-// expanded to bytes q' = 1 - 2q (the negated +-1 form of Sec. III-A's inner
-// product) and the train bits to bytes t in {0, 1},
-//   sum_k q'_k t_k = |t| - 2 |q AND t|,   so   d_H(q, t) = |q| + q'.t,
-// exactly, in int32: the MFMA chain starts from |q| and ends on the
-// distance.  One v_mfma_i32_16x16x64_i8 takes one 64-bit word of 16 queries
-// x 16 train codes: lane (g, m) supplies bits 16g..16g+15 of the word of
-// query row m (A) and of train row m (B), the same byte order on both
-// sides, and receives the distances of query rows 4g..4g+3 to train row m
-// (D).
+// The Hamming distance as a dense contraction that ends on the sort key.
+// With the query bits as bytes -64 q (q in {0, 1}) and the train bits as
+// bytes t' = 2t - 1 in {-1, +1} (the +-1 form of Sec. III-A's inner
+// product),
+//   sum_k (-64 q_k) t'_k = 64 (|q| - 2 |q AND t|) = 64 (d_H(q, t) - |t|),
+// exactly, in int32.  One v_mfma_i32_32x32x32_i8 takes 32 bits of 32
+// queries x 32 train codes: lane (g, m) supplies bits 16g..16g+15 of the
+// 32-bit slice of query row m (A) and of train row m (B), the same byte
+// order on both sides, and receives the products of query rows
+// 8j + 4g + i (j, i < 4) with train row m (D).  Each chain starts with one
+// more slice whose bytes add 64 |t| + tag (A: four columns of -64 and one of
+// -1; B: -|t| cut into four parts of at most 128, and -tag), so the MFMA
+// delivers key = 64 d_H + tag < 2^16, where tag < 64 numbers the 32-row tile
+// inside the split (so splits hold at most 2048 rows) and the lane numbers
+// the row inside the tile.  Two keys of neighbouring query rows share a
+// register as 16-bit halves, and the top-2 update is three packed 16-bit
+// min/max per pair, after one byte permute.  After the split the lists are
+// rewritten as (d << 22 | row within the split) and merged over the 32 lanes
+// that share a query row by a transposing butterfly.
 //
-// A block of four wavefronts holds 16 QM queries per wavefront as operands
-// in registers and streams its train split through LDS in chunks of four
-// 16-row tiles.  Codes stay packed in memory (expanding them there would
+// A block of four wavefronts holds 32 QM queries per wavefront as operands
+// in registers and streams its train split through LDS in chunks of two
+// 32-row tiles.  Codes stay packed in memory (expanding them there would
 // multiply the operand traffic by eight); they are expanded on chip through
-// two 256-entry LDS tables (a byte to its eight bit-bytes, in {0, 1} and in
-// {+1, -1}).  Each thread loads 16 bytes of the next chunk while the
-// current one is multiplied, and expands them into the other LDS buffer;
-// one barrier per chunk.  Keys and the top-k update are those of the
-// lane-per-query kernel (d << 22 | row within the split; top-2 by min and
-// med3); the 16 lanes sharing a query row merge their lists by a butterfly
-// at the end.
+// two 256-entry LDS tables (a byte to its eight bit-bytes, in {0, -64} and
+// in {-1, +1}).  Each thread loads a quarter row of the next chunk while the
+// current one is multiplied and expands it into the other LDS buffer; one
+// barrier per chunk.  The 32x32 form is used because it leaves issue cycles
+// for the selection between matrix instructions, where the 16x16x64 form
+// does not; for 4-word codes the keys of one tile are inserted between the
+// MFMAs of the next.
 typedef int int32x4 __attribute__((ext_vector_type(4)));
+typedef int int32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMfmaWaves = 4;
-constexpr int kMfmaChunk = 64;  // train rows per LDS stage: four 16-row tiles
-// query tiles of 16 per wavefront: every B operand read from LDS feeds QM
-// MFMAs; the A operands take 4 QM NW VGPRs
+constexpr int kMfmaTile = 32;                            // train rows per MFMA tile
+constexpr int kMfmaChunk = 2 * kMfmaTile;                // train rows per LDS stage
+// 32-query tiles per wavefront (four for 8-word codes was tried: the
+// operands then exceed even the accumulation registers and spill)
+constexpr int kMfmaQM = 2;
+constexpr int kMfmaQueries = kMfmaWaves * 32 * kMfmaQM;  // queries per block
+constexpr uint32_t kTagBits = 6;
+constexpr int kMfmaMaxRows = (1 << kTagBits) * kMfmaTile;  // train rows per split
+constexpr uint32_t kEmpty16 = 0xffffu;
+// Resident blocks per CU the kernels are compiled for.  8-word operands take
+// 128 registers per lane: the single-problem kernel keeps two blocks per CU
+// (a few spilled registers) so that it shares the CUs with a concurrent
+// 4-word matcher; the persistent batch kernel, whose unit loop holds more
+// state, runs one wavefront per SIMD, where the compiler keeps the operands
+// in accumulation registers, which MFMAs read directly, instead of spilling
+// them.
+constexpr int kMfmaMinBlocks = 2;
 template <int NW>
-constexpr int mfma_qm() { return 4; }
+constexpr int kMfmaBatchMinBlocks = NW == 8 ? 1 : 2;
+static_assert(kMfmaMaxRows == BD_BATCH_MFMA_MAX_ROWS, "the batch limit is the key tag's range");
 
-__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c)
-{
-    uint32_t r;
-    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
-// Insert into a sorted top-k list (best[0] <= best[1]).
+// Insert a pair of 16-bit keys (two query rows, one per half) into the
+// pair's sorted top-k lists (best[0] <= best[1] in each half).
 template <int KK>
-__device__ __forceinline__ void topk_insert_med3(uint32_t (&best)[KK], uint32_t key)
+__device__ __forceinline__ void topk_insert_pair(uint32_t (&best)[KK], uint32_t keys)
 {
-    if constexpr (KK == 2) best[1] = med3u(best[0], best[1], key);
-    best[0] = min(best[0], key);
+    const u16x2 k = __builtin_bit_cast(u16x2, keys);
+    const u16x2 b0 = __builtin_bit_cast(u16x2, best[0]);
+    if constexpr (KK == 2) {
+        const u16x2 b1 = __builtin_bit_cast(u16x2, best[1]);
+        best[1] = __builtin_bit_cast(uint32_t, __builtin_elementwise_min(b1, __builtin_elementwise_max(b0, k)));
+    }
+    best[0] = __builtin_bit_cast(uint32_t, __builtin_elementwise_min(b0, k));
 }
 
-// Merge the top-k list of the lane CTRL (a DPP row rotation) away inside
-// the lane's row of 16: after rotations by 8, 4, 2 and 1 every lane of the
-// row has merged the 16 disjoint lists of the row.
-template <int KK, int CTRL>
-__device__ __forceinline__ void topk_merge_ror(uint32_t (&best)[KK])
+// The 16-bit keys of query rows 2p and 2p + 1 of a product tile as one
+// register (the keys are below 2^16).
+__device__ __forceinline__ uint32_t key_pair(const int32x16& D, int p)
 {
-    const uint32_t p0 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best[0], CTRL, 0xf, 0xf, false);
-    if constexpr (KK == 2) {
-        const uint32_t p1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best[1], CTRL, 0xf, 0xf, false);
-        best[1] = min(max(best[0], p0), min(best[1], p1));
-    }
-    best[0] = min(best[0], p0);
+    return __builtin_amdgcn_perm((uint32_t)D[2 * p + 1], (uint32_t)D[2 * p], 0x05040100u);
+}
+
+// Merge two disjoint sorted top-k lists into `best`.
+template <int KK>
+__device__ __forceinline__ void topk_merge(uint32_t (&best)[KK], const uint32_t (&other)[KK])
+{
+    if constexpr (KK == 2) best[1] = min(max(best[0], other[0]), min(best[1], other[1]));
+    best[0] = min(best[0], other[0]);
 }
 
 // Eight bytes of a 16-byte operand from two table entries: bytes lo and hi
@@ -322,221 +349,351 @@ __device__ __forceinline__ int32x4 expand16(const uint2* table, uint32_t piece)
     return int32x4{(int)a.x, (int)a.y, (int)b.x, (int)b.y};
 }
 
-// LDS of a block: the two chunk buffers and the two expansion tables.
+// LDS of a block: the two chunk buffers of B operands ([tile][slice][lane],
+// slice 0 the key slice) and the two expansion tables.
 template <int NW>
 struct MfmaShared {
-    int32x4 tiles[2][4 * NW * kWave];
-    uint2 bits01[256], bits_pm[256];
+    int32x4 tiles[2][2 * (2 * NW + 1) * kWave];
+    uint2 bits_q[256], bits_t[256];
 };
 
-// The expansion tables: byte v -> bit j of v as byte j, in {0, 1} and in
-// {+1, -1} (0x01 / 0xff).  Followed by a barrier in the block body.
+// The expansion tables: byte v -> bit j of v as byte j, as {0, -64} for
+// queries and {-1, +1} for train codes.  Followed by a barrier in the block
+// body.
 template <int NW>
 __device__ __forceinline__ void mfma_tables(MfmaShared<NW>& sh)
 {
     const uint32_t v = threadIdx.x;
-    uint32_t lo = 0u, hi = 0u, plo = 0u, phi = 0u;
+    uint32_t qlo = 0u, qhi = 0u, tlo = 0u, thi = 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint32_t b0 = (v >> j) & 1u, b1 = (v >> (j + 4)) & 1u;
-        lo |= b0 << (8 * j);
-        hi |= b1 << (8 * j);
-        plo |= (b0 ? 0xffu : 0x01u) << (8 * j);
-        phi |= (b1 ? 0xffu : 0x01u) << (8 * j);
+        qlo |= (b0 ? 0xc0u : 0x00u) << (8 * j);
+        qhi |= (b1 ? 0xc0u : 0x00u) << (8 * j);
+        tlo |= (b0 ? 0x01u : 0xffu) << (8 * j);
+        thi |= (b1 ? 0x01u : 0xffu) << (8 * j);
     }
-    sh.bits01[v] = make_uint2(lo, hi);
-    sh.bits_pm[v] = make_uint2(plo, phi);
+    sh.bits_q[v] = make_uint2(qlo, qhi);
+    sh.bits_t[v] = make_uint2(tlo, thi);
 }
 
-// Distances of the wavefront's 16 QM queries to the 16 rows of tile tau of
-// an LDS chunk: D[qm] = |q| + sum over the NW words of the MFMA products.
-template <int NW, int QM>
-__device__ __forceinline__ void mfma_tile(const int32x4* chunk, int tau, int lane, const int32x4 (&A)[QM][NW],
-                                          const int32x4 (&pa)[QM], int32x4 (&D)[QM])
+// Keys of the wavefront's QM query tiles against train tile tau of an LDS
+// chunk: D[qm] = the key slice's product plus the 2 NW code slices'.  The
+// operand reads run kAhead slices ahead of their MFMAs (the LDS latency
+// would otherwise stall every slice).  With PIPE, the keys Dp of the previous
+// tile are inserted between the MFMAs, a share after each, so that the
+// selection issues in the matrix pipe's shadow; side(step) adds other work
+// after MFMA step s QM + qm; scheduling barriers keep that order.
+template <int NW, int KK, int QM, bool PIPE, typename Side>
+__device__ __forceinline__ void mfma_tile(const int32x4* chunk, int tau, int lane, const int32x4& Ak,
+                                          const int32x4 (&A)[QM][2 * NW], int32x16 (&D)[QM],
+                                          const int32x16 (&Dp)[QM], uint32_t (&best)[QM][8][KK], Side&& side)
 {
-    {
-        const int32x4 b = chunk[(tau * NW) * kWave + lane];
+    constexpr int S = 2 * NW + 1;
+    constexpr int kAhead = NW == 4 ? 3 : 2;
+    constexpr int kPairs = QM * 8;
+    int32x4 b[S];
 #pragma unroll
-        for (int qm = 0; qm < QM; ++qm) D[qm] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qm][0], b, pa[qm], 0, 0, 0);
-    }
+    for (int s = 0; s < kAhead; ++s) b[s] = chunk[(tau * S + s) * kWave + lane];
 #pragma unroll
-    for (int kc = 1; kc < NW; ++kc) {
-        const int32x4 b = chunk[(tau * NW + kc) * kWave + lane];
+    for (int s = 0; s < S; ++s) {
+        if (s + kAhead < S) b[s + kAhead] = chunk[(tau * S + s + kAhead) * kWave + lane];
 #pragma unroll
-        for (int qm = 0; qm < QM; ++qm) D[qm] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qm][kc], b, D[qm], 0, 0, 0);
+        for (int qm = 0; qm < QM; ++qm) {
+            if (s == 0) {
+                const int32x16 zero = {};
+                D[qm] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Ak, b[0], zero, 0, 0, 0);
+            } else {
+                D[qm] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[qm][s - 1], b[s], D[qm], 0, 0, 0);
+            }
+            if constexpr (PIPE) {
+                // key pairs j0 .. j1 - 1 of the previous tile after MFMA (s, qm)
+                constexpr int kSteps = S * QM;
+                const int step = s * QM + qm;
+                const int j0 = step * kPairs / kSteps, j1 = (step + 1) * kPairs / kSteps;
+#pragma unroll
+                for (int j = j0; j < j1; ++j) {
+                    topk_insert_pair<KK>(best[j / 8][j % 8], key_pair(Dp[j / 8], j % 8));
+                    // a use of the lists here keeps the compiler from sinking
+                    // the updates out of the MFMA sequence
+#pragma unroll
+                    for (int k = 0; k < KK; ++k) asm volatile("" ::"v"(best[j / 8][j % 8][k]));
+                }
+            }
+            side(s * QM + qm);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 }
 
-// One block (256 threads): queries 64 QM qb .. of one problem against train
-// split `split` (splits start on 16-row tiles: rows_per_split is a multiple
-// of 16).  Every thread of the block calls it with the same arguments.
-template <int NW, int KK>
+// Insert the keys of each query tile (invalid train rows give none).
+template <int KK, int QM>
+__device__ __forceinline__ void mfma_select(const int32x16 (&D)[QM], bool valid, uint32_t (&best)[QM][8][KK])
+{
+    const uint32_t mask = valid ? 0u : 0xffffffffu;
+#pragma unroll
+    for (int qm = 0; qm < QM; ++qm)
+#pragma unroll
+        for (int p = 0; p < 8; ++p) topk_insert_pair<KK>(best[qm][p], key_pair(D[qm], p) | mask);
+}
+
+// One round of the transposing butterfly over H-slot halves: `lo` and `hi`
+// are the lane's slots, `upper` selects the half it keeps; CTRL is the DPP
+// control that reaches the partner (0: the lane 16 away, through the LDS
+// crossbar).
+template <int H, int KK, int CTRL>
+__device__ __forceinline__ void bfly_round(const uint32_t (*lo)[KK], const uint32_t (*hi)[KK], uint32_t (&out)[H][KK],
+                                           int upper)
+{
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        uint32_t recv[KK];
+#pragma unroll
+        for (int s = 0; s < KK; ++s) {
+            const uint32_t keep = upper ? hi[j][s] : lo[j][s];
+            const uint32_t send = upper ? lo[j][s] : hi[j][s];
+            out[j][s] = keep;
+            if constexpr (CTRL == 0)
+                recv[s] = (uint32_t)__shfl_xor((int)send, 16, kWave);
+            else
+                recv[s] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)send, CTRL, 0xf, 0xf, false);
+        }
+        topk_merge<KK>(out[j], recv);
+    }
+}
+template <int H, int KK, int CTRL>
+__device__ __forceinline__ void bfly_round(const uint32_t (&in)[2 * H][KK], uint32_t (&out)[H][KK], int upper)
+{
+    bfly_round<H, KK, CTRL>(&in[0], &in[H], out, upper);
+}
+
+// After the split: rewrite the lane's lists as (d << 22 | row within the
+// split), then merge the 32 lanes of each half-wave by a transposing
+// butterfly: in each round a lane keeps one half of its slots and merges
+// into it the partner's lists of that half (the partner keeps the other
+// half); after five rounds lane (g, n) holds the lists of slots
+// QM / 2 n + i (i < QM / 2), slot 16 qm + v.
+template <int KK, int QM>
+__device__ __forceinline__ void mfma_merge(const uint32_t (&best)[QM][8][KK], int n, uint32_t (&out)[QM / 2][KK])
+{
+    uint32_t w[16 * QM][KK];
+#pragma unroll
+    for (int qm = 0; qm < QM; ++qm)
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+#pragma unroll
+            for (int s = 0; s < KK; ++s)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t k = (best[qm][p][s] >> (16 * h)) & 0xffffu;
+                    const uint32_t row = (uint32_t)n + kMfmaTile * (k & ((1u << kTagBits) - 1u));
+                    w[16 * qm + 2 * p + h][s] = k == kEmpty16 ? kEmpty : ((k >> kTagBits) << kRowBits) | row;
+                }
+    uint32_t c16[8 * QM][KK], c8[4 * QM][KK], c4[2 * QM][KK], c2[QM][KK];
+    bfly_round<8 * QM, KK, 0>(w, c16, (n >> 4) & 1);
+    bfly_round<4 * QM, KK, 0x128>(c16, c8, (n >> 3) & 1);  // row_ror:8 (lane ^ 8)
+    bfly_round<2 * QM, KK, 0x141>(c8, c4, (n >> 2) & 1);   // row_half_mirror (lane ^ 7)
+    bfly_round<QM, KK, 0x4E>(c4, c2, (n >> 1) & 1);        // quad_perm 2,3,0,1 (lane ^ 2)
+    bfly_round<QM / 2, KK, 0xB1>(c2, out, n & 1);          // quad_perm 1,0,3,2 (lane ^ 1)
+}
+
+// One block (256 threads): queries 128 QM qb .. of one problem against
+// train split `split` (splits start on 16-row boundaries: rows_per_split is
+// a multiple of 16, at most kMfmaMaxRows).  Every thread of the block calls
+// it with the same arguments.
+template <int NW, int KK, int QM>
 __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ query, int32_t n_q,
                                                 const uint64_t* __restrict__ train, int32_t n_t,
                                                 int32_t rows_per_split, int qb, int split,
                                                 uint32_t* __restrict__ partial, int32_t* __restrict__ out_idx,
                                                 uint32_t* __restrict__ out_dist, bool direct, MfmaShared<NW>& sh)
 {
-    constexpr int QM = mfma_qm<NW>();
+    constexpr int S = 2 * NW + 1;   // slices of a tile: the key slice, then 32-bit code slices
+    constexpr int WPT = NW / 4;     // words per loader thread
     auto& tiles = sh.tiles;
-    const uint2* bits01 = sh.bits01;
-    const uint2* bits_pm = sh.bits_pm;
+    const uint2* bits_q = sh.bits_q;
+    const uint2* bits_t = sh.bits_t;
     const int lane = threadIdx.x % kWave;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
-    const int g = lane >> 4, m = lane & 15;
+    const int g = lane >> 5, m = lane & 31;
     const int qt0 = (qb * kMfmaWaves + wave) * QM;
     const int t0 = split * rows_per_split;
     const int t1 = min(n_t, t0 + rows_per_split);
 
-    // chunk staging: 64 rows x NW words, 16 bytes (two words) per thread;
-    // thread t < 32 NW holds words 2 (t % (NW / 2)), +1 of chunk row
-    // t / (NW / 2)
-    constexpr int kLoaders = 32 * NW;
-    const bool loader = (int)threadIdx.x < kLoaders;
-    const int s_row = (int)threadIdx.x / (NW / 2), s_word = ((int)threadIdx.x % (NW / 2)) * 2;
-    uint4 pre = make_uint4(0u, 0u, 0u, 0u);
+    // chunk staging: thread t holds words WPT (t % 4) .. of chunk row t / 4
+    const int s_row = (int)threadIdx.x >> 2, s_q = (int)threadIdx.x & 3;
+    uint2 pre[WPT];
     auto load_chunk = [&](int c0) {
         const int r = c0 + s_row;
-        if (loader) {
-            // two 8-byte loads: codes are only guaranteed 8-byte aligned
-            const uint2* src = reinterpret_cast<const uint2*>(train + (int64_t)r * NW + s_word);
-            const uint2 a = r < t1 ? src[0] : make_uint2(0u, 0u), b = r < t1 ? src[1] : make_uint2(0u, 0u);
-            pre = make_uint4(a.x, a.y, b.x, b.y);
-        }
+        const uint2* src = reinterpret_cast<const uint2*>(train + (int64_t)r * NW + WPT * s_q);
+#pragma unroll
+        for (int w = 0; w < WPT; ++w) pre[w] = r < t1 ? src[w] : make_uint2(0u, 0u);
     };
-    auto store_chunk = [&](int b) {
-        if (!loader) return;
-        const int tau = s_row >> 4, n = s_row & 15;
-        const uint32_t w[4] = {pre.x, pre.y, pre.z, pre.w};  // words s_word, s_word + 1 (low, high halves)
+    // expansion of the staged chunk into LDS buffer b, in phases: phase 2w
+    // reads word w's four table entries (piece p = bits 16p..16p+15 of the
+    // row goes to code slice p / 2, half-wave p % 2 of the row's tile), phase
+    // 2w + 1 stores them (one LDS round trip per word instead of one per
+    // piece), phase 2 WPT writes the row's key slice
+    int32x4 e[4];
+    uint32_t pc = 0u;
+    auto expand_phase = [&](int ph, int b, int c0) {
+        const int tau = s_row >> 5, n = s_row & 31;
+        int32x4* tile = &tiles[b][tau * S * kWave];
+        if (ph < 2 * WPT && (ph & 1) == 0) {
+            const uint2 v = pre[ph >> 1];
+            if (ph == 0) pc = 0u;
+            pc += (uint32_t)__popc(v.x) + (uint32_t)__popc(v.y);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            int32x4* dst = &tiles[b][(tau * NW + s_word + h) * kWave + n];
+            for (int h = 0; h < 4; ++h) e[h] = expand16(bits_t, ((h < 2 ? v.x : v.y) >> (16 * (h & 1))) & 0xffffu);
+        } else if (ph < 2 * WPT) {
+            const int p0 = 4 * (WPT * s_q + (ph >> 1));
 #pragma unroll
-            for (int gg = 0; gg < 4; ++gg)
-                dst[16 * gg] = expand16(bits01, (w[2 * h + (gg >> 1)] >> (16 * (gg & 1))) & 0xffffu);
-        }
-    };
-
-    // the wavefront's query codes (rows past n_q read as zero codes; a zero
-    // code yields zero operands below), loaded before the table barrier
-    uint32_t qcode[QM][NW];  // bits 16g..16g+15 of each word
-    uint32_t pc[QM];         // |q| of query row m
-    {
-        const bool all_in = (qt0 + QM) * 16 <= n_q;
-#pragma unroll
-        for (int qm = 0; qm < QM; ++qm) {
-            const int qi = (qt0 + qm) * 16 + m;
-            const bool in = all_in || qi < n_q;
-            pc[qm] = 0u;
-#pragma unroll
-            for (int kc = 0; kc < NW; ++kc) {
-                const uint64_t v = in ? query[(int64_t)qi * NW + kc] : 0ull;
-                pc[qm] += (uint32_t)__popcll(v);
-                qcode[qm][kc] = (uint32_t)(v >> (16 * g)) & 0xffffu;
+            for (int h = 0; h < 4; ++h) {
+                const int p = p0 + h;
+                tile[(1 + (p >> 1)) * kWave + (p & 1) * 32 + n] = e[h];
             }
+        } else {
+            // |t| of the row (its four threads are adjacent lanes); key slice:
+            // bytes -x1..-x4 (x1 + .. + x4 = |t|, each at most 128) and -tag in
+            // half-wave 0, zeros in half-wave 1 (threads 0, 2 and 1, 3 of the
+            // row store the same values)
+            uint32_t t = pc;
+            t += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0xB1, 0xf, 0xf, false);  // quad_perm 1,0,3,2
+            t += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0x4E, 0xf, 0xf, false);  // quad_perm 2,3,0,1
+            const uint32_t tag = (uint32_t)((c0 - t0) / kMfmaTile + tau);
+            uint32_t x = 0u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) x |= ((0u - ((t + 3u - (uint32_t)i) >> 2)) & 0xffu) << (8 * i);
+            const bool hi = (s_q & 1) != 0;
+            tile[(hi ? 32 : 0) + n] = hi ? int32x4{0, 0, 0, 0} : int32x4{(int)x, (int)((0u - tag) & 0xffu), 0, 0};
         }
-    }
-    load_chunk(t0);
-    __syncthreads();  // tables; the previous unit's reads of the buffers
+    };
+    auto store_chunk = [&](int b, int c0) {
+#pragma unroll
+        for (int ph = 0; ph <= 2 * WPT; ++ph) {
+            expand_phase(ph, b, c0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
 
-    // queries as -+1 operands (zero for rows past n_q); |q| of the rows this
-    // lane receives in D
-    int32x4 A[QM][NW], pa[QM];
+    // the wavefront's query codes, loaded coalesced (lane l: word l % NW of
+    // tile row l / NW, 64 / NW rows per load) and staged in the second chunk
+    // buffer, which is free until the first chunk has been multiplied;
+    // rows past n_q read as zero codes, which give zero operands
+    constexpr int kQWords = QM * 32 * NW;  // words of the wavefront's queries
+    uint2* qstage = reinterpret_cast<uint2*>(&tiles[1][0]) + wave * kQWords;
+    {
+        const int64_t w0 = (int64_t)qt0 * 32 * NW;
+        const int64_t w_end = (int64_t)n_q * NW;
+        uint2 v[kQWords / kWave];
+#pragma unroll
+        for (int k = 0; k < kQWords / kWave; ++k) {
+            const int64_t w = w0 + k * kWave + lane;
+            v[k] = w < w_end ? reinterpret_cast<const uint2*>(query)[w] : make_uint2(0u, 0u);
+        }
+        load_chunk(t0);
+#pragma unroll
+        for (int k = 0; k < kQWords / kWave; ++k) qstage[k * kWave + lane] = v[k];
+    }
+    __syncthreads();  // tables, staged queries; the previous unit's reads of the buffers
+
+    // query operands: code slice s of query row m of tile qm is word s / 2,
+    // bits 32 (s % 2) + 16 g ..; the key slice's A is four columns of -64 and
+    // one of -1 in half-wave 0
+    int32x4 A[QM][S - 1];
 #pragma unroll
     for (int qm = 0; qm < QM; ++qm) {
-        const bool in = (qt0 + qm) * 16 + m < n_q;
 #pragma unroll
-        for (int kc = 0; kc < NW; ++kc)
-            A[qm][kc] = in ? expand16(bits_pm, qcode[qm][kc]) : int32x4{0, 0, 0, 0};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) pa[qm][i] = __shfl((int)pc[qm], 4 * g + i, kWave);
+        for (int w = 0; w < NW; ++w) {
+            const uint2 q = qstage[(qm * 32 + m) * NW + w];
+            A[qm][2 * w] = expand16(bits_q, (q.x >> (16 * g)) & 0xffffu);
+            A[qm][2 * w + 1] = expand16(bits_q, (q.y >> (16 * g)) & 0xffffu);
+        }
     }
-    uint32_t best[QM][4][KK];
+    const int32x4 Ak = g == 0 ? int32x4{(int)0xc0c0c0c0u, 0xff, 0, 0} : int32x4{0, 0, 0, 0};
+    uint32_t best[QM][8][KK];  // key pairs of query rows 2p, 2p + 1
 #pragma unroll
     for (int qm = 0; qm < QM; ++qm)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int p = 0; p < 8; ++p)
 #pragma unroll
-            for (int s = 0; s < KK; ++s) best[qm][i][s] = kEmpty;
+            for (int s = 0; s < KK; ++s) best[qm][p][s] = kEmpty;
 
-    store_chunk(0);
-    __syncthreads();
+    store_chunk(0, t0);
+    __syncthreads();  // chunk 0; the staged queries have been read
+
+    // full chunks; for 4-word codes software-pipelined over tiles: the keys
+    // of one tile are inserted while those of the next are computed (the
+    // first insertion takes kEmpty keys, a no-op); 8-word operands leave no
+    // registers for the second key set
+    constexpr bool kPipe = NW == 4;
+    int32x16 Dp[QM];
+#pragma unroll
+    for (int qm = 0; qm < QM; ++qm)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) Dp[qm][v] = (int)kEmpty;
+    const int t_full = t0 + (t1 - t0) / kMfmaChunk * kMfmaChunk;
     int buf = 0;
-    for (int c0 = t0; c0 < t1; c0 += kMfmaChunk) {
+    int c0 = t0;
+    for (; c0 < t_full; c0 += kMfmaChunk) {
+        // the next chunk is loaded during the MFMAs and expanded after them
+        // (spreading the expansion over the MFMAs was measured slower: both
+        // compete for LDS)
         const bool more = c0 + kMfmaChunk < t1;
         if (more) load_chunk(c0 + kMfmaChunk);
-        const bool full = c0 + kMfmaChunk <= t1;
-        const uint32_t row0 = (uint32_t)(c0 - t0 + m);
-        if (NW == 4 && full) {
-            // software pipeline over the four tiles: the MFMAs of tile tau + 1
-            // run while tile tau's distances are inserted (8-word operands
-            // leave no registers for the second accumulator set)
-            int32x4 D[2][QM];
-            mfma_tile<NW, QM>(tiles[buf], 0, lane, A, pa, D[0]);
 #pragma unroll
-            for (int tau = 0; tau < 4; ++tau) {
-                if (tau < 3) mfma_tile<NW, QM>(tiles[buf], tau + 1, lane, A, pa, D[(tau + 1) & 1]);
+        for (int tau = 0; tau < 2; ++tau) {
+            int32x16 D[QM];
+            mfma_tile<NW, KK, QM, kPipe>(tiles[buf], tau, lane, Ak, A, D, Dp, best, [](int) {});
+            if constexpr (kPipe) {
 #pragma unroll
-                for (int qm = 0; qm < QM; ++qm)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        topk_insert_med3<KK>(best[qm][i], ((uint32_t)D[tau & 1][qm][i] << kRowBits) | (row0 + 16 * tau));
-            }
-        } else {
-            // 8-word codes, and partial chunks: one tile at a time
-#pragma unroll
-            for (int tau = 0; tau < 4; ++tau) {
-                if (!full && c0 + 16 * tau >= t1) break;  // tiles past the split end
-                int32x4 D[QM];
-                mfma_tile<NW, QM>(tiles[buf], tau, lane, A, pa, D);
-                const bool valid = full || c0 + 16 * tau + m < t1;
-#pragma unroll
-                for (int qm = 0; qm < QM; ++qm)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        topk_insert_med3<KK>(best[qm][i],
-                                             valid ? ((uint32_t)D[qm][i] << kRowBits) | (row0 + 16 * tau) : kEmpty);
+                for (int qm = 0; qm < QM; ++qm) Dp[qm] = D[qm];
+            } else {
+                mfma_select<KK, QM>(D, true, best);
             }
         }
-        if (more) store_chunk(buf ^ 1);
+        if (more) store_chunk(buf ^ 1, c0 + kMfmaChunk);
         __syncthreads();
         buf ^= 1;
     }
-
-    // merge over the 16 lanes of each query row (DPP row_ror:8, 4, 2, 1),
-    // then lane m == 0 writes
+    if constexpr (kPipe) mfma_select<KK, QM>(Dp, true, best);
+    // the partial last chunk, one tile at a time
+    if (c0 < t1) {
 #pragma unroll
-    for (int qm = 0; qm < QM; ++qm)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            topk_merge_ror<KK, 0x128>(best[qm][i]);
-            topk_merge_ror<KK, 0x124>(best[qm][i]);
-            topk_merge_ror<KK, 0x122>(best[qm][i]);
-            topk_merge_ror<KK, 0x121>(best[qm][i]);
+        for (int tau = 0; tau < 2; ++tau) {
+            if (c0 + kMfmaTile * tau >= t1) break;
+            int32x16 D[QM];
+            mfma_tile<NW, KK, QM, false>(tiles[buf], tau, lane, Ak, A, D, Dp, best, [](int) {});
+            mfma_select<KK, QM>(D, c0 + kMfmaTile * tau + m < t1, best);
         }
-    if (m != 0) return;
+        __syncthreads();  // a persistent block reuses the buffers
+    }
+    uint32_t glob[QM / 2][KK];
+    mfma_merge<KK, QM>(best, m, glob);
+
+    // slot j = QM / 2 m + i of lane (g, m) is query row 8 (v / 4) + 4 g + v % 4
+    // of tile qm, j = 16 qm + v
 #pragma unroll
-    for (int qm = 0; qm < QM; ++qm)
+    for (int i = 0; i < QM / 2; ++i) {
+        const int j = QM / 2 * m + i;
+        const int qi = (qt0 + (j >> 4)) * 32 + 8 * ((j >> 2) & 3) + 4 * g + (j & 3);
+        if (qi >= n_q) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int qi = (qt0 + qm) * 16 + 4 * g + i;
-            if (qi >= n_q) continue;
-#pragma unroll
-            for (int s = 0; s < KK; ++s) {
-                const uint32_t key = best[qm][i][s];
-                if (direct) {
-                    const bool empty = key == kEmpty;
-                    out_idx[(int64_t)qi * KK + s] = empty ? -1 : (int32_t)(t0 + (key & kRowMask));
-                    out_dist[(int64_t)qi * KK + s] = empty ? kEmpty : key >> kRowBits;
-                } else {
-                    partial[((int64_t)split * n_q + qi) * KK + s] = key;
-                }
+        for (int s = 0; s < KK; ++s) {
+            const uint32_t key = glob[i][s];
+            if (direct) {
+                const bool empty = key == kEmpty;
+                out_idx[(int64_t)qi * KK + s] = empty ? -1 : (int32_t)(t0 + (key & kRowMask));
+                out_dist[(int64_t)qi * KK + s] = empty ? kEmpty : key >> kRowBits;
+            } else {
+                partial[((int64_t)split * n_q + qi) * KK + s] = key;
             }
         }
+    }
 }
 
 template <int NW, int KK>
-__global__ __launch_bounds__(256, 2) void hamming_mfma_kernel(const uint64_t* __restrict__ query, int32_t n_q,
+__global__ __launch_bounds__(256, kMfmaMinBlocks) void hamming_mfma_kernel(const uint64_t* __restrict__ query, int32_t n_q,
                                                               const uint64_t* __restrict__ train, int32_t n_t,
                                                               int32_t rows_per_split, uint32_t* __restrict__ partial,
                                                               int32_t* __restrict__ out_idx,
@@ -544,14 +701,14 @@ __global__ __launch_bounds__(256, 2) void hamming_mfma_kernel(const uint64_t* __
 {
     __shared__ MfmaShared<NW> sh;
     mfma_tables<NW>(sh);
-    mfma_block_body<NW, KK>(query, n_q, train, n_t, rows_per_split, blockIdx.x, blockIdx.y, partial, out_idx, out_dist,
+    mfma_block_body<NW, KK, kMfmaQM>(query, n_q, train, n_t, rows_per_split, blockIdx.x, blockIdx.y, partial, out_idx, out_dist,
                             direct != 0, sh);
 }
 
-// Batch: units are (problem, split, block of 256 queries), problem-major and
+// Batch: units are (problem, split, block of kMfmaQueries queries), problem-major and
 // query block fastest, so consecutive units share a train split.
 template <int NW, int KK>
-__global__ __launch_bounds__(256, 2) void hamming_mfma_batch(const BatchMatch* __restrict__ mt, int32_t n_m,
+__global__ __launch_bounds__(256, kMfmaBatchMinBlocks<NW>) void hamming_mfma_batch(const BatchMatch* __restrict__ mt, int32_t n_m,
                                                              const int32_t* __restrict__ pre,
                                                              const uint64_t* __restrict__ codes,
                                                              int32_t rows_per_split, uint32_t* __restrict__ partial,
@@ -567,7 +724,7 @@ __global__ __launch_bounds__(256, 2) void hamming_mfma_batch(const BatchMatch* _
         const int local = u - pre[i];
         const int split = local / b.qgroups;
         const int qb = local - split * b.qgroups;
-        mfma_block_body<NW, KK>(codes + (int64_t)b.q_off * NW, b.n_q, codes + (int64_t)b.t_off * NW, b.n_t,
+        mfma_block_body<NW, KK, kMfmaQM>(codes + (int64_t)b.q_off * NW, b.n_q, codes + (int64_t)b.t_off * NW, b.n_t,
                                 rows_per_split, qb, split, partial + b.part_off, out_idx + (int64_t)b.out_off * KK,
                                 out_dist + (int64_t)b.out_off * KK, b.splits == 1, sh);
     }
@@ -578,7 +735,7 @@ void launch_mfma_nw_k(const KnnPlan& p, const uint64_t* query, const uint64_t* t
                       uint32_t* dist, hipStream_t stream)
 {
     const int direct = p.splits == 1;
-    const int per_block = kMfmaWaves * 16 * mfma_qm<NW>();
+    const int per_block = kMfmaQueries;
     const dim3 grid((p.n_q + per_block - 1) / per_block, p.splits);
     hipLaunchKernelGGL((hamming_mfma_kernel<NW, KK>), grid, dim3(kMfmaWaves * kWave), 0, stream, query, p.n_q, train,
                        p.n_t, p.rows_per_split, partial, idx, dist, direct);
@@ -678,7 +835,7 @@ void launch_batch_nw(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, co
 
 int knn_queries_per_unit(int qpl, int n_words)
 {
-    return qpl == 0 ? kMfmaWaves * 16 * (n_words == 4 ? mfma_qm<4>() : mfma_qm<8>()) : kWave * qpl;
+    return qpl == 0 ? kMfmaQueries : kWave * qpl;
 }
 
 void launch_knn_batch(const KnnBatchPlan& p, const BatchMatch* m, int32_t n_m, const int32_t* pre,
@@ -704,26 +861,27 @@ KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_c
     p.n_words = n_words;
     p.k = k;
     if (n_words == 4 || n_words == 8) {
-        // MFMA engine: blocks of 64 QM queries; as many splits as fill one
-        // round of one block per CU (a small problem then leaves room for a
-        // concurrent one on another stream), or of two blocks per CU when
-        // splits would exceed 1024 rows (a wavefront alone on its SIMD does
-        // not keep the matrix pipe busy); splits of at least one 64-row chunk
+        // MFMA engine: blocks of kMfmaQueries queries; as many splits as
+        // fill one round of one block per CU (a small problem then leaves
+        // room for a concurrent one on another stream), or, for 4-word codes
+        // (two resident blocks per CU), of two blocks per CU when splits
+        // would exceed 1024 rows; splits of at least one 64-row chunk and at
+        // most kMfmaMaxRows rows
         p.mfma = 1;
         p.qpl = 0;
         const int64_t per_block = knn_queries_per_unit(0, n_words);
         const int64_t qblocks = n_q > 0 ? ((int64_t)n_q + per_block - 1) / per_block : 1;
         const int64_t cus = num_cus > 0 ? num_cus : 256;
         int64_t splits = cus / qblocks;
-        if (splits >= 1 && ((int64_t)n_t + splits - 1) / splits > 1024) splits = 2 * cus / qblocks;
+        if (n_words == 4 && splits >= 1 && ((int64_t)n_t + splits - 1) / splits > 1024) splits = 2 * cus / qblocks;
         const int64_t max_splits = (n_t + 63) / 64;
         if (splits > max_splits) splits = max_splits;
         const int64_t min_splits = ((int64_t)n_t + kRowMask) / (kRowMask + 1);
         if (splits < min_splits) splits = min_splits;
         if (splits < 1) splits = 1;
-        // splits start on 16-row tiles; at most 2^22 - 16 rows keep keys in 32 bits
+        // splits start on 16-row tiles and hold at most 128 tiles (the key's tag)
         int64_t rows = ((n_t + splits - 1) / splits + 15) / 16 * 16;
-        if (rows > (int64_t)kRowMask + 1 - 16) rows = (int64_t)kRowMask + 1 - 16;
+        if (rows > kMfmaMaxRows) rows = kMfmaMaxRows;
         if (rows < 16) rows = 16;
         p.rows_per_split = (int32_t)rows;
         p.splits = (int32_t)((n_t + rows - 1) / rows);

@@ -139,7 +139,7 @@ def test_batch_outputs_do_not_depend_on_tuning(dev):
         dict(knn_qpl=[4, 2], knn_rows=[1 << 22, 300], knn_blocks_per_cu=[16, 16]),
         # the MFMA engine: one-unit splits, several per problem, one for all
         dict(knn_qpl=[0, 0], knn_rows=[256, 272], knn_blocks_per_cu=[1, 3]),
-        dict(knn_qpl=[0, 1], knn_rows=[1 << 22, 1024], knn_blocks_per_cu=[2, 4]),
+        dict(knn_qpl=[0, 1], knn_rows=[2048, 1024], knn_blocks_per_cu=[2, 4]),
     ]
     for tn in tunings:
         b.tuning = tn
@@ -209,6 +209,8 @@ def test_batch_validation_errors(dev):
         b.tuning = dict(knn_qpl=[3, 1])
     with pytest.raises(bd.BDError, match="multiple of 16"):
         b.tuning = dict(knn_qpl=[0, 1], knn_rows=[300, 1024])
+    with pytest.raises(bd.BDError, match="up to 2048"):
+        b.tuning = dict(knn_qpl=[1, 0], knn_rows=[1024, 2048 + 16])
     # a rejected tuning leaves the batch usable
     assert_same(b.run(kps, pairs, B, t), single_image_outputs(w, imgs, hs, kps, pairs, B, t))
 

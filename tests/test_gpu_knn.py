@@ -114,9 +114,10 @@ def test_train_set_beyond_packed_row_range(ref, dev):
 
 @pytest.mark.parametrize("n_words", [4, 8])
 @pytest.mark.parametrize("k", [1, 2])
-@pytest.mark.parametrize("n_q,n_t", [(15, 63), (16, 64), (17, 65), (255, 129), (256, 300), (257, 1031)])
+@pytest.mark.parametrize("n_q,n_t", [(15, 63), (16, 64), (17, 65), (31, 95), (33, 97), (255, 129), (256, 300),
+                                     (257, 1031)])
 def test_mfma_tile_and_chunk_boundaries(ref, dev, n_words, k, n_q, n_t):
-    """Codes of 4 and 8 words run on the int8 MFMA engine (16-query x 16-row
+    """Codes of 4 and 8 words run on the int8 MFMA engine (32-query x 32-row
     tiles, 64-row LDS chunks, 256 queries per block): query and train counts
     around those sizes, with equal codes planted across tiles and chunks so
     ties must resolve to the lower index, and a partial last chunk."""
@@ -149,3 +150,27 @@ def test_mfma_train_set_beyond_packed_row_range(ref, dev):
         np.testing.assert_array_equal(to_np(dist), ed)
         np.testing.assert_array_equal(to_np(idx), ei)
     assert ei[0, 0] == (1 << 22) - 7 and ei[1, 0] == (1 << 22) + 100 and ei[2, 0] == n_t - 1
+
+
+def test_mfma_splits_of_full_tag_range(ref, dev):
+    """8-word codes, few queries and 2^21 + 100 train codes: the plan cuts the
+    train set into splits of 4096 rows, the most the key's 7-bit tile tag
+    covers, so tags 0 and 127 both occur; duplicates planted across a split
+    boundary and across the first and last tile of one split must resolve to
+    the lower index."""
+    rng = np.random.default_rng(83)
+    n_t = (1 << 21) + 100
+    q = synth.random_codes(rng, 8, 8)
+    t = synth.random_codes(rng, n_t, 8)
+    t[4096 * 5 + 4095] = q[0]             # last row of a split (tag 127)
+    t[4096 * 6] = q[0]                    # first row of the next split
+    t[4096 * 9 + 31] = q[1] ^ np.uint64(1)
+    t[4096 * 9 + 127 * 32] = q[1] ^ np.uint64(2)   # tie: tag 0 vs tag 127 of one split
+    t[n_t - 1] = q[2]
+    t[n_t - 100] = q[2]
+    for k in (1, 2):
+        idx, dist = bd.match_hamming_knn(torch.from_numpy(q).to(dev), torch.from_numpy(t).to(dev), k=k)
+        ei, ed = ref.match_knn(q, t, k)
+        np.testing.assert_array_equal(to_np(dist), ed)
+        np.testing.assert_array_equal(to_np(idx), ei)
+    assert ei[0, 0] == 4096 * 5 + 4095 and ei[1, 0] == 4096 * 9 + 31 and ei[2, 0] == n_t - 100
