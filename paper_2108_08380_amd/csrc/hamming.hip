@@ -296,6 +296,7 @@ constexpr int kMfmaChunk = 2 * kMfmaTile;                // train rows per LDS s
 constexpr int kMfmaQM = 2;
 constexpr int kMfmaQueries = kMfmaWaves * 32 * kMfmaQM;  // queries per block
 constexpr uint32_t kTagBits = 6;
+constexpr uint32_t kTagMask = (1u << kTagBits) - 1u;
 constexpr int kMfmaMaxRows = (1 << kTagBits) * kMfmaTile;  // train rows per split
 constexpr uint32_t kEmpty16 = 0xffffu;
 // Resident blocks per CU the kernels are compiled for.  8-word operands take
@@ -467,12 +468,13 @@ __device__ __forceinline__ void bfly_round(const uint32_t (&in)[2 * H][KK], uint
     bfly_round<H, KK, CTRL>(&in[0], &in[H], out, upper);
 }
 
-// After the split: rewrite the lane's lists as (d << 22 | row within the
-// split), then merge the 32 lanes of each half-wave by a transposing
-// butterfly: in each round a lane keeps one half of its slots and merges
-// into it the partner's lists of that half (the partner keeps the other
-// half); after five rounds lane (g, n) holds the lists of slots
-// QM / 2 n + i (i < QM / 2), slot 16 qm + v.
+// After the split: widen the lane's 16-bit keys to (key << 16 | tag << 5 |
+// lane row), which order as (d, row within the split) across lanes, merge
+// the 32 lanes of each half-wave by a transposing butterfly (in each round a
+// lane keeps one half of its slots and merges into it the partner's lists
+// of that half; after five rounds lane (g, n) holds the lists of slots
+// QM / 2 n + i, i < QM / 2, slot 16 qm + v) and rewrite those as
+// (d << 22 | row within the split).
 template <int KK, int QM>
 __device__ __forceinline__ void mfma_merge(const uint32_t (&best)[QM][8][KK], int n, uint32_t (&out)[QM / 2][KK])
 {
@@ -482,19 +484,24 @@ __device__ __forceinline__ void mfma_merge(const uint32_t (&best)[QM][8][KK], in
 #pragma unroll
         for (int p = 0; p < 8; ++p)
 #pragma unroll
-            for (int s = 0; s < KK; ++s)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const uint32_t k = (best[qm][p][s] >> (16 * h)) & 0xffffu;
-                    const uint32_t row = (uint32_t)n + kMfmaTile * (k & ((1u << kTagBits) - 1u));
-                    w[16 * qm + 2 * p + h][s] = k == kEmpty16 ? kEmpty : ((k >> kTagBits) << kRowBits) | row;
-                }
-    uint32_t c16[8 * QM][KK], c8[4 * QM][KK], c4[2 * QM][KK], c2[QM][KK];
+            for (int s = 0; s < KK; ++s) {
+                const uint32_t k2 = best[qm][p][s];  // keys of slots 2p (low half) and 2p + 1
+                w[16 * qm + 2 * p][s] = (k2 << 16) | ((k2 & kTagMask) << 5) | (uint32_t)n;
+                w[16 * qm + 2 * p + 1][s] = (k2 & 0xffff0000u) | (((k2 >> 16) & kTagMask) << 5) | (uint32_t)n;
+            }
+    uint32_t c16[8 * QM][KK], c8[4 * QM][KK], c4[2 * QM][KK], c2[QM][KK], c1[QM / 2][KK];
     bfly_round<8 * QM, KK, 0>(w, c16, (n >> 4) & 1);
     bfly_round<4 * QM, KK, 0x128>(c16, c8, (n >> 3) & 1);  // row_ror:8 (lane ^ 8)
     bfly_round<2 * QM, KK, 0x141>(c8, c4, (n >> 2) & 1);   // row_half_mirror (lane ^ 7)
     bfly_round<QM, KK, 0x4E>(c4, c2, (n >> 1) & 1);        // quad_perm 2,3,0,1 (lane ^ 2)
-    bfly_round<QM / 2, KK, 0xB1>(c2, out, n & 1);          // quad_perm 1,0,3,2 (lane ^ 1)
+    bfly_round<QM / 2, KK, 0xB1>(c2, c1, n & 1);           // quad_perm 1,0,3,2 (lane ^ 1)
+#pragma unroll
+    for (int i = 0; i < QM / 2; ++i)
+#pragma unroll
+        for (int s = 0; s < KK; ++s) {
+            const uint32_t k = c1[i][s] >> 16;
+            out[i][s] = k == kEmpty16 ? kEmpty : ((k >> kTagBits) << kRowBits) | (c1[i][s] & (kTagMask << 5 | 31u));
+        }
 }
 
 // One block (256 threads): queries 128 QM qb .. of one problem against
