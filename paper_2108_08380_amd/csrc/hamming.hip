@@ -277,14 +277,16 @@ __global__ __launch_bounds__(256) void hamming_merge_batch(const BatchMatch* __r
 // A block of four wavefronts holds 32 QM queries per wavefront as operands
 // in registers and streams its train split through LDS in chunks of two
 // 32-row tiles.  Codes stay packed in memory (expanding them there would
-// multiply the operand traffic by eight); they are expanded on chip through
-// two 256-entry LDS tables (a byte to its eight bit-bytes, in {0, -64} and
-// in {-1, +1}).  Each thread loads a quarter row of the next chunk while the
-// current one is multiplied and expands it into the other LDS buffer; one
-// barrier per chunk.  The 32x32 form is used because it leaves issue cycles
-// for the selection between matrix instructions, where the 16x16x64 form
-// does not; for 4-word codes the keys of one tile are inserted between the
-// MFMAs of the next.
+// multiply the operand traffic by eight) and are expanded on chip: the
+// queries once per block through a 256-entry LDS table (a byte to its eight
+// bit-bytes), the train rows on the VALU (a nibble spread to four bytes by a
+// multiply and a mask, then a byte permute).  Each thread loads a quarter
+// row of the next chunk at the start of a chunk and expands it into the
+// other LDS buffer in steps between the MFMAs of the chunk's second tile;
+// one barrier per chunk.  The 32x32 form is used because it leaves issue
+// cycles for VALU work between matrix instructions, where the 16x16x64 form
+// does not; for 4-word codes the keys of one tile are also inserted between
+// the MFMAs of the next.
 typedef int int32x4 __attribute__((ext_vector_type(4)));
 typedef int int32x16 __attribute__((ext_vector_type(16)));
 
@@ -299,16 +301,10 @@ constexpr uint32_t kTagBits = 6;
 constexpr uint32_t kTagMask = (1u << kTagBits) - 1u;
 constexpr int kMfmaMaxRows = (1 << kTagBits) * kMfmaTile;  // train rows per split
 constexpr uint32_t kEmpty16 = 0xffffu;
-// Resident blocks per CU the kernels are compiled for.  8-word operands take
-// 128 registers per lane: the single-problem kernel keeps two blocks per CU
-// (a few spilled registers) so that it shares the CUs with a concurrent
-// 4-word matcher; the persistent batch kernel, whose unit loop holds more
-// state, runs one wavefront per SIMD, where the compiler keeps the operands
-// in accumulation registers, which MFMAs read directly, instead of spilling
-// them.
+// Resident blocks per CU the kernels are compiled for: two, so that a
+// wavefront's MFMAs overlap the other block's expansion and barrier, and a
+// small problem shares the CUs with a concurrent matcher.
 constexpr int kMfmaMinBlocks = 2;
-template <int NW>
-constexpr int kMfmaBatchMinBlocks = NW == 8 ? 1 : 2;
 static_assert(kMfmaMaxRows == BD_BATCH_MFMA_MAX_ROWS, "the batch limit is the key tag's range");
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -350,32 +346,40 @@ __device__ __forceinline__ int32x4 expand16(const uint2* table, uint32_t piece)
     return int32x4{(int)a.x, (int)a.y, (int)b.x, (int)b.y};
 }
 
+// The same sixteen bytes from VALU alone: a nibble spread to the low bits of
+// four bytes by one 24-bit multiply and a mask, then a byte permute that
+// maps 0 / 1 to bytes 0 / 1 of `lut`.  Four instructions per dword, no LDS
+// traffic.
+__device__ __forceinline__ int32x4 expand16_valu(uint32_t piece, uint32_t lut)
+{
+    int32x4 r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        r[j] = (int)__builtin_amdgcn_perm(0u, lut, (((piece >> (4 * j)) & 15u) * 0x00204081u) & 0x01010101u);
+    return r;
+}
+
 // LDS of a block: the two chunk buffers of B operands ([tile][slice][lane],
-// slice 0 the key slice) and the two expansion tables.
+// slice 0 the key slice) and the query expansion table.
 template <int NW>
 struct MfmaShared {
     int32x4 tiles[2][2 * (2 * NW + 1) * kWave];
-    uint2 bits_q[256], bits_t[256];
+    uint2 bits_q[256];
 };
 
-// The expansion tables: byte v -> bit j of v as byte j, as {0, -64} for
-// queries and {-1, +1} for train codes.  Followed by a barrier in the block
-// body.
+// The query expansion table: byte v -> bit j of v as byte j in {0, -64}.
+// Followed by a barrier in the block body.
 template <int NW>
 __device__ __forceinline__ void mfma_tables(MfmaShared<NW>& sh)
 {
     const uint32_t v = threadIdx.x;
-    uint32_t qlo = 0u, qhi = 0u, tlo = 0u, thi = 0u;
+    uint32_t qlo = 0u, qhi = 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const uint32_t b0 = (v >> j) & 1u, b1 = (v >> (j + 4)) & 1u;
-        qlo |= (b0 ? 0xc0u : 0x00u) << (8 * j);
-        qhi |= (b1 ? 0xc0u : 0x00u) << (8 * j);
-        tlo |= (b0 ? 0x01u : 0xffu) << (8 * j);
-        thi |= (b1 ? 0x01u : 0xffu) << (8 * j);
+        qlo |= (((v >> j) & 1u) ? 0xc0u : 0x00u) << (8 * j);
+        qhi |= (((v >> (j + 4)) & 1u) ? 0xc0u : 0x00u) << (8 * j);
     }
     sh.bits_q[v] = make_uint2(qlo, qhi);
-    sh.bits_t[v] = make_uint2(tlo, thi);
 }
 
 // Keys of the wavefront's QM query tiles against train tile tau of an LDS
@@ -519,7 +523,6 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
     constexpr int WPT = NW / 4;     // words per loader thread
     auto& tiles = sh.tiles;
     const uint2* bits_q = sh.bits_q;
-    const uint2* bits_t = sh.bits_t;
     const int lane = threadIdx.x % kWave;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
     const int g = lane >> 5, m = lane & 31;
@@ -536,35 +539,34 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
 #pragma unroll
         for (int w = 0; w < WPT; ++w) pre[w] = r < t1 ? src[w] : make_uint2(0u, 0u);
     };
-    // expansion of the staged chunk into LDS buffer b, in phases: phase 2w
-    // reads word w's four table entries (piece p = bits 16p..16p+15 of the
-    // row goes to code slice p / 2, half-wave p % 2 of the row's tile), phase
-    // 2w + 1 stores them (one LDS round trip per word instead of one per
-    // piece), phase 2 WPT writes the row's key slice
-    int32x4 e[4];
+    // expansion of the staged chunk into LDS buffer b, in 4 WPT + 1 steps
+    // that can be spread over the MFMAs of the current chunk: step k < 4 WPT
+    // expands piece k of the thread's words on the VALU (piece p = bits
+    // 16p..16p+15 of the row goes to code slice p / 2, half-wave p % 2 of
+    // the row's tile) and stores it; the last step writes the row's key
+    // slice
+    constexpr int kExpandSteps = 4 * WPT + 1;
     uint32_t pc = 0u;
-    auto expand_phase = [&](int ph, int b, int c0) {
+    auto expand_step = [&](int k, int b, int c0) {
         const int tau = s_row >> 5, n = s_row & 31;
         int32x4* tile = &tiles[b][tau * S * kWave];
-        if (ph < 2 * WPT && (ph & 1) == 0) {
-            const uint2 v = pre[ph >> 1];
-            if (ph == 0) pc = 0u;
-            pc += (uint32_t)__popc(v.x) + (uint32_t)__popc(v.y);
-#pragma unroll
-            for (int h = 0; h < 4; ++h) e[h] = expand16(bits_t, ((h < 2 ? v.x : v.y) >> (16 * (h & 1))) & 0xffffu);
-        } else if (ph < 2 * WPT) {
-            const int p0 = 4 * (WPT * s_q + (ph >> 1));
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int p = p0 + h;
-                tile[(1 + (p >> 1)) * kWave + (p & 1) * 32 + n] = e[h];
-            }
+        if (k < 4 * WPT) {
+            const int w = k >> 2, h = k & 3;
+            uint2 v = pre[w];
+            // pin the step here: without it the compiler hoists the VALU
+            // work above the MFMAs, where it also waits for the load
+            asm volatile("" : "+v"(v.x), "+v"(v.y));
+            if (h == 0) pc = (w == 0 ? 0u : pc) + (uint32_t)__popc(v.x) + (uint32_t)__popc(v.y);
+            const int p = 4 * (WPT * s_q + w) + h;
+            tile[(1 + (p >> 1)) * kWave + (p & 1) * 32 + n] =
+                expand16_valu(((h < 2 ? v.x : v.y) >> (16 * (h & 1))) & 0xffffu, 0x01ffu);
         } else {
             // |t| of the row (its four threads are adjacent lanes); key slice:
             // bytes -x1..-x4 (x1 + .. + x4 = |t|, each at most 128) and -tag in
             // half-wave 0, zeros in half-wave 1 (threads 0, 2 and 1, 3 of the
             // row store the same values)
             uint32_t t = pc;
+            asm volatile("" : "+v"(t));
             t += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0xB1, 0xf, 0xf, false);  // quad_perm 1,0,3,2
             t += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t, 0x4E, 0xf, 0xf, false);  // quad_perm 2,3,0,1
             const uint32_t tag = (uint32_t)((c0 - t0) / kMfmaTile + tau);
@@ -573,13 +575,6 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
             for (int i = 0; i < 4; ++i) x |= ((0u - ((t + 3u - (uint32_t)i) >> 2)) & 0xffu) << (8 * i);
             const bool hi = (s_q & 1) != 0;
             tile[(hi ? 32 : 0) + n] = hi ? int32x4{0, 0, 0, 0} : int32x4{(int)x, (int)((0u - tag) & 0xffu), 0, 0};
-        }
-    };
-    auto store_chunk = [&](int b, int c0) {
-#pragma unroll
-        for (int ph = 0; ph <= 2 * WPT; ++ph) {
-            expand_phase(ph, b, c0);
-            __builtin_amdgcn_sched_barrier(0);
         }
     };
 
@@ -626,7 +621,8 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
 #pragma unroll
             for (int s = 0; s < KK; ++s) best[qm][p][s] = kEmpty;
 
-    store_chunk(0, t0);
+#pragma unroll
+    for (int k = 0; k < kExpandSteps; ++k) expand_step(k, 0, t0);
     __syncthreads();  // chunk 0; the staged queries have been read
 
     // full chunks; for 4-word codes software-pipelined over tiles: the keys
@@ -643,15 +639,18 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
     int buf = 0;
     int c0 = t0;
     for (; c0 < t_full; c0 += kMfmaChunk) {
-        // the next chunk is loaded during the MFMAs and expanded after them
-        // (spreading the expansion over the MFMAs was measured slower: both
-        // compete for LDS)
-        const bool more = c0 + kMfmaChunk < t1;
-        if (more) load_chunk(c0 + kMfmaChunk);
+        // the next chunk (rows past t1 load as zeros) is loaded here and
+        // expanded into the other buffer between the MFMAs of tile 1, one
+        // step after every kEvery MFMAs
+        load_chunk(c0 + kMfmaChunk);
 #pragma unroll
         for (int tau = 0; tau < 2; ++tau) {
             int32x16 D[QM];
-            mfma_tile<NW, KK, QM, kPipe>(tiles[buf], tau, lane, Ak, A, D, Dp, best, [](int) {});
+            mfma_tile<NW, KK, QM, kPipe>(tiles[buf], tau, lane, Ak, A, D, Dp, best, [&](int step) {
+                constexpr int kEvery = S * QM / kExpandSteps;
+                if (tau == 1 && step % kEvery == kEvery - 1 && step / kEvery < kExpandSteps)
+                    expand_step(step / kEvery, buf ^ 1, c0 + kMfmaChunk);
+            });
             if constexpr (kPipe) {
 #pragma unroll
                 for (int qm = 0; qm < QM; ++qm) Dp[qm] = D[qm];
@@ -659,7 +658,6 @@ __device__ __forceinline__ void mfma_block_body(const uint64_t* __restrict__ que
                 mfma_select<KK, QM>(D, true, best);
             }
         }
-        if (more) store_chunk(buf ^ 1, c0 + kMfmaChunk);
         __syncthreads();
         buf ^= 1;
     }
@@ -715,7 +713,7 @@ __global__ __launch_bounds__(256, kMfmaMinBlocks) void hamming_mfma_kernel(const
 // Batch: units are (problem, split, block of kMfmaQueries queries), problem-major and
 // query block fastest, so consecutive units share a train split.
 template <int NW, int KK>
-__global__ __launch_bounds__(256, kMfmaBatchMinBlocks<NW>) void hamming_mfma_batch(const BatchMatch* __restrict__ mt, int32_t n_m,
+__global__ __launch_bounds__(256, kMfmaMinBlocks) void hamming_mfma_batch(const BatchMatch* __restrict__ mt, int32_t n_m,
                                                              const int32_t* __restrict__ pre,
                                                              const uint64_t* __restrict__ codes,
                                                              int32_t rows_per_split, uint32_t* __restrict__ partial,
@@ -870,17 +868,16 @@ KnnPlan plan_knn(int32_t n_q, int32_t n_t, int32_t n_words, int32_t k, int num_c
     if (n_words == 4 || n_words == 8) {
         // MFMA engine: blocks of kMfmaQueries queries; as many splits as
         // fill one round of one block per CU (a small problem then leaves
-        // room for a concurrent one on another stream), or, for 4-word codes
-        // (two resident blocks per CU), of two blocks per CU when splits
-        // would exceed 1024 rows; splits of at least one 64-row chunk and at
-        // most kMfmaMaxRows rows
+        // room for a concurrent one on another stream), or of two blocks per
+        // CU when splits would exceed 1024 rows; splits of at least one
+        // 64-row chunk and at most kMfmaMaxRows rows
         p.mfma = 1;
         p.qpl = 0;
         const int64_t per_block = knn_queries_per_unit(0, n_words);
         const int64_t qblocks = n_q > 0 ? ((int64_t)n_q + per_block - 1) / per_block : 1;
         const int64_t cus = num_cus > 0 ? num_cus : 256;
         int64_t splits = cus / qblocks;
-        if (n_words == 4 && splits >= 1 && ((int64_t)n_t + splits - 1) / splits > 1024) splits = 2 * cus / qblocks;
+        if (splits >= 1 && ((int64_t)n_t + splits - 1) / splits > 1024) splits = 2 * cus / qblocks;
         const int64_t max_splits = (n_t + 63) / 64;
         if (splits > max_splits) splits = max_splits;
         const int64_t min_splits = ((int64_t)n_t + kRowMask) / (kRowMask + 1);
