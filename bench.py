@@ -168,8 +168,8 @@ PMC_TRAFFIC = {
     "bad_describe": ("bad.hip", "884a2f98d19ec233", 18582403 + 163696),
     "hashsift_features": ("hashsift.hip", "46a4763e3e99df95", 18959425 + 2560000),
     "hashsift_project": ("hashsift.hip", "46a4763e3e99df95", 4846378 + 320000),
-    "match_bad256": ("hamming.hip", "881fa699bd3545f0", 1859212 + 607170 + 480000 + 80000),
-    "match_hashsift512": ("hamming.hip", "881fa699bd3545f0", 3471593 + 607170 + 480201 + 80000),
+    "match_bad256": ("hamming.hip", "b45b06214a9c6ad9", 1805936 + 615381 + 480000 + 80000),
+    "match_hashsift512": ("hamming.hip", "b45b06214a9c6ad9", 3450095 + 615381 + 480000 + 80000),
 }
 
 

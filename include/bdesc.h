@@ -200,9 +200,9 @@ int bd_hashsift_project(bd_context* ctx, const float* hist, const bd_keypoint* k
  * lexicographic order (equal distances: lower index first).  Slots beyond
  * n_t get idx = -1 and dist = 0xFFFFFFFF.  n_words in 1..8, k in 1..2.
  * Codes of 4 and 8 words (256 and 512 bits) run on the int8 MFMA units as
- * the inner product of -+1 query bytes with 0/1 train bytes (exact); other
- * widths on a lane-per-query XOR/popcount kernel.  Codes must be 8-byte
- * aligned.
+ * the inner product of {0, -64} query bytes with +-1 train bytes (exact);
+ * other widths on a lane-per-query XOR/popcount kernel.  Codes must be
+ * 8-byte aligned.
  */
 int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q,
                          const uint64_t* train, int32_t n_t, int32_t n_words, int32_t k,
