@@ -19,6 +19,17 @@ def test_integral_matches_oracle(ref, dev, H, W):
     np.testing.assert_array_equal(got, ref.build_integral(img))
 
 
+@pytest.mark.parametrize("tail", range(1, 17))
+@pytest.mark.parametrize("W", [300, 512])
+def test_integral_every_strip_tail(ref, dev, tail, W):
+    """The last strip of 16 rows holds 1 .. 16 rows (every tail of a tile),
+    on an edge slab (W = 300) and on whole slabs (W = 512)."""
+    H = 32 + tail
+    img = np.random.default_rng(tail * 31 + W).integers(0, 256, (H, W), dtype=np.uint8)
+    got = to_np(bd.build_integral(torch.from_numpy(img).to(dev)))
+    np.testing.assert_array_equal(got, ref.build_integral(img))
+
+
 def test_integral_full_size_batched_image(ref, dev):
     """Largest image of the batched workload: 4000 x 3000 (wraps mod 2^32 nowhere, 3.06e9 < 2^32)."""
     img = np.full((3000, 4000), 255, dtype=np.uint8)
