@@ -166,8 +166,8 @@ PMC_TRAFFIC = {
     "keypoint_order": ("order.hip", "b9c2afd100b6dde1", 89637 + 20000),
     "integral": ("integral.hip", "64d461e94933cbb9", 2164929 + 749657 + 2840902 + 630528 + 593792 + 8354530),
     "bad_describe": ("bad.hip", "884a2f98d19ec233", 18582403 + 163696),
-    "hashsift_features": ("hashsift.hip", "46a4763e3e99df95", 18959425 + 2560000),
-    "hashsift_project": ("hashsift.hip", "46a4763e3e99df95", 4846378 + 320000),
+    "hashsift_features": ("hashsift.hip", "b81e18b37e77e4e5", 18967507 + 2560000),
+    "hashsift_project": ("hashsift.hip", "b81e18b37e77e4e5", 4846376 + 320000),
     "match_bad256": ("hamming.hip", "b45b06214a9c6ad9", 1805936 + 615381 + 480000 + 80000),
     "match_hashsift512": ("hamming.hip", "b45b06214a9c6ad9", 3450095 + 615381 + 480000 + 80000),
 }
@@ -179,7 +179,7 @@ PMC_TRAFFIC = {
 # accesses / (duration x 256 CUs x 2.4 GHz) is the kernel's fraction of that
 # limit; the histogram's bilinear gathers run at it.
 PMC_L1_ACCESSES = {
-    "hashsift_features": ("hashsift.hip", "46a4763e3e99df95", 22956186),
+    "hashsift_features": ("hashsift.hip", "b81e18b37e77e4e5", 23220000),
 }
 L1_ACCESS_PEAK_PER_S = 256 * 2.4e9
 

@@ -8,12 +8,13 @@
 //      nested linear interpolation so flat regions give exactly zero
 //      gradients) go to LDS, stored relative to the pixel under the keypoint
 //      so small gradients in near-flat patches keep their relative precision
-//      in FP32.  Positions are 32.32 fixed point: lane (h, c) walks patch
-//      column c + 1 down rows 1 + h, 3 + h, ... with one uniform 64-bit
-//      step, so a sample costs two 64-bit adds instead of FP64 arithmetic;
-//      two more steps take the apron rows and columns (the four apron
-//      corners are never read).  Keypoints whose patch may reach beyond
-//      2^30 pixels take the FP64 position path.
+//      in FP32.  Positions are 32.32 fixed point: the wavefront walks the
+//      interior in 8x8 blocks of samples (lane = position in the block), and
+//      every lane moves by the same 64-bit step from one block to the next,
+//      so a sample costs two 64-bit adds instead of FP64 arithmetic; two more
+//      steps take the apron rows and columns (the four apron corners are
+//      never read).  Keypoints whose patch may reach beyond 2^30 pixels take
+//      the FP64 position path.
 //   2. Lane (h, j) owns patch column j and 16 rows (rows 0..15 top-down for
 //      h = 0, rows 31..16 bottom-up for h = 1).  With the bottom-up order the
 //      vertical cell weights and Gaussian row weights of step k are the same
@@ -228,45 +229,62 @@ __device__ __forceinline__ void fetch_fixed(const uint8_t* __restrict__ img, int
 }
 
 // Resampling with fixed-point positions (every sample within 2^30 pixels of
-// the origin).  Core: 16 steps over the 32x32 interior, lane (h, c) at
-// sample (1 + h + 2t, 1 + c); apron: rows 0 and 33 (columns 1..32) and
-// columns 0 and 33 (rows 1..32), fetched with the last round.  Every load
-// of a round of R steps is in flight before any is used: R = 8 (two round
-// trips) where a launch holds about one keypoint per wavefront and so is
-// bound by these round trips, R = 4 (fewer registers) for persistent loops.
+// the origin).  Core: 16 steps over the 32x32 interior in 8x8 blocks of
+// samples, lane (a, b) at sample (1 + 8 bi + a, 1 + 8 bj + b) in step
+// 4 bi + bj.  A block's 64 samples are neighbours in the image at any
+// rotation, so one gather instruction touches few cache lines (a row or a
+// column of lanes along the patch axes touches up to one line per lane when
+// that axis runs vertically).  Apron: rows 0 and 33 (columns 1..32) and
+// columns 0 and 33 (rows 1..32), lane (h, c) with h = lane / 32 choosing
+// the side, fetched with the last round.  Every load of a round of R steps
+// is in flight before any is used: R = 8 (two round trips) where a launch
+// holds about one keypoint per wavefront and so is bound by these round
+// trips, R = 4 (fewer registers) for persistent loops.
 template <int DT, int R>
 __device__ __forceinline__ void resample_fixed(const uint8_t* __restrict__ img, int32_t W, int32_t H,
                                                uint32_t upitch, double kx, double ky, double sa, double sb,
                                                float base, float* P, int lane)
 {
-    static_assert(16 % R == 0, "rounds must tile the 16 core steps");
+    static_assert(16 % R == 0 && R % 4 == 0, "rounds must tile the 16 core steps by whole block rows");
     const int wm1 = W - 1, hm1 = H - 1;
-    const int h = lane >> 5, c = lane & 31;
-    const double ux = (double)c - 15.5, uy = (double)h - 15.5;
+    const int a = lane >> 3, b = lane & 7;
+    const double ux = (double)b - 15.5, uy = (double)a - 15.5;
     int64_t X = to_fixed(fma(sa, ux, fma(-sb, uy, kx)));
     int64_t Y = to_fixed(fma(sb, ux, fma(sa, uy, ky)));
-    const int64_t dX = to_fixed(-2.0 * sb), dY = to_fixed(2.0 * sa);
-    float* dst = P + (1 + h) * kApron + 1 + c;
+    // next block along the row (8 columns on), and from the last block of a
+    // row to the first of the next (8 rows down, 24 columns back)
+    const int64_t cX = to_fixed(8.0 * sa), cY = to_fixed(8.0 * sb);
+    const int64_t nX = to_fixed(-8.0 * sb) - 3 * cX, nY = to_fixed(8.0 * sa) - 3 * cY;
+    float* dst = P + (1 + a) * kApron + 1 + b;
+    auto advance = [&](int t) {
+        if ((t & 3) == 3) {
+            X += nX;
+            Y += nY;
+        } else {
+            X += cX;
+            Y += cY;
+        }
+    };
+    auto offset = [](int t) { return (t >> 2) * 8 * kApron + (t & 3) * 8; };
 #pragma unroll 1
     for (int t0 = 0; t0 < 16 - R; t0 += R) {
         float v[R][4], fx[R], fy[R];
 #pragma unroll
         for (int g = 0; g < R; ++g) {
             fetch_fixed<DT>(img, wm1, hm1, upitch, X, Y, v[g], fx[g], fy[g]);
-            X += dX;
-            Y += dY;
+            advance(g);  // t0 is a multiple of 4
         }
 #pragma unroll
-        for (int g = 0; g < R; ++g) dst[(t0 + g) * 2 * kApron] = bilinear<DT>(v[g], fx[g], fy[g], base);
+        for (int g = 0; g < R; ++g) dst[offset(t0 + g)] = bilinear<DT>(v[g], fx[g], fy[g], base);
     }
     // last round: core steps 16 - R .. 15, then rows 0 / 33 at column 1 + c
     // and columns 0 / 33 at row 1 + c
+    const int h = lane >> 5, c = lane & 31;
     float v[R + 2][4], fx[R + 2], fy[R + 2];
 #pragma unroll
     for (int g = 0; g < R; ++g) {
         fetch_fixed<DT>(img, wm1, hm1, upitch, X, Y, v[g], fx[g], fy[g]);
-        X += dX;
-        Y += dY;
+        advance(g);
     }
     const double ar = h ? 16.5 : -16.5, ac = (double)c - 15.5;
     fetch_fixed<DT>(img, wm1, hm1, upitch, to_fixed(fma(sa, ac, fma(-sb, ar, kx))),
@@ -274,7 +292,7 @@ __device__ __forceinline__ void resample_fixed(const uint8_t* __restrict__ img, 
     fetch_fixed<DT>(img, wm1, hm1, upitch, to_fixed(fma(sa, ar, fma(-sb, ac, kx))),
                     to_fixed(fma(sb, ar, fma(sa, ac, ky))), v[R + 1], fx[R + 1], fy[R + 1]);
 #pragma unroll
-    for (int g = 0; g < R; ++g) dst[(16 - R + g) * 2 * kApron] = bilinear<DT>(v[g], fx[g], fy[g], base);
+    for (int g = 0; g < R; ++g) dst[offset(16 - R + g)] = bilinear<DT>(v[g], fx[g], fy[g], base);
     P[(h ? 33 : 0) * kApron + 1 + c] = bilinear<DT>(v[R], fx[R], fy[R], base);
     P[(1 + c) * kApron + (h ? 33 : 0)] = bilinear<DT>(v[R + 1], fx[R + 1], fy[R + 1], base);
 }
