@@ -175,9 +175,11 @@ PMC_TRAFFIC = {
 
 # Vector-L1 (TCP) cache accesses per launch, from rocprofv3 --pmc
 # TCP_TOTAL_CACHE_ACCESSES_sum on the same launch (a gather instruction counts
-# one access per lane).  The L1 of a CU serves one access per clock, so
+# one access per lane).  The L1 of a CU serves about one scattered lane access
+# per clock (lanes of one instruction that fall in the same cache line can be
+# served together, so a gather with some locality can pass 1 slightly), so
 # accesses / (duration x 256 CUs x 2.4 GHz) is the kernel's fraction of that
-# limit; the histogram's bilinear gathers run at it.
+# rate; the histogram's bilinear gathers run at it.
 PMC_L1_ACCESSES = {
     "hashsift_features": ("hashsift.hip", "b81e18b37e77e4e5", 23220000),
 }
