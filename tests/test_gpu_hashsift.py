@@ -6,6 +6,8 @@ Tolerance (FP32 kernel vs FP64 oracle), fixed here and in the design notes:
   codes      every bit equal wherever |r_64| >= 2e-4 (the stated margin);
              bits inside the margin are counted and reported, not failed.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -52,6 +54,25 @@ def test_config_workload(ref, dev, n_bits):
     w = synth.hashsift512_pair(n_bits=n_bits)
     compare(ref, dev, w.image1, w.kp1, w.B, w.t, "view1")
     compare(ref, dev, w.image2, w.kp2, w.B, w.t, "view2")
+
+
+def test_rotations_on_and_between_the_axes(ref, dev):
+    """Angles on the image axes, on the diagonals and just off them, at
+    small to large scales: every orientation of the 8x8 sample blocks the
+    resampling walks (the block steps change sign and axis with the angle)."""
+    rng = np.random.default_rng(77)
+    img = (synth.grey_image(rng, 640, 480, n_rect=60) / 255.0).astype(np.float32)
+    base = [k * math.pi / 4 for k in range(8)]
+    angles = base + [a + d for a in base for d in (-1e-6, 1e-6)] + [-math.pi / 2, 1e-30]
+    scales = [0.5, 1.6, 8.0, 20.0]
+    kps = np.empty(len(angles) * len(scales), dtype=synth.KEYPOINT_DTYPE)
+    i = 0
+    for a in angles:
+        for sc in scales:
+            kps[i] = (rng.uniform(80.0, 560.0), rng.uniform(80.0, 400.0), sc, a)
+            i += 1
+    B, t = synth.projection(rng, 256)
+    compare(ref, dev, img, kps, B, t, "rotations")
 
 
 def test_u8_image(ref, dev):
