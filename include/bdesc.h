@@ -233,7 +233,7 @@ int bd_match_mutual(bd_context* ctx, const uint64_t* query, int32_t n_q, const u
  * f = mean(box 1) - mean(box 2), boxes of side 2r+1 (r <= 15) centred at
  * 16 + (x, y) clamped to [r, 31 - r]; its bin is q = floor((f + 255) * 10),
  * one of m = 5110 bins (precision 0.1 over [-255, 255]).  The stump after
- * bin b is h(x) = +1 if q(x) <= b, else -1, with the loss of Eq. 3
+ * bin b is h(x) = +1 if q(x) <= b, else -1, with the loss of Eq. 2
  *   L(b) = sum_i [tau - s_ap - h(a)h(p) + s_an + h(a)h(n)]_+.
  * Outputs per candidate (device): best_bin = the lowest b of smallest L(b),
  * best_theta = (best_bin + 1 - 2550) / 10 (so h = +1 iff f < best_theta;
@@ -250,7 +250,8 @@ int bd_find_threshold(bd_context* ctx, const uint8_t* patches, int32_t n_triplet
  * in [0, n_pairs); out-of-range values are clamped), forms triplets by
  * in-batch hardest negatives on the codes of the k bits selected so far,
  * with anchor swap (for pair s the nearest positive p_j of a_s, j != s, and
- * the nearest anchor a_j of p_s; ties: lowest j, then the positive; an
+ * the nearest anchor a_j of p_s; equal distances go to the first j in
+ * cyclic order s+1, s+2, ..., and a positive beats an anchor; an
  * anchor winner makes the triplet (p_s, a_s, a_j)), runs the threshold
  * search of bd_find_threshold with s_ap = k - 2 d(anchor, positive),
  * s_an = k - 2 d(anchor, negative) over the n_cands candidates
@@ -421,7 +422,7 @@ int bd_batch_set_tuning(bd_batch* b, const bd_batch_tuning* t);
 int bd_batch_info(const bd_batch* b, int64_t* total_kp, int32_t* match_rows);
 
 /* ------------------------------------------------------------------------
- * HashSIFT training (Sec. III-B, Eq. 4): Adam on B and t for the relaxed
+ * HashSIFT training (Sec. III-B, Eq. 3): Adam on B and t for the relaxed
  * descriptors tanh(beta (B f - t)) under the triplet ranking loss with
  * in-batch hardest negatives and anchor swap (bd_trl_hnm_fwd), every patch
  * augmented.  pool: 2 n_pairs float32 32x32 patches, pair i = (anchor 2i,

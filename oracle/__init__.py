@@ -375,7 +375,7 @@ def adam_step(param, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2
 
 def hashsift_train_step(pool, batch, params, noise, B, t, state, lr=2e-4, tau=0.5, beta=1.0,
                         beta1=0.9, beta2=0.999, eps=1e-8):
-    """One training iteration of the HashSIFT projection (Sec. III-B, Eq. 4):
+    """One training iteration of the HashSIFT projection (Sec. III-B, Eq. 3):
     pair s of the batch is pool pair batch[s] (anchor 2 batch[s], positive
     2 batch[s] + 1), augmented with params / noise rows 2s (anchor) and 2s + 1
     (positive); relaxed descriptors tanh(beta (B f - t)); triplet loss with

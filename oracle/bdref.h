@@ -150,7 +150,7 @@ int32_t bdref_match_mutual(const uint64_t* query, int32_t n_q, const uint64_t* t
  * side 2r+1 (r <= 15) centred at 16 + (x, y) clamped to [r, 31 - r]; its
  * bin is q = floor((f + 255) * 10) in [0, 5100] of BDREF_THRESHOLD_BINS =
  * 5110 (precision 0.1 over [-255, 255]).  A threshold after bin b gives the
- * stump h(x) = +1 if q(x) <= b, else -1, and the loss of Eq. 3,
+ * stump h(x) = +1 if q(x) <= b, else -1, and the loss of Eq. 2,
  *   L(b) = sum_i [tau - s_ap[i] - h(a_i) h(p_i) + s_an[i] + h(a_i) h(n_i)]_+,
  * with s_ap, s_an the similarities of the previously selected bits.  Per
  * candidate: best_bin = the lowest b with the smallest L(b), best_loss =
@@ -193,8 +193,9 @@ void bdref_select_features(const uint8_t* pool, int32_t n_pairs, const int32_t* 
                            uint64_t* pool_codes);
 
 /* Data augmentation of 32x32 float patches for HashSIFT training (Sec.
- * III-B: small random rotation, scale, illumination change, blurring and
- * pixel Gaussian noise; the random draws are inputs).  params: n x 5
+ * III-B lists the kinds of perturbation; here each patch is rotated and
+ * rescaled about its centre, blurred, given a gain and a bias, and has
+ * Gaussian noise added; the random draws are inputs).  params: n x 5
  * (angle, scale, gain, bias, sigma) per patch.  Output pixel (i, j) takes
  *   1. the bilinear sample (clamp-to-edge) of the source at
  *      (15.5, 15.5) + scale * Rot(angle) (j - 15.5, i - 15.5),

@@ -2,7 +2,7 @@
 // integer-sorting speed-up): for every candidate box pair, the feature
 // f = mean(box 1) - mean(box 2) of all 3N triplet patches is binned at a
 // precision of 0.1 over [-255, 255] (m = 5110 bins), each triplet's loss
-// change (Eq. 3) as the threshold passes each of its patches is added to the
+// change (Eq. 2) as the threshold passes each of its patches is added to the
 // patch's bin, and a prefix sum over the bins gives the loss of every
 // threshold; the first minimum is the candidate's threshold.
 //
@@ -32,7 +32,7 @@ constexpr int kCandsPerPass = kThreads / kTileTriplets;  // 64
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Twice the hinge of Eq. 3 for one triplet, from twice tau (an integer).
+// Twice the hinge of Eq. 2 for one triplet, from twice tau (an integer).
 __device__ __forceinline__ int trl2(int tau2, int s_ap, int s_an, int ha, int hp, int hn)
 {
     const int v = tau2 + 2 * (-s_ap - ha * hp + s_an + ha * hn);

@@ -222,3 +222,67 @@ def test_config_workload_has_no_near_ties(ref, seed_offset):
     for img, kp in ((w.image1, w.kp1), (w.image2, w.kp2)):
         _, ties = ref.describe_bad(ref.build_integral(img), kp, w.pairs)
         assert ties == 0
+
+
+def _exact_centre_half_up(k, s, u):
+    """Nearest pixel to k + s*u with halves rounded up, in exact rationals
+    (k and s are float32 values, u an integer offset)."""
+    from fractions import Fraction
+    return math.floor(Fraction(float(k)) + Fraction(float(s)) * u + Fraction(1, 2))
+
+
+def _exact_radius_half_up(r, s):
+    from fractions import Fraction
+    return math.floor(Fraction(int(r)) * Fraction(float(s)) + Fraction(1, 2))
+
+
+@pytest.mark.parametrize("scale", [1.5, 2.5, 3.5, 3.49])
+def test_fractional_scale_radius_rounds_to_nearest(ref, scale):
+    """Sec. III-A gives both boxes one size s; the scaled radius r*scale is
+    rounded to the nearest integer (halves up).  At these scales r*scale has a
+    fractional part >= 0.5 for some r, so truncation would give a smaller box.
+    Expected bits come from direct pixel sums over boxes whose radius and
+    centres are computed in exact rationals."""
+    rng = np.random.default_rng(100 + int(scale * 100))
+    img = rng.integers(0, 256, (220, 240), dtype=np.uint8)
+    pairs = synth.box_pairs(rng, 256, max_offset=14, radius_range=(1, 5), threshold_range=(-30, 30))
+    s32 = np.float32(scale)
+    # a .25 offset keeps every centre of the half-integer scales off a rounding tie
+    kps = kp_array([(120.25, 110.25, s32, 0.0), (118.25, 107.75, s32, 0.0)])
+    bits, ties = describe(ref, img, kps, pairs)
+    assert ties == 0
+    n_round_up = 0
+    for i, kp in enumerate(kps):
+        for j, p in enumerate(pairs):
+            R = _exact_radius_half_up(p["radius"], s32)
+            n_round_up += R != math.floor(float(p["radius"]) * float(s32))
+            c1 = (_exact_centre_half_up(kp["x"], s32, int(p["x1"])), _exact_centre_half_up(kp["y"], s32, int(p["y1"])))
+            c2 = (_exact_centre_half_up(kp["x"], s32, int(p["x2"])), _exact_centre_half_up(kp["y"], s32, int(p["y2"])))
+            d = direct_box_sum(img, *c1, R) - direct_box_sum(img, *c2, R)
+            assert bits[i, j] == int(d <= float(p["threshold"]) * (2 * R + 1) ** 2), (i, j, R)
+    assert n_round_up > 0  # the pin exercises radii that truncation would shrink
+
+
+@pytest.mark.parametrize("scale", [1.0, 2.0, 3.0])
+def test_half_pixel_centres_round_up(ref, scale):
+    """A keypoint on a half-pixel position with angle 0 and integer scale puts
+    every box centre exactly halfway between two pixels; the centre is the
+    pixel above (x + 1/2 -> x + 1), on both axes and for even and odd pixels.
+    Expected bits from direct pixel sums at those centres."""
+    rng = np.random.default_rng(200 + int(scale))
+    img = rng.integers(0, 256, (200, 210), dtype=np.uint8)
+    pairs = synth.box_pairs(rng, 512, max_offset=14, radius_range=(1, 5), threshold_range=(-30, 30))
+    kps = kp_array([(100.5, 90.5, scale, 0.0), (101.5, 91.5, scale, 0.0), (100.5, 91.0, scale, 0.0)])
+    bits, ties = describe(ref, img, kps, pairs)
+    assert ties == 0
+    s = int(scale)
+    for i, kp in enumerate(kps):
+        xf, yf = math.floor(float(kp["x"])), math.floor(float(kp["y"]))
+        up_x = 1 if float(kp["x"]) != xf else 0
+        up_y = 1 if float(kp["y"]) != yf else 0
+        for j, p in enumerate(pairs):
+            R = int(p["radius"]) * s
+            c1 = (xf + s * int(p["x1"]) + up_x, yf + s * int(p["y1"]) + up_y)
+            c2 = (xf + s * int(p["x2"]) + up_x, yf + s * int(p["y2"]) + up_y)
+            d = direct_box_sum(img, *c1, R) - direct_box_sum(img, *c2, R)
+            assert bits[i, j] == int(d <= float(p["threshold"]) * (2 * R + 1) ** 2), (i, j)

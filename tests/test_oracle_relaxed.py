@@ -201,3 +201,65 @@ def test_tanh_slope_at_zero_is_beta(ref):
     _, Dp, _, _ = ref.relaxed_bad(b.anchor, pairs, np.ones(64), np.ones(64), th0 + h, BETA)
     _, Dm, _, _ = ref.relaxed_bad(b.anchor, pairs, np.ones(64), np.ones(64), th0 - h, BETA)
     np.testing.assert_allclose((Dp[0] - Dm[0]) / (2 * h), BETA, rtol=1e-6)
+
+
+def _hnm_by_matrix(A, P, tau):
+    """Hardest negatives and loss from the full similarity matrix S = A P^T / K
+    (numpy's product): row candidates S[i, j], column candidates S[j, i],
+    j != i, each taking its first maximum; the row candidate is kept when the
+    two maxima are equal."""
+    n, K = A.shape
+    S = (A @ P.T) / K
+    neg = np.zeros(n, dtype=np.int64)
+    loss = 0.0
+    for i in range(n):
+        others = [j for j in range(n) if j != i]
+        row = S[i, others]
+        col = S[others, i]
+        jr, jc = others[int(np.argmax(row))], others[int(np.argmax(col))]
+        if row.max() >= col.max():
+            neg[i], best = jr, row.max()
+        else:
+            neg[i], best = -1 - jc, col.max()
+        loss += max(0.0, tau - S[i, i] + best) / n
+    return neg, loss
+
+
+def test_hardest_negative_ties_keep_first_row_candidate(ref):
+    """With +-1 codes of 4 bits every similarity is a multiple of 1/4, so equal
+    row and column maxima and equal candidates inside a row or a column are
+    common.  The reading: the first maximum in index order, and the row
+    candidate (a positive p_j) when its similarity equals the column
+    candidate's (an anchor a_j)."""
+    rng = np.random.default_rng(45)
+    n_row_col_ties = 0
+    for trial in range(20):
+        A = np.sign(rng.normal(size=(12, 4)))
+        P = np.sign(rng.normal(size=(12, 4)))
+        loss, neg, _, _ = ref.trl_hnm(A, P, TAU, grads=False)
+        expect, expect_loss = _hnm_by_matrix(A, P, TAU)
+        np.testing.assert_array_equal(neg, expect)
+        assert abs(loss - expect_loss) < 1e-12
+        S = A @ P.T
+        for i in range(12):
+            others = [j for j in range(12) if j != i]
+            n_row_col_ties += S[i, others].max() == S[others, i].max()
+    assert n_row_col_ties > 50
+
+
+def test_planted_row_column_tie(ref):
+    """For triplet 0 the best row candidate s(a_0, p_5) and the best column
+    candidate s(a_6, p_0) are both 60/64; the row candidate p_5 is the hardest
+    negative."""
+    rng = np.random.default_rng(46)
+    A = np.sign(rng.normal(size=(8, 64)))
+    P = A.copy()
+    P[5] = A[0]
+    P[5, :2] *= -1  # s(a_0, p_5) = 60/64
+    A[6] = P[0]
+    A[6, 10:12] *= -1  # s(a_6, p_0) = 60/64
+    S = A @ P.T / 64
+    assert S[0, 5] == S[6, 0] == 60 / 64
+    assert S[0, [1, 2, 3, 4, 5, 6, 7]].max() == S[[1, 2, 3, 4, 5, 6, 7], 0].max()
+    _, neg, _, _ = ref.trl_hnm(A, P, TAU, grads=False)
+    assert neg[0] == 5

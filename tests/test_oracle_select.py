@@ -4,7 +4,7 @@ sorting into m bins).
 * The bin count is the paper's m = 5110 (tests/golden/threshold_search.txt).
 * Bins are pinned by exact rational arithmetic on box sums computed with
   numpy slicing, including clamped boxes and the extreme features +-255.
-* The whole search is pinned by brute force: the loss of Eq. 3 evaluated
+* The whole search is pinned by brute force: the loss of Eq. 2 evaluated
   directly at every one of the 5110 thresholds (the O(P^2)-type search the
   paper contrasts with), on sets with tied feature values inside triplets.
 * A one-triplet closed form: the best stump separates the negative from the
@@ -180,7 +180,7 @@ def test_hardest_negatives_by_distance_matrix(ref):
 
 def select_by_brute_force(pool, samples, cands, tau):
     """Alg. 1 written out with numpy: exact bins, HNM by distance matrices and the
-    loss of Eq. 3 at all 5110 thresholds."""
+    loss of Eq. 2 at all 5110 thresholds."""
     K, N = samples.shape
     P2 = len(pool)
     bits = np.zeros((P2, K), dtype=np.int64)  # 1 where the stump is +1
