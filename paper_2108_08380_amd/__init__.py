@@ -31,6 +31,8 @@ BD_DTYPE_U8, BD_DTYPE_F32 = 0, 1
 BD_PREC_FP32, BD_PREC_BF16, BD_PREC_FP8 = 0, 1, 2
 _PRECISIONS = {"fp32": BD_PREC_FP32, "bf16": BD_PREC_BF16, "fp8": BD_PREC_FP8}
 DEFAULT_MARGIN = 1e-3
+# train rows per split of the int8 MFMA k-NN engine (BD_BATCH_MFMA_MAX_ROWS)
+MFMA_MAX_ROWS = 2048
 
 # Exported symbols of include/bdesc.h with their C signatures.
 _P, _I32, _I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64

@@ -36,6 +36,15 @@ def test_every_declared_symbol_is_exported(L):
     assert set(names) == set(bd.SIGNATURES), "binding signatures out of sync with the header"
 
 
+def test_header_constants_match_the_binding():
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define (BD_\w+) \(?(-?\d+)\)?", text))
+    for name in ("BD_OK", "BD_EINVAL", "BD_EUNSUPPORTED", "BD_ENOMEM", "BD_EDEVICE", "BD_DTYPE_U8", "BD_DTYPE_F32",
+                 "BD_PREC_FP32", "BD_PREC_BF16", "BD_PREC_FP8"):
+        assert int(defs[name]) == getattr(bd, name), name
+    assert int(defs["BD_BATCH_MFMA_MAX_ROWS"]) == bd.MFMA_MAX_ROWS
+
+
 def test_version_and_error_strings(L):
     assert L.bd_version().decode().startswith("bdesc")
     assert isinstance(L.bd_last_error(), bytes)

@@ -215,11 +215,15 @@ def test_batch_validation_errors(dev):
     assert_same(b.run(kps, pairs, B, t), single_image_outputs(w, imgs, hs, kps, pairs, B, t))
 
 
-def test_batched_workload_full_size(dev):
+def test_batched_workload_full_size(dev, ref):
     """The 64-scene workload (128 images, 320x240 .. 4000x3000, 500 .. 20000
     keypoints, BAD-512 + HashSIFT-256, 2-NN against each copy) in the launch
     configuration the benchmark times: autotuned and replayed as a graph,
-    checked against the single-image calls on every image."""
+    checked against the single-image calls on every image, and the largest
+    scene (both views, every keypoint) against the oracle directly: BAD-512
+    codes bit for bit, HashSIFT-256 bits wherever the FP64 response is at
+    least 2e-4 from its threshold, and the BAD 2-NN of 1000 sampled queries
+    bit for bit."""
     w = synth.batched()
     print(f"\n[batched full] {len(w.images)} images, {w.total_kp} keypoints", flush=True)
     imgs, hs, kps, pairs, B, t = upload(w, dev)
@@ -229,4 +233,32 @@ def test_batched_workload_full_size(dev):
     got = b.run(kps, pairs, B, t, out=out, graph=True)
     ref_out = single_image_outputs(w, imgs, hs, kps, pairs, B, t)
     assert_same(got, ref_out, "full")
+    match_rows = list(b.match_offsets)
     b.close()
+
+    offs = np.concatenate([[0], np.cumsum([len(x) for x in w.kps])])
+    m = max(range(len(w.matches)), key=lambda i: w.images[w.matches[i][0]].size)
+    qi, ti = w.matches[m]
+    H, W = w.images[qi].shape
+    print(f"[batched full] oracle check of scene {m}: {W}x{H}, {len(w.kps[qi])} keypoints per view", flush=True)
+    bad_ref = {}
+    for j in (qi, ti):
+        ii = ref.build_integral(w.images[j])
+        codes, _ = ref.describe_bad(ii, w.kps[j], w.pairs)
+        np.testing.assert_array_equal(to_np(got["bad_codes"])[offs[j]:offs[j + 1]], codes, err_msg=f"BAD image {j}")
+        bad_ref[j] = codes
+        _, resp, hcodes = ref.describe_hashsift(w.images[j], w.kps[j], w.B, w.t)
+        gbits = np.unpackbits(to_np(got["hs_codes"])[offs[j]:offs[j + 1]].view(np.uint8), axis=1, bitorder="little")
+        obits = np.unpackbits(hcodes.view(np.uint8), axis=1, bitorder="little")
+        safe = np.abs(resp) >= 2e-4
+        assert safe.mean() > 0.99
+        np.testing.assert_array_equal(gbits[safe], obits[safe], err_msg=f"HashSIFT image {j}")
+    # 2-NN of 1000 sampled queries against the whole train view (each query is
+    # independent, so the sample is checked exactly)
+    sel = np.sort(np.random.default_rng(6).choice(len(w.kps[qi]), min(1000, len(w.kps[qi])), replace=False))
+    ei, ed = ref.match_knn(bad_ref[qi][sel], bad_ref[ti], 2)
+    lo = int(match_rows[m])
+    assert int(match_rows[m + 1]) - lo == len(w.kps[qi])
+    np.testing.assert_array_equal(to_np(got["bad_idx"])[lo + sel], ei)
+    np.testing.assert_array_equal(to_np(got["bad_dist"])[lo + sel], ed)
+

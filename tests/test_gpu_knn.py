@@ -154,18 +154,21 @@ def test_mfma_train_set_beyond_packed_row_range(ref, dev):
 
 def test_mfma_splits_of_full_tag_range(ref, dev):
     """8-word codes, few queries and 2^21 + 100 train codes: the plan cuts the
-    train set into splits of 4096 rows, the most the key's 7-bit tile tag
-    covers, so tags 0 and 127 both occur; duplicates planted across a split
-    boundary and across the first and last tile of one split must resolve to
-    the lower index."""
+    train set into splits of bd.MFMA_MAX_ROWS rows (2048: 64 tiles of 32 rows,
+    the most the key's 6-bit tile tag covers), so tags 0 and 63 both occur;
+    duplicates planted across a split boundary and across the first and the
+    last tile of one split must resolve to the lower index."""
     rng = np.random.default_rng(83)
+    S, T = bd.MFMA_MAX_ROWS, 32
     n_t = (1 << 21) + 100
     q = synth.random_codes(rng, 8, 8)
     t = synth.random_codes(rng, n_t, 8)
-    t[4096 * 5 + 4095] = q[0]             # last row of a split (tag 127)
-    t[4096 * 6] = q[0]                    # first row of the next split
-    t[4096 * 9 + 31] = q[1] ^ np.uint64(1)
-    t[4096 * 9 + 127 * 32] = q[1] ^ np.uint64(2)   # tie: tag 0 vs tag 127 of one split
+    t[S * 5 + S - 1] = q[0]               # last row of a split (tag 63)
+    t[S * 6] = q[0]                       # first row of the next split (tag 0)
+    t[S * 9 + T - 1] = q[1] ^ np.uint64(1)                 # last row of tile 0 of split 9
+    t[S * 9 + (S // T - 1) * T] = q[1] ^ np.uint64(2)      # first row of tile 63 of split 9: a tie
+    t[S * 11 + 3] = q[3] ^ np.uint64(4)                    # tile 0 ...
+    t[S * 11 + S - 2] = q[3] ^ np.uint64(8)                # ... against tile 63, second neighbour
     t[n_t - 1] = q[2]
     t[n_t - 100] = q[2]
     for k in (1, 2):
@@ -173,4 +176,5 @@ def test_mfma_splits_of_full_tag_range(ref, dev):
         ei, ed = ref.match_knn(q, t, k)
         np.testing.assert_array_equal(to_np(dist), ed)
         np.testing.assert_array_equal(to_np(idx), ei)
-    assert ei[0, 0] == 4096 * 5 + 4095 and ei[1, 0] == 4096 * 9 + 31 and ei[2, 0] == n_t - 100
+    assert ei[0, 0] == S * 5 + S - 1 and ei[1, 0] == S * 9 + T - 1 and ei[2, 0] == n_t - 100
+    assert ei[1, 1] == S * 9 + (S // T - 1) * T and ei[3, 0] == S * 11 + 3 and ei[3, 1] == S * 11 + S - 2

@@ -71,15 +71,15 @@ def test_triplet_loss_forward_backward(ref, dev, n, K):
     neg = to_np(neg)
     same = neg == n64
     print(f"n={n} K={K} loss {l64:.6f} hardest-negative agreement {same.mean():.4f}")
-    # a differing choice must be a near tie of the FP64 similarities
+    # the inputs are seeded, so every choice must agree; the message gives the
+    # FP64 similarity gap of any that does not
     S = A.astype(np.float64) @ P.astype(np.float64).T / K
     val = lambda i, c: S[i, c] if c >= 0 else S[-1 - c, i]
-    for i in np.nonzero(~same)[0]:
-        assert abs(val(i, neg[i]) - val(i, n64[i])) < 1e-5
-    if same.all():
-        scale = max(np.abs(gA64).max(), np.abs(gP64).max())
-        np.testing.assert_allclose(to_np(gA), gA64, atol=1e-5 * scale)
-        np.testing.assert_allclose(to_np(gP), gP64, atol=1e-5 * scale)
+    gaps = [(int(i), abs(val(i, neg[i]) - val(i, n64[i]))) for i in np.nonzero(~same)[0]]
+    assert same.all(), f"hardest negatives differ from the oracle at (triplet, FP64 gap) {gaps[:8]}"
+    scale = max(np.abs(gA64).max(), np.abs(gP64).max())
+    np.testing.assert_allclose(to_np(gA), gA64, atol=1e-5 * scale)
+    np.testing.assert_allclose(to_np(gP), gP64, atol=1e-5 * scale)
 
 
 def test_hub_negative_gathers_many_sources(ref, dev):
