@@ -66,7 +66,9 @@ typedef struct bd_box_pair {
 
 typedef struct bd_context bd_context;
 
-/* Create a context bound to HIP device `device`.  *out receives the context. */
+/* Create a context bound to HIP device `device`.  *out receives the context.
+ * The first context on a device also resolves that device's address of the
+ * fixed scratch array of bd_match_hamming_knn_noalloc. */
 int bd_context_create(bd_context** out, int device);
 
 /* Free the context's workspace (synchronizes the device).  NULL is a no-op. */
@@ -207,6 +209,27 @@ int bd_hashsift_project(bd_context* ctx, const float* hist, const bd_keypoint* k
 int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q,
                          const uint64_t* train, int32_t n_t, int32_t n_words, int32_t k,
                          int32_t* idx, uint32_t* dist, void* stream);
+
+/* bd_match_hamming_knn without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops
+ * and harnesses that forbid hipMalloc.  Same arguments, kernels, launch
+ * shapes and results as bd_match_hamming_knn; the per-split partial keys go
+ * to a fixed scratch array of BD_NOALLOC_SCRATCH_BYTES in device memory
+ * instead of the context workspace (its address on each device is resolved
+ * once, by bd_context_create; each device keeps its copy until the process
+ * ends).  A problem whose partial keys, 4 * k * n_q * splits bytes with
+ * splits = ceil(n_t / rows per split) (the planner's choice, up to 2048 rows
+ * for 256/512-bit codes), exceed that size is rejected with BD_EINVAL
+ * before anything is enqueued.  The call never allocates, frees or
+ * synchronizes.  Every call on one device shares that device's array and
+ * leaves its last contents there (nothing needs to start at zero: each slot
+ * is written before it is read), so calls that overlap in time on one
+ * device, on any stream or context, race and must be serialized by the
+ * caller. */
+#define BD_NOALLOC_SCRATCH_BYTES (16 * 1024 * 1024)
+int bd_match_hamming_knn_noalloc(bd_context* ctx, const uint64_t* query, int32_t n_q,
+                                 const uint64_t* train, int32_t n_t, int32_t n_words, int32_t k,
+                                 int32_t* idx, uint32_t* dist, void* stream);
 
 /* Mutual nearest neighbours with a distance-ratio filter: the Hamming MNN
  * matcher of the paper's pipeline timing (Sec. IV, Table of the pipeline

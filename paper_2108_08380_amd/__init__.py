@@ -33,6 +33,8 @@ _PRECISIONS = {"fp32": BD_PREC_FP32, "bf16": BD_PREC_BF16, "fp8": BD_PREC_FP8}
 DEFAULT_MARGIN = 1e-3
 # train rows per split of the int8 MFMA k-NN engine (BD_BATCH_MFMA_MAX_ROWS)
 MFMA_MAX_ROWS = 2048
+# fixed device scratch of bd_match_hamming_knn_noalloc (BD_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 16 * 1024 * 1024
 
 # Exported symbols of include/bdesc.h with their C signatures.
 _P, _I32, _I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -52,6 +54,7 @@ SIGNATURES = {
     "bd_hashsift_features": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P], ctypes.c_int),
     "bd_hashsift_project": ([_P, _P, _P, _I32, _P, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
     "bd_match_hamming_knn": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
+    "bd_match_hamming_knn_noalloc": ([_P, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
     "bd_match_mutual": ([_P, _P, _I32, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P, _P], ctypes.c_int),
     "bd_find_threshold": ([_P, _P, _I32, _P, _P, ctypes.c_float, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "bd_select_features": ([_P, _P, _I32, _P, _I32, _P, _I32, _I32, ctypes.c_float, _P, _P, _P, _P, _P, _P],
@@ -443,6 +446,36 @@ def match_hamming_knn(query, train, k: int = 1, idx=None, dist=None):
     dev, stream = _device_and_stream(query, train, idx, dist)
     _check(lib().bd_match_hamming_knn(context(dev, stream), query.data_ptr(), n_q, train.data_ptr(), train.shape[0],
                                       n_words, k, idx.data_ptr(), dist.data_ptr(), stream))
+    return idx, dist
+
+
+def match_hamming_knn_noalloc(query, train, idx, dist):
+    """bd_match_hamming_knn_noalloc: the k-NN of match_hamming_knn with the
+    library's fixed device scratch instead of the context workspace.  The
+    caller supplies idx (n_q, k) int32 and dist (n_q, k) uint32; k is their
+    column count.  The context of (device, stream) must already exist
+    (context() creates it; creation is the only step that allocates)."""
+    torch = _torch()
+    _require(query, torch.uint64, 2, "query")
+    _require(train, torch.uint64, 2, "train")
+    _contig(query, "query")
+    _contig(train, "train")
+    _require(idx, torch.int32, 2, "idx")
+    _require(dist, torch.uint32, 2, "dist")
+    _contig(idx, "idx")
+    _contig(dist, "dist")
+    if query.shape[1] != train.shape[1]:
+        raise ValueError("query and train codes differ in length")
+    n_q, n_words = query.shape
+    k = idx.shape[1]
+    if idx.shape != (n_q, k) or dist.shape != (n_q, k):
+        raise ValueError("idx and dist must both be (n_q, k)")
+    dev, stream = _device_and_stream(query, train, idx, dist)
+    ctx = _contexts.get((dev, stream))
+    if ctx is None:
+        raise RuntimeError("no library context for this device and stream; create it with context() first")
+    _check(lib().bd_match_hamming_knn_noalloc(ctx, query.data_ptr(), n_q, train.data_ptr(), train.shape[0], n_words,
+                                              k, idx.data_ptr(), dist.data_ptr(), stream))
     return idx, dist
 
 

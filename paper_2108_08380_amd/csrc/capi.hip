@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "bd_internal.hpp"
@@ -51,6 +52,41 @@ struct DeviceGuard {
     }
 };
 }  // namespace
+
+// Fixed device scratch for the entry points that allocate nothing.  Each
+// device holds its own copy of the array from the first context created on
+// it until the process ends; host code never uses the array's name as an
+// address (that is a host-side stand-in), only the device address resolved
+// once per device by hipGetSymbolAddress with that device current.
+static __device__ __align__(256) uint8_t scratch[BD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int resolve_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(BD_EINVAL, "device %d beyond the scratch table", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return BD_OK;
+    DeviceGuard guard(device);
+    if (guard.err != hipSuccess) return fail(BD_EDEVICE, "hipSetDevice(%d): %s", device, hipGetErrorString(guard.err));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(BD_EDEVICE, "scratch address on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return BD_OK;
+}
+
+void* scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_ptr[device];
+}
 
 int reserve_workspace(bd_context* ctx, size_t bytes, hipStream_t stream, void** out)
 {
@@ -117,6 +153,7 @@ int bd_context_create(bd_context** out, int device)
     hipDeviceProp_t prop;
     e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) return fail(BD_EDEVICE, "bd_context_create: %s", hipGetErrorString(e));
+    if (int rc = resolve_scratch(device)) return rc;
     bd_context* ctx = new (std::nothrow) bd_context();
     if (!ctx) return fail(BD_ENOMEM, "bd_context_create: out of host memory");
     ctx->device = device;
@@ -350,6 +387,30 @@ int bd_match_hamming_knn(bd_context* ctx, const uint64_t* query, int32_t n_q, co
     void* ws = nullptr;
     if (int rc = reserve_workspace(ctx, plan.workspace_bytes(), s, &ws)) return rc;
     launch_knn(plan, query, train, idx, dist, ws, s);
+    return check_launch(fn);
+}
+
+int bd_match_hamming_knn_noalloc(bd_context* ctx, const uint64_t* query, int32_t n_q, const uint64_t* train,
+                                 int32_t n_t, int32_t n_words, int32_t k, int32_t* idx, uint32_t* dist, void* stream)
+{
+    const char* fn = "bd_match_hamming_knn_noalloc";
+    if (n_words < 1 || n_words > 8) return fail(BD_EUNSUPPORTED, "%s: n_words %d (1..8)", fn, n_words);
+    if (k < 1 || k > 2) return fail(BD_EUNSUPPORTED, "%s: k %d (1 or 2)", fn, k);
+    if (n_q < 0 || n_t < 0) return fail(BD_EINVAL, "%s: negative count", fn);
+    if (n_q > 0 && (!query || !idx || !dist)) return fail(BD_EINVAL, "%s: null query or output pointer", fn);
+    if (n_q > 0 && n_t > 0 && !train) return fail(BD_EINVAL, "%s: null train pointer", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    if (n_q == 0) return BD_OK;
+    // the same plan, hence the same kernels and launch shapes, as bd_match_hamming_knn
+    const KnnPlan plan = plan_knn(n_q, n_t, n_words, k, ctx->num_cus);
+    const size_t need = plan.workspace_bytes();
+    if (need > (size_t)BD_NOALLOC_SCRATCH_BYTES)
+        return fail(BD_EINVAL, "%s: %d queries x %d train codes need %zu bytes of scratch, above the fixed %d", fn,
+                    n_q, n_t, need, (int)BD_NOALLOC_SCRATCH_BYTES);
+    void* ws = scratch_of(ctx->device);
+    if (!ws) return fail(BD_EDEVICE, "%s: no scratch resolved for device %d", fn, ctx->device);
+    // every per-split slot is written before the merge reads it: nothing to clear
+    launch_knn(plan, query, train, idx, dist, ws, static_cast<hipStream_t>(stream));
     return check_launch(fn);
 }
 

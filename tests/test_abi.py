@@ -138,6 +138,13 @@ def test_match_validation(L):
     assert L.bd_match_hamming_knn(None, p, 4, None, 4, 4, 1, p, p, None) == bd.BD_EINVAL
     assert L.bd_match_hamming_knn(None, p, 4, None, 0, 4, 1, p, p, None) == bd.BD_EINVAL
     assert "null context" in err(L)
+    assert L.bd_match_hamming_knn_noalloc(None, p, 4, p, 4, 9, 1, p, p, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_match_hamming_knn_noalloc(None, p, 4, p, 4, 4, 3, p, p, None) == bd.BD_EUNSUPPORTED
+    assert L.bd_match_hamming_knn_noalloc(None, p, -1, p, 4, 4, 1, p, p, None) == bd.BD_EINVAL
+    assert L.bd_match_hamming_knn_noalloc(None, p, 4, None, 4, 4, 1, p, p, None) == bd.BD_EINVAL
+    assert L.bd_match_hamming_knn_noalloc(None, p, 4, p, 4, 4, 1, None, p, None) == bd.BD_EINVAL
+    assert L.bd_match_hamming_knn_noalloc(None, p, 4, p, 4, 4, 1, p, p, None) == bd.BD_EINVAL
+    assert "null context" in err(L)
 
 
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
