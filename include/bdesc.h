@@ -74,6 +74,19 @@ int bd_context_create(bd_context** out, int device);
 /* Free the context's workspace (synchronizes the device).  NULL is a no-op. */
 int bd_context_destroy(bd_context* ctx);
 
+/* Invalid keypoints (Sec. III-A, III-B: one code per keypoint; a keypoint
+ * with a non-finite field or scale <= 0 has no patch and gets an all-zero
+ * code, or a zero feature row).  Every describe call made with this context
+ * adds one to a device counter per invalid keypoint it meets:
+ * bd_describe_bad, bd_describe_bad_table, bd_describe_hashsift (once per
+ * keypoint, although it also projects), bd_hashsift_features, and the BAD
+ * and HashSIFT stages of bd_batch_run.  bd_hashsift_project does not count
+ * (its kps argument only masks codes).  bd_context_poll synchronizes the
+ * context's device, stores the count accumulated since the context was
+ * created or last polled in *invalid_count, and resets the counter to zero.
+ * Errors: BD_EINVAL (null pointer), BD_EDEVICE. */
+int bd_context_poll(bd_context* ctx, uint64_t* invalid_count);
+
 /* Message describing the last non-zero return on the calling thread. */
 const char* bd_last_error(void);
 

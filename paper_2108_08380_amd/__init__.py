@@ -41,6 +41,7 @@ _P, _I32, _I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 SIGNATURES = {
     "bd_context_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int], ctypes.c_int),
     "bd_context_destroy": ([_P], ctypes.c_int),
+    "bd_context_poll": ([_P, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "bd_last_error": ([], ctypes.c_char_p),
     "bd_version": ([], ctypes.c_char_p),
     "bd_build_integral": ([_P, _P, _I32, _I32, _I64, _P, _I64, _P], ctypes.c_int),
@@ -163,6 +164,14 @@ def context(device: int, stream=None) -> int:
                 ctx = out.value
                 _contexts[key] = ctx
     return ctx
+
+
+def context_poll(device: int, stream=None) -> int:
+    """bd_context_poll on the context of (device, stream): the number of invalid
+    keypoints its describe calls met since the last poll (synchronizes)."""
+    n = ctypes.c_uint64()
+    _check(lib().bd_context_poll(context(device, stream), ctypes.byref(n)))
+    return int(n.value)
 
 
 def _torch():

@@ -39,7 +39,8 @@ __device__ __forceinline__ void bad_block_body(const uint32_t* __restrict__ ii, 
                                                int64_t ii_pitch, const bd_keypoint* __restrict__ kps, int32_t n_kp,
                                                const int32_t* __restrict__ order,
                                                const bd_box_pair* __restrict__ pairs, int32_t n_words,
-                                               uint64_t* __restrict__ codes, int lb, KpFrame* frames, int* index)
+                                               uint64_t* __restrict__ codes, int lb, KpFrame* frames, int* index,
+                                               unsigned long long* __restrict__ invalid)
 {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x % kWave;
@@ -73,6 +74,7 @@ __device__ __forceinline__ void bad_block_body(const uint32_t* __restrict__ ii, 
         uint64_t* out = codes + (int64_t)i * n_words;
         if (!f.valid) {
             if (lane < n_words) out[lane] = 0ull;
+            if (invalid && lane == 0) atomicAdd(invalid, 1ull);
         } else {
             const int r_cap = ((W < H ? W : H) - 1) / 2;
             const uint32_t pitch = (uint32_t)ii_pitch;
@@ -135,14 +137,15 @@ __global__ __launch_bounds__(256) void bad_describe_kernel(const uint32_t* __res
                                                            int64_t ii_pitch, const bd_keypoint* __restrict__ kps,
                                                            int32_t n_kp, const int32_t* __restrict__ order,
                                                            const bd_box_pair* __restrict__ pairs, int32_t n_words,
-                                                           uint64_t* __restrict__ codes)
+                                                           uint64_t* __restrict__ codes,
+                                                           unsigned long long* __restrict__ invalid)
 {
     __shared__ KpFrame frames[kKpPerBlock];
     __shared__ int index[kKpPerBlock];
     const int nb = (n_kp + kKpPerBlock - 1) / kKpPerBlock;
     const int lb = xcd_logical_block(blockIdx.x, nb);
     if (lb >= nb) return;
-    bad_block_body(ii, W, H, ii_pitch, kps, n_kp, order, pairs, n_words, codes, lb, frames, index);
+    bad_block_body(ii, W, H, ii_pitch, kps, n_kp, order, pairs, n_words, codes, lb, frames, index, invalid);
 }
 
 // Batch: units are blocks of four keypoints of every image in turn (pre is
@@ -152,7 +155,8 @@ __global__ __launch_bounds__(256) void bad_describe_batch(const BatchImage* __re
                                                           const bd_keypoint* __restrict__ kps,
                                                           const int32_t* __restrict__ order,
                                                           const bd_box_pair* __restrict__ pairs, int32_t n_words,
-                                                          uint64_t* __restrict__ codes)
+                                                          uint64_t* __restrict__ codes,
+                                                          unsigned long long* __restrict__ invalid)
 {
     __shared__ KpFrame frames[kKpPerBlock];
     __shared__ int index[kKpPerBlock];
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(256) void bad_describe_batch(const BatchImage* __re
         const int i = segment_of(pre, n_img, u);
         const BatchImage& im = imgs[i];
         bad_block_body(im.ii, im.W, im.H, im.ii_pitch, kps + im.kp_offset, im.n_kp, order + im.kp_offset, pairs,
-                       n_words, codes + (int64_t)im.kp_offset * n_words, u - pre[i], frames, index);
+                       n_words, codes + (int64_t)im.kp_offset * n_words, u - pre[i], frames, index, invalid);
     }
 }
 
@@ -275,7 +279,8 @@ __device__ __forceinline__ void bad_compiled_body(const uint32_t* __restrict__ i
                                                   int32_t n_kp, const int32_t* __restrict__ order,
                                                   const uint8_t* __restrict__ table, int32_t n_words,
                                                   uint64_t* __restrict__ codes, int lb, KpFrame* frames,
-                                                  int* index, uint32_t (*sums)[kMaxBoxes])
+                                                  int* index, uint32_t (*sums)[kMaxBoxes],
+                                                  unsigned long long* __restrict__ invalid)
 {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x % kWave;
@@ -309,6 +314,7 @@ __device__ __forceinline__ void bad_compiled_body(const uint32_t* __restrict__ i
         uint64_t* out = codes + (int64_t)i * n_words;
         if (!f.valid) {
             if (lane < n_words) out[lane] = 0ull;
+            if (invalid && lane == 0) atomicAdd(invalid, 1ull);
         } else {
             const int n_bits = n_words * 64;
             const int32_t nb_raw = *reinterpret_cast<const int32_t*>(table);
@@ -380,7 +386,8 @@ __global__ __launch_bounds__(256) void bad_compiled_kernel(const uint32_t* __res
                                                            int64_t ii_pitch, const bd_keypoint* __restrict__ kps,
                                                            int32_t n_kp, const int32_t* __restrict__ order,
                                                            const uint8_t* __restrict__ table, int32_t n_words,
-                                                           uint64_t* __restrict__ codes)
+                                                           uint64_t* __restrict__ codes,
+                                                           unsigned long long* __restrict__ invalid)
 {
     __shared__ KpFrame frames[kKpPerBlock];
     __shared__ int index[kKpPerBlock];
@@ -388,7 +395,7 @@ __global__ __launch_bounds__(256) void bad_compiled_kernel(const uint32_t* __res
     const int nb = (n_kp + kKpPerBlock - 1) / kKpPerBlock;
     const int lb = xcd_logical_block(blockIdx.x, nb);
     if (lb >= nb) return;
-    bad_compiled_body(ii, W, H, ii_pitch, kps, n_kp, order, table, n_words, codes, lb, frames, index, sums);
+    bad_compiled_body(ii, W, H, ii_pitch, kps, n_kp, order, table, n_words, codes, lb, frames, index, sums, invalid);
 }
 
 __global__ __launch_bounds__(256) void bad_compiled_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
@@ -396,7 +403,8 @@ __global__ __launch_bounds__(256) void bad_compiled_batch(const BatchImage* __re
                                                           const bd_keypoint* __restrict__ kps,
                                                           const int32_t* __restrict__ order,
                                                           const uint8_t* __restrict__ table, int32_t n_words,
-                                                          uint64_t* __restrict__ codes)
+                                                          uint64_t* __restrict__ codes,
+                                                          unsigned long long* __restrict__ invalid)
 {
     __shared__ KpFrame frames[kKpPerBlock];
     __shared__ int index[kKpPerBlock];
@@ -406,7 +414,8 @@ __global__ __launch_bounds__(256) void bad_compiled_batch(const BatchImage* __re
         const int i = segment_of(pre, n_img, u);
         const BatchImage& im = imgs[i];
         bad_compiled_body(im.ii, im.W, im.H, im.ii_pitch, kps + im.kp_offset, im.n_kp, order + im.kp_offset, table,
-                          n_words, codes + (int64_t)im.kp_offset * n_words, u - pre[i], frames, index, sums);
+                          n_words, codes + (int64_t)im.kp_offset * n_words, u - pre[i], frames, index, sums,
+                          invalid);
     }
 }
 
@@ -421,36 +430,36 @@ void launch_bad_compile(const bd_box_pair* pairs, int32_t n_bits, uint8_t* table
 
 void launch_bad_compiled(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch, const bd_keypoint* kps,
                          int32_t n_kp, const int32_t* order, const uint8_t* table, int32_t n_words, uint64_t* codes,
-                         hipStream_t stream)
+                         unsigned long long* invalid, hipStream_t stream)
 {
     const int nb = (n_kp + kKpPerBlock - 1) / kKpPerBlock;
     hipLaunchKernelGGL(bad_compiled_kernel, dim3(xcd_grid(nb)), dim3(kKpPerBlock * kWave), 0, stream, ii, W, H,
-                       ii_pitch, kps, n_kp, order, table, n_words, codes);
+                       ii_pitch, kps, n_kp, order, table, n_words, codes, invalid);
 }
 
 void launch_bad_compiled_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
                                const int32_t* order, const uint8_t* table, int32_t n_words, uint64_t* codes, int grid,
-                               hipStream_t stream)
+                               unsigned long long* invalid, hipStream_t stream)
 {
     hipLaunchKernelGGL(bad_compiled_batch, dim3(grid), dim3(kKpPerBlock * kWave), 0, stream, imgs, n_img, pre, kps,
-                       order, table, n_words, codes);
+                       order, table, n_words, codes, invalid);
 }
 
 void launch_bad(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch, const bd_keypoint* kps,
                 int32_t n_kp, const int32_t* order, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes,
-                hipStream_t stream)
+                unsigned long long* invalid, hipStream_t stream)
 {
     const int blocks = (n_kp + kKpPerBlock - 1) / kKpPerBlock;
     hipLaunchKernelGGL(bad_describe_kernel, dim3(xcd_grid(blocks)), dim3(kKpPerBlock * kWave), 0, stream, ii, W, H,
-                       ii_pitch, kps, n_kp, order, pairs, n_words, codes);
+                       ii_pitch, kps, n_kp, order, pairs, n_words, codes, invalid);
 }
 
 void launch_bad_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
                       const int32_t* order, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes, int grid,
-                      hipStream_t stream)
+                      unsigned long long* invalid, hipStream_t stream)
 {
     hipLaunchKernelGGL(bad_describe_batch, dim3(grid), dim3(kKpPerBlock * kWave), 0, stream, imgs, n_img, pre, kps,
-                       order, pairs, n_words, codes);
+                       order, pairs, n_words, codes, invalid);
 }
 
 }  // namespace bd

@@ -237,13 +237,14 @@ void launch_stage(bd_batch* b, int stage, const RunArgs& a, hipStream_t s)
                 launch_bad_compile(a.pairs, b->bad_bits, b->d_bad_table, s);
                 launch_bad_compiled_batch(b->d_images, b->n_img, b->d_kpb_pre, a.kps, b->d_order, b->d_bad_table,
                                           b->bad_bits / 64, a.bad_codes,
-                                          grid_for(b->kpb_units, b->tune.bad_blocks_per_cu, cus), s);
+                                          grid_for(b->kpb_units, b->tune.bad_blocks_per_cu, cus), b->ctx->invalid, s);
             }
             break;
         case kHist:
             if (b->hs_bits)
                 launch_hashsift_hist_batch(b->d_images, b->n_img, b->hs_dtypes, b->d_kpb_pre, a.kps, b->d_order, b->d_hist,
-                                           grid_for(b->kpb_units, b->tune.hist_blocks_per_cu, cus), s);
+                                           grid_for(b->kpb_units, b->tune.hist_blocks_per_cu, cus), b->ctx->invalid,
+                                           s);
             break;
         case kProject:
             if (b->hs_bits)

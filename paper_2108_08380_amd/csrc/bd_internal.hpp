@@ -14,6 +14,7 @@ struct bd_context {
     void* workspace = nullptr;  // device memory, grown on demand
     size_t workspace_bytes = 0;
     int num_cus = 0;
+    unsigned long long* invalid = nullptr;  // device counter of invalid keypoints met by describe calls
 };
 
 namespace bd {
@@ -121,19 +122,19 @@ void launch_integral_batch(const BatchImage* imgs, int32_t n_img, const int32_t*
 // ---- BAD (bad.hip)
 void launch_bad(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch, const bd_keypoint* kps,
                 int32_t n_kp, const int32_t* order, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes,
-                hipStream_t stream);
+                unsigned long long* invalid, hipStream_t stream);
 
 size_t bad_table_bytes(int32_t n_bits);
 void launch_bad_compile(const bd_box_pair* pairs, int32_t n_bits, uint8_t* table, hipStream_t stream);
 void launch_bad_compiled(const uint32_t* ii, int32_t W, int32_t H, int64_t ii_pitch, const bd_keypoint* kps,
                          int32_t n_kp, const int32_t* order, const uint8_t* table, int32_t n_words, uint64_t* codes,
-                         hipStream_t stream);
+                         unsigned long long* invalid, hipStream_t stream);
 void launch_bad_compiled_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
                                const int32_t* order, const uint8_t* table, int32_t n_words, uint64_t* codes, int grid,
-                               hipStream_t stream);
+                               unsigned long long* invalid, hipStream_t stream);
 void launch_bad_batch(const BatchImage* imgs, int32_t n_img, const int32_t* pre, const bd_keypoint* kps,
                       const int32_t* order, const bd_box_pair* pairs, int32_t n_words, uint64_t* codes, int grid,
-                      hipStream_t stream);
+                      unsigned long long* invalid, hipStream_t stream);
 
 // ---- spatial keypoint order (order.hip)
 float order_inv_cell(int32_t W, int32_t H);
@@ -151,12 +152,12 @@ inline bool hashsift_image_fits(int64_t pitch, int32_t H)
 }
 void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
                           const bd_keypoint* kps, int32_t n_kp, const int32_t* order, float* hist,
-                          hipStream_t stream);
+                          unsigned long long* invalid, hipStream_t stream);
 void launch_hashsift_patch_features(const float* patches, int32_t n, float* hist, hipStream_t stream);
 // dtypes: bit (1 << dtype) set for every dtype among the images.
 void launch_hashsift_hist_batch(const BatchImage* imgs, int32_t n_img, int32_t dtypes, const int32_t* pre,
                                 const bd_keypoint* kps, const int32_t* order, float* hist, int grid,
-                                hipStream_t stream);
+                                unsigned long long* invalid, hipStream_t stream);
 void launch_hashsift_project(int32_t precision, const float* hist, const bd_keypoint* kps, int32_t n_kp,
                              const float* B, const float* t, int32_t n_words, float margin, uint64_t* codes,
                              float* resp, uint32_t* recheck_count, hipStream_t stream);

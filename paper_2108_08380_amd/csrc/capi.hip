@@ -158,7 +158,36 @@ int bd_context_create(bd_context** out, int device)
     if (!ctx) return fail(BD_ENOMEM, "bd_context_create: out of host memory");
     ctx->device = device;
     ctx->num_cus = prop.multiProcessorCount;
+    {
+        DeviceGuard guard(device);
+        e = guard.err;
+        if (e == hipSuccess) e = hipMalloc((void**)&ctx->invalid, sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipMemset(ctx->invalid, 0, sizeof(unsigned long long));
+    }
+    if (e != hipSuccess) {
+        if (ctx->invalid) (void)hipFree(ctx->invalid);
+        delete ctx;
+        return fail(BD_ENOMEM, "bd_context_create: invalid-keypoint counter: %s", hipGetErrorString(e));
+    }
     *out = ctx;
+    return BD_OK;
+}
+
+int bd_context_poll(bd_context* ctx, uint64_t* invalid_count)
+{
+    const char* fn = "bd_context_poll";
+    if (!invalid_count) return fail(BD_EINVAL, "%s: null output pointer", fn);
+    *invalid_count = 0;
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    DeviceGuard guard(ctx->device);
+    hipError_t e = guard.err;
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    unsigned long long v = 0;
+    if (e == hipSuccess) e = hipMemcpy(&v, ctx->invalid, sizeof v, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemset(ctx->invalid, 0, sizeof v);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(BD_EDEVICE, "%s: %s", fn, hipGetErrorString(e));
+    *invalid_count = v;
     return BD_OK;
 }
 
@@ -166,11 +195,12 @@ int bd_context_destroy(bd_context* ctx)
 {
     if (!ctx) return BD_OK;
     int rc = BD_OK;
-    if (ctx->workspace) {
+    {
         DeviceGuard guard(ctx->device);
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) rc = fail(BD_EDEVICE, "bd_context_destroy: %s", hipGetErrorString(e));
-        (void)hipFree(ctx->workspace);
+        if (ctx->workspace) (void)hipFree(ctx->workspace);
+        if (ctx->invalid) (void)hipFree(ctx->invalid);
     }
     delete ctx;
     return rc;
@@ -221,7 +251,8 @@ int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, i
     if (n_kp > 0 && (!ii || !kps || !pairs || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
     if (int rc = check_ctx(ctx, fn)) return rc;
     if (n_kp == 0) return BD_OK;
-    launch_bad(ii, W, H, ii_pitch, kps, n_kp, order, pairs, n_bits / 64, codes, static_cast<hipStream_t>(stream));
+    launch_bad(ii, W, H, ii_pitch, kps, n_kp, order, pairs, n_bits / 64, codes, ctx->invalid,
+               static_cast<hipStream_t>(stream));
     return check_launch(fn);
 }
 
@@ -292,7 +323,7 @@ int bd_describe_bad_table(bd_context* ctx, const uint32_t* ii, int32_t W, int32_
     if (int rc = check_ctx(ctx, fn)) return rc;
     if (table->device != ctx->device) return fail(BD_EINVAL, "%s: table belongs to device %d", fn, table->device);
     if (n_kp == 0) return BD_OK;
-    launch_bad_compiled(ii, W, H, ii_pitch, kps, n_kp, order, table->data, table->n_bits / 64, codes,
+    launch_bad_compiled(ii, W, H, ii_pitch, kps, n_kp, order, table->data, table->n_bits / 64, codes, ctx->invalid,
                         static_cast<hipStream_t>(stream));
     return check_launch(fn);
 }
@@ -328,7 +359,8 @@ int bd_hashsift_features(bd_context* ctx, const void* img, int32_t dtype, int32_
     if (n_kp > 0 && (!img || !kps || !hist)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
     if (int rc = check_ctx(ctx, fn)) return rc;
     if (n_kp == 0) return BD_OK;
-    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, order, hist, static_cast<hipStream_t>(stream));
+    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, order, hist, ctx->invalid,
+                         static_cast<hipStream_t>(stream));
     return check_launch(fn);
 }
 
@@ -366,7 +398,7 @@ int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_
         if (int rc = reserve_workspace(ctx, sizeof(float) * 128 * (size_t)n_kp, s, &ws)) return rc;
         hist = static_cast<float*>(ws);
     }
-    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, order, hist, s);
+    launch_hashsift_hist(img, dtype, W, H, img_pitch, kps, n_kp, order, hist, ctx->invalid, s);
     launch_hashsift_project(precision, hist, kps, n_kp, B, t, n_bits / 64, margin, codes, resp_out, recheck_count, s);
     return check_launch(fn);
 }

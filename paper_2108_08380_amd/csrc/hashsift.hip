@@ -344,11 +344,13 @@ __device__ __forceinline__ void resample_f64(const uint8_t* __restrict__ img, in
 // kWaveLds-float LDS slice P; writes the 128 features to out.
 template <int DT, int R>
 __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_t W, int32_t H, int64_t pitch,
-                                         const bd_keypoint kp, float* __restrict__ out, float* P, int lane)
+                                         const bd_keypoint kp, float* __restrict__ out, float* P, int lane,
+                                         unsigned long long* __restrict__ invalid)
 {
     if (!(finite_f(kp.x) && finite_f(kp.y) && finite_f(kp.scale) && finite_f(kp.angle) && kp.scale > 0.0f)) {
         out[lane] = 0.0f;
         out[lane + kWave] = 0.0f;
+        if (invalid && lane == 0) atomicAdd(invalid, 1ull);
         return;
     }
     double sn, cs;
@@ -457,7 +459,8 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
                                                             int32_t H, int64_t pitch,
                                                             const bd_keypoint* __restrict__ kps,
                                                             int32_t n_kp, const int32_t* __restrict__ order,
-                                                            float* __restrict__ hist)
+                                                            float* __restrict__ hist,
+                                                            unsigned long long* __restrict__ invalid)
 {
     __shared__ float smem[kHistWaves][kWaveLds];
     const int lane = threadIdx.x % kWave;
@@ -469,7 +472,7 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
     if (pos >= n_kp) return;
     const int n = order ? order[pos] : pos;
     if (n < 0 || n >= n_kp) return;  // malformed order entries are skipped
-    hist_one<DT, 8>(img, W, H, pitch, kps[n], hist + (int64_t)n * 128, smem[wave], lane);
+    hist_one<DT, 8>(img, W, H, pitch, kps[n], hist + (int64_t)n * 128, smem[wave], lane, invalid);
 }
 
 // Batch: units are blocks of four keypoints of every image in turn (pre is
@@ -484,7 +487,8 @@ __global__ __launch_bounds__(256, DT == BD_DTYPE_U8 ? 5 : 4) void hashsift_hist_
                                                               const int32_t* __restrict__ pre,
                                                               const bd_keypoint* __restrict__ kps,
                                                               const int32_t* __restrict__ order,
-                                                              float* __restrict__ hist)
+                                                              float* __restrict__ hist,
+                                                              unsigned long long* __restrict__ invalid)
 {
     __shared__ float smem[kHistWaves][kWaveLds];
     const int wave = threadIdx.x / kWave;
@@ -502,13 +506,14 @@ __global__ __launch_bounds__(256, DT == BD_DTYPE_U8 ? 5 : 4) void hashsift_hist_
         int lane = threadIdx.x % kWave;
         asm volatile("" : "+v"(lane));
         if constexpr (DT != kMixedDtypes) {
-            hist_one<DT, 4>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave], lane);
+            hist_one<DT, 4>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave], lane,
+                            invalid);
         } else if (im.hs_dtype == BD_DTYPE_U8) {
             hist_one<BD_DTYPE_U8, 4>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave],
-                                  lane);
+                                     lane, invalid);
         } else {
             hist_one<BD_DTYPE_F32, 4>(im.img_hs, im.W, im.H, im.pitch_hs, kps[g], hist + (int64_t)g * 128, smem[wave],
-                                   lane);
+                                      lane, invalid);
         }
     }
 }
@@ -526,7 +531,7 @@ __global__ __launch_bounds__(256) void hashsift_patch_kernel(const float* __rest
     if (i >= n) return;
     const bd_keypoint kp{15.5f, 15.5f, 1.0f, 0.0f};
     hist_one<BD_DTYPE_F32, 4>(reinterpret_cast<const uint8_t*>(patches + (int64_t)i * 1024), 32, 32, 128, kp,
-                           hist + (int64_t)i * 128, smem[wave], lane);
+                           hist + (int64_t)i * 128, smem[wave], lane, nullptr);
 }
 
 // ---------------------------------------------------------------- projection
@@ -818,31 +823,32 @@ __global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* _
 
 void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch,
                           const bd_keypoint* kps, int32_t n_kp, const int32_t* order, float* hist,
-                          hipStream_t stream)
+                          unsigned long long* invalid, hipStream_t stream)
 {
     const int blocks = xcd_grid((n_kp + kHistWaves - 1) / kHistWaves);
     const uint8_t* p = static_cast<const uint8_t*>(img);
     if (dtype == BD_DTYPE_U8)
         hipLaunchKernelGGL(hashsift_hist_kernel<BD_DTYPE_U8>, dim3(blocks), dim3(kHistWaves * kWave), 0, stream,
-                           p, W, H, img_pitch, kps, n_kp, order, hist);
+                           p, W, H, img_pitch, kps, n_kp, order, hist, invalid);
     else
         hipLaunchKernelGGL(hashsift_hist_kernel<BD_DTYPE_F32>, dim3(blocks), dim3(kHistWaves * kWave), 0,
-                           stream, p, W, H, img_pitch, kps, n_kp, order, hist);
+                           stream, p, W, H, img_pitch, kps, n_kp, order, hist, invalid);
 }
 
 void launch_hashsift_hist_batch(const BatchImage* imgs, int32_t n_img, int32_t dtypes, const int32_t* pre,
-                                const bd_keypoint* kps, const int32_t* order, float* hist, int grid, hipStream_t stream)
+                                const bd_keypoint* kps, const int32_t* order, float* hist, int grid,
+                                unsigned long long* invalid, hipStream_t stream)
 {
     const dim3 block(kHistWaves * kWave);
     if (dtypes == (1 << BD_DTYPE_U8))
         hipLaunchKernelGGL(hashsift_hist_batch<BD_DTYPE_U8>, dim3(grid), block, 0, stream, imgs, n_img, pre, kps,
-                           order, hist);
+                           order, hist, invalid);
     else if (dtypes == (1 << BD_DTYPE_F32))
         hipLaunchKernelGGL(hashsift_hist_batch<BD_DTYPE_F32>, dim3(grid), block, 0, stream, imgs, n_img, pre, kps,
-                           order, hist);
+                           order, hist, invalid);
     else
         hipLaunchKernelGGL(hashsift_hist_batch<kMixedDtypes>, dim3(grid), block, 0, stream, imgs, n_img, pre, kps,
-                           order, hist);
+                           order, hist, invalid);
 }
 
 void launch_hashsift_patch_features(const float* patches, int32_t n, float* hist, hipStream_t stream)

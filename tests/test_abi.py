@@ -60,6 +60,14 @@ def test_context_create_null_output(L):
     assert L.bd_context_destroy(None) == bd.BD_OK
 
 
+def test_context_poll_validation(L):
+    n = ctypes.c_uint64(5)
+    assert L.bd_context_poll(None, None) == bd.BD_EINVAL
+    assert "null output" in err(L)
+    assert L.bd_context_poll(None, ctypes.byref(n)) == bd.BD_EINVAL
+    assert "null context" in err(L) and n.value == 0
+
+
 def test_build_integral_validation(L):
     p = ctypes.c_void_p(16)  # never dereferenced: validation fails first or the context is null
     assert L.bd_build_integral(None, p, 0, 5, 5, p, 6, None) == bd.BD_EINVAL
