@@ -47,7 +47,7 @@ extern "C" {
 
 #define BD_PREC_FP32 0 /* FP32 operands, FP32 MFMA */
 #define BD_PREC_BF16 1 /* bfloat16 operands (round to nearest even), FP32 accumulation */
-#define BD_PREC_FP8 2  /* OCP float8 e4m3 operands with per-row scales, FP32 accumulation */
+#define BD_PREC_FP8 2  /* OCP float8 e4m3 operands, each row scaled by a power of two, FP32 accumulation */
 
 typedef struct bd_keypoint {
     float x, y, scale, angle;
@@ -167,9 +167,11 @@ int bd_describe_bad_table(bd_context* ctx, const uint32_t* ii, int32_t W, int32_
  *   precision BD_PREC_FP32, BD_PREC_BF16 or BD_PREC_FP8 (the reduced-precision
  *            forms are an extension: the paper fixes no precision).  With
  *            BF16/FP8 every response with |r| < margin is recomputed from the
- *            unrounded FP32 operands (products summed by a fixed pairwise
- *            tree; in FP64 when that FP32 value is within 1e-6 of the
- *            threshold) and decides the bit;
+ *            unrounded FP32 operands (products of the elements k mod 4 in four
+ *            running sums over k, added as (s0 + s1) + (s2 + s3); in FP64 when
+ *            that FP32 value is within 1e-6 of the threshold) and decides the
+ *            bit.  FP8 scales every row of f and of B by the smallest power of
+ *            two s >= 2^-126 with max|row| <= 448 s before rounding to e4m3;
  *            recheck_count (optional device u32, caller-zeroed) is increased
  *            by the number of such responses.  margin is ignored for FP32.
  * n_bits is 256 or 512.  f: 34x34 bilinear

@@ -408,6 +408,9 @@ float bdref_round_e4m3(float x)
     return (float)(x < 0 ? -q : q);
 }
 
+/* float8 e4m3 scale of a row: the smallest power of two s >= 2^-126 with
+ * max|row| <= 448 s (448 is the largest e4m3 value), 1 for an all-zero row.
+ * A power of two makes the rescaling v / s exact. */
 static float row_scale_e4m3(const float* row, int len)
 {
     float m = 0.0f;
@@ -415,7 +418,12 @@ static float row_scale_e4m3(const float* row, int len)
         float v = fabsf(row[i]);
         if (v > m) m = v;
     }
-    return m > 0.0f ? m / 448.0f : 1.0f;
+    if (m == 0.0f) return 1.0f;
+    int E;
+    const double f = frexp((double)m, &E); /* m = f 2^E, f in [0.5, 1) */
+    int e = f <= 0.875 ? E - 9 : E - 8;    /* 448 = 0.875 2^9 */
+    if (e < -126) e = -126;
+    return ldexpf(1.0f, e);
 }
 
 void bdref_project_lowp(const float* hist, int32_t n_kp, const float* B, const float* t, int32_t n_bits,

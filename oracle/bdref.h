@@ -69,9 +69,10 @@ float bdref_round_e4m3(float x);
 
 /* Responses of the projection with rounded operands, accumulated exactly in
  * FP64: precision 1 = BF16 (both operands rounded to bfloat16), 2 = FP8
- * (per-row scales s = max|row| / 448 computed in float32 for every feature
- * row and every B row, operands x / s rounded to e4m3; response =
- * s_f * s_B * sum q_B q_f - t).  hist is n_kp x 128 float32. */
+ * (per-row scale s = the smallest power of two >= 2^-126 with
+ * max|row| <= 448 s, for every feature row and every B row, so that x / s is
+ * exact; operands x / s rounded to e4m3; response = s_f * s_B * sum q_B q_f
+ * - t).  hist is n_kp x 128 float32. */
 void bdref_project_lowp(const float* hist, int32_t n_kp, const float* B, const float* t, int32_t n_bits,
                         int32_t precision, double* resp);
 

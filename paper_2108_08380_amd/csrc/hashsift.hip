@@ -547,44 +547,6 @@ constexpr int kProjBlocksPerCu = 2;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Largest |value| of a 128-float row held as 32 floats by each of the four
-// lanes m, m+16, m+32, m+48.
-__device__ __forceinline__ float row_maxabs(const float (&v)[32])
-{
-    float m = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 32; ++i) m = fmaxf(m, fabsf(v[i]));
-    m = fmaxf(m, __shfl_xor(m, 16, kWave));
-    m = fmaxf(m, __shfl_xor(m, 32, kWave));
-    return m;
-}
-
-// float8 e4m3 scale of a row: max|row| / 448 (1 for an all-zero row).
-__device__ __forceinline__ float e4m3_scale(float maxabs) { return maxabs > 0.0f ? maxabs / 448.0f : 1.0f; }
-
-// Eight consecutive values (starting at v[8s]) scaled by 1/scale, rounded to
-// e4m3 (round to nearest even) and packed into 64 bits.
-__device__ __forceinline__ long pack_e4m3(const float (&v)[32], int s, float scale)
-{
-    int lo = 0, hi = 0;
-    float q[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) q[e] = fminf(fmaxf(v[8 * s + e] / scale, -448.0f), 448.0f);
-    lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], lo, false);
-    lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], lo, true);
-    hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[4], q[5], hi, false);
-    hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[6], q[7], hi, true);
-    return (long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
-__device__ __forceinline__ bf16x8 pack_bf16(const float (&v)[32], int s)
-{
-    bf16x8 r;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = (__bf16)v[8 * s + e];
-    return r;
-}
-
 // 32 consecutive floats of an LDS row.
 __device__ __forceinline__ void lds_row32(const float* src, float (&v)[32])
 {
@@ -598,31 +560,22 @@ __device__ __forceinline__ void lds_row32(const float* src, float (&v)[32])
     }
 }
 
-// Persistent, B-stationary projection.  Block b works on XCD b % 8 for the
-// chunk of 64 bits (b / 8) % n_words over that XCD's contiguous range of
-// 64-keypoint tiles, so the n_words blocks that need one tile run on the
-// same XCD and share its rows through L2.  The block keeps its chunk of B in
-// LDS as FP32 (64 rows) and in registers as the MFMA operand of the chosen
-// precision; each wavefront streams 16-keypoint tiles through its own LDS
-// slice, the next tile's rows in flight (registers) while the current one is
-// multiplied.  Lane (g, m) holds elements 32g..32g+31 of keypoint row m and
-// of B row m of each 16-bit subtile, so the k order of the MFMA chain is one
-// permutation applied to both operands.
-//   PREC = FP32: v_mfma_f32_16x16x4_f32, 32 steps per subtile.
-//   PREC = BF16: operands rounded to bfloat16, v_mfma_f32_16x16x32_bf16.
-//   PREC = FP8:  operands scaled per row (max|row| / 448) and rounded to
-//                OCP e4m3, v_mfma_f32_16x16x32_fp8_fp8, response rescaled.
-// With BF16/FP8 every response within `margin` of its threshold is
-// recomputed by its own lane in FP32 from the unrounded rows in LDS (in FP64
-// when that result is within 1e-6 of the threshold) and counted.
-template <int PREC>
+// FP32 projection: persistent and B-stationary.  Block b works on XCD b % 8
+// for the chunk of 64 bits (b / 8) % n_words over that XCD's contiguous
+// range of 64-keypoint tiles, so the n_words blocks that need one tile run on
+// the same XCD and share its rows through L2.  The block keeps its chunk of
+// B in registers as the MFMA operand; each wavefront streams 16-keypoint
+// tiles through its own LDS slice, the next tile's rows in flight
+// (registers) while the current one is multiplied with
+// v_mfma_f32_16x16x4_f32, 32 steps per subtile.  Lane (g, m) holds elements
+// 32g..32g+31 of keypoint row m and of B row m of each 16-bit subtile, so the
+// k order of the MFMA chain is one permutation applied to both operands.
 __global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* __restrict__ hist,
                                                                  const bd_keypoint* __restrict__ kps, int32_t n_kp,
                                                                  const float* __restrict__ B,
                                                                  const float* __restrict__ t, int32_t n_words,
-                                                                 float margin, uint64_t* __restrict__ codes,
-                                                                 float* __restrict__ resp,
-                                                                 uint32_t* __restrict__ recheck_count)
+                                                                 uint64_t* __restrict__ codes,
+                                                                 float* __restrict__ resp)
 {
     __shared__ __align__(16) float Bs[64 * kProjStride];
     __shared__ __align__(16) float As[kProjWaves][kProjRows * kProjStride];
@@ -651,27 +604,9 @@ __global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* _
     float bf[4][32];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) lds_row32(&Bs[(16 * nt + m) * kProjStride + 32 * g], bf[nt]);
-    float tv[4], sb[4];
+    float tv[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        tv[nt] = t[chunk * 64 + 16 * nt + m];
-        sb[nt] = 1.0f;
-    }
-    bf16x8 bb[4][4];
-    long bq[4][4];
-    if constexpr (PREC == BD_PREC_BF16) {
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) bb[nt][s] = pack_bf16(bf[nt], s);
-    } else if constexpr (PREC == BD_PREC_FP8) {
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            sb[nt] = e4m3_scale(row_maxabs(bf[nt]));  // scale of B row 16nt + m
-#pragma unroll
-            for (int s = 0; s < 4; ++s) bq[nt][s] = pack_e4m3(bf[nt], s, sb[nt]);
-        }
-    }
+    for (int nt = 0; nt < 4; ++nt) tv[nt] = t[chunk * 64 + 16 * nt + m];
 
     float* A = As[wave];
     // tile rows for this wavefront: 16 rows x 128 floats, lane l loads row l / 4, floats 32 (l % 4) ..
@@ -689,7 +624,6 @@ __global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* _
         }
     };
     load_tile(tile_first);
-    uint32_t rechecked = 0;
 
     for (int tile = tile_first; tile < tile_end; tile += n_groups) {
         wave_sync();  // the previous tile's LDS reads are done
@@ -704,83 +638,18 @@ __global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* _
         floatx4 acc[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        float sk[4] = {1.0f, 1.0f, 1.0f, 1.0f};
-        if constexpr (PREC == BD_PREC_FP32) {
 #pragma unroll
-            for (int k = 0; k < 32; ++k)
+        for (int k = 0; k < 32; ++k)
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bf[nt][k], acc[nt], 0, 0, 0);
-        } else if constexpr (PREC == BD_PREC_BF16) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const bf16x8 av = pack_bf16(a, s);
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bb[nt][s], acc[nt], 0, 0, 0);
-            }
-        } else {
-            const float sa = e4m3_scale(row_maxabs(a));  // scale of keypoint row m
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const long av = pack_e4m3(a, s, sa);
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bq[nt][s], acc[nt], 0, 0, 0);
-            }
-            // the accumulator of register i belongs to keypoint row 4g + i,
-            // whose scale lane 4g + i computed
-#pragma unroll
-            for (int i = 0; i < 4; ++i) sk[i] = __shfl(sa, 4 * g + i, kWave);
-        }
+            for (int nt = 0; nt < 4; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k], bf[nt][k], acc[nt], 0, 0, 0);
 
         // lane holds D[kp = 4g + i][bit = 16nt + m]
         float rv[4][4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) rv[nt][i] = acc[nt][i] * (sk[i] * sb[nt]) - tv[nt];
-
-        if constexpr (PREC != BD_PREC_FP32) {
-            uint32_t pending = 0;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (fabsf(rv[nt][i]) < margin && kp0 + 4 * g + i < n_kp) pending |= 1u << (4 * nt + i);
-            rechecked += __popc(pending);
-            // each lane re-checks its own responses, one per pass
-            while (__ballot(pending != 0u)) {
-                if (pending) {
-                    const int slot = __builtin_ctz(pending);
-                    pending &= pending - 1u;
-                    const int nt = slot >> 2, i = slot & 3;
-                    const float* arow = &A[(4 * g + i) * kProjStride];
-                    const float* brow = &Bs[(16 * nt + m) * kProjStride];
-                    // four independent chains (elements k mod 4), then a fixed tree
-                    float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, d3 = 0.0f;
-#pragma unroll 8
-                    for (int q = 0; q < 32; ++q) {
-                        const float4 av = reinterpret_cast<const float4*>(arow)[q];
-                        const float4 bv = reinterpret_cast<const float4*>(brow)[q];
-                        d0 = fmaf(av.x, bv.x, d0);
-                        d1 = fmaf(av.y, bv.y, d1);
-                        d2 = fmaf(av.z, bv.z, d2);
-                        d3 = fmaf(av.w, bv.w, d3);
-                    }
-                    float res = ((d0 + d1) + (d2 + d3)) - tv[nt];
-                    if (fabsf(res) < 1e-6f) {
-                        double d = 0.0;
-                        for (int k = 0; k < 128; ++k) d = fma((double)arow[k], (double)brow[k], d);
-                        res = (float)(d - (double)tv[nt]);
-                    }
-                    // write back to the slot without dynamic register indexing
-#pragma unroll
-                    for (int s2 = 0; s2 < 16; ++s2)
-                        if (s2 == slot) rv[s2 >> 2][s2 & 3] = res;
-                }
-            }
-        }
+            for (int i = 0; i < 4; ++i) rv[nt][i] = acc[nt][i] - tv[nt];
 
         uint64_t mask[4][4];
 #pragma unroll
@@ -814,11 +683,371 @@ __global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* _
             }
         }
     }
-    if constexpr (PREC != BD_PREC_FP32) {
-        // one atomic per wavefront
-        for (int d = 32; d >= 1; d >>= 1) rechecked += __shfl_xor(rechecked, d, kWave);
-        if (recheck_count && lane == 0 && rechecked) atomicAdd(recheck_count, rechecked);
+}
+
+
+// ---------------------------------------------------------------- reduced-precision projection, tile-shared
+//
+// BF16 / FP8 projection: one 512-thread block per CU walks 64-keypoint tiles
+// (grid stride).  A tile is read from HBM once, kept in LDS as FP32 (for the
+// re-check) and as the MFMA operand type, and shared by all eight
+// wavefronts: wavefront w owns the 64-bit chunk w % NW of B and the tile rows
+// (w / NW) * 16 * kRowSubs onwards.  The chunk's B operands stay in
+// registers for the whole kernel (lane (g, n) holds row 16 nt + n, elements
+// 32 s + 8 g .. + 7 of k-step s), rounded once; the next tile's rows are in
+// flight while the current one is multiplied (v_mfma_f32_16x16x32_bf16 /
+// _fp8_fp8, FP32 accumulation).  With FP8 every row of the tile and of B is
+// scaled by a power of two s (the smallest with max|row| <= 448 s, at least
+// 2^-126), so the rescaling is exact; the response is acc * s_row * s_b - t.
+//
+// The sign bits are gathered by ballots into the tile's code words in LDS.
+// Responses within `margin` of the threshold are then queued per wavefront
+// in LDS (row, column) and re-checked one per lane from the unrounded FP32
+// operands (the tile row from LDS, the row of B from memory): four chains
+// over the elements k mod 4, summed as (c0 + c1) + (c2 + c3), then FP64 when
+// that result is within 1e-6 of the threshold.  The re-checking lane sets or
+// clears its code bit in LDS and overwrites the response; the words are
+// written out last.
+constexpr int kLpRows = 64;       // keypoints per tile
+constexpr int kLpThreads = 512;   // eight wavefronts
+constexpr int kLpS32 = 132;       // FP32 tile row stride (floats)
+constexpr int kLpS16 = 136;       // BF16 tile row stride (elements, 272 bytes)
+constexpr int kLpS8 = 144;        // FP8 tile row stride (bytes)
+
+template <int PREC>
+struct LpOperand;
+template <>
+struct LpOperand<BD_PREC_BF16> {
+    typedef bf16x8 type;
+    static constexpr int row_bytes = kLpS16 * 2;
+};
+template <>
+struct LpOperand<BD_PREC_FP8> {
+    typedef long type;
+    static constexpr int row_bytes = kLpS8;
+};
+
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b)
+{
+    const __bf16 x = (__bf16)a, y = (__bf16)b;
+    return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+}
+
+// Exponent e of the FP8 row scale 2^e: the smallest with m <= 448 * 2^e
+// (448 = 0.875 * 2^9), at least -126; 0 for m = 0.
+__device__ __forceinline__ int e4m3_pow2_exp(float m)
+{
+    if (!(m > 0.0f)) return 0;
+    const int E = __builtin_amdgcn_frexp_expf(m);
+    const float f = __builtin_amdgcn_frexp_mantf(m);  // m = f * 2^E, f in [0.5, 1)
+    const int e = f <= 0.875f ? E - 9 : E - 8;
+    return e < -126 ? -126 : e;
+}
+
+// Eight values times 2^-e (exact), rounded to e4m3, packed into 64 bits.
+__device__ __forceinline__ long pack_e4m3_pow2(const float (&v)[8], int e)
+{
+    float q[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[i] = fminf(fmaxf(__builtin_amdgcn_ldexpf(v[i], -e), -448.0f), 448.0f);
+    int lo = 0, hi = 0;
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], lo, false);
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], lo, true);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[4], q[5], hi, false);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[6], q[7], hi, true);
+    return (long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// max over the 8-lane groups 8j .. 8j + 7 (lane-local DPP moves, no LDS)
+__device__ __forceinline__ float max8_dpp(float v)
+{
+    int x = __float_as_int(v);
+    // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false)));
+    x = __float_as_int(v);
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false)));
+    x = __float_as_int(v);
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x141, 0xF, 0xF, false)));
+    return v;
+}
+
+template <int PREC, int NW>
+__global__ __launch_bounds__(kLpThreads, 1) void hashsift_project_lowp_kernel(
+    const float* __restrict__ hist, const bd_keypoint* __restrict__ kps, int32_t n_kp, const float* __restrict__ B,
+    const float* __restrict__ t, float margin, uint64_t* __restrict__ codes, float* __restrict__ resp,
+    uint32_t* __restrict__ recheck_count)
+{
+    constexpr int kRowSubs = NW == 8 ? 4 : 2;   // 16-row subtiles per wavefront
+    constexpr int kWaveRows = 16 * kRowSubs;    // tile rows of a wavefront
+    constexpr int kQueue = kWaveRows * 64;      // every response of a wavefront can be queued
+    constexpr int kRowBytes = LpOperand<PREC>::row_bytes;
+    typedef typename LpOperand<PREC>::type op_t;
+    __shared__ __align__(16) float A32[kLpRows * kLpS32];
+    __shared__ __align__(16) uint8_t Alp[kLpRows * kRowBytes];
+    __shared__ float Asc[kLpRows];
+    __shared__ uint64_t W[2][kLpThreads / kWave][kWaveRows];  // by tile parity
+    __shared__ uint16_t Q[kLpThreads / kWave][kQueue + kWave];  // + a slot per lane for writes that drop
+
+    const int tid = (int)threadIdx.x;
+    const int lane = tid % kWave, wave = tid / kWave;
+    const int g = lane >> 4, n = lane & 15;
+    const int chunk = wave % NW;
+    const int rbase = (wave / NW) * kWaveRows;
+    constexpr int n_bits = NW * 64;
+    uint16_t* Qw = Q[wave];
+
+    // B operands of this lane: rows 64 chunk + 16 nt + n, elements 32 s + 8 g .. + 7
+    op_t bop[4][4];
+    float tv[4], sb[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const float* brow = B + (int64_t)(chunk * 64 + 16 * nt + n) * 128;
+        float v[4][8];
+        float mx = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float4 lo = *reinterpret_cast<const float4*>(brow + 32 * s + 8 * g);
+            const float4 hi = *reinterpret_cast<const float4*>(brow + 32 * s + 8 * g + 4);
+            v[s][0] = lo.x, v[s][1] = lo.y, v[s][2] = lo.z, v[s][3] = lo.w;
+            v[s][4] = hi.x, v[s][5] = hi.y, v[s][6] = hi.z, v[s][7] = hi.w;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(v[s][e]));
+        }
+        tv[nt] = t[chunk * 64 + 16 * nt + n];
+        sb[nt] = 1.0f;
+        if constexpr (PREC == BD_PREC_BF16) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bop[nt][s][e] = (__bf16)v[s][e];
+        } else {
+            // the row's four lanes (g = 0..3) share its maximum
+            mx = fmaxf(mx, __shfl_xor(mx, 16, kWave));
+            mx = fmaxf(mx, __shfl_xor(mx, 32, kWave));
+            const int e = e4m3_pow2_exp(mx);
+            sb[nt] = __builtin_amdgcn_ldexpf(1.0f, e);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) bop[nt][s] = pack_e4m3_pow2(v[s], e);
+        }
     }
+
+    // staging: thread tid moves row tid / 8, elements 16 (tid % 8) .. + 15
+    const int prow = tid >> 3, pcol = (tid & 7) * 16;
+    const int n_tiles = (n_kp + kLpRows - 1) / kLpRows;
+    float4 pf[4];
+    auto load_tile = [&](int tile) {
+        const int row = tile * kLpRows + prow;
+        if (row < n_kp) {
+            const float4* src = reinterpret_cast<const float4*>(hist + (int64_t)row * 128 + pcol);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pf[q] = src[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pf[q] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    };
+    if ((int)blockIdx.x < n_tiles) load_tile((int)blockIdx.x);
+    uint32_t rechecked = 0;
+
+    int parity = 0;
+    for (int tile = (int)blockIdx.x; tile < n_tiles; tile += (int)gridDim.x, parity ^= 1) {
+        // the barrier before the previous tile's code words went out also
+        // ended every read of its rows; its words are in the other W buffer
+        uint64_t* Ww = W[parity][wave];
+        {
+            float4* d32 = reinterpret_cast<float4*>(&A32[prow * kLpS32 + pcol]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d32[q] = pf[q];
+            uint8_t* dlp = &Alp[prow * kRowBytes];
+            if constexpr (PREC == BD_PREC_BF16) {
+                uint4 w0, w1;
+                w0.x = pk_bf16(pf[0].x, pf[0].y);
+                w0.y = pk_bf16(pf[0].z, pf[0].w);
+                w0.z = pk_bf16(pf[1].x, pf[1].y);
+                w0.w = pk_bf16(pf[1].z, pf[1].w);
+                w1.x = pk_bf16(pf[2].x, pf[2].y);
+                w1.y = pk_bf16(pf[2].z, pf[2].w);
+                w1.z = pk_bf16(pf[3].x, pf[3].y);
+                w1.w = pk_bf16(pf[3].z, pf[3].w);
+                reinterpret_cast<uint4*>(dlp + 2 * pcol)[0] = w0;
+                reinterpret_cast<uint4*>(dlp + 2 * pcol)[1] = w1;
+            } else {
+                float mx = 0.0f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    mx = fmaxf(mx, fmaxf(fmaxf(fabsf(pf[q].x), fabsf(pf[q].y)), fmaxf(fabsf(pf[q].z), fabsf(pf[q].w))));
+                mx = max8_dpp(mx);
+                const int e = e4m3_pow2_exp(mx);
+                if ((tid & 7) == 0) Asc[prow] = __builtin_amdgcn_ldexpf(1.0f, e);
+                const float v0[8] = {pf[0].x, pf[0].y, pf[0].z, pf[0].w, pf[1].x, pf[1].y, pf[1].z, pf[1].w};
+                const float v1[8] = {pf[2].x, pf[2].y, pf[2].z, pf[2].w, pf[3].x, pf[3].y, pf[3].z, pf[3].w};
+                const long q0 = pack_e4m3_pow2(v0, e), q1 = pack_e4m3_pow2(v1, e);
+                *reinterpret_cast<uint4*>(dlp + pcol) =
+                    uint4{(uint32_t)q0, (uint32_t)((uint64_t)q0 >> 32), (uint32_t)q1, (uint32_t)((uint64_t)q1 >> 32)};
+            }
+        }
+        if (tile + (int)gridDim.x < n_tiles) load_tile(tile + (int)gridDim.x);
+        __syncthreads();
+        const int row0 = tile * kLpRows;
+        const int limit = n_kp - (row0 + rbase);  // wavefront rows below this exist
+
+        // two 16-row subtiles at a time: 1. responses (lane (g, n) holds the
+        // response of wavefront row 16 p + 4 g + i to column 16 nt + n);
+        // 2. responses out, sign bits into the code words, pending responses queued
+        int queued = 0;
+#pragma unroll
+        for (int pp = 0; pp < kRowSubs; pp += 2) {
+            floatx4 acc[2][4];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) acc[r][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                op_t av[2];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int row = rbase + 16 * (pp + r) + n;  // A operand: lane (g, m = n) holds row m
+                    if constexpr (PREC == BD_PREC_BF16)
+                        av[r] = *reinterpret_cast<const bf16x8*>(&Alp[row * kRowBytes + 2 * (32 * s + 8 * g)]);
+                    else
+                        av[r] = *reinterpret_cast<const long*>(&Alp[row * kRowBytes + 32 * s + 8 * g]);
+                }
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                    for (int r = 0; r < 2; ++r) {
+                        if constexpr (PREC == BD_PREC_BF16)
+                            acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bop[nt][s], acc[r][nt], 0, 0, 0);
+                        else
+                            acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[r], bop[nt][s], acc[r][nt], 0, 0, 0);
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int p = pp + r;
+                float sk[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+                if constexpr (PREC == BD_PREC_FP8) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) sk[i] = Asc[rbase + 16 * p + 4 * g + i];
+                }
+                float rv[4][4];
+                uint64_t mask[4][4];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        rv[nt][i] = acc[r][nt][i] * (sk[i] * sb[nt]) - tv[nt];
+                        mask[nt][i] = __ballot(rv[nt][i] > 0.0f);
+                    }
+                if (margin > 0.0f) {
+                    // all sixteen ballots first, then the (scalar) walk over the non-empty ones
+                    uint64_t pend[4][4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            pend[nt][i] = __ballot(16 * p + 4 * g + i < limit && fabsf(rv[nt][i]) < margin);
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const uint64_t pm = pend[nt][i];
+                            if (pm) {
+                                // queue position, or this lane's spare slot when it has nothing to queue
+                                const bool hit = (pm >> lane) & 1ull;
+                                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(pm >> 32),
+                                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
+                                Qw[hit ? queued + rank : kQueue + lane] = (uint16_t)((16 * p + 4 * g + i) << 6 | (16 * nt + n));
+                                queued += __popcll(pm);
+                            }
+                        }
+                }
+                if (resp) {
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int wr = 16 * p + 4 * g + i;
+                            if (wr < limit) resp[(int64_t)(row0 + rbase + wr) * n_bits + chunk * 64 + 16 * nt + n] = rv[nt][i];
+                        }
+                }
+                if (lane < 16) {
+                    const int gq = lane >> 2, iq = lane & 3;
+                    uint64_t word = 0ull;
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const uint64_t mk =
+                            iq == 0 ? mask[nt][0] : iq == 1 ? mask[nt][1] : iq == 2 ? mask[nt][2] : mask[nt][3];
+                        word |= ((mk >> (16 * gq)) & 0xffffull) << (16 * nt);
+                    }
+                    Ww[16 * p + lane] = word;
+                }
+            }
+        }
+        rechecked += (uint32_t)queued;
+
+        // 3. re-check the queued responses, one per lane
+        wave_sync();
+        for (int b0 = 0; b0 < queued; b0 += kWave) {
+            if (b0 + lane < queued) {
+                const int item = Qw[b0 + lane];
+                const int wr = item >> 6, col = item & 63;
+                const float* arow = &A32[(rbase + wr) * kLpS32];
+                const float* brow = B + (int64_t)(chunk * 64 + col) * 128;
+                const float tcol = t[chunk * 64 + col];
+                // the row of B in quarters, each in flight at once
+                float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, d3 = 0.0f;
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    float4 bv[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) bv[q] = reinterpret_cast<const float4*>(brow)[8 * h + q];
+                    // the loads above stay ahead of the arithmetic below
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const float4 av = reinterpret_cast<const float4*>(arow)[8 * h + q];
+                        d0 = fmaf(av.x, bv[q].x, d0);
+                        d1 = fmaf(av.y, bv[q].y, d1);
+                        d2 = fmaf(av.z, bv[q].z, d2);
+                        d3 = fmaf(av.w, bv[q].w, d3);
+                    }
+                }
+                float res = ((d0 + d1) + (d2 + d3)) - tcol;
+                if (fabsf(res) < 1e-6f) {
+                    double d = 0.0;
+                    for (int k = 0; k < 128; ++k) d = fma((double)arow[k], (double)brow[k], d);
+                    res = (float)(d - (double)tcol);
+                }
+                const uint64_t bit = 1ull << col;
+                if (res > 0.0f)
+                    __hip_atomic_fetch_or(&Ww[wr], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                else
+                    __hip_atomic_fetch_and(&Ww[wr], ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                const int kp = row0 + rbase + wr;
+                if (resp) resp[(int64_t)kp * n_bits + chunk * 64 + col] = res;
+            }
+        }
+        __syncthreads();
+
+        // 4. the tile's code rows out, coalesced: thread tid writes word tid % NW of row tid / NW
+        if (tid < kLpRows * NW) {
+            const int row = tid / NW, c = tid % NW;
+            const int kp = row0 + row;
+            if (kp < n_kp) {
+                bool valid = true;
+                if (kps) {
+                    const bd_keypoint k = kps[kp];
+                    valid = finite_f(k.x) && finite_f(k.y) && finite_f(k.scale) && finite_f(k.angle) && k.scale > 0.0f;
+                }
+                // chunk c of row `row` belongs to wavefront c + NW * (row / kWaveRows)
+                codes[(int64_t)kp * NW + c] = valid ? W[parity][c + NW * (row / kWaveRows)][row % kWaveRows] : 0ull;
+            }
+        }
+    }
+    // rechecked is the wavefront's count (the same in every lane)
+    if (recheck_count && lane == 0 && rechecked) atomicAdd(recheck_count, rechecked);
 }
 
 }  // namespace
@@ -872,15 +1101,25 @@ void launch_hashsift_project(int32_t precision, const float* hist, const bd_keyp
     if (groups < 1) groups = 1;
     const dim3 grid(kXcds * n_words * groups);
     const dim3 block(kProjWaves * kWave);
-    if (precision == BD_PREC_BF16)
-        hipLaunchKernelGGL(hashsift_project_kernel<BD_PREC_BF16>, grid, block, 0, stream, hist, kps, n_kp, B, t,
-                           n_words, margin, codes, resp, recheck_count);
-    else if (precision == BD_PREC_FP8)
-        hipLaunchKernelGGL(hashsift_project_kernel<BD_PREC_FP8>, grid, block, 0, stream, hist, kps, n_kp, B, t,
-                           n_words, margin, codes, resp, recheck_count);
-    else
-        hipLaunchKernelGGL(hashsift_project_kernel<BD_PREC_FP32>, grid, block, 0, stream, hist, kps, n_kp, B, t,
-                           n_words, margin, codes, resp, recheck_count);
+    if (precision == BD_PREC_BF16 || precision == BD_PREC_FP8) {
+        // tile-shared kernel: one block per CU at most, grid stride over the tiles
+        const int lp_grid = n_tiles < 256 ? n_tiles : 256;
+        const dim3 lp_block(kLpThreads);
+        if (precision == BD_PREC_BF16 && n_words == 8)
+            hipLaunchKernelGGL((hashsift_project_lowp_kernel<BD_PREC_BF16, 8>), dim3(lp_grid), lp_block, 0, stream,
+                               hist, kps, n_kp, B, t, margin, codes, resp, recheck_count);
+        else if (precision == BD_PREC_BF16)
+            hipLaunchKernelGGL((hashsift_project_lowp_kernel<BD_PREC_BF16, 4>), dim3(lp_grid), lp_block, 0, stream,
+                               hist, kps, n_kp, B, t, margin, codes, resp, recheck_count);
+        else if (n_words == 8)
+            hipLaunchKernelGGL((hashsift_project_lowp_kernel<BD_PREC_FP8, 8>), dim3(lp_grid), lp_block, 0, stream,
+                               hist, kps, n_kp, B, t, margin, codes, resp, recheck_count);
+        else
+            hipLaunchKernelGGL((hashsift_project_lowp_kernel<BD_PREC_FP8, 4>), dim3(lp_grid), lp_block, 0, stream,
+                               hist, kps, n_kp, B, t, margin, codes, resp, recheck_count);
+        return;
+    }
+    hipLaunchKernelGGL(hashsift_project_kernel, grid, block, 0, stream, hist, kps, n_kp, B, t, n_words, codes, resp);
 }
 
 }  // namespace bd

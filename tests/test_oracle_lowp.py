@@ -32,6 +32,8 @@ def test_e4m3_saturates(ref):
 
 
 def test_project_lowp_matches_library_rounding(ref):
+    """BF16 and FP8 operands rounded by torch's own casts; FP8 rows scaled by
+    a power of two so that the rescaling itself is exact."""
     rng = np.random.default_rng(42)
     h = rng.random((9, 128)).astype(np.float32)
     h /= np.linalg.norm(h, axis=1, keepdims=True)
@@ -39,8 +41,18 @@ def test_project_lowp_matches_library_rounding(ref):
     bf = lambda a: torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_allclose(ref.project_lowp(h, B, t, "bf16"), bf(h) @ bf(B).T - t.astype(np.float64),
                                rtol=0, atol=1e-12)
-    sf = (np.abs(h).max(1) / np.float32(448)).astype(np.float32)
-    sb = (np.abs(B).max(1) / np.float32(448)).astype(np.float32)
+    # per-row scale: the smallest power of two s (>= 2^-126) with max|row| <= 448 s, found by search
+    def pow2_scale(a):
+        out = []
+        for m in np.abs(a).max(1).astype(np.float64):
+            k = -126
+            while m > 448.0 * 2.0 ** k:
+                k += 1
+            out.append(2.0 ** k)
+        return np.array(out, dtype=np.float32)
+
+    sf, sb = pow2_scale(h), pow2_scale(B)
+    assert ((np.abs(h).max(1) / sf > 224) & (np.abs(h).max(1) / sf <= 448)).all()
     f8 = lambda a, s: torch.from_numpy((a / s[:, None]).astype(np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
     exp = (f8(h, sf) @ f8(B, sb).T) * (sf.astype(np.float64)[:, None] * sb.astype(np.float64)[None, :]) - t
     np.testing.assert_allclose(ref.project_lowp(h, B, t, "fp8"), exp, rtol=0, atol=1e-12)
