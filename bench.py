@@ -232,6 +232,162 @@ def time_stages(wl, reps):
     return out
 
 
+def graph_time(fn, reps=100, warmup=5):
+    """ms per replay of `fn` captured as one HIP graph (after eager warm-up)."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        fn()
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        fn()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        g.replay()
+    end.record()
+    end.synchronize()
+    return start.elapsed_time(end) / reps
+
+
+def describe_rates(wl, reps=200):
+    """Keypoints described per second on the step's workload without matching:
+    describe-only (keypoint order, BAD from the integral images, HashSIFT),
+    integral + describe, and each descriptor alone, both views on two streams
+    as in the step, each timed as a graph replay."""
+    import torch
+
+    def two_views(body):
+        def run():
+            cur = torch.cuda.current_stream()
+            if not hasattr(wl, "side_d"):
+                wl.side_d = torch.cuda.Stream()
+            wl.side_d.wait_stream(cur)
+            with torch.cuda.stream(wl.side_d):
+                body(1)
+            body(0)
+            cur.wait_stream(wl.side_d)
+        return run
+
+    import paper_2108_08380_amd as bd
+
+    def order(v):
+        bd.keypoint_order(wl.kps[v], W, H, out=wl.order[v])
+
+    def bad(v):
+        bd.describe_bad(wl.ii[v], wl.kps[v], out=wl.bad[v], order=wl.order[v], table=wl.table)
+
+    def hs(v):
+        bd.hashsift_features(wl.f32[v], wl.kps[v], out=wl.hist[v], order=wl.order[v])
+        bd.hashsift_project(wl.hist[v], wl.B, wl.t, wl.kps[v], out=wl.hs[v])
+
+    variants = {
+        "describe_only": lambda v: (order(v), bad(v), hs(v)),
+        "integral_plus_describe": lambda v: (order(v), bd.build_integral(wl.u8[v], out=wl.ii[v]), bad(v), hs(v)),
+        "bad256_only": lambda v: (order(v), bad(v)),
+        "integral_plus_bad256": lambda v: (order(v), bd.build_integral(wl.u8[v], out=wl.ii[v]), bad(v)),
+        "hashsift512_only": lambda v: (order(v), hs(v)),
+    }
+    out = {}
+    for name, body in variants.items():
+        ms = graph_time(two_views(body), reps)
+        out[name] = {"ms": round(ms, 4), "keypoints_per_s": round(2 * N_KP / (ms * 1e-3), 1)}
+    return out
+
+
+def config0_step(dev, reps=200):
+    """The plain BAD-256 workload: one 640x480 u8 image pair, 1000 keypoints per
+    view (scale U[1, 4]), 256 box pairs; integral images and BAD-256 of both
+    views, then Hamming 1-NN 1000x1000, as one graph replay (the two views on
+    two streams).  Also the describe-only and integral + describe parts."""
+    import torch
+
+    import paper_2108_08380_amd as bd
+    from paper_2108_08380_amd import synth
+
+    w = synth.bad256_pair(synth.SEED_BASE + 0)
+    Hc, Wc = w.image1.shape
+    n = len(w.kp1)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    imgs = [T(w.image1), T(w.image2)]
+    kps = [bd.keypoints_tensor(w.kp1, dev), bd.keypoints_tensor(w.kp2, dev)]
+    pairs = bd.pairs_tensor(w.pairs, dev)
+    table = bd.BadTable(pairs)
+    order = [torch.empty((n,), dtype=torch.int32, device=dev) for _ in range(2)]
+    ii = [bd.integral_buffer(Hc, Wc, dev) for _ in range(2)]
+    codes = [torch.empty((n, 4), dtype=torch.uint64, device=dev) for _ in range(2)]
+    idx = torch.empty((n, 1), dtype=torch.int32, device=dev)
+    dist = torch.empty((n, 1), dtype=torch.uint32, device=dev)
+    side = torch.cuda.Stream()
+
+    def view(v, integral=True):
+        bd.keypoint_order(kps[v], Wc, Hc, out=order[v])
+        if integral:
+            bd.build_integral(imgs[v], out=ii[v])
+        bd.describe_bad(ii[v], kps[v], out=codes[v], order=order[v], table=table)
+
+    def run(integral=True, match=True):
+        cur = torch.cuda.current_stream()
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            view(1, integral)
+        view(0, integral)
+        cur.wait_stream(side)
+        if match:
+            bd.match_hamming_knn(codes[0], codes[1], 1, idx, dist)
+
+    ms = graph_time(run, reps)
+    ms_desc = graph_time(lambda: run(False, False), reps)
+    ms_int_desc = graph_time(lambda: run(True, False), reps)
+    torch.cuda.synchronize()
+    true_rate = float((idx[:, 0] == torch.arange(n, device=dev, dtype=torch.int32)).float().mean())
+    return {
+        "workload": f"BAD-256, {Wc}x{Hc} u8 image pair, {n} keypoints per view, Hamming 1-NN {n}x{n}",
+        "ms_per_step": round(ms, 4),
+        "keypoints_per_s": round(2 * n / (ms * 1e-3), 1),
+        "hamming_pairs_per_s": round(n * n / (ms * 1e-3), 1),
+        "describe_only": {"ms": round(ms_desc, 4), "keypoints_per_s": round(2 * n / (ms_desc * 1e-3), 1)},
+        "integral_plus_describe": {"ms": round(ms_int_desc, 4),
+                                   "keypoints_per_s": round(2 * n / (ms_int_desc * 1e-3), 1)},
+        "true_match_rate": round(true_rate, 4),
+    }
+
+
+def hbm_copy_rate(dev, mib=1024, reps=10):
+    """Measured device-to-device copy bandwidth (read + write bytes per second)
+    of a `mib` MiB buffer, the denominator the HBM fractions can be read
+    against beside the 8 TB/s specification."""
+    import torch
+
+    n = mib << 20
+    src = torch.empty((n,), dtype=torch.uint8, device=dev)
+    src.fill_(7)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    end.record()
+    end.synchronize()
+    ms = start.elapsed_time(end) / reps
+    del src, dst
+    return {"bytes_per_copy": 2 * n, "ms": round(ms, 4), "gbs": round(2 * n / (ms * 1e-3) / 1e9, 1),
+            "spec_gbs": HBM_PEAK_GBS}
+
+
 def precision_projection(wl, n_rows=200000, reps=20):
     """HashSIFT-512 projection of 200000 feature rows (the bench features tiled)
     in FP32, BF16 and FP8 with the 1e-3 FP32 re-check margin: time per launch,
@@ -566,38 +722,81 @@ def batched_step(dev, reps=5):
     }
 
 
-def cpu_baseline(sample: int):
-    """The oracle on `sample` keypoints per view (full integral images), scaled to the full step."""
+def cpu_baseline(sample: int, runs: int = 5):
+    """The oracle timed the way the paper's Table V times description: the mean
+    and standard deviation of `runs` runs after one warm-up, here both on one
+    core and on all host cores given to this process (at most 16, the CPU
+    share of one GPU).  One run: integral images of both views, BAD-256 and
+    HashSIFT-512 of `sample` keypoints per view, their 2-NN against the other
+    view's full code set; scaled to the step's keypoint count.  With several
+    cores the keypoint and query ranges are split over threads (the oracle's
+    C calls run outside the interpreter lock); the oracle itself is the same
+    single-threaded code."""
+    import concurrent.futures as cf
+
     import oracle
     from paper_2108_08380_amd import synth
 
     w = synth.hashsift512_pair(synth.SEED_BASE + 1, W, H, N_KP, HS_BITS, with_bad_bits=BAD_BITS)
     oracle.lib()
-    t0 = time.perf_counter()
-    ii = [oracle.build_integral(w.extra["image1_u8"]), oracle.build_integral(w.extra["image2_u8"])]
-    t_int = time.perf_counter() - t0
+    imgs_u8 = [w.extra["image1_u8"], w.extra["image2_u8"]]
+    imgs_f = [w.image1, w.image2]
     kps = [w.kp1[:sample], w.kp2[:sample]]
-    t0 = time.perf_counter()
-    bad = [oracle.describe_bad(ii[v], kps[v], w.pairs)[0] for v in (0, 1)]
-    hs = [oracle.describe_hashsift([w.image1, w.image2][v], kps[v], w.B, w.t)[2] for v in (0, 1)]
-    t_desc = time.perf_counter() - t0
-    # the sample's queries against the full train set of the other view
-    bad_train = oracle.describe_bad(ii[1], w.kp2, w.pairs)[0]
+    ii_train = oracle.build_integral(imgs_u8[1])
+    bad_train = oracle.describe_bad(ii_train, w.kp2, w.pairs)[0]
     hs_train = oracle.describe_hashsift(w.image2, w.kp2, w.B, w.t)[2]
-    t0 = time.perf_counter()
-    oracle.match_knn(bad[0], bad_train, K)
-    oracle.match_knn(hs[0], hs_train, K)
-    t_match = time.perf_counter() - t0
-    scale = N_KP / sample
-    t_step = t_int + scale * t_desc + scale * t_match
+    try:
+        n_all = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n_all = os.cpu_count() or 1
+    n_all = max(1, min(16, n_all))
+
+    def one_run(pool, threads):
+        cuts = np.linspace(0, sample, threads + 1).astype(int)
+        parts = [(cuts[i], cuts[i + 1]) for i in range(threads) if cuts[i + 1] > cuts[i]]
+        t0 = time.perf_counter()
+        ii = list(pool.map(oracle.build_integral, imgs_u8))
+        t_int = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        jobs = [(v, a, b) for v in (0, 1) for a, b in parts]
+        bad = list(pool.map(lambda j: oracle.describe_bad(ii[j[0]], kps[j[0]][j[1]:j[2]], w.pairs)[0], jobs))
+        hs = list(pool.map(lambda j: oracle.describe_hashsift(imgs_f[j[0]], kps[j[0]][j[1]:j[2]], w.B, w.t)[2], jobs))
+        t_desc = time.perf_counter() - t0
+        q_bad = np.concatenate([c for (v, _, _), c in zip(jobs, bad) if v == 0])
+        q_hs = np.concatenate([c for (v, _, _), c in zip(jobs, hs) if v == 0])
+        t0 = time.perf_counter()
+        list(pool.map(lambda ab: oracle.match_knn(q_bad[ab[0]:ab[1]], bad_train, K), parts))
+        list(pool.map(lambda ab: oracle.match_knn(q_hs[ab[0]:ab[1]], hs_train, K), parts))
+        t_match = time.perf_counter() - t0
+        scale = N_KP / sample
+        return t_int + scale * (t_desc + t_match), t_int + t_desc + t_match
+
+    def protocol(threads):
+        with cf.ThreadPoolExecutor(max_workers=threads) as pool:
+            one_run(pool, threads)  # warm-up
+            res = [one_run(pool, threads) for _ in range(runs)]
+        rates = np.array([2 * N_KP / r[0] for r in res])
+        return {"value": round(float(rates.mean()), 1), "std": round(float(rates.std()), 1),
+                "step_ms_mean": round(float(np.mean([r[0] for r in res])) * 1e3, 1),
+                "step_ms_std": round(float(np.std([r[0] for r in res])) * 1e3, 1),
+                "seconds": round(float(sum(r[1] for r in res)), 2), "cores": threads}
+
+    one = protocol(1)
+    allc = protocol(n_all)
     return {
-        "value": round(2 * N_KP / t_step, 1),
+        "value": one["value"],
         "unit": "keypoints/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"full integral images of both views; BAD-256 + HashSIFT-512 of {sample} keypoints per view; "
-                  f"{sample} queries x {N_KP} train codes 2-NN per code type; scaled to {N_KP} keypoints per view",
-        "seconds": round(t_int + t_desc + t_match, 2),
+                  f"{sample} queries x {N_KP} train codes 2-NN per code type; scaled to {N_KP} keypoints per view; "
+                  f"mean +- std of {runs} runs after one warm-up",
+        "std": one["std"],
+        "runs": runs,
+        "step_ms_mean": one["step_ms_mean"],
+        "step_ms_std": one["step_ms_std"],
+        "seconds": one["seconds"],
+        "all_cores": allc,
     }
 
 
@@ -715,6 +914,10 @@ def main():
         "checks": check,
         "roofline": roofline,
     }
+    if not args.only:
+        result["describe_rates"] = describe_rates(wl)
+        result["config0_bad256_640x480"] = config0_step(dev)
+        result["hbm_copy"] = hbm_copy_rate(dev)
     if not args.only and not args.step_only:
         result["same_step_via_batched_entry_point"] = pair_via_batch(wl)
         result["mutual_nn_ratio0.8"] = mutual_matching(wl)
