@@ -156,20 +156,21 @@ def stage_work():
 
 
 # HBM bytes per launch of each stage (sum over its kernels), from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
 #   bench.py --step-only --steps 2 --warmup 1 --stage-reps 2 --graph 0
 # scaled by the same counters on a plain 256 MiB device copy (FETCH_SIZE
-# reads half the copied bytes: x2.000; WRITE_SIZE exact: x1.000).  A value
+# reads half the copied bytes: x2 KiB -> 2048 bytes; WRITE_SIZE exact:
+# 1024 bytes per KiB).  A value
 # is reported only while the stage's source file still has the recorded
 # SHA-256 prefix: any change to the kernels invalidates the counters.
 PMC_TRAFFIC = {
-    "keypoint_order": ("order.hip", "b9c2afd100b6dde1", 89637 + 20000),
-    "integral": ("integral.hip", "64d461e94933cbb9", 2164929 + 749657 + 2840902 + 630528 + 593792 + 8354530),
-    "bad_describe": ("bad.hip", "884a2f98d19ec233", 18582403 + 163696),
-    "hashsift_features": ("hashsift.hip", "b81e18b37e77e4e5", 18967507 + 2560000),
-    "hashsift_project": ("hashsift.hip", "b81e18b37e77e4e5", 4846376 + 320000),
-    "match_bad256": ("hamming.hip", "b45b06214a9c6ad9", 1805936 + 615381 + 480000 + 80000),
-    "match_hashsift512": ("hamming.hip", "b45b06214a9c6ad9", 3450095 + 615381 + 480000 + 80000),
+    "keypoint_order": ("order.hip", "b9c2afd100b6dde1", 44 * 2048 + 20 * 1024),
+    "integral": ("integral.hip", "64d461e94933cbb9", (366 + 1057 + 1387) * 2048 + (580 + 616 + 8158) * 1024),
+    "bad_describe": ("bad.hip", "ad09d5e017d700e6", 9075 * 2048 + 160 * 1024),
+    "hashsift_features": ("hashsift.hip", "44f47f97598e58b9", 9270 * 2048 + 2500 * 1024),
+    "hashsift_project": ("hashsift.hip", "44f47f97598e58b9", 2367 * 2048 + 312 * 1024),
+    "match_bad256": ("hamming.hip", "b45b06214a9c6ad9", (882 + 300) * 2048 + (469 + 78) * 1024),
+    "match_hashsift512": ("hamming.hip", "b45b06214a9c6ad9", (1684 + 300) * 2048 + (469 + 78) * 1024),
 }
 
 
@@ -181,7 +182,8 @@ PMC_TRAFFIC = {
 # accesses / (duration x 256 CUs x 2.4 GHz) is the kernel's fraction of that
 # rate; the histogram's bilinear gathers run at it.
 PMC_L1_ACCESSES = {
-    "hashsift_features": ("hashsift.hip", "b81e18b37e77e4e5", 23220000),
+    "hashsift_features": ("hashsift.hip", "44f47f97598e58b9", 22133716),
+    "bad_describe": ("bad.hip", "ad09d5e017d700e6", 10092917),
 }
 L1_ACCESS_PEAK_PER_S = 256 * 2.4e9
 
@@ -914,11 +916,10 @@ def main():
         "checks": check,
         "roofline": roofline,
     }
-    if not args.only:
+    if not args.only and not args.step_only:
         result["describe_rates"] = describe_rates(wl)
         result["config0_bad256_640x480"] = config0_step(dev)
         result["hbm_copy"] = hbm_copy_rate(dev)
-    if not args.only and not args.step_only:
         result["same_step_via_batched_entry_point"] = pair_via_batch(wl)
         result["mutual_nn_ratio0.8"] = mutual_matching(wl)
         result["precision_projection_200k"] = precision_projection(wl)
