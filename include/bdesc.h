@@ -167,10 +167,11 @@ int bd_describe_bad_table(bd_context* ctx, const uint32_t* ii, int32_t W, int32_
  *   precision BD_PREC_FP32, BD_PREC_BF16 or BD_PREC_FP8 (the reduced-precision
  *            forms are an extension: the paper fixes no precision).  With
  *            BF16/FP8 every response with |r| < margin is recomputed from the
- *            unrounded FP32 operands (products of the elements k mod 4 in four
- *            running sums over k, added as (s0 + s1) + (s2 + s3); in FP64 when
- *            that FP32 value is within 1e-6 of the threshold) and decides the
- *            bit.  FP8 scales every row of f and of B by the smallest power of
+ *            unrounded FP32 operands and decides the bit: four partial sums
+ *            over the float4 groups k/4 = j mod 4, each in four running sums
+ *            over the components (added as (s0 + s1) + (s2 + s3)), the four
+ *            partials added in pairs; in FP64 when that FP32 value is within
+ *            1e-6 of the threshold.  A NaN response gives bit 0.  FP8 scales every row of f and of B by the smallest power of
  *            two s >= 2^-126 with max|row| <= 448 s before rounding to e4m3;
  *            recheck_count (optional device u32, caller-zeroed) is increased
  *            by the number of such responses.  margin is ignored for FP32.

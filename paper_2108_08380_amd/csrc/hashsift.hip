@@ -689,30 +689,54 @@ __global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* _
 // ---------------------------------------------------------------- reduced-precision projection, tile-shared
 //
 // BF16 / FP8 projection: one 512-thread block per CU walks 64-keypoint tiles
-// (grid stride).  A tile is read from HBM once, kept in LDS as FP32 (for the
-// re-check) and as the MFMA operand type, and shared by all eight
-// wavefronts: wavefront w owns the 64-bit chunk w % NW of B and the tile rows
-// (w / NW) * 16 * kRowSubs onwards.  The chunk's B operands stay in
-// registers for the whole kernel (lane (g, n) holds row 16 nt + n, elements
-// 32 s + 8 g .. + 7 of k-step s), rounded once; the next tile's rows are in
-// flight while the current one is multiplied (v_mfma_f32_16x16x32_bf16 /
-// _fp8_fp8, FP32 accumulation).  With FP8 every row of the tile and of B is
-// scaled by a power of two s (the smallest with max|row| <= 448 s, at least
-// 2^-126), so the rescaling is exact; the response is acc * s_row * s_b - t.
+// (grid stride).  A tile is read from HBM once and kept in LDS twice, as
+// FP32 (for the re-check) and rounded to the MFMA operand type, in one of two
+// buffers: the next tile is staged while the current one is multiplied, with
+// one block barrier per tile.  All eight wavefronts share the tile:
+// wavefront w owns the 64-bit chunk w % NW of B and the tile rows
+// (w / NW) * 16 * kRowSubs onwards.  The chunk's operands stay in registers
+// for the whole kernel, rounded and negated once.
 //
-// The sign bits are gathered by ballots into the tile's code words in LDS.
-// Responses within `margin` of the threshold are then queued per wavefront
-// in LDS (row, column) and re-checked one per lane from the unrounded FP32
-// operands (the tile row from LDS, the row of B from memory): four chains
-// over the elements k mod 4, summed as (c0 + c1) + (c2 + c3), then FP64 when
-// that result is within 1e-6 of the threshold.  The re-checking lane sets or
-// clears its code bit in LDS and overwrites the response; the words are
-// written out last.
-constexpr int kLpRows = 64;       // keypoints per tile
-constexpr int kLpThreads = 512;   // eight wavefronts
-constexpr int kLpS32 = 132;       // FP32 tile row stride (floats)
-constexpr int kLpS16 = 136;       // BF16 tile row stride (elements, 272 bytes)
-constexpr int kLpS8 = 144;        // FP8 tile row stride (bytes)
+// The product is taken transposed, D = (-B) f^T + C (v_mfma_f32_16x16x32_bf16
+// / _fp8_fp8, FP32 accumulation), so after a 16-keypoint subtile lane (g, n)
+// holds z = t - r for keypoint n and 16 bits of its chunk: MFMA row 4 g + i
+// of column tile nt is chunk bit lp_bit(nt, g, i), an assignment made when
+// the rows of B are loaded so that the packing below lands every bit in
+// place.  BF16 starts the accumulation at C = t; FP8 scales every row of the
+// tile and of B by a power of two s (the smallest with max|row| <= 448 s, at
+// least 2^-126; exact) and forms z = t + (s_row s_b) acc.
+//
+// Bit j is set when r_j > 0, i.e. when z_j < 0.  Thresholds are made +0
+// when they are -0, so z is never -0, and while every operand is finite and
+// at most 2^59 in magnitude z is finite: the sign bit of z is the code bit.
+// (Other rows take min(z, 0) first, which gives +0, bit 0, for a NaN.)  Byte
+// permutes spread the sign bits of four responses over four bytes, masks
+// place them (bit 8 i + 7 - nt, or 8 i + 3 - nt in the odd g lanes), lanes
+// g and g ^ 1 merge their halves of each byte, and the even g lanes store
+// the two 32-bit halves of the keypoint's code word in LDS.  No ballots.
+//
+// Margin re-check: a lane whose 16 responses hold one with |z| < margin
+// (a min over |z| and one compare) appends them, as an entry, to a
+// per-wavefront LDS list.  When the tile is done (or the list is full) the
+// entries are expanded into (row, bit) items, and four lanes re-check each
+// item from the unrounded FP32 operands (the feature row from the FP32 tile,
+// the row of B from memory, L2-resident): lane j of the four takes the
+// float4 groups j, j + 4, ..., j + 28, accumulates the four components in
+// four chains over its groups, adds them as (c0 + c1) + (c2 + c3), and the
+// four lane sums are added in pairs, then the two pair sums; the same in
+// FP64 when that FP32 value is within 1e-6 of the threshold.  The result
+// sets or clears the bit in LDS, and each wavefront writes its own code words.
+constexpr int kLpRows = 64;        // keypoints per tile
+constexpr int kLpThreads = 512;    // eight wavefronts
+constexpr int kLpWaves = kLpThreads / kWave;
+constexpr int kLpS16 = 136;        // BF16 tile row stride (elements, 272 bytes)
+constexpr int kLpS8 = 144;         // FP8 tile row stride (bytes)
+constexpr int kLpEntries = 64;     // pending lanes listed per wavefront
+constexpr int kLpS32 = 132;        // FP32 tile row stride (floats)
+constexpr float kLpSafe = 0x1p59f; // operands up to this magnitude cannot overflow a response
+
+// state of a tile row, one byte each
+constexpr uint8_t kRowExists = 1, kRowValid = 2, kRowSafe = 4;
 
 template <int PREC>
 struct LpOperand;
@@ -726,6 +750,9 @@ struct LpOperand<BD_PREC_FP8> {
     typedef long type;
     static constexpr int row_bytes = kLpS8;
 };
+
+// chunk bit of MFMA row 4 g + i of column tile nt (a bijection onto 0..63)
+__device__ __forceinline__ int lp_bit(int nt, int g, int i) { return 32 * (g >> 1) + 8 * i + 7 - nt - 4 * (g & 1); }
 
 __device__ __forceinline__ uint32_t pk_bf16(float a, float b)
 {
@@ -744,18 +771,19 @@ __device__ __forceinline__ int e4m3_pow2_exp(float m)
     return e < -126 ? -126 : e;
 }
 
-// Eight values times 2^-e (exact), rounded to e4m3, packed into 64 bits.
-__device__ __forceinline__ long pack_e4m3_pow2(const float (&v)[8], int e)
+// v times 2^-e, saturated to the e4m3 range; a NaN stays NaN
+__device__ __forceinline__ float e4m3_scaled(float v, int e)
 {
-    float q[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) q[i] = fminf(fmaxf(__builtin_amdgcn_ldexpf(v[i], -e), -448.0f), 448.0f);
-    int lo = 0, hi = 0;
-    lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], lo, false);
-    lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], lo, true);
-    hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[4], q[5], hi, false);
-    hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[6], q[7], hi, true);
-    return (long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    const float x = __builtin_amdgcn_ldexpf(v, -e);
+    return x == x ? fminf(fmaxf(x, -448.0f), 448.0f) : x;
+}
+
+// four values times 2^-e (exact), rounded to e4m3, packed into 32 bits
+__device__ __forceinline__ uint32_t pack4_e4m3_pow2(float a, float b, float c, float d, int e)
+{
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_scaled(a, e), e4m3_scaled(b, e), 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_scaled(c, e), e4m3_scaled(d, e), w, true);
+    return (uint32_t)w;
 }
 
 // max over the 8-lane groups 8j .. 8j + 7 (lane-local DPP moves, no LDS)
@@ -771,50 +799,86 @@ __device__ __forceinline__ float max8_dpp(float v)
     return v;
 }
 
+// Sum over the 4-lane groups 4j .. 4j + 3 (pairs, then pairs of pairs);
+// every lane of a group ends with the same value.
+__device__ __forceinline__ float sum4_dpp(float v)
+{
+    int x = __float_as_int(v);
+    v = v + __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+    x = __float_as_int(v);
+    v = v + __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
+    return v;
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+    const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)h2 << 32) | l2));
+}
+
+__device__ __forceinline__ double sum4_dpp_f64(double v)
+{
+    v = v + dpp_f64<0xB1>(v);
+    v = v + dpp_f64<0x4E>(v);
+    return v;
+}
+
 template <int PREC, int NW>
 __global__ __launch_bounds__(kLpThreads, 1) void hashsift_project_lowp_kernel(
     const float* __restrict__ hist, const bd_keypoint* __restrict__ kps, int32_t n_kp, const float* __restrict__ B,
     const float* __restrict__ t, float margin, uint64_t* __restrict__ codes, float* __restrict__ resp,
     uint32_t* __restrict__ recheck_count)
 {
-    constexpr int kRowSubs = NW == 8 ? 4 : 2;   // 16-row subtiles per wavefront
-    constexpr int kWaveRows = 16 * kRowSubs;    // tile rows of a wavefront
-    constexpr int kQueue = kWaveRows * 64;      // every response of a wavefront can be queued
+    constexpr int kRowSubs = NW == 8 ? 4 : 2;  // 16-row subtiles per wavefront
+    constexpr int kWaveRows = 16 * kRowSubs;   // tile rows of a wavefront
     constexpr int kRowBytes = LpOperand<PREC>::row_bytes;
+    constexpr int n_bits = NW * 64;
     typedef typename LpOperand<PREC>::type op_t;
-    __shared__ __align__(16) float A32[kLpRows * kLpS32];
-    __shared__ __align__(16) uint8_t Alp[kLpRows * kRowBytes];
-    __shared__ float Asc[kLpRows];
-    __shared__ uint64_t W[2][kLpThreads / kWave][kWaveRows];  // by tile parity
-    __shared__ uint16_t Q[kLpThreads / kWave][kQueue + kWave];  // + a slot per lane for writes that drop
+    __shared__ __align__(16) uint8_t Alp[2][kLpRows * kRowBytes];
+    __shared__ __align__(16) float A32[2][kLpRows * kLpS32];
+    __shared__ float Asc[2][kLpRows];
+    __shared__ uint8_t Ast[2][kLpRows];
+    __shared__ uint64_t Wd[kLpWaves][kWaveRows];
+    __shared__ __align__(16) float Ez[kLpWaves][kLpEntries][16];
+    __shared__ uint8_t Eh[kLpWaves][kLpEntries];
+    __shared__ uint16_t Qi[kLpWaves][kWave * 16];  // items of up to 64 entries
+    __shared__ uint32_t Qn[kLpWaves];
 
     const int tid = (int)threadIdx.x;
     const int lane = tid % kWave, wave = tid / kWave;
     const int g = lane >> 4, n = lane & 15;
     const int chunk = wave % NW;
     const int rbase = (wave / NW) * kWaveRows;
-    constexpr int n_bits = NW * 64;
-    uint16_t* Qw = Q[wave];
+    uint64_t* Ww = Wd[wave];
+    uint32_t* Ww32 = reinterpret_cast<uint32_t*>(Ww);
 
-    // B operands of this lane: rows 64 chunk + 16 nt + n, elements 32 s + 8 g .. + 7
+    // B operands of this lane: MFMA row n of column tile nt is chunk bit
+    // lp_bit(nt, n >> 2, n & 3); elements 32 s + 8 g .. + 7 of k-step s; negated
     op_t bop[4][4];
-    float tv[4], sb[4];
+    float sbrow[4];
+    bool safe = true;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-        const float* brow = B + (int64_t)(chunk * 64 + 16 * nt + n) * 128;
+        const float* brow = B + (int64_t)(chunk * 64 + lp_bit(nt, n >> 2, n & 3)) * 128;
         float v[4][8];
         float mx = 0.0f;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const float4 lo = *reinterpret_cast<const float4*>(brow + 32 * s + 8 * g);
             const float4 hi = *reinterpret_cast<const float4*>(brow + 32 * s + 8 * g + 4);
-            v[s][0] = lo.x, v[s][1] = lo.y, v[s][2] = lo.z, v[s][3] = lo.w;
-            v[s][4] = hi.x, v[s][5] = hi.y, v[s][6] = hi.z, v[s][7] = hi.w;
+            v[s][0] = -lo.x, v[s][1] = -lo.y, v[s][2] = -lo.z, v[s][3] = -lo.w;
+            v[s][4] = -hi.x, v[s][5] = -hi.y, v[s][6] = -hi.z, v[s][7] = -hi.w;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(v[s][e]));
+            for (int e = 0; e < 8; ++e) {
+                mx = fmaxf(mx, fabsf(v[s][e]));
+                safe = safe && fabsf(v[s][e]) <= kLpSafe;  // false for NaN
+            }
         }
-        tv[nt] = t[chunk * 64 + 16 * nt + n];
-        sb[nt] = 1.0f;
+        sbrow[nt] = 1.0f;
         if constexpr (PREC == BD_PREC_BF16) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
@@ -825,228 +889,336 @@ __global__ __launch_bounds__(kLpThreads, 1) void hashsift_project_lowp_kernel(
             mx = fmaxf(mx, __shfl_xor(mx, 16, kWave));
             mx = fmaxf(mx, __shfl_xor(mx, 32, kWave));
             const int e = e4m3_pow2_exp(mx);
-            sb[nt] = __builtin_amdgcn_ldexpf(1.0f, e);
+            sbrow[nt] = __builtin_amdgcn_ldexpf(1.0f, e);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) bop[nt][s] = pack_e4m3_pow2(v[s], e);
+            for (int s = 0; s < 4; ++s) {
+                const uint32_t lo = pack4_e4m3_pow2(v[s][0], v[s][1], v[s][2], v[s][3], e);
+                const uint32_t hi = pack4_e4m3_pow2(v[s][4], v[s][5], v[s][6], v[s][7], e);
+                bop[nt][s] = (long)(((uint64_t)hi << 32) | lo);
+            }
         }
     }
+    // thresholds (and FP8 row scales of B) of this lane's responses: bit lp_bit(nt, g, i)
+    floatx4 tz[4];
+    float sbz[4][4];
+    uint32_t msk[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float tv = t[chunk * 64 + lp_bit(nt, g, i)];
+            safe = safe && fabsf(tv) <= kLpSafe;
+            tz[nt][i] = tv == 0.0f ? 0.0f : tv;  // -0 becomes +0
+            sbz[nt][i] = 1.0f;
+            if constexpr (PREC == BD_PREC_FP8) sbz[nt][i] = __shfl(sbrow[nt], 4 * g + i, kWave);
+        }
+        msk[nt] = (0x80808080u >> nt) >> (4 * (g & 1));
+    }
+    const bool chunk_safe = __all(safe);
 
-    // staging: thread tid moves row tid / 8, elements 16 (tid % 8) .. + 15
-    const int prow = tid >> 3, pcol = (tid & 7) * 16;
+    // staging: thread tid moves row tid / 8, float4 groups j, j + 8, j + 16, j + 24 (j = tid % 8)
+    const int prow = tid >> 3, pj = tid & 7;
     const int n_tiles = (n_kp + kLpRows - 1) / kLpRows;
     float4 pf[4];
+    bool pvalid = true;
     auto load_tile = [&](int tile) {
-        const int row = tile * kLpRows + prow;
-        if (row < n_kp) {
-            const float4* src = reinterpret_cast<const float4*>(hist + (int64_t)row * 128 + pcol);
+        const int kp = tile * kLpRows + prow;
+        if (kp < n_kp) {
+            const float4* src = reinterpret_cast<const float4*>(hist + (int64_t)kp * 128);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) pf[q] = src[q];
+            for (int q = 0; q < 4; ++q) pf[q] = src[pj + 8 * q];
+            if (kps && pj == 0) {
+                const bd_keypoint k = kps[kp];
+                pvalid = finite_f(k.x) && finite_f(k.y) && finite_f(k.scale) && finite_f(k.angle) && k.scale > 0.0f;
+            }
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q) pf[q] = float4{0.0f, 0.0f, 0.0f, 0.0f};
         }
     };
-    if ((int)blockIdx.x < n_tiles) load_tile((int)blockIdx.x);
-    uint32_t rechecked = 0;
+    auto store_tile = [&](int buf, int tile) {
+        const int kp = tile * kLpRows + prow;
+        bool ok = true;
+        float mx = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float m4 = fmaxf(fmaxf(fabsf(pf[q].x), fabsf(pf[q].y)), fmaxf(fabsf(pf[q].z), fabsf(pf[q].w)));
+            mx = fmaxf(mx, m4);
+            ok = ok && fabsf(pf[q].x) <= kLpSafe && fabsf(pf[q].y) <= kLpSafe && fabsf(pf[q].z) <= kLpSafe &&
+                 fabsf(pf[q].w) <= kLpSafe;
+        }
+        float4* d32 = reinterpret_cast<float4*>(&A32[buf][prow * kLpS32]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d32[pj + 8 * q] = pf[q];
+        uint8_t* dlp = &Alp[buf][prow * kRowBytes];
+        if constexpr (PREC == BD_PREC_BF16) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<uint2*>(dlp + 8 * (pj + 8 * q)) =
+                    uint2{pk_bf16(pf[q].x, pf[q].y), pk_bf16(pf[q].z, pf[q].w)};
+        } else {
+            mx = max8_dpp(mx);
+            const int e = e4m3_pow2_exp(mx);
+            if (pj == 0) Asc[buf][prow] = __builtin_amdgcn_ldexpf(1.0f, e);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<uint32_t*>(dlp + 4 * (pj + 8 * q)) = pack4_e4m3_pow2(pf[q].x, pf[q].y, pf[q].z, pf[q].w, e);
+        }
+        // the row is safe when all eight of its threads are
+        const uint64_t unsafe = __ballot(!ok);
+        const bool row_safe = ((unsafe >> (lane & 56)) & 0xffull) == 0ull;
+        if (pj == 0)
+            Ast[buf][prow] = (uint8_t)((kp < n_kp ? kRowExists : 0) | (pvalid ? kRowValid : 0) | (row_safe ? kRowSafe : 0));
+    };
 
-    int parity = 0;
-    for (int tile = (int)blockIdx.x; tile < n_tiles; tile += (int)gridDim.x, parity ^= 1) {
-        // the barrier before the previous tile's code words went out also
-        // ended every read of its rows; its words are in the other W buffer
-        uint64_t* Ww = W[parity][wave];
-        {
-            float4* d32 = reinterpret_cast<float4*>(&A32[prow * kLpS32 + pcol]);
+    int tile = (int)blockIdx.x;
+    const int stride = (int)gridDim.x;
+    if (tile < n_tiles) {
+        load_tile(tile);
+        store_tile(0, tile);
+        if (tile + stride < n_tiles) load_tile(tile + stride);
+    }
+    uint32_t rechecked = 0;  // per lane; summed over the wavefront at the end
+    uint16_t* Qw = Qi[wave];
+    const int gi = lane >> 2, j = lane & 3;
+
+    // Re-check items (row << 6 | bit) of the tile at row r0: four lanes per
+    // item, two sets of sixteen items, the rows of B of one set loaded while
+    // the other set is summed (the feature rows come from the FP32 tile in LDS).
+    float4 bv[2][8];
+    float tc[2];
+    int itm[2];
+    auto fetch = [&](int set, int base, int total) {
+        const int it = base + gi;
+        if (it < total) {
+            const int item = Qw[it];
+            itm[set] = item;
+            const int col = item & 63;
+            const float4* brow = reinterpret_cast<const float4*>(B + (int64_t)(chunk * 64 + col) * 128);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) d32[q] = pf[q];
-            uint8_t* dlp = &Alp[prow * kRowBytes];
-            if constexpr (PREC == BD_PREC_BF16) {
-                uint4 w0, w1;
-                w0.x = pk_bf16(pf[0].x, pf[0].y);
-                w0.y = pk_bf16(pf[0].z, pf[0].w);
-                w0.z = pk_bf16(pf[1].x, pf[1].y);
-                w0.w = pk_bf16(pf[1].z, pf[1].w);
-                w1.x = pk_bf16(pf[2].x, pf[2].y);
-                w1.y = pk_bf16(pf[2].z, pf[2].w);
-                w1.z = pk_bf16(pf[3].x, pf[3].y);
-                w1.w = pk_bf16(pf[3].z, pf[3].w);
-                reinterpret_cast<uint4*>(dlp + 2 * pcol)[0] = w0;
-                reinterpret_cast<uint4*>(dlp + 2 * pcol)[1] = w1;
-            } else {
-                float mx = 0.0f;
+            for (int q = 0; q < 8; ++q) bv[set][q] = brow[j + 4 * q];
+            tc[set] = t[chunk * 64 + col];
+        } else {
+            // defined either way, so the sets are not live between uses
+            itm[set] = 0;
+            tc[set] = 0.0f;
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    mx = fmaxf(mx, fmaxf(fmaxf(fabsf(pf[q].x), fabsf(pf[q].y)), fmaxf(fabsf(pf[q].z), fabsf(pf[q].w))));
-                mx = max8_dpp(mx);
-                const int e = e4m3_pow2_exp(mx);
-                if ((tid & 7) == 0) Asc[prow] = __builtin_amdgcn_ldexpf(1.0f, e);
-                const float v0[8] = {pf[0].x, pf[0].y, pf[0].z, pf[0].w, pf[1].x, pf[1].y, pf[1].z, pf[1].w};
-                const float v1[8] = {pf[2].x, pf[2].y, pf[2].z, pf[2].w, pf[3].x, pf[3].y, pf[3].z, pf[3].w};
-                const long q0 = pack_e4m3_pow2(v0, e), q1 = pack_e4m3_pow2(v1, e);
-                *reinterpret_cast<uint4*>(dlp + pcol) =
-                    uint4{(uint32_t)q0, (uint32_t)((uint64_t)q0 >> 32), (uint32_t)q1, (uint32_t)((uint64_t)q1 >> 32)};
+            for (int q = 0; q < 8; ++q) bv[set][q] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    };
+    auto check = [&](int set, int base, int total, int r0, const float* a32) {
+        if (base + gi < total) {
+            const int wr = itm[set] >> 6, col = itm[set] & 63;
+            const float4* arow = reinterpret_cast<const float4*>(a32 + (rbase + wr) * kLpS32);
+            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float4 a = arow[j + 4 * q];
+                c0 = fmaf(a.x, bv[set][q].x, c0);
+                c1 = fmaf(a.y, bv[set][q].y, c1);
+                c2 = fmaf(a.z, bv[set][q].z, c2);
+                c3 = fmaf(a.w, bv[set][q].w, c3);
+            }
+            float res = sum4_dpp((c0 + c1) + (c2 + c3)) - tc[set];
+            if (fabsf(res) < 1e-6f) {  // the same in all four lanes
+                double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const float4 a = arow[j + 4 * q];
+                    d0 = fma((double)a.x, (double)bv[set][q].x, d0);
+                    d1 = fma((double)a.y, (double)bv[set][q].y, d1);
+                    d2 = fma((double)a.z, (double)bv[set][q].z, d2);
+                    d3 = fma((double)a.w, (double)bv[set][q].w, d3);
+                }
+                res = (float)(sum4_dpp_f64((d0 + d1) + (d2 + d3)) - (double)tc[set]);
+            }
+            if (j == 0) {
+                const uint64_t bit = 1ull << col;
+                if (res > 0.0f)
+                    __hip_atomic_fetch_or(&Ww[wr], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                else
+                    __hip_atomic_fetch_and(&Ww[wr], ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                if (resp) resp[(int64_t)(r0 + rbase + wr) * n_bits + chunk * 64 + col] = res;
             }
         }
-        if (tile + (int)gridDim.x < n_tiles) load_tile(tile + (int)gridDim.x);
-        __syncthreads();
-        const int row0 = tile * kLpRows;
-        const int limit = n_kp - (row0 + rbase);  // wavefront rows below this exist
+    };
+    // items of the tile at row r0, its FP32 rows in a32
+    auto drain = [&](int total, int r0, const float* a32) {
+        fetch(0, 0, total);
+        for (int b0 = 0; b0 < total; b0 += 32) {
+            fetch(1, b0 + 16, total);
+            check(0, b0, total, r0, a32);
+            fetch(0, b0 + 32, total);
+            check(1, b0 + 16, total, r0, a32);
+        }
+        wave_sync();
+    };
+    // entries e0 .. min(ne, e0 + 64) - 1 into items (in any order); returns their number
+    auto expand = [&](int e0, int ne) -> int {
+        if (lane == 0) Qn[wave] = 0;
+        wave_sync();
+        const int e = e0 + lane;
+        if (e < ne) {
+            const int hdr = Eh[wave][e];
+            const float4* ez = reinterpret_cast<const float4*>(Ez[wave][e]);
+            uint32_t flags = 0;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const float4 v = ez[nt];
+                flags |= (uint32_t)(fabsf(v.x) < margin) << (4 * nt) | (uint32_t)(fabsf(v.y) < margin) << (4 * nt + 1) |
+                         (uint32_t)(fabsf(v.z) < margin) << (4 * nt + 2) | (uint32_t)(fabsf(v.w) < margin) << (4 * nt + 3);
+            }
+            const int cnt = __popc(flags);
+            rechecked += (uint32_t)cnt;
+            if (cnt) {
+                int o = (int)__hip_atomic_fetch_add(&Qn[wave], (uint32_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                const int wr = 16 * (hdr >> 6) + (hdr & 15), eg = (hdr >> 4) & 3;
+                while (flags) {
+                    const int v = __builtin_ctz(flags);
+                    flags &= flags - 1u;
+                    Qw[o++] = (uint16_t)((wr << 6) | lp_bit(v >> 2, eg, v & 3));
+                }
+            }
+        }
+        wave_sync();
+        return __builtin_amdgcn_readfirstlane((int)Qn[wave]);
+    };
+    auto flush_now = [&](int ne, int r0, const float* a32) {
+        for (int e0 = 0; e0 < ne; e0 += kWave) drain(expand(e0, ne), r0, a32);
+    };
+    // this wavefront's code words of the tile at row r0 out (rows of invalid keypoints are zero)
+    auto write_words = [&](int r0, uint32_t st) {
+        wave_sync();
+        if (lane < kWaveRows && (st & kRowExists))
+            codes[(int64_t)(r0 + rbase + lane) * NW + chunk] = (st & kRowValid) ? Ww[lane] : 0ull;
+        wave_sync();
+    };
 
-        // two 16-row subtiles at a time: 1. responses (lane (g, n) holds the
-        // response of wavefront row 16 p + 4 g + i to column 16 nt + n);
-        // 2. responses out, sign bits into the code words, pending responses queued
-        int queued = 0;
-#pragma unroll
+    for (int buf = 0; tile < n_tiles; tile += stride, buf ^= 1) {
+        // buffer buf is complete, and every read of buffer buf ^ 1 (the previous tile) is done
+        __syncthreads();
+        if (tile + stride < n_tiles) {
+            store_tile(buf ^ 1, tile + stride);
+            if (tile + 2 * stride < n_tiles) load_tile(tile + 2 * stride);
+        }
+        const int row0 = tile * kLpRows;
+        const uint8_t* Ab = Alp[buf];
+        const float* A32b = A32[buf];
+
+        int n_ent = 0;  // wavefront-uniform
+#pragma unroll 1
         for (int pp = 0; pp < kRowSubs; pp += 2) {
+
+            // 1. D = (-B) f^T + C for two subtiles: lane (g, n) ends with the
+            //    responses of keypoint rbase + 16 p + n to bits lp_bit(nt, g, i)
             floatx4 acc[2][4];
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) acc[r][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 op_t av[2];
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
-                    const int row = rbase + 16 * (pp + r) + n;  // A operand: lane (g, m = n) holds row m
+                    const int row = rbase + 16 * (pp + r) + n;
                     if constexpr (PREC == BD_PREC_BF16)
-                        av[r] = *reinterpret_cast<const bf16x8*>(&Alp[row * kRowBytes + 2 * (32 * s + 8 * g)]);
+                        av[r] = *reinterpret_cast<const bf16x8*>(&Ab[row * kRowBytes + 2 * (32 * s + 8 * g)]);
                     else
-                        av[r] = *reinterpret_cast<const long*>(&Alp[row * kRowBytes + 32 * s + 8 * g]);
+                        av[r] = *reinterpret_cast<const long*>(&Ab[row * kRowBytes + 32 * s + 8 * g]);
                 }
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
                     for (int r = 0; r < 2; ++r) {
                         if constexpr (PREC == BD_PREC_BF16)
-                            acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bop[nt][s], acc[r][nt], 0, 0, 0);
+                            acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bop[nt][s], av[r],
+                                                                                  s == 0 ? tz[nt] : acc[r][nt], 0, 0, 0);
                         else
-                            acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[r], bop[nt][s], acc[r][nt], 0, 0, 0);
+                            acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(
+                                bop[nt][s], av[r], s == 0 ? floatx4{0.0f, 0.0f, 0.0f, 0.0f} : acc[r][nt], 0, 0, 0);
                     }
             }
+
+            // 2. per subtile: pending lanes listed, responses out, sign bits packed
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int p = pp + r;
-                float sk[4] = {1.0f, 1.0f, 1.0f, 1.0f};
-                if constexpr (PREC == BD_PREC_FP8) {
+                const int wr = 16 * (pp + r) + n;  // this lane's row within the wavefront's rows
+                const uint8_t st = Ast[buf][rbase + wr];
+                float z[4][4];
+                if constexpr (PREC == BD_PREC_BF16) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) sk[i] = Asc[rbase + 16 * p + 4 * g + i];
+                    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) z[nt][i] = acc[r][nt][i];
+                } else {
+                    const float sk = Asc[buf][rbase + wr];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) z[nt][i] = fmaf(acc[r][nt][i], sk * sbz[nt][i], tz[nt][i]);
                 }
-                float rv[4][4];
-                uint64_t mask[4][4];
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        rv[nt][i] = acc[r][nt][i] * (sk[i] * sb[nt]) - tv[nt];
-                        mask[nt][i] = __ballot(rv[nt][i] > 0.0f);
-                    }
                 if (margin > 0.0f) {
-                    // all sixteen ballots first, then the (scalar) walk over the non-empty ones
-                    uint64_t pend[4][4];
+                    float mq[4];
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            pend[nt][i] = __ballot(16 * p + 4 * g + i < limit && fabsf(rv[nt][i]) < margin);
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const uint64_t pm = pend[nt][i];
-                            if (pm) {
-                                // queue position, or this lane's spare slot when it has nothing to queue
-                                const bool hit = (pm >> lane) & 1ull;
-                                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(pm >> 32),
-                                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
-                                Qw[hit ? queued + rank : kQueue + lane] = (uint16_t)((16 * p + 4 * g + i) << 6 | (16 * nt + n));
-                                queued += __popcll(pm);
+                        mq[nt] = fminf(fminf(fabsf(z[nt][0]), fabsf(z[nt][1])), fminf(fabsf(z[nt][2]), fabsf(z[nt][3])));
+                    const float m = fminf(fminf(mq[0], mq[1]), fminf(mq[2], mq[3]));
+                    const bool pend = (st & kRowExists) && m < margin;
+                    const uint64_t L = __ballot(pend);
+                    if (L) {
+                        if (n_ent + __popcll(L) > kLpEntries) {
+                            // the list is full: re-check it now, one set at a time (few registers are free here)
+                            for (int e0 = 0; e0 < n_ent; e0 += kWave) {
+                                const int total = expand(e0, n_ent);
+                                for (int b0 = 0; b0 < total; b0 += 16) {
+                                    fetch(0, b0, total);
+                                    check(0, b0, total, row0, A32b);
+                                }
+                                wave_sync();
                             }
+                            n_ent = 0;
                         }
+                        if (pend) {
+                            const int e = n_ent + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(L >> 32),
+                                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)L, 0u));
+                            float4* ez = reinterpret_cast<float4*>(Ez[wave][e]);
+#pragma unroll
+                            for (int nt = 0; nt < 4; ++nt) ez[nt] = float4{z[nt][0], z[nt][1], z[nt][2], z[nt][3]};
+                            Eh[wave][e] = (uint8_t)(((pp + r) << 6) | lane);
+                        }
+                        n_ent += __popcll(L);
+                    }
                 }
-                if (resp) {
+                if (resp && (st & kRowExists)) {
+                    const int64_t kp = row0 + rbase + wr;
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int wr = 16 * p + 4 * g + i;
-                            if (wr < limit) resp[(int64_t)(row0 + rbase + wr) * n_bits + chunk * 64 + 16 * nt + n] = rv[nt][i];
-                        }
+                        for (int i = 0; i < 4; ++i) resp[kp * n_bits + chunk * 64 + lp_bit(nt, g, i)] = -z[nt][i];
                 }
-                if (lane < 16) {
-                    const int gq = lane >> 2, iq = lane & 3;
-                    uint64_t word = 0ull;
+                if (!chunk_safe || !(st & kRowSafe)) {
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
-                        const uint64_t mk =
-                            iq == 0 ? mask[nt][0] : iq == 1 ? mask[nt][1] : iq == 2 ? mask[nt][2] : mask[nt][3];
-                        word |= ((mk >> (16 * gq)) & 0xffffull) << (16 * nt);
-                    }
-                    Ww[16 * p + lane] = word;
+                    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) z[nt][i] = fminf(z[nt][i], 0.0f);
                 }
+                uint32_t X = 0;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    // byte i = sign of z[nt][i] spread over the byte (selectors 9 and 11)
+                    const uint32_t pa = __builtin_amdgcn_perm(__float_as_uint(z[nt][1]), __float_as_uint(z[nt][0]), 0x0c0c0b09u);
+                    const uint32_t pb = __builtin_amdgcn_perm(__float_as_uint(z[nt][3]), __float_as_uint(z[nt][2]), 0x0b090c0cu);
+                    X |= (pa | pb) & msk[nt];
+                }
+                const uint32_t half = X | (uint32_t)__shfl_xor((int)X, 16, kWave);
+                if (!(g & 1)) Ww32[2 * wr + (g >> 1)] = half;
             }
         }
-        rechecked += (uint32_t)queued;
 
-        // 3. re-check the queued responses, one per lane
-        wave_sync();
-        for (int b0 = 0; b0 < queued; b0 += kWave) {
-            if (b0 + lane < queued) {
-                const int item = Qw[b0 + lane];
-                const int wr = item >> 6, col = item & 63;
-                const float* arow = &A32[(rbase + wr) * kLpS32];
-                const float* brow = B + (int64_t)(chunk * 64 + col) * 128;
-                const float tcol = t[chunk * 64 + col];
-                // the row of B in quarters, each in flight at once
-                float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, d3 = 0.0f;
-#pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    float4 bv[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) bv[q] = reinterpret_cast<const float4*>(brow)[8 * h + q];
-                    // the loads above stay ahead of the arithmetic below
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const float4 av = reinterpret_cast<const float4*>(arow)[8 * h + q];
-                        d0 = fmaf(av.x, bv[q].x, d0);
-                        d1 = fmaf(av.y, bv[q].y, d1);
-                        d2 = fmaf(av.z, bv[q].z, d2);
-                        d3 = fmaf(av.w, bv[q].w, d3);
-                    }
-                }
-                float res = ((d0 + d1) + (d2 + d3)) - tcol;
-                if (fabsf(res) < 1e-6f) {
-                    double d = 0.0;
-                    for (int k = 0; k < 128; ++k) d = fma((double)arow[k], (double)brow[k], d);
-                    res = (float)(d - (double)tcol);
-                }
-                const uint64_t bit = 1ull << col;
-                if (res > 0.0f)
-                    __hip_atomic_fetch_or(&Ww[wr], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                else
-                    __hip_atomic_fetch_and(&Ww[wr], ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                const int kp = row0 + rbase + wr;
-                if (resp) resp[(int64_t)kp * n_bits + chunk * 64 + col] = res;
-            }
-        }
-        __syncthreads();
-
-        // 4. the tile's code rows out, coalesced: thread tid writes word tid % NW of row tid / NW
-        if (tid < kLpRows * NW) {
-            const int row = tid / NW, c = tid % NW;
-            const int kp = row0 + row;
-            if (kp < n_kp) {
-                bool valid = true;
-                if (kps) {
-                    const bd_keypoint k = kps[kp];
-                    valid = finite_f(k.x) && finite_f(k.y) && finite_f(k.scale) && finite_f(k.angle) && k.scale > 0.0f;
-                }
-                // chunk c of row `row` belongs to wavefront c + NW * (row / kWaveRows)
-                codes[(int64_t)kp * NW + c] = valid ? W[parity][c + NW * (row / kWaveRows)][row % kWaveRows] : 0ull;
-            }
-        }
+        // 3. re-check the listed entries, then the code words out
+        if (n_ent > 0) flush_now(n_ent, row0, A32b);
+        write_words(row0, lane < kWaveRows ? Ast[buf][rbase + lane] : 0u);
     }
-    // rechecked is the wavefront's count (the same in every lane)
+    // each lane counted the responses of the entries it expanded
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) rechecked += (uint32_t)__shfl_xor((int)rechecked, off, kWave);
     if (recheck_count && lane == 0 && rechecked) atomicAdd(recheck_count, rechecked);
 }
 

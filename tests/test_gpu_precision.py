@@ -96,3 +96,52 @@ def test_full_size_200k_keypoints(dev):
         print(f"{p}: flipped {fl}/{nb} = {fl / nb:.2e}, re-checked {rc} ({rc / nb:.2e}), max|r - r32| {e:.2e}")
     assert stats["bf16"][0] / stats["bf16"][1] <= 1e-4
     assert stats["fp8"][0] / stats["fp8"][1] <= 5e-2
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+@pytest.mark.parametrize("n_bits", [256, 512])
+def test_margin_covering_every_response(dev, precision, n_bits):
+    """margin 10: every response is re-checked from the unrounded FP32
+    operands, so each code bit is the sign of the exact response (FP32 sum,
+    FP64 within 1e-6 of the threshold) and every response is counted.  The
+    per-wavefront list of pending lanes fills and is re-checked part-way
+    through each tile."""
+    w = synth.hashsift512_pair(n_kp=700, n_bits=n_bits)
+    _, kps, f = features(dev, w)
+    B, t = torch.from_numpy(w.B).to(dev), torch.from_numpy(w.t).to(dev)
+    count = torch.zeros(1, dtype=torch.uint32, device=dev)
+    codes, resp = bd.hashsift_project(f, B, t, kps, precision=precision, with_resp=True, margin=10.0,
+                                      recheck_count=count)
+    exact = to_np(f).astype(np.float64) @ w.B.astype(np.float64).T - w.t.astype(np.float64)
+    assert int(to_np(count)[0]) == exact.size
+    assert np.abs(to_np(resp) - exact).max() <= 2e-6
+    assert (unpack(to_np(codes), n_bits) == (exact > 0)).all()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_nan_rows_zero_rows_and_signed_zero_thresholds(ref, dev, precision):
+    """Without a margin the code bit is r > 0 from the rounded operands:
+    a row of NaN gives zero bits, a zero row against thresholds +0 and -0
+    gives r = +0 (bit 0), and a row scaled by 2^70 (beyond the range where
+    the sign is read without a check) keeps the signs of the emulation."""
+    rng = np.random.default_rng(2108)
+    n = 203
+    f = rng.random((n, 128)).astype(np.float32)
+    f /= np.linalg.norm(f, axis=1, keepdims=True)
+    B = rng.normal(0.0, 1.0 / np.sqrt(128.0), (512, 128)).astype(np.float32)
+    t = rng.normal(0.0, 0.01, 512).astype(np.float32)
+    t[0::3] = -0.0
+    t[1::3] = 0.0
+    f[3] = 0.0
+    f[4] = np.nan
+    f[130] *= np.float32(2.0 ** 70)
+    codes, resp = bd.hashsift_project(torch.from_numpy(f).to(dev), torch.from_numpy(B).to(dev),
+                                      torch.from_numpy(t).to(dev), precision=precision, with_resp=True, margin=0.0)
+    bits = unpack(to_np(codes), 512)
+    emul = ref.project_lowp(np.nan_to_num(f, nan=0.0), B, t, precision)
+    assert not bits[4].any()
+    assert (bits[3] == (-t.astype(np.float64) > 0)).all()
+    assert not bits[3][0::3].any() and not bits[3][1::3].any()
+    rows = [i for i in range(n) if i != 4]
+    clear = np.abs(emul[rows]) > np.abs(emul[rows]).max(axis=1, keepdims=True) * 1e-3
+    assert (bits[rows] == (emul[rows] > 0))[clear].all()
