@@ -775,7 +775,7 @@ __device__ __forceinline__ int e4m3_pow2_exp(float m)
 __device__ __forceinline__ float e4m3_scaled(float v, int e)
 {
     const float x = __builtin_amdgcn_ldexpf(v, -e);
-    return x == x ? fminf(fmaxf(x, -448.0f), 448.0f) : x;
+    return x == x ? __builtin_amdgcn_fmed3f(x, -448.0f, 448.0f) : x;
 }
 
 // four values times 2^-e (exact), rounded to e4m3, packed into 32 bits
@@ -784,6 +784,14 @@ __device__ __forceinline__ uint32_t pack4_e4m3_pow2(float a, float b, float c, f
     int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_scaled(a, e), e4m3_scaled(b, e), 0, false);
     w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_scaled(c, e), e4m3_scaled(d, e), w, true);
     return (uint32_t)w;
+}
+
+// min(|a|, |b|, |c|) in one instruction (fminf would quiet each input first)
+__device__ __forceinline__ float min3_abs(float a, float b, float c)
+{
+    float r;
+    asm("v_min3_f32 %0, |%1|, |%2|, |%3|" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
 }
 
 // max over the 8-lane groups 8j .. 8j + 7 (lane-local DPP moves, no LDS)
@@ -1102,6 +1110,7 @@ __global__ __launch_bounds__(kLpThreads, 1) void hashsift_project_lowp_kernel(
             if (tile + 2 * stride < n_tiles) load_tile(tile + 2 * stride);
         }
         const int row0 = tile * kLpRows;
+        const bool full = row0 + kLpRows <= n_kp;  // every row of the tile exists
         const uint8_t* Ab = Alp[buf];
         const float* A32b = A32[buf];
 
@@ -1155,12 +1164,14 @@ __global__ __launch_bounds__(kLpThreads, 1) void hashsift_project_lowp_kernel(
                         for (int i = 0; i < 4; ++i) z[nt][i] = fmaf(acc[r][nt][i], sk * sbz[nt][i], tz[nt][i]);
                 }
                 if (margin > 0.0f) {
-                    float mq[4];
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt)
-                        mq[nt] = fminf(fminf(fabsf(z[nt][0]), fabsf(z[nt][1])), fminf(fabsf(z[nt][2]), fabsf(z[nt][3])));
-                    const float m = fminf(fminf(mq[0], mq[1]), fminf(mq[2], mq[3]));
-                    const bool pend = (st & kRowExists) && m < margin;
+                    // smallest |z| of the lane (a NaN never is the smallest of finite values; all NaN: not pending)
+                    const float m0 = min3_abs(z[0][0], z[0][1], z[0][2]);
+                    const float m1 = min3_abs(z[0][3], z[1][0], z[1][1]);
+                    const float m2 = min3_abs(z[1][2], z[1][3], z[2][0]);
+                    const float m3 = min3_abs(z[2][1], z[2][2], z[2][3]);
+                    const float m4 = min3_abs(z[3][0], z[3][1], z[3][2]);
+                    const float m = min3_abs(min3_abs(m0, m1, m2), min3_abs(m3, m4, z[3][3]), m0);
+                    const bool pend = m < margin && (full || (st & kRowExists));
                     const uint64_t L = __ballot(pend);
                     if (L) {
                         if (n_ent + __popcll(L) > kLpEntries) {
