@@ -211,23 +211,41 @@ __device__ __forceinline__ int clampi(int v, int hi)
 // 32.32 fixed point of v (|v| < 2^31).
 __device__ __forceinline__ int64_t to_fixed(double v) { return (int64_t)rint(v * 4294967296.0); }
 
+typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
 // The four corner pixels and weights of the sample at fixed-point image
 // position (X, Y).  Row offsets use 24-bit multiplies: the host admits only
-// images with pitch < 2^24, H < 2^24 and pitch * H <= 2^32.
-template <int DT>
+// images with pitch < 2^24, H < 2^24 and pitch * H <= 2^32.  PAIR (float
+// images at least 2 pixels wide): each row's two pixels come from one 8-byte
+// load of the pair starting at the column clamped to [0, W - 2], the first
+// or second of it standing for both when the sample lies left of column 0 or
+// right of column W - 1 (clamp to edge), which halves the lane accesses.
+template <int DT, bool PAIR>
 __device__ __forceinline__ void fetch_fixed(const uint8_t* __restrict__ img, int wm1, int hm1, uint32_t upitch,
                                             int64_t X, int64_t Y, float (&v)[4], float& fx, float& fy)
 {
     const int xi = (int)(X >> 32), yi = (int)(Y >> 32);
     fx = (float)(uint32_t)X * 0x1p-32f;
     fy = (float)(uint32_t)Y * 0x1p-32f;
-    const int xa = clampi(xi, wm1), xb = clampi(xi + 1, wm1);
     const uint32_t ra = __umul24((uint32_t)clampi(yi, hm1), upitch);
     const uint32_t rb = __umul24((uint32_t)clampi(yi + 1, hm1), upitch);
-    v[0] = pixel_at<DT>(img, ra, xa);
-    v[1] = pixel_at<DT>(img, ra, xb);
-    v[2] = pixel_at<DT>(img, rb, xa);
-    v[3] = pixel_at<DT>(img, rb, xb);
+    if constexpr (PAIR) {
+        static_assert(DT == BD_DTYPE_F32, "pairs of float pixels");
+        const uint32_t xo = 4u * (uint32_t)clampi(xi, wm1 - 1);
+        const float2_a4 pa = *reinterpret_cast<const float2_a4*>(img + ra + xo);
+        const float2_a4 pb = *reinterpret_cast<const float2_a4*>(img + rb + xo);
+        const bool left = xi < 0, right = xi >= wm1;
+        v[0] = right ? pa.y : pa.x;
+        v[1] = left ? pa.x : pa.y;
+        v[2] = right ? pb.y : pb.x;
+        v[3] = left ? pb.x : pb.y;
+    } else {
+        const int xa = clampi(xi, wm1), xb = clampi(xi + 1, wm1);
+        v[0] = pixel_at<DT>(img, ra, xa);
+        v[1] = pixel_at<DT>(img, ra, xb);
+        v[2] = pixel_at<DT>(img, rb, xa);
+        v[3] = pixel_at<DT>(img, rb, xb);
+    }
 }
 
 // Resampling with fixed-point positions (every sample within 2^30 pixels of
@@ -242,7 +260,7 @@ __device__ __forceinline__ void fetch_fixed(const uint8_t* __restrict__ img, int
 // is in flight before any is used: R = 8 (two round trips) where a launch
 // holds about one keypoint per wavefront and so is bound by these round
 // trips, R = 4 (fewer registers) for persistent loops.
-template <int DT, int R>
+template <int DT, int R, bool PAIR>
 __device__ __forceinline__ void resample_fixed(const uint8_t* __restrict__ img, int32_t W, int32_t H,
                                                uint32_t upitch, double kx, double ky, double sa, double sb,
                                                float base, float* P, int lane)
@@ -273,7 +291,7 @@ __device__ __forceinline__ void resample_fixed(const uint8_t* __restrict__ img, 
         float v[R][4], fx[R], fy[R];
 #pragma unroll
         for (int g = 0; g < R; ++g) {
-            fetch_fixed<DT>(img, wm1, hm1, upitch, X, Y, v[g], fx[g], fy[g]);
+            fetch_fixed<DT, PAIR>(img, wm1, hm1, upitch, X, Y, v[g], fx[g], fy[g]);
             advance(g);  // t0 is a multiple of 4
         }
 #pragma unroll
@@ -285,13 +303,13 @@ __device__ __forceinline__ void resample_fixed(const uint8_t* __restrict__ img, 
     float v[R + 2][4], fx[R + 2], fy[R + 2];
 #pragma unroll
     for (int g = 0; g < R; ++g) {
-        fetch_fixed<DT>(img, wm1, hm1, upitch, X, Y, v[g], fx[g], fy[g]);
+        fetch_fixed<DT, PAIR>(img, wm1, hm1, upitch, X, Y, v[g], fx[g], fy[g]);
         advance(g);
     }
     const double ar = h ? 16.5 : -16.5, ac = (double)c - 15.5;
-    fetch_fixed<DT>(img, wm1, hm1, upitch, to_fixed(fma(sa, ac, fma(-sb, ar, kx))),
+    fetch_fixed<DT, PAIR>(img, wm1, hm1, upitch, to_fixed(fma(sa, ac, fma(-sb, ar, kx))),
                     to_fixed(fma(sb, ac, fma(sa, ar, ky))), v[R], fx[R], fy[R]);
-    fetch_fixed<DT>(img, wm1, hm1, upitch, to_fixed(fma(sa, ar, fma(-sb, ac, kx))),
+    fetch_fixed<DT, PAIR>(img, wm1, hm1, upitch, to_fixed(fma(sa, ar, fma(-sb, ac, kx))),
                     to_fixed(fma(sb, ar, fma(sa, ac, ky))), v[R + 1], fx[R + 1], fy[R + 1]);
 #pragma unroll
     for (int g = 0; g < R; ++g) dst[offset(16 - R + g)] = bilinear<DT>(v[g], fx[g], fy[g], base);
@@ -369,7 +387,12 @@ __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_
     // (j - 16.5, i - 16.5); its image position is (kx, ky) plus that offset
     // rotated and scaled by (sa, sb).
     if (fabs((double)kp.x) + 24.0 * kp.scale < 1073741824.0 && fabs((double)kp.y) + 24.0 * kp.scale < 1073741824.0)
-        resample_fixed<DT, R>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
+    {
+        if (DT == BD_DTYPE_F32 && W >= 2)
+            resample_fixed<DT, R, DT == BD_DTYPE_F32>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
+        else
+            resample_fixed<DT, R, false>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
+    }
     else
         resample_f64<DT>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
     wave_sync();
