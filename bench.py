@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-batched", action="store_true", help="skip the 128-image batched workload")
     p.add_argument("--batched-only", action="store_true", help="run only the batched workload and print its JSON")
+    p.add_argument("--precision-only", action="store_true",
+                   help="run only the 200000-row FP32/BF16/FP8 projection comparison and print its JSON")
     p.add_argument("--step-only", action="store_true", help="only the step, its stage timings and the checks")
     p.add_argument("--only", default="", help="profile helper: run only this stage in the step loop")
     p.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -167,8 +169,8 @@ PMC_TRAFFIC = {
     "keypoint_order": ("order.hip", "b9c2afd100b6dde1", 44 * 2048 + 20 * 1024),
     "integral": ("integral.hip", "64d461e94933cbb9", (366 + 1057 + 1387) * 2048 + (580 + 616 + 8158) * 1024),
     "bad_describe": ("bad.hip", "ad09d5e017d700e6", 9075 * 2048 + 160 * 1024),
-    "hashsift_features": ("hashsift.hip", "44f47f97598e58b9", 9270 * 2048 + 2500 * 1024),
-    "hashsift_project": ("hashsift.hip", "44f47f97598e58b9", 2367 * 2048 + 312 * 1024),
+    "hashsift_features": ("hashsift.hip", "7959e8350953f487", 9277 * 2048 + 2500 * 1024),
+    "hashsift_project": ("hashsift.hip", "7959e8350953f487", 2367 * 2048 + 312 * 1024),
     "match_bad256": ("hamming.hip", "b45b06214a9c6ad9", (882 + 300) * 2048 + (469 + 78) * 1024),
     "match_hashsift512": ("hamming.hip", "b45b06214a9c6ad9", (1684 + 300) * 2048 + (469 + 78) * 1024),
 }
@@ -180,9 +182,9 @@ PMC_TRAFFIC = {
 # per clock (lanes of one instruction that fall in the same cache line can be
 # served together, so a gather with some locality can pass 1 slightly), so
 # accesses / (duration x 256 CUs x 2.4 GHz) is the kernel's fraction of that
-# rate; the histogram's bilinear gathers run at it.
+# rate.
 PMC_L1_ACCESSES = {
-    "hashsift_features": ("hashsift.hip", "44f47f97598e58b9", 22133716),
+    "hashsift_features": ("hashsift.hip", "7959e8350953f487", 11332771),
     "bad_describe": ("bad.hip", "ad09d5e017d700e6", 10092917),
 }
 L1_ACCESS_PEAK_PER_S = 256 * 2.4e9
@@ -830,6 +832,9 @@ def main():
     for _ in range(max(1, args.warmup)):
         wl.step(args.only)
     torch.cuda.synchronize()
+    if args.precision_only:  # the features of the step's two views, tiled to 200000 rows
+        print(json.dumps({"precision_projection_200k": precision_projection(wl)}))
+        return
 
     graph = None
     if args.graph and not args.only:
