@@ -171,8 +171,9 @@ int bd_describe_bad_table(bd_context* ctx, const uint32_t* ii, int32_t W, int32_
  *            over the float4 groups k/4 = j mod 4, each in four running sums
  *            over the components (added as (s0 + s1) + (s2 + s3)), the four
  *            partials added in pairs; in FP64 when that FP32 value is within
- *            1e-6 of the threshold.  A NaN response gives bit 0.  FP8 scales every row of f and of B by the smallest power of
- *            two s >= 2^-126 with max|row| <= 448 s before rounding to e4m3;
+ *            1e-6 of the threshold.  A NaN response gives bit 0.  FP8 scales
+ *            every row of f and of B by the smallest power of two
+ *            s >= 2^-126 with max|row| <= 448 s before rounding to e4m3;
  *            recheck_count (optional device u32, caller-zeroed) is increased
  *            by the number of such responses.  margin is ignored for FP32.
  * n_bits is 256 or 512.  f: 34x34 bilinear
