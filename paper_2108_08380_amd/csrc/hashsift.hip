@@ -738,10 +738,11 @@ __global__ __launch_bounds__(256, 2) void hashsift_project_kernel(const float* _
 // g and g ^ 1 merge their halves of each byte, and the even g lanes store
 // the two 32-bit halves of the keypoint's code word in LDS.  No ballots.
 //
-// Margin re-check: a lane whose 16 responses hold one with |z| < margin
-// (a min over |z| and one compare) appends them, as an entry, to a
-// per-wavefront LDS list.  When the tile is done (or the list is full) the
-// entries are expanded into (row, bit) items, and four lanes re-check each
+// Margin re-check: the sign bits of |z| - margin, packed like the code bits,
+// are a lane's pending flags; a lane with any appends them (one 32-bit word
+// and its subtile and lane) to a per-wavefront LDS list with room for every
+// lane of the tile.  When the tile is done the entries are expanded into
+// (row, bit) items, and four lanes re-check each
 // item from the unrounded FP32 operands (the feature row from the FP32 tile,
 // the row of B from memory, L2-resident): lane j of the four takes the
 // float4 groups j, j + 4, ..., j + 28, accumulates the four components in
@@ -754,7 +755,7 @@ constexpr int kLpThreads = 512;    // eight wavefronts
 constexpr int kLpWaves = kLpThreads / kWave;
 constexpr int kLpS16 = 136;        // BF16 tile row stride (elements, 272 bytes)
 constexpr int kLpS8 = 144;         // FP8 tile row stride (bytes)
-constexpr int kLpEntries = 64;     // pending lanes listed per wavefront
+constexpr int kLpEntries = 256;    // pending lanes listed per wavefront: every lane of four subtiles
 constexpr int kLpS32 = 132;        // FP32 tile row stride (floats)
 constexpr float kLpSafe = 0x1p59f; // operands up to this magnitude cannot overflow a response
 
@@ -807,14 +808,6 @@ __device__ __forceinline__ uint32_t pack4_e4m3_pow2(float a, float b, float c, f
     int w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_scaled(a, e), e4m3_scaled(b, e), 0, false);
     w = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_scaled(c, e), e4m3_scaled(d, e), w, true);
     return (uint32_t)w;
-}
-
-// min(|a|, |b|, |c|) in one instruction (fminf would quiet each input first)
-__device__ __forceinline__ float min3_abs(float a, float b, float c)
-{
-    float r;
-    asm("v_min3_f32 %0, |%1|, |%2|, |%3|" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
 }
 
 // max over the 8-lane groups 8j .. 8j + 7 (lane-local DPP moves, no LDS)
@@ -874,8 +867,8 @@ __global__ __launch_bounds__(kLpThreads, 1) void hashsift_project_lowp_kernel(
     __shared__ float Asc[2][kLpRows];
     __shared__ uint8_t Ast[2][kLpRows];
     __shared__ uint64_t Wd[kLpWaves][kWaveRows];
-    __shared__ __align__(16) float Ez[kLpWaves][kLpEntries][16];
-    __shared__ uint8_t Eh[kLpWaves][kLpEntries];
+    __shared__ uint32_t Ef[kLpWaves][kLpEntries];  // pending flags of a lane: response (nt, i) at bit 8 i + nt
+    __shared__ uint8_t Eh[kLpWaves][kLpEntries];   // its subtile and lane
     __shared__ uint16_t Qi[kLpWaves][kWave * 16];  // items of up to 64 entries
     __shared__ uint32_t Qn[kLpWaves];
 
@@ -1091,24 +1084,15 @@ __global__ __launch_bounds__(kLpThreads, 1) void hashsift_project_lowp_kernel(
         const int e = e0 + lane;
         if (e < ne) {
             const int hdr = Eh[wave][e];
-            const float4* ez = reinterpret_cast<const float4*>(Ez[wave][e]);
-            uint32_t flags = 0;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const float4 v = ez[nt];
-                flags |= (uint32_t)(fabsf(v.x) < margin) << (4 * nt) | (uint32_t)(fabsf(v.y) < margin) << (4 * nt + 1) |
-                         (uint32_t)(fabsf(v.z) < margin) << (4 * nt + 2) | (uint32_t)(fabsf(v.w) < margin) << (4 * nt + 3);
-            }
+            uint32_t flags = Ef[wave][e];
             const int cnt = __popc(flags);
             rechecked += (uint32_t)cnt;
-            if (cnt) {
-                int o = (int)__hip_atomic_fetch_add(&Qn[wave], (uint32_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                const int wr = 16 * (hdr >> 6) + (hdr & 15), eg = (hdr >> 4) & 3;
-                while (flags) {
-                    const int v = __builtin_ctz(flags);
-                    flags &= flags - 1u;
-                    Qw[o++] = (uint16_t)((wr << 6) | lp_bit(v >> 2, eg, v & 3));
-                }
+            int o = (int)__hip_atomic_fetch_add(&Qn[wave], (uint32_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            const int wr = 16 * (hdr >> 6) + (hdr & 15), eg = (hdr >> 4) & 3;
+            while (flags) {
+                const int b = __builtin_ctz(flags);  // 8 i + nt
+                flags &= flags - 1u;
+                Qw[o++] = (uint16_t)((wr << 6) | lp_bit(b & 7, eg, b >> 3));
             }
         }
         wave_sync();
@@ -1187,34 +1171,25 @@ __global__ __launch_bounds__(kLpThreads, 1) void hashsift_project_lowp_kernel(
                         for (int i = 0; i < 4; ++i) z[nt][i] = fmaf(acc[r][nt][i], sk * sbz[nt][i], tz[nt][i]);
                 }
                 if (margin > 0.0f) {
-                    // smallest |z| of the lane (a NaN never is the smallest of finite values; all NaN: not pending)
-                    const float m0 = min3_abs(z[0][0], z[0][1], z[0][2]);
-                    const float m1 = min3_abs(z[0][3], z[1][0], z[1][1]);
-                    const float m2 = min3_abs(z[1][2], z[1][3], z[2][0]);
-                    const float m3 = min3_abs(z[2][1], z[2][2], z[2][3]);
-                    const float m4 = min3_abs(z[3][0], z[3][1], z[3][2]);
-                    const float m = min3_abs(min3_abs(m0, m1, m2), min3_abs(m3, m4, z[3][3]), m0);
-                    const bool pend = m < margin && (full || (st & kRowExists));
-                    const uint64_t L = __ballot(pend);
+                    // pending flags: the sign bit of |z| - margin is set exactly when |z| < margin
+                    // (|NaN| is a positive NaN and |inf| - margin is +inf: neither is pending)
+                    uint32_t F = 0;
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        float d[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) d[i] = fabsf(z[nt][i]) - margin;
+                        const uint32_t pa = __builtin_amdgcn_perm(__float_as_uint(d[1]), __float_as_uint(d[0]), 0x0c0c0b09u);
+                        const uint32_t pb = __builtin_amdgcn_perm(__float_as_uint(d[3]), __float_as_uint(d[2]), 0x0b090c0cu);
+                        F |= (pa | pb) & (0x01010101u << nt);
+                    }
+                    if (!(full || (st & kRowExists))) F = 0u;
+                    const uint64_t L = __ballot(F != 0u);
                     if (L) {
-                        if (n_ent + __popcll(L) > kLpEntries) {
-                            // the list is full: re-check it now, one set at a time (few registers are free here)
-                            for (int e0 = 0; e0 < n_ent; e0 += kWave) {
-                                const int total = expand(e0, n_ent);
-                                for (int b0 = 0; b0 < total; b0 += 16) {
-                                    fetch(0, b0, total);
-                                    check(0, b0, total, row0, A32b);
-                                }
-                                wave_sync();
-                            }
-                            n_ent = 0;
-                        }
-                        if (pend) {
+                        if (F) {
                             const int e = n_ent + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(L >> 32),
                                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)L, 0u));
-                            float4* ez = reinterpret_cast<float4*>(Ez[wave][e]);
-#pragma unroll
-                            for (int nt = 0; nt < 4; ++nt) ez[nt] = float4{z[nt][0], z[nt][1], z[nt][2], z[nt][3]};
+                            Ef[wave][e] = F;
                             Eh[wave][e] = (uint8_t)(((pp + r) << 6) | lane);
                         }
                         n_ent += __popcll(L);
