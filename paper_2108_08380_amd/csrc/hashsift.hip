@@ -795,12 +795,11 @@ __device__ __forceinline__ int e4m3_pow2_exp(float m)
     return e < -126 ? -126 : e;
 }
 
-// v times 2^-e, saturated to the e4m3 range; a NaN stays NaN
-__device__ __forceinline__ float e4m3_scaled(float v, int e)
-{
-    const float x = __builtin_amdgcn_ldexpf(v, -e);
-    return x == x ? __builtin_amdgcn_fmed3f(x, -448.0f, 448.0f) : x;
-}
+// v times 2^-e.  With e the row's exponent every finite element of the row
+// lands within [-448, 448] exactly (max|row| <= 448 * 2^e), so no clamp is
+// needed before the conversion; a NaN stays NaN, and a row holding an
+// infinity is outside the safe range anyway.
+__device__ __forceinline__ float e4m3_scaled(float v, int e) { return __builtin_amdgcn_ldexpf(v, -e); }
 
 // four values times 2^-e (exact), rounded to e4m3, packed into 32 bits
 __device__ __forceinline__ uint32_t pack4_e4m3_pow2(float a, float b, float c, float d, int e)
