@@ -145,3 +145,33 @@ def test_nan_rows_zero_rows_and_signed_zero_thresholds(ref, dev, precision):
     rows = [i for i in range(n) if i != 4]
     clear = np.abs(emul[rows]) > np.abs(emul[rows]).max(axis=1, keepdims=True) * 1e-3
     assert (bits[rows] == (emul[rows] > 0))[clear].all()
+
+
+@pytest.mark.parametrize("margin", [0.0, 1e-3])
+def test_fp8_extreme_row_scales(ref, dev, margin):
+    """FP8 rows of B (and their thresholds) scaled by 2^-70 and 2^40, so row
+    scales of one chunk differ by up to 2^110: bits match the emulation of
+    the same rounding wherever the response is clear of zero, and with a
+    margin the re-check decides the rest."""
+    rng = np.random.default_rng(70)
+    n = 333
+    f = rng.random((n, 128)).astype(np.float32)
+    f /= np.linalg.norm(f, axis=1, keepdims=True)
+    B = rng.normal(0.0, 1.0 / np.sqrt(128.0), (512, 128)).astype(np.float32)
+    t = rng.normal(0.0, 0.01, 512).astype(np.float32)
+    B[5:9] *= np.float32(2.0 ** -70)
+    t[5:9] *= np.float32(2.0 ** -70)
+    B[300:303] *= np.float32(2.0 ** 40)
+    t[300:303] *= np.float32(2.0 ** 40)
+    codes, resp = bd.hashsift_project(torch.from_numpy(f).to(dev), torch.from_numpy(B).to(dev),
+                                      torch.from_numpy(t).to(dev), precision="fp8", with_resp=True, margin=margin)
+    bits = unpack(to_np(codes), 512)
+    emul = ref.project_lowp(f, B, t, "fp8")
+    scale = np.abs(emul).max(axis=0, keepdims=True)  # per bit: rows of B differ by 2^110
+    # the FP8 rounding moves a response by a few per cent of its bit's scale
+    clear = np.abs(emul) > 0.2 * scale
+    assert (bits == (emul > 0))[clear].all()
+    assert (np.abs(to_np(resp) - emul) / scale).max() <= 0.15
+    if margin == 0.0:
+        # without a re-check every bit is the sign of the emulated response, up to FP32 accumulation
+        assert (bits == (emul > 0))[np.abs(emul) > 1e-4 * scale].all()
