@@ -203,3 +203,22 @@ def test_hashsift_image_size_limits(ref, dev):
     kp = np.zeros(2, dtype=synth.KEYPOINT_DTYPE)
     kp[:] = [(1.0, 16777000.0, 2.0, 0.3), (1.5, 16777210.0, 1.0, 1.3)]
     compare(ref, dev, tall_ok, kp, B, t, "tall")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
+def test_empty_keypoint_set(dev, precision):
+    """No keypoints: every HashSIFT call succeeds with empty outputs and the
+    re-check counter is untouched."""
+    rng = np.random.default_rng(7)
+    img = torch.from_numpy((synth.grey_image(rng, 64, 48, n_rect=4) / 255.0).astype(np.float32)).to(dev)
+    B, t = (torch.from_numpy(a).to(dev) for a in synth.projection(rng, 512))
+    kps = torch.zeros((0, 4), dtype=torch.float32, device=dev)
+    count = torch.zeros((1,), dtype=torch.uint32, device=dev)
+    codes, hist, resp = bd.describe_hashsift(img, kps, B, t, precision=precision, with_hist=True,
+                                             with_resp=True, recheck_count=count)
+    assert codes.shape == (0, 8) and hist.shape == (0, 128) and resp.shape == (0, 512)
+    assert bd.hashsift_features(img, kps).shape == (0, 128)
+    hist0 = torch.zeros((0, 128), dtype=torch.float32, device=dev)
+    assert bd.hashsift_project(hist0, B, t, precision=precision, recheck_count=count).shape == (0, 8)
+    torch.cuda.synchronize()
+    assert int(count.item()) == 0
