@@ -213,8 +213,13 @@ def peak_of(bound):
     return {"hbm": HBM_PEAK_GBS, "alu": ALU_PEAK_TOPS, "mfma": FP32_MFMA_PEAK_TFLOPS}[bound]
 
 
+PER_VIEW_STAGES = ("keypoint_order", "integral", "bad_describe", "hashsift_features", "hashsift_project")
+
+
 def time_stages(wl, reps):
-    """Average duration of each stage's launches, with HIP events on the launch stream."""
+    """Per-launch duration of each stage, with HIP events on the launch stream:
+    (average over `reps` back-to-back repetitions, median and minimum of
+    `reps` repetitions timed one by one)."""
     import torch
 
     out = {}
@@ -228,12 +233,23 @@ def time_stages(wl, reps):
             fn()
         end.record(stream)
         end.synchronize()
-        ms = start.elapsed_time(end) / reps
         # two launches per rep for per-view stages
-        per_launch = ms / (2 if name in ("keypoint_order", "integral", "bad_describe", "hashsift_features",
-                                         "hashsift_project") else 1)
-        out[name] = per_launch
+        launches = 2 if name in PER_VIEW_STAGES else 1
+        avg = start.elapsed_time(end) / reps / launches
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for r in range(reps):
+            fn()
+            ev[r + 1].record(stream)
+        ev[-1].synchronize()
+        each = sorted(ev[r].elapsed_time(ev[r + 1]) / launches for r in range(reps))
+        out[name] = (avg, float(np.median(each)), each[0])
     return out
+
+
+def roof_ms(bound, units, peak):
+    """Time of `units` of work at `peak` (GB/s for hbm, T ops/s otherwise), in ms."""
+    return units / (peak * (1e9 if bound == "hbm" else 1e12)) * 1e3
 
 
 def graph_time(fn, reps=100, warmup=5):
@@ -712,6 +728,19 @@ def batched_step(dev, reps=5):
     total = b.total_kp
     pairs_n = float(sum(n_kp[q] * n_kp[tr] for q, tr in w.matches))
     b.close()
+    # each stage of the batch at the roof of its binding resource (the units of
+    # stage_work: HBM bytes, histogram lane-ops, MFMA operations)
+    px = float(sum(im.numel() for im in imgs))
+    edges = float(sum(im.shape[0] + im.shape[1] + 1 for im in imgs))
+    roof = {
+        "keypoint_order": roof_ms("hbm", 20.0 * total, HBM_PEAK_GBS),
+        "integral": roof_ms("hbm", 5.0 * px, HBM_PEAK_GBS),
+        "bad_describe": roof_ms("hbm", (16.0 + 512 / 8) * total + 4.0 * (px + edges), HBM_PEAK_GBS),
+        "hashsift_features": roof_ms("alu", (1156 * 14 + 1024 * 50) * float(total), ALU_PEAK_TOPS),
+        "hashsift_project": roof_ms("mfma", 2.0 * 256 * 128 * total, FP32_MFMA_PEAK_TFLOPS),
+        "match_bad512": roof_ms("mfma", 2.0 * 512 * pairs_n, INT8_MFMA_PEAK_TOPS),
+        "match_hashsift256": roof_ms("mfma", 2.0 * 256 * pairs_n, INT8_MFMA_PEAK_TOPS),
+    }
     return {
         "workload": f"{len(imgs)} u8 images (64 scenes + shifted noisy copies), {total} keypoints, "
                     f"{sum(im.numel() for im in imgs) / 1e6:.1f} Mpx, BAD-512 + HashSIFT-256, 2-NN per scene",
@@ -720,6 +749,9 @@ def batched_step(dev, reps=5):
         "hamming_pairs_per_s": round(2 * pairs_n / (ms_batch * 1e-3), 1),
         "ms_per_batch_single_image_calls": round(ms_plain, 3),
         "speedup_vs_single_image_calls": round(ms_plain / ms_batch, 3),
+        "roofline": {"roof_ms": round(sum(roof.values()), 4), "measured_ms": round(ms_batch, 3),
+                     "frac": round(sum(roof.values()) / ms_batch, 4),
+                     "roof_ms_by_stage": {k: round(v, 4) for k, v in roof.items()}},
         "bit_identical_to_single_image_calls": bool(same),
         "autotune_s": round(tune_s, 2),
         "tuning": tuning,
@@ -852,16 +884,25 @@ def main():
             graph.replay()
         torch.cuda.synchronize()
 
+    # five runs inside the timed region (events between groups of steps, no
+    # extra synchronization) for the mean +- std the paper reports
+    n_runs = 5 if args.steps >= 5 else 1
+    marks = [args.steps * r // n_runs for r in range(n_runs + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_runs + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for i in range(args.steps):
         if graph is not None:
             graph.replay()
         else:
             wl.step(args.only)
+        if i + 1 in marks:
+            ev[marks.index(i + 1)].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
+    run_ms = [ev[r].elapsed_time(ev[r + 1]) / (marks[r + 1] - marks[r]) for r in range(n_runs)]
 
     # the replayed graph must reproduce the eager results; also the sanity rate of
     # true matches (keypoint i of view 1 is keypoint i of view 2)
@@ -879,13 +920,16 @@ def main():
     stage_ms = time_stages(wl, args.stage_reps) if not args.only else {}
     work = stage_work()
     stages = {}
-    for name, ms in stage_ms.items():
+    step_roof = {}
+    for name, (ms, ms_med, ms_min) in stage_ms.items():
         bound, units, unit = work[name][:3]
         peak = work[name][3] if len(work[name]) > 3 else peak_of(bound)
         achieved = units / (ms * 1e-3) / 1e9 if bound == "hbm" else units / (ms * 1e-3) / 1e12
-        stages[name] = {"ms_per_launch": round(ms, 5), "bound": bound, "achieved": round(achieved, 2),
+        stages[name] = {"ms_per_launch": round(ms, 5), "ms_median": round(ms_med, 5), "ms_min": round(ms_min, 5),
+                        "bound": bound, "achieved": round(achieved, 2),
                         "unit": unit, "peak": peak, "frac": round(achieved / peak, 4),
                         "traffic_bytes_per_launch": pmc_traffic(name)}
+        step_roof[name] = roof_ms(bound, units, peak) * (2 if name in PER_VIEW_STAGES else 1)
         l1 = pmc_traffic(name, PMC_L1_ACCESSES)
         if l1 is not None:
             stages[name]["vector_l1_accesses_per_launch"] = l1
@@ -917,10 +961,18 @@ def main():
                                f"HashSIFT-512, Hamming 2-NN {N_KP}x{N_KP} per code type",
                    "graph": bool(graph is not None), "only": args.only or None},
         "hamming_pairs_per_s": round(2 * N_KP * N_KP / (ms_per_step * 1e-3), 1),
+        "ms_per_step_5_runs": {"mean": round(float(np.mean(run_ms)), 4), "std": round(float(np.std(run_ms)), 4),
+                               "steps_per_run": marks[1] - marks[0]},
         "stages": stages,
         "checks": check,
         "roofline": roofline,
     }
+    if step_roof:
+        # every launch of the step at the roof of its own binding resource, against the step time
+        total = sum(step_roof.values())
+        result["step_roofline"] = {"roof_ms": round(total, 5), "measured_ms": round(ms_per_step, 4),
+                                   "frac": round(total / ms_per_step, 4),
+                                   "roof_us_by_stage": {k: round(v * 1e3, 3) for k, v in step_roof.items()}}
     if not args.only and not args.step_only:
         result["describe_rates"] = describe_rates(wl)
         result["config0_bad256_640x480"] = config0_step(dev)
