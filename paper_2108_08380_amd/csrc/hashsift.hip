@@ -212,14 +212,19 @@ __device__ __forceinline__ int clampi(int v, int hi)
 __device__ __forceinline__ int64_t to_fixed(double v) { return (int64_t)rint(v * 4294967296.0); }
 
 typedef float float2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint16_t u16_a1 __attribute__((aligned(1)));
 
 // The four corner pixels and weights of the sample at fixed-point image
 // position (X, Y).  Row offsets use 24-bit multiplies: the host admits only
-// images with pitch < 2^24, H < 2^24 and pitch * H <= 2^32.  PAIR (float
-// images at least 2 pixels wide): each row's two pixels come from one 8-byte
-// load of the pair starting at the column clamped to [0, W - 2], the first
-// or second of it standing for both when the sample lies left of column 0 or
-// right of column W - 1 (clamp to edge), which halves the lane accesses.
+// images with pitch < 2^24, H < 2^24 and pitch * H <= 2^32, so a pixel's
+// byte offset is one 32-bit sum, which the loads take as a lane offset from
+// the image's scalar base (added to the pointer term by term, the offsets
+// would make 64-bit lane addresses).  PAIR (images at least 2 pixels wide):
+// each row's two pixels come from one load of the pair starting at the
+// column clamped to [0, W - 2] (8 bytes for float images, 2 for u8, at any
+// byte offset), which halves the lane accesses; left of column 0 or right of
+// column W - 1 (clamp to edge) the first or second pixel of the pair stands
+// for both (float) or the weight selects it (u8).
 template <int DT, bool PAIR>
 __device__ __forceinline__ void fetch_fixed(const uint8_t* __restrict__ img, int wm1, int hm1, uint32_t upitch,
                                             int64_t X, int64_t Y, float (&v)[4], float& fx, float& fy)
@@ -229,16 +234,30 @@ __device__ __forceinline__ void fetch_fixed(const uint8_t* __restrict__ img, int
     fy = (float)(uint32_t)Y * 0x1p-32f;
     const uint32_t ra = __umul24((uint32_t)clampi(yi, hm1), upitch);
     const uint32_t rb = __umul24((uint32_t)clampi(yi + 1, hm1), upitch);
-    if constexpr (PAIR) {
-        static_assert(DT == BD_DTYPE_F32, "pairs of float pixels");
+    if constexpr (PAIR && DT == BD_DTYPE_F32) {
         const uint32_t xo = 4u * (uint32_t)clampi(xi, wm1 - 1);
-        const float2_a4 pa = *reinterpret_cast<const float2_a4*>(img + ra + xo);
-        const float2_a4 pb = *reinterpret_cast<const float2_a4*>(img + rb + xo);
+        const float2_a4 pa = *reinterpret_cast<const float2_a4*>(img + (ra + xo));
+        const float2_a4 pb = *reinterpret_cast<const float2_a4*>(img + (rb + xo));
         const bool left = xi < 0, right = xi >= wm1;
         v[0] = right ? pa.y : pa.x;
         v[1] = left ? pa.x : pa.y;
         v[2] = right ? pb.y : pb.x;
         v[3] = left ? pb.x : pb.y;
+    } else if constexpr (PAIR) {
+        // u8: both bytes of the pair as they are, and the edge cases through
+        // the weight instead: left of column 0 the pair (0, 1) with weight 0,
+        // right of column W - 1 the pair (W - 2, W - 1) with weight 1.  The
+        // differences are small integers, so bilinear<u8> then forms exactly
+        // the value of the clamped corners (fma(1, b - a, a - base) = b - base)
+        static_assert(DT == BD_DTYPE_U8, "pairs of u8 or float pixels");
+        const uint32_t xo = (uint32_t)clampi(xi, wm1 - 1);
+        const uint32_t pa = *reinterpret_cast<const u16_a1*>(img + (ra + xo));  // byte 0: column xo
+        const uint32_t pb = *reinterpret_cast<const u16_a1*>(img + (rb + xo));
+        fx = xi < 0 ? 0.0f : xi >= wm1 ? 1.0f : fx;
+        v[0] = (float)(pa & 0xffu);
+        v[1] = (float)(pa >> 8);
+        v[2] = (float)(pb & 0xffu);
+        v[3] = (float)(pb >> 8);
     } else {
         const int xa = clampi(xi, wm1), xb = clampi(xi + 1, wm1);
         v[0] = pixel_at<DT>(img, ra, xa);
@@ -388,8 +407,8 @@ __device__ __forceinline__ void hist_one(const uint8_t* __restrict__ img, int32_
     // rotated and scaled by (sa, sb).
     if (fabs((double)kp.x) + 24.0 * kp.scale < 1073741824.0 && fabs((double)kp.y) + 24.0 * kp.scale < 1073741824.0)
     {
-        if (DT == BD_DTYPE_F32 && W >= 2)
-            resample_fixed<DT, R, DT == BD_DTYPE_F32>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
+        if (W >= 2)
+            resample_fixed<DT, R, true>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
         else
             resample_fixed<DT, R, false>(img, W, H, (uint32_t)pitch, kx, ky, sa, sb, base, P, lane);
     }
@@ -503,12 +522,12 @@ __global__ __launch_bounds__(256) void hashsift_hist_kernel(const uint8_t* __res
 // Batch: units are blocks of four keypoints of every image in turn (pre is
 // the prefix of ceil(n_kp / 4)); order entries are image-local; features are
 // written to the flat array at the keypoint's global index.  DT is the
-// dtype of every image's HashSIFT source, or kMixedDtypes.  The u8 form runs
-// at 5 waves per SIMD, as LDS allows; the others need more registers (4).
+// dtype of every image's HashSIFT source, or kMixedDtypes.  Four waves per
+// SIMD: LDS would allow five, but the 96 registers of five spill.
 constexpr int kMixedDtypes = -1;
 
 template <int DT>
-__global__ __launch_bounds__(256, DT == BD_DTYPE_U8 ? 5 : 4) void hashsift_hist_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
+__global__ __launch_bounds__(256, 4) void hashsift_hist_batch(const BatchImage* __restrict__ imgs, int32_t n_img,
                                                               const int32_t* __restrict__ pre,
                                                               const bd_keypoint* __restrict__ kps,
                                                               const int32_t* __restrict__ order,

@@ -113,13 +113,17 @@ def test_image_corners_clamp_to_edge(ref, dev):
     compare(ref, dev, img, kps, B, t, "corners")
 
 
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
 @pytest.mark.parametrize("width", [1, 2, 3])
-def test_narrow_float_images(ref, dev, width):
-    """Float images 1, 2 and 3 pixels wide: the sampler reads each row's two
-    pixels as one pair clamped to columns [0, W - 2] (width 1 reads them one
-    by one); samples left, right and inside the columns clamp like the oracle."""
+def test_narrow_images(ref, dev, width, dtype):
+    """Float and u8 images 1, 2 and 3 pixels wide: the sampler reads each
+    row's two pixels as one pair clamped to columns [0, W - 2] (width 1 reads
+    them one by one); samples left, right and inside the columns clamp like
+    the oracle."""
     rng = np.random.default_rng(20 + width)
     img = rng.random((9, width)).astype(np.float32)
+    if dtype == "u8":
+        img = rng.integers(0, 256, (9, width), dtype=np.uint8)
     kps = np.zeros(4, dtype=synth.KEYPOINT_DTYPE)
     kps[:] = [(0, 0, 1, 0), (width - 1, 8, 0.5, 1.0), (0.5, 4, 2.0, 2.0), (width + 3.0, -2, 1.0, 3.0)]
     B, t = synth.projection(rng, 256)
