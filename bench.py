@@ -169,8 +169,8 @@ PMC_TRAFFIC = {
     "keypoint_order": ("order.hip", "b9c2afd100b6dde1", 44 * 2048 + 20 * 1024),
     "integral": ("integral.hip", "64d461e94933cbb9", (366 + 1057 + 1387) * 2048 + (580 + 616 + 8158) * 1024),
     "bad_describe": ("bad.hip", "ad09d5e017d700e6", 9075 * 2048 + 160 * 1024),
-    "hashsift_features": ("hashsift.hip", "66e96bfc7a1306c9", 9278 * 2048 + 2500 * 1024),
-    "hashsift_project": ("hashsift.hip", "66e96bfc7a1306c9", 2367 * 2048 + 312 * 1024),
+    "hashsift_features": ("hashsift.hip", "49cbd2d03e6da357", 9264 * 2048 + 2500 * 1024),
+    "hashsift_project": ("hashsift.hip", "49cbd2d03e6da357", 2367 * 2048 + 312 * 1024),
     "match_bad256": ("hamming.hip", "b45b06214a9c6ad9", (882 + 300) * 2048 + (469 + 78) * 1024),
     "match_hashsift512": ("hamming.hip", "b45b06214a9c6ad9", (1684 + 300) * 2048 + (469 + 78) * 1024),
 }
@@ -184,7 +184,7 @@ PMC_TRAFFIC = {
 # accesses / (duration x 256 CUs x 2.4 GHz) is the kernel's fraction of that
 # rate.
 PMC_L1_ACCESSES = {
-    "hashsift_features": ("hashsift.hip", "66e96bfc7a1306c9", 11332771),
+    "hashsift_features": ("hashsift.hip", "49cbd2d03e6da357", 11332771),
     "bad_describe": ("bad.hip", "ad09d5e017d700e6", 10092917),
 }
 L1_ACCESS_PEAK_PER_S = 256 * 2.4e9
@@ -860,7 +860,10 @@ def main():
     wl = Workload(dev)
     torch.cuda.synchronize()
 
-    # warm-up (allocates the library workspace before any graph capture)
+    # one full step first, so that a single stage run with --only reads the
+    # keypoint orders, integral images and features it depends on; then the
+    # warm-up (it also allocates the library workspace before any graph capture)
+    wl.step()
     for _ in range(max(1, args.warmup)):
         wl.step(args.only)
     torch.cuda.synchronize()
