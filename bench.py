@@ -102,8 +102,7 @@ class Workload:
         import paper_2108_08380_amd as bd
 
         s = self
-        bd.keypoint_order(s.kps[v], W, H, out=s.order[v])
-        bd.build_integral(s.u8[v], out=s.ii[v])
+        bd.build_integral_order(s.u8[v], s.kps[v], out=s.ii[v], order=s.order[v])
         bd.describe_bad(s.ii[v], s.kps[v], out=s.bad[v], order=s.order[v], table=s.table)
         bd.hashsift_features(s.f32[v], s.kps[v], out=s.hist[v], order=s.order[v])
         bd.hashsift_project(s.hist[v], s.B, s.t, s.kps[v], out=s.hs[v])
@@ -304,6 +303,9 @@ def describe_rates(wl, reps=200):
     def order(v):
         bd.keypoint_order(wl.kps[v], W, H, out=wl.order[v])
 
+    def integral_order(v):
+        bd.build_integral_order(wl.u8[v], wl.kps[v], out=wl.ii[v], order=wl.order[v])
+
     def bad(v):
         bd.describe_bad(wl.ii[v], wl.kps[v], out=wl.bad[v], order=wl.order[v], table=wl.table)
 
@@ -313,9 +315,9 @@ def describe_rates(wl, reps=200):
 
     variants = {
         "describe_only": lambda v: (order(v), bad(v), hs(v)),
-        "integral_plus_describe": lambda v: (order(v), bd.build_integral(wl.u8[v], out=wl.ii[v]), bad(v), hs(v)),
+        "integral_plus_describe": lambda v: (integral_order(v), bad(v), hs(v)),
         "bad256_only": lambda v: (order(v), bad(v)),
-        "integral_plus_bad256": lambda v: (order(v), bd.build_integral(wl.u8[v], out=wl.ii[v]), bad(v)),
+        "integral_plus_bad256": lambda v: (integral_order(v), bad(v)),
         "hashsift512_only": lambda v: (order(v), hs(v)),
     }
     out = {}
@@ -351,9 +353,10 @@ def config0_step(dev, reps=200):
     side = torch.cuda.Stream()
 
     def view(v, integral=True):
-        bd.keypoint_order(kps[v], Wc, Hc, out=order[v])
         if integral:
-            bd.build_integral(imgs[v], out=ii[v])
+            bd.build_integral_order(imgs[v], kps[v], out=ii[v], order=order[v])
+        else:
+            bd.keypoint_order(kps[v], Wc, Hc, out=order[v])
         bd.describe_bad(ii[v], kps[v], out=codes[v], order=order[v], table=table)
 
     def run(integral=True, match=True):

@@ -119,6 +119,21 @@ int bd_keypoint_order(bd_context* ctx, const bd_keypoint* kps, int32_t n_kp, int
                       int32_t* order, void* stream);
 
 /*
+ * bd_build_integral and bd_keypoint_order of one view in one call: the
+ * integral image of img and the processing order of kps over the same
+ * W x H image, with the sort running in one extra workgroup of the integral
+ * image's first pass instead of in a launch of its own (the two results
+ * share nothing, so a chain integral -> describe waits for one launch
+ * fewer).  Arguments, layouts and errors as in the two calls; ii is written
+ * exactly as bd_build_integral writes it and order is a permutation with
+ * the same cell grouping as bd_keypoint_order's (keypoints within a cell
+ * in no fixed order).  n_kp = 0 builds the integral image only.
+ */
+int bd_build_integral_order(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch,
+                            uint32_t* ii, int64_t ii_pitch, const bd_keypoint* kps, int32_t n_kp,
+                            int32_t* order, void* stream);
+
+/*
  * BAD codes (Sec. III-A: weak descriptor h(x; f, theta) = +1 when
  * f(x; u1, u2, s) <= theta, f the difference of the mean grey levels of two
  * boxes of side s; the bits of h(x) = [h_1 .. h_K]).

@@ -49,6 +49,7 @@ SIGNATURES = {
     "bd_bad_table_destroy": ([_P], ctypes.c_int),
     "bd_describe_bad_table": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "bd_keypoint_order": ([_P, _P, _I32, _I32, _I32, _P, _P], ctypes.c_int),
+    "bd_build_integral_order": ([_P, _P, _I32, _I32, _I64, _P, _I64, _P, _I32, _P, _P], ctypes.c_int),
     "bd_describe_bad": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _P, _I32, _P, _P], ctypes.c_int),
     "bd_describe_hashsift": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P, _I32, _I32, ctypes.c_float,
                               _P, _P, _P, _P, _P], ctypes.c_int),
@@ -272,6 +273,27 @@ def keypoint_order(kps, width: int, height: int, out=None):
     dev, stream = _device_and_stream(kps, out)
     _check(lib().bd_keypoint_order(context(dev, stream), kps.data_ptr(), n, width, height, out.data_ptr(), stream))
     return out
+
+
+def build_integral_order(img, kps, out=None, order=None):
+    """Integral image and keypoint order of one view in one call
+    (bd_build_integral_order) -> (ii, order), as build_integral and
+    keypoint_order would return them."""
+    torch = _torch()
+    _require(img, torch.uint8, 2, "img")
+    _require(kps, torch.float32, 2, "kps")
+    _contig(kps, "kps")
+    H, W = img.shape
+    n = kps.shape[0]
+    if out is None:
+        out = integral_buffer(H, W, img.device)
+    _require(out, torch.uint32, 2, "out")
+    if order is None:
+        order = torch.empty((n,), dtype=torch.int32, device=img.device)
+    dev, stream = _device_and_stream(img, kps, out, order)
+    _check(lib().bd_build_integral_order(context(dev, stream), img.data_ptr(), W, H, img.stride(0), out.data_ptr(),
+                                         out.stride(0), kps.data_ptr(), n, _order_arg(order, n), stream))
+    return out, order
 
 
 def describe_bad(ii, kps, pairs=None, n_bits: int | None = None, out=None, order=None, table=None):

@@ -114,6 +114,11 @@ struct IntegralPlan {
 IntegralPlan plan_integral(int32_t W, int32_t H);
 void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
                      int64_t ii_pitch, void* workspace, hipStream_t stream);
+// launch_integral with the keypoint order of the same view computed in one
+// block of the first pass (order as launch_keypoint_order writes it).
+void launch_integral_order(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
+                           int64_t ii_pitch, void* workspace, const bd_keypoint* kps, int32_t n_kp,
+                           int32_t* order, hipStream_t stream);
 int integral_tile_blocks(const IntegralPlan& p);   // units of the tile passes
 int integral_carry_blocks(const IntegralPlan& p);  // units of the carry pass
 void launch_integral_batch(const BatchImage* imgs, int32_t n_img, const int32_t* tile_pre, const int32_t* carry_pre,

@@ -225,6 +225,31 @@ int bd_build_integral(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H,
     return check_launch(fn);
 }
 
+int bd_build_integral_order(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch,
+                            uint32_t* ii, int64_t ii_pitch, const bd_keypoint* kps, int32_t n_kp, int32_t* order,
+                            void* stream)
+{
+    const char* fn = "bd_build_integral_order";
+    if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
+    if (img_pitch < W) return fail(BD_EINVAL, "%s: img_pitch %lld < W %d", fn, (long long)img_pitch, W);
+    if (ii_pitch < (int64_t)W + 1) return fail(BD_EINVAL, "%s: ii_pitch %lld < W+1", fn, (long long)ii_pitch);
+    if (((int64_t)H + 1) * ii_pitch >= (int64_t)1 << 31)
+        return fail(BD_EINVAL, "%s: integral image of %lld elements exceeds 2^31", fn, (long long)(((int64_t)H + 1) * ii_pitch));
+    if (!img || !ii) return fail(BD_EINVAL, "%s: null image or output pointer", fn);
+    if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
+    if (n_kp > 0 && (!kps || !order)) return fail(BD_EINVAL, "%s: null keypoint or order pointer", fn);
+    if (int rc = check_ctx(ctx, fn)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const IntegralPlan plan = plan_integral(W, H);
+    void* ws = nullptr;
+    if (int rc = reserve_workspace(ctx, plan.workspace_bytes(), s, &ws)) return rc;
+    if (n_kp == 0)
+        launch_integral(plan, img, img_pitch, ii, ii_pitch, ws, s);
+    else
+        launch_integral_order(plan, img, img_pitch, ii, ii_pitch, ws, kps, n_kp, order, s);
+    return check_launch(fn);
+}
+
 int bd_keypoint_order(bd_context* ctx, const bd_keypoint* kps, int32_t n_kp, int32_t W, int32_t H,
                       int32_t* order, void* stream)
 {

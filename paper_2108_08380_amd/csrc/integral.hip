@@ -17,7 +17,7 @@
 //      + sum_{y0<=y'<=y, x0<=x'<=x} I    (in-tile prefix)
 // All sums are u32 and wrap modulo 2^32 consistently.  HBM traffic is about
 // 2 bytes read and 4 written per pixel plus 0.5 byte of carries.
-#include "bd_internal.hpp"
+#include "order_body.hpp"
 
 namespace bd {
 namespace {
@@ -334,6 +334,28 @@ __global__ __launch_bounds__(256) void integral_tile_sums(const uint8_t* __restr
     tile_sums_body(img, pitch, W, H, slabs, col_pitch, aligned, colsum, rowsum, tile, threadIdx.x % kWave);
 }
 
+// The first pass with the keypoint order of the same view alongside
+// (bd_build_integral_order): block 0 sorts the keypoints, blocks 1.. take
+// four tiles each with their first four wavefronts, as integral_tile_sums.
+// The two jobs share no data; in one launch the sort runs beside the tile
+// sums instead of before them.
+__global__ __launch_bounds__(order_impl::kOrderThreads) void integral_tile_sums_order(
+    const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H, int32_t strips, int32_t slabs,
+    int64_t col_pitch, bool aligned, uint32_t* __restrict__ colsum, uint32_t* __restrict__ rowsum,
+    const bd_keypoint* __restrict__ kps, int32_t n_kp, float inv_cell, int32_t* __restrict__ order)
+{
+    __shared__ uint32_t bins[order_impl::kOrderBins];
+    __shared__ uint32_t part[order_impl::kOrderThreads];
+    if (blockIdx.x == 0) {
+        order_impl::order_body(kps, n_kp, inv_cell, order, bins, part);
+        return;
+    }
+    const int wave = threadIdx.x / kWave;
+    const int tile = ((int)blockIdx.x - 1) * kWavesPerBlock + wave;
+    if (wave >= kWavesPerBlock || tile >= strips * slabs) return;
+    tile_sums_body(img, pitch, W, H, slabs, col_pitch, aligned, colsum, rowsum, tile, threadIdx.x % kWave);
+}
+
 // Blocks [0, col_blocks): column scans; remaining blocks: row scans.
 __global__ __launch_bounds__(256) void integral_carry_scan(uint32_t* __restrict__ colsum,
                                                            uint32_t* __restrict__ rowsum, int32_t H,
@@ -432,6 +454,23 @@ IntegralPlan plan_integral(int32_t W, int32_t H)
     return p;
 }
 
+namespace {
+
+// The carry scans and the tile writes, after the tile sums.
+void launch_carry_and_write(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, bool aligned,
+                            uint32_t* colsum, uint32_t* rowsum, uint32_t* ii, int64_t ii_pitch, int tile_blocks,
+                            hipStream_t stream)
+{
+    const int col_blocks = (int)((p.col_pitch + 255) / 256);
+    const int row_blocks = (p.H + 255) / 256;
+    hipLaunchKernelGGL(integral_carry_scan, dim3(col_blocks + row_blocks), dim3(256), 0, stream, colsum,
+                       rowsum, p.H, p.strips, p.slabs, p.col_pitch, col_blocks);
+    hipLaunchKernelGGL(integral_tile_write, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W,
+                       p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, ii, ii_pitch);
+}
+
+}  // namespace
+
 void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
                      int64_t ii_pitch, void* workspace, hipStream_t stream)
 {
@@ -442,12 +481,22 @@ void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitc
     const int tile_blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     hipLaunchKernelGGL(integral_tile_sums, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W,
                        p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum);
-    const int col_blocks = (int)((p.col_pitch + 255) / 256);
-    const int row_blocks = (p.H + 255) / 256;
-    hipLaunchKernelGGL(integral_carry_scan, dim3(col_blocks + row_blocks), dim3(256), 0, stream, colsum,
-                       rowsum, p.H, p.strips, p.slabs, p.col_pitch, col_blocks);
-    hipLaunchKernelGGL(integral_tile_write, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W,
-                       p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, ii, ii_pitch);
+    launch_carry_and_write(p, img, img_pitch, aligned, colsum, rowsum, ii, ii_pitch, tile_blocks, stream);
+}
+
+void launch_integral_order(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
+                           int64_t ii_pitch, void* workspace, const bd_keypoint* kps, int32_t n_kp,
+                           int32_t* order, hipStream_t stream)
+{
+    uint32_t* colsum = static_cast<uint32_t*>(workspace);
+    uint32_t* rowsum = colsum + (size_t)p.strips * (size_t)p.col_pitch;
+    const bool aligned = (img_pitch % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 4 == 0);
+    const int tiles = p.strips * p.slabs;
+    const int tile_blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(integral_tile_sums_order, dim3(tile_blocks + 1), dim3(order_impl::kOrderThreads), 0, stream,
+                       img, img_pitch, p.W, p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, kps,
+                       n_kp, order_inv_cell(p.W, p.H), order);
+    launch_carry_and_write(p, img, img_pitch, aligned, colsum, rowsum, ii, ii_pitch, tile_blocks, stream);
 }
 
 int integral_tile_blocks(const IntegralPlan& p) { return (p.strips * p.slabs + kWavesPerBlock - 1) / kWavesPerBlock; }

@@ -52,6 +52,10 @@ int main(void)
     EXPECT(bd_build_integral(NULL, NULL, 8, 5, 8, p, 9, NULL), BD_EINVAL);
     EXPECT(bd_build_integral(NULL, p, 8, 5, 8, p, 9, NULL), BD_EINVAL);
 
+    EXPECT(bd_build_integral_order(NULL, p, 0, 5, 5, p, 6, p, 3, p, NULL), BD_EINVAL);
+    EXPECT(bd_build_integral_order(NULL, p, 8, 5, 8, p, 9, p, -1, p, NULL), BD_EINVAL);
+    EXPECT(bd_build_integral_order(NULL, p, 8, 5, 8, p, 9, NULL, 3, p, NULL), BD_EINVAL);
+    EXPECT(bd_build_integral_order(NULL, p, 8, 5, 8, p, 9, NULL, 0, NULL, NULL), BD_EINVAL);
     EXPECT(bd_keypoint_order(NULL, p, 5, 0, 10, p, NULL), BD_EINVAL);
     EXPECT(bd_keypoint_order(NULL, p, -1, 10, 10, p, NULL), BD_EINVAL);
     EXPECT(bd_keypoint_order(NULL, NULL, 5, 10, 10, p, NULL), BD_EINVAL);

@@ -84,6 +84,25 @@ def test_build_integral_validation(L):
     assert "null context" in err(L)
 
 
+def test_build_integral_order_validation(L):
+    p = ctypes.c_void_p(16)
+    assert L.bd_build_integral_order(None, p, 0, 5, 5, p, 6, p, 3, p, None) == bd.BD_EINVAL
+    assert "at least 1x1" in err(L)
+    assert L.bd_build_integral_order(None, p, 8, 5, 7, p, 9, p, 3, p, None) == bd.BD_EINVAL
+    assert "img_pitch" in err(L)
+    assert L.bd_build_integral_order(None, p, 8, 5, 8, p, 8, p, 3, p, None) == bd.BD_EINVAL
+    assert "ii_pitch" in err(L)
+    assert L.bd_build_integral_order(None, p, 40000, 60000, 40000, p, 40001, p, 3, p, None) == bd.BD_EINVAL
+    assert "2^31" in err(L)
+    assert L.bd_build_integral_order(None, p, 8, 5, 8, p, 9, p, -1, p, None) == bd.BD_EINVAL
+    assert "n_kp" in err(L)
+    assert L.bd_build_integral_order(None, p, 8, 5, 8, p, 9, None, 3, p, None) == bd.BD_EINVAL
+    assert "null keypoint" in err(L)
+    assert L.bd_build_integral_order(None, p, 8, 5, 8, p, 9, p, 3, None, None) == bd.BD_EINVAL
+    assert L.bd_build_integral_order(None, p, 8, 5, 8, p, 9, None, 0, None, None) == bd.BD_EINVAL
+    assert "null context" in err(L)
+
+
 def test_describe_bad_validation(L):
     p = ctypes.c_void_p(16)
     assert L.bd_describe_bad(None, p, 10, 10, 11, p, 4, None, p, 128, p, None) == bd.BD_EUNSUPPORTED

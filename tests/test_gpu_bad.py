@@ -119,6 +119,45 @@ def test_keypoint_order_groups_cells(dev):
     assert step(xy[order]) < 0.2 * step(xy)
 
 
+def _cell_keys(kps, W, H):
+    """Morton cell key of each keypoint in the 64 x 64 grid of the order, in
+    float32 as the device forms it (cell side ceil(max(W, H) / 64))."""
+    inv = np.float32(1.0) / np.float32(max((max(W, H) + 63) // 64, 1))
+
+    def cell(v):
+        f = v.astype(np.float32) * inv
+        return np.where(f >= 64, 63, np.where(f >= 0, np.floor(f), 0)).astype(np.uint32)
+
+    def spread(v):
+        out = np.zeros_like(v)
+        for b in range(6):
+            out |= ((v >> b) & 1) << (2 * b)
+        return out
+
+    return spread(cell(kps["x"])) | (spread(cell(kps["y"])) << 1)
+
+
+@pytest.mark.parametrize("W,H,n", [(1920, 1080, 5000), (640, 480, 1000), (37, 29, 40), (4000, 3000, 20000),
+                                   (300, 200, 1), (300, 200, 0)])
+def test_integral_and_order_in_one_call(dev, W, H, n):
+    """bd_build_integral_order: the integral image equals bd_build_integral's
+    bit for bit, and the order is a permutation whose cell keys never
+    decrease, like bd_keypoint_order's (more than 8192 keypoints take the
+    sort's second loop)."""
+    rng = np.random.default_rng(W + n)
+    img = torch.from_numpy(synth.quantize_u8(synth.grey_image(rng, W, H, n_rect=20))).to(dev)
+    kps_np = synth.keypoints(rng, n, W, H, border=0.0)
+    kps = bd.keypoints_tensor(kps_np, dev)
+    ii, order = bd.build_integral_order(img, kps)
+    np.testing.assert_array_equal(to_np(ii), to_np(bd.build_integral(img)))
+    o_fused, o_sep = to_np(order), to_np(bd.keypoint_order(kps, W, H))
+    keys = _cell_keys(kps_np, W, H)
+    for o in (o_fused, o_sep):
+        np.testing.assert_array_equal(np.sort(o), np.arange(n))
+        assert (np.diff(keys[o].astype(np.int64)) >= 0).all()
+    np.testing.assert_array_equal(keys[o_fused], keys[o_sep])
+
+
 def test_ordered_describe_equals_unordered(ref, dev):
     w = synth.hashsift512_pair(n_kp=3000, n_bits=512, with_bad_bits=512)
     img = torch.from_numpy(w.extra["image1_u8"]).to(dev)
