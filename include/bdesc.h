@@ -152,15 +152,16 @@ int bd_describe_bad(bd_context* ctx, const uint32_t* ii, int32_t W, int32_t H, i
                     const bd_keypoint* kps, int32_t n_kp, const int32_t* order,
                     const bd_box_pair* pairs, int32_t n_bits, uint64_t* codes, void* stream);
 
-/* Compiled BAD table: the distinct boxes of the pairs sorted by the Morton
- * code of their centre offsets, each pair referring to its two boxes.
- * bd_describe_bad_table then sums each keypoint's boxes in that order (so
- * a load instruction's 64 corner gathers fall on fewer cache lines) and
- * forms the bits from those sums; the codes are identical to
- * bd_describe_bad's.  Create enqueues the compilation on `stream` (use the
- * table on that stream, or after synchronizing it); the table holds its
- * own device memory until destroyed (destroy synchronizes the device).
- * n_bits 256 or 512. */
+/* Compiled BAD table: the distinct boxes of the pairs, each pair referring
+ * to its two boxes, and for each of 32 bins of the keypoint angle an order
+ * of all box corners sorted by their image position at the bin's central
+ * angle.  bd_describe_bad_table gathers a keypoint's corners in its bin's
+ * order (so the lanes of a load instruction and the next loads fall on few
+ * cache lines), forms the box sums and the bits from them; the codes are
+ * identical to bd_describe_bad's.  Create enqueues the compilation on
+ * `stream` (use the table on that stream, or after synchronizing it); the
+ * table holds its own device memory (16 + 16 n_bits + 512 n_bits bytes)
+ * until destroyed (destroy synchronizes the device).  n_bits 256 or 512. */
 typedef struct bd_bad_table bd_bad_table;
 int bd_bad_table_create(bd_context* ctx, const bd_box_pair* pairs, int32_t n_bits, bd_bad_table** out, void* stream);
 int bd_bad_table_destroy(bd_bad_table* table);
