@@ -161,13 +161,13 @@ def stage_work():
 #   bench.py --step-only --steps 2 --warmup 1 --stage-reps 2 --graph 0
 # scaled by the same counters on a plain 256 MiB device copy (FETCH_SIZE
 # reads half the copied bytes: x2 KiB -> 2048 bytes; WRITE_SIZE exact:
-# 1024 bytes per KiB).  A value
-# is reported only while the stage's source file still has the recorded
-# SHA-256 prefix: any change to the kernels invalidates the counters.
+# 1024 bytes per KiB).  A value is reported only while the stage's source
+# files still have the recorded SHA-256 prefix (of their concatenation): any
+# change to the kernels invalidates the counters.
 PMC_TRAFFIC = {
-    "keypoint_order": ("order.hip", "b9c2afd100b6dde1", 44 * 2048 + 20 * 1024),
-    "integral": ("integral.hip", "64d461e94933cbb9", (366 + 1057 + 1387) * 2048 + (580 + 616 + 8158) * 1024),
-    "bad_describe": ("bad.hip", "ad09d5e017d700e6", 9075 * 2048 + 160 * 1024),
+    "keypoint_order": (("order.hip", "order_body.hpp"), "b6dbfa27dc112f78", 44 * 2048 + 20 * 1024),
+    "integral": ("integral.hip", "a626f04ab56ad8c7", (371 + 1061 + 1390) * 2048 + (580 + 616 + 8158) * 1024),
+    "bad_describe": ("bad.hip", "73b96b61b0287a2a", 9644 * 2048 + 161 * 1024),
     "hashsift_features": ("hashsift.hip", "49cbd2d03e6da357", 9264 * 2048 + 2500 * 1024),
     "hashsift_project": ("hashsift.hip", "49cbd2d03e6da357", 2367 * 2048 + 312 * 1024),
     "match_bad256": ("hamming.hip", "b45b06214a9c6ad9", (882 + 300) * 2048 + (469 + 78) * 1024),
@@ -184,7 +184,7 @@ PMC_TRAFFIC = {
 # rate.
 PMC_L1_ACCESSES = {
     "hashsift_features": ("hashsift.hip", "49cbd2d03e6da357", 11332771),
-    "bad_describe": ("bad.hip", "ad09d5e017d700e6", 10092917),
+    "bad_describe": ("bad.hip", "73b96b61b0287a2a", 10315006),
 }
 L1_ACCESS_PEAK_PER_S = 256 * 2.4e9
 
@@ -197,12 +197,14 @@ def pmc_traffic(stage, table=None):
     entry = (PMC_TRAFFIC if table is None else table).get(stage)
     if entry is None:
         return None
-    fname, digest, nbytes = entry
-    path = os.path.join(ROOT, "paper_2108_08380_amd", "csrc", fname)
+    fnames, digest, nbytes = entry
+    if isinstance(fnames, str):
+        fnames = (fnames,)
     try:
-        cur = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+        data = b"".join(open(os.path.join(ROOT, "paper_2108_08380_amd", "csrc", f), "rb").read() for f in fnames)
     except OSError:
         return None
+    cur = hashlib.sha256(data).hexdigest()[:16]
     return nbytes if cur == digest else None
 
 
