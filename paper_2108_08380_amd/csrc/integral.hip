@@ -10,6 +10,11 @@
 //   3. tile_write  re-reads the u8 tile, forms the in-tile 2-D prefix with
 //                  an in-lane prefix plus a wavefront scan per row and adds
 //                  the three carries.
+// Single images of up to kMaxRawGroups groups of four strips (2048 rows)
+// skip pass 2: pass 1 (group_sums) also writes the totals of each group of
+// strips, and the write pass sums its carries from the unscanned tables
+// (at most groups + 3 column-table rows, the row totals of the slabs to the
+// left), one dependent launch fewer.  The batch keeps the three passes.
 // For output entry (y+1, x+1) with (y, x) in tile (s, c) at origin (y0, x0):
 //   ii = sum_{x'<x0, y'<y0} I           (corner: 2-D prefix of tile totals)
 //      + sum_{x0<=x'<=x} colcarry[x']    (pixels above the strip)
@@ -149,18 +154,19 @@ __device__ __forceinline__ uint32_t wave_sum16(const uint32_t (&rs)[16], int lan
 
 // ---- bodies shared by the single-image and the batched kernels
 
-// One wavefront: the sums of tile `tile`.
+// One wavefront: the sums of tile `tile` (its column totals and tile total
+// are also left in col / tile_total).
 __device__ __forceinline__ void tile_sums_body(const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H,
                                                int32_t slabs, int64_t col_pitch, bool aligned,
                                                uint32_t* __restrict__ colsum, uint32_t* __restrict__ rowsum,
-                                               int tile, int lane)
+                                               int tile, int lane, uint32_t (&col)[4], uint32_t& tile_total)
 {
     const int s = tile / slabs, c = tile % slabs;
     const int y0 = s * kTileRows, x = c * kTileCols + 4 * lane;
     const int rows = min(kTileRows, H - y0);
     uint32_t q[kTileRows];
     load_tile(img, pitch, W, y0, rows, c * kTileCols, x, aligned, q);
-    uint32_t col[4] = {0u, 0u, 0u, 0u};
+    col[0] = col[1] = col[2] = col[3] = 0u;
     uint32_t rs[kTileRows];
 #pragma unroll
     for (int r = 0; r < kTileRows; ++r) {
@@ -169,11 +175,20 @@ __device__ __forceinline__ void tile_sums_body(const uint8_t* __restrict__ img, 
         rs[r] = quad_sum(q[r]);
     }
     const uint32_t row_total = wave_sum16(rs, lane);  // row lane >> 2 of the tile
-    const uint32_t tile_total = wave_sum((lane & 3) == 0 ? row_total : 0u);
+    tile_total = wave_sum((lane & 3) == 0 ? row_total : 0u);
     if ((lane & 3) == 0 && (lane >> 2) < rows) rowsum[(int64_t)(y0 + (lane >> 2)) * slabs + c] = row_total;
     uint32_t* dst = colsum + (int64_t)s * col_pitch + x;
     *reinterpret_cast<uint4*>(dst) = make_uint4(col[0], col[1], col[2], col[3]);
     if (lane == 0) colsum[(int64_t)s * col_pitch + (int64_t)slabs * kTileCols + c] = tile_total;
+}
+
+__device__ __forceinline__ void tile_sums_body(const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H,
+                                               int32_t slabs, int64_t col_pitch, bool aligned,
+                                               uint32_t* __restrict__ colsum, uint32_t* __restrict__ rowsum,
+                                               int tile, int lane)
+{
+    uint32_t col[4], total;
+    tile_sums_body(img, pitch, W, H, slabs, col_pitch, aligned, colsum, rowsum, tile, lane, col, total);
 }
 
 // One thread: exclusive scan down the strips of column x of the column table.
@@ -225,12 +240,94 @@ __device__ __forceinline__ void carry_row_body(uint32_t* __restrict__ rowsum, in
     }
 }
 
-// One wavefront: the integral-image entries of tile `tile`.
+// Carries of a tile from the exclusive scans of the carry pass: the row
+// totals of the slabs to the left, the column totals of the strips above
+// and, summed over the slabs to the left, the tile totals above.
+struct ScannedCarries {
+    const uint32_t* __restrict__ colcarry;
+    const uint32_t* __restrict__ rowcarry;
+
+    __device__ __forceinline__ void load(int s, int c, int slabs, int64_t col_pitch, int y0, int rows, int x,
+                                         int lane, uint32_t (&rc)[kTileRows], uint4& cv,
+                                         uint32_t& corner_part) const
+    {
+        if (rows == kTileRows) {
+#pragma unroll
+            for (int r = 0; r < kTileRows; ++r) rc[r] = rowcarry[(int64_t)(y0 + r) * slabs + c];
+        } else {
+#pragma unroll
+            for (int r = 0; r < kTileRows; ++r) rc[r] = r < rows ? rowcarry[(int64_t)(y0 + r) * slabs + c] : 0u;
+        }
+        const uint32_t* strip_row = colcarry + (int64_t)s * col_pitch;
+        cv = *reinterpret_cast<const uint4*>(strip_row + x);
+        corner_part = 0u;
+        for (int cc = lane; cc < c; cc += kWave) corner_part += strip_row[(int64_t)slabs * kTileCols + cc];
+    }
+};
+
+// Carries of a tile summed directly from the unscanned tables: the column
+// totals of each strip (colsum), of each group of kGroupStrips strips
+// (group) and the row totals of each slab (rowsum).  The strips above a tile
+// are the whole groups above its own plus the strips of its group above it.
+constexpr int kGroupStrips = 4;
+
+struct RawCarries {
+    const uint32_t* __restrict__ colsum;
+    const uint32_t* __restrict__ rowsum;
+    const uint32_t* __restrict__ group;
+
+    __device__ __forceinline__ void load(int s, int c, int slabs, int64_t col_pitch, int y0, int rows, int x,
+                                         int lane, uint32_t (&rc)[kTileRows], uint4& cv,
+                                         uint32_t& corner_part) const
+    {
+        const int kg = s / kGroupStrips, s_first = kg * kGroupStrips;
+        const int n_col = kg + (s - s_first);  // column-total rows to add
+        // pixels above the strip in this lane's four columns, 16 rows of a table in flight at a time
+        uint32_t a0 = 0u, a1 = 0u, a2 = 0u, a3 = 0u;
+        for (int k0 = 0; k0 < n_col; k0 += 16) {
+            uint4 v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int k = k0 + j;
+                const uint32_t* row = k < kg ? group + (int64_t)k * col_pitch
+                                             : colsum + (int64_t)(s_first + (k - kg)) * col_pitch;
+                v[j] = k < n_col ? *reinterpret_cast<const uint4*>(row + x) : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                a0 += v[j].x;
+                a1 += v[j].y;
+                a2 += v[j].z;
+                a3 += v[j].w;
+            }
+        }
+        cv = make_uint4(a0, a1, a2, a3);
+        // tiles above-left: entry (k, cc), k < n_col, cc < c, of the tile-total columns
+        corner_part = 0u;
+        for (int e = lane; e < n_col * c; e += kWave) {
+            const int k = e / c, cc = e - k * c;
+            const uint32_t* row = k < kg ? group + (int64_t)k * col_pitch
+                                         : colsum + (int64_t)(s_first + (k - kg)) * col_pitch;
+            corner_part += row[(int64_t)slabs * kTileCols + cc];
+        }
+        // row r of the tile: lanes r, r + 16, r + 32, r + 48 add the slabs to the left
+        const int r = lane & 15;
+        uint32_t part = 0u;
+        if (r < rows)
+            for (int cc = lane >> 4; cc < c; cc += 4) part += rowsum[(int64_t)(y0 + r) * slabs + cc];
+        part += (uint32_t)__shfl_xor((int)part, 16, kWave);
+        part += (uint32_t)__shfl_xor((int)part, 32, kWave);
+#pragma unroll
+        for (int rr = 0; rr < kTileRows; ++rr) rc[rr] = (uint32_t)__builtin_amdgcn_readlane((int)part, rr);
+    }
+};
+
+// One wavefront: the integral-image entries of tile `tile`, with the
+// carries of `cr` (ScannedCarries or RawCarries).
+template <class Carries>
 __device__ __forceinline__ void tile_write_body(const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H,
-                                                int32_t slabs, int64_t col_pitch, bool aligned,
-                                                const uint32_t* __restrict__ colcarry,
-                                                const uint32_t* __restrict__ rowcarry, uint32_t* __restrict__ ii,
-                                                int64_t ii_pitch, int tile, int lane)
+                                                int32_t slabs, int64_t col_pitch, bool aligned, const Carries& cr,
+                                                uint32_t* __restrict__ ii, int64_t ii_pitch, int tile, int lane)
 {
     const int s = tile / slabs, c = tile % slabs;
     const int y0 = s * kTileRows, x0 = c * kTileCols, x = x0 + 4 * lane;
@@ -239,17 +336,9 @@ __device__ __forceinline__ void tile_write_body(const uint8_t* __restrict__ img,
     // every load of the tile is issued before any arithmetic
     uint32_t q[kTileRows], rc[kTileRows];
     load_tile(img, pitch, W, y0, rows, x0, x, aligned, q);
-    if (rows == kTileRows) {
-#pragma unroll
-        for (int r = 0; r < kTileRows; ++r) rc[r] = rowcarry[(int64_t)(y0 + r) * slabs + c];
-    } else {
-#pragma unroll
-        for (int r = 0; r < kTileRows; ++r) rc[r] = r < rows ? rowcarry[(int64_t)(y0 + r) * slabs + c] : 0u;
-    }
-    const uint32_t* strip_row = colcarry + (int64_t)s * col_pitch;
-    const uint4 cv = *reinterpret_cast<const uint4*>(strip_row + x);
-    uint32_t corner_part = 0u;
-    for (int cc = lane; cc < c; cc += kWave) corner_part += strip_row[(int64_t)slabs * kTileCols + cc];
+    uint4 cv;
+    uint32_t corner_part;
+    cr.load(s, c, slabs, col_pitch, y0, rows, x, lane, rc, cv, corner_part);
 
     // corner (tiles above-left) plus the pixels above the strip, summed along the slab
     const uint32_t corner = wave_sum(corner_part);
@@ -334,28 +423,6 @@ __global__ __launch_bounds__(256) void integral_tile_sums(const uint8_t* __restr
     tile_sums_body(img, pitch, W, H, slabs, col_pitch, aligned, colsum, rowsum, tile, threadIdx.x % kWave);
 }
 
-// The first pass with the keypoint order of the same view alongside
-// (bd_build_integral_order): block 0 sorts the keypoints, blocks 1.. take
-// four tiles each with their first four wavefronts, as integral_tile_sums.
-// The two jobs share no data; in one launch the sort runs beside the tile
-// sums instead of before them.
-__global__ __launch_bounds__(order_impl::kOrderThreads) void integral_tile_sums_order(
-    const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H, int32_t strips, int32_t slabs,
-    int64_t col_pitch, bool aligned, uint32_t* __restrict__ colsum, uint32_t* __restrict__ rowsum,
-    const bd_keypoint* __restrict__ kps, int32_t n_kp, float inv_cell, int32_t* __restrict__ order)
-{
-    __shared__ uint32_t bins[order_impl::kOrderBins];
-    __shared__ uint32_t part[order_impl::kOrderThreads];
-    if (blockIdx.x == 0) {
-        order_impl::order_body(kps, n_kp, inv_cell, order, bins, part);
-        return;
-    }
-    const int wave = threadIdx.x / kWave;
-    const int tile = ((int)blockIdx.x - 1) * kWavesPerBlock + wave;
-    if (wave >= kWavesPerBlock || tile >= strips * slabs) return;
-    tile_sums_body(img, pitch, W, H, slabs, col_pitch, aligned, colsum, rowsum, tile, threadIdx.x % kWave);
-}
-
 // Blocks [0, col_blocks): column scans; remaining blocks: row scans.
 __global__ __launch_bounds__(256) void integral_carry_scan(uint32_t* __restrict__ colsum,
                                                            uint32_t* __restrict__ rowsum, int32_t H,
@@ -380,8 +447,107 @@ __global__ __launch_bounds__(256) void integral_tile_write(const uint8_t* __rest
 {
     const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (tile >= strips * slabs) return;
-    tile_write_body(img, pitch, W, H, slabs, col_pitch, aligned, colcarry, rowcarry, ii, ii_pitch, tile,
+    tile_write_body(img, pitch, W, H, slabs, col_pitch, aligned, ScannedCarries{colcarry, rowcarry}, ii, ii_pitch, tile,
                     threadIdx.x % kWave);
+}
+
+// ---- single-image kernels without the carry pass (images of up to
+// kMaxRawGroups groups of strips): the first pass also writes the column and
+// tile totals of each group of kGroupStrips strips, and the write pass sums
+// its carries from the unscanned tables.
+
+constexpr int kMaxRawGroups = 32;
+
+// Block g of the group pass takes slab g / groups and group g % groups; its
+// wavefront w < kGroupStrips sums strip kGroupStrips * group + w as
+// tile_sums_body, and the block adds the column and tile totals of its
+// strips into the group table.
+__device__ __forceinline__ void group_sums_body(const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H,
+                                                int32_t strips, int32_t slabs, int64_t col_pitch, bool aligned,
+                                                uint32_t* __restrict__ colsum, uint32_t* __restrict__ rowsum,
+                                                uint32_t* __restrict__ group, int g, uint4 (*part)[kWave],
+                                                uint32_t* tot)
+{
+    const int groups = (strips + kGroupStrips - 1) / kGroupStrips;
+    const int c = g / groups, k = g % groups;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (wave < kGroupStrips) {
+        const int s = k * kGroupStrips + wave;
+        uint32_t col[4] = {0u, 0u, 0u, 0u}, total = 0u;
+        if (s < strips)
+            tile_sums_body(img, pitch, W, H, slabs, col_pitch, aligned, colsum, rowsum, s * slabs + c, lane, col,
+                           total);
+        part[wave][lane] = make_uint4(col[0], col[1], col[2], col[3]);
+        if (lane == 0) tot[wave] = total;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        uint4 a = part[0][lane];
+#pragma unroll
+        for (int w = 1; w < kGroupStrips; ++w) {
+            const uint4 b = part[w][lane];
+            a.x += b.x;
+            a.y += b.y;
+            a.z += b.z;
+            a.w += b.w;
+        }
+        uint32_t* row = group + (int64_t)k * col_pitch;
+        *reinterpret_cast<uint4*>(row + c * kTileCols + 4 * lane) = a;
+        if (lane == 0) {
+            uint32_t t = 0u;
+#pragma unroll
+            for (int w = 0; w < kGroupStrips; ++w) t += tot[w];
+            row[(int64_t)slabs * kTileCols + c] = t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void integral_group_sums(const uint8_t* __restrict__ img, int64_t pitch, int32_t W,
+                                                           int32_t H, int32_t strips, int32_t slabs,
+                                                           int64_t col_pitch, bool aligned,
+                                                           uint32_t* __restrict__ colsum,
+                                                           uint32_t* __restrict__ rowsum,
+                                                           uint32_t* __restrict__ group)
+{
+    __shared__ uint4 part[kGroupStrips][kWave];
+    __shared__ uint32_t tot[kGroupStrips];
+    group_sums_body(img, pitch, W, H, strips, slabs, col_pitch, aligned, colsum, rowsum, group, blockIdx.x, part, tot);
+}
+
+// The group pass with the keypoint order of the same view alongside
+// (bd_build_integral_order): block 0 sorts the keypoints, blocks 1.. are the
+// group pass (its first kGroupStrips wavefronts).  The two jobs share no
+// data; in one launch the sort runs beside the sums instead of before them.
+__global__ __launch_bounds__(order_impl::kOrderThreads) void integral_group_sums_order(
+    const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H, int32_t strips, int32_t slabs,
+    int64_t col_pitch, bool aligned, uint32_t* __restrict__ colsum, uint32_t* __restrict__ rowsum,
+    uint32_t* __restrict__ group, const bd_keypoint* __restrict__ kps, int32_t n_kp, float inv_cell,
+    int32_t* __restrict__ order)
+{
+    __shared__ uint32_t bins[order_impl::kOrderBins];
+    __shared__ uint32_t opart[order_impl::kOrderThreads];
+    __shared__ uint4 part[kGroupStrips][kWave];
+    __shared__ uint32_t tot[kGroupStrips];
+    if (blockIdx.x == 0) {
+        order_impl::order_body(kps, n_kp, inv_cell, order, bins, opart);
+        return;
+    }
+    group_sums_body(img, pitch, W, H, strips, slabs, col_pitch, aligned, colsum, rowsum, group,
+                    (int)blockIdx.x - 1, part, tot);
+}
+
+__global__ __launch_bounds__(256) void integral_tile_write_raw(const uint8_t* __restrict__ img, int64_t pitch,
+                                                               int32_t W, int32_t H, int32_t strips, int32_t slabs,
+                                                               int64_t col_pitch, bool aligned,
+                                                               const uint32_t* __restrict__ colsum,
+                                                               const uint32_t* __restrict__ rowsum,
+                                                               const uint32_t* __restrict__ group,
+                                                               uint32_t* __restrict__ ii, int64_t ii_pitch)
+{
+    const int tile = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile >= strips * slabs) return;
+    tile_write_body(img, pitch, W, H, slabs, col_pitch, aligned, RawCarries{colsum, rowsum, group}, ii, ii_pitch,
+                    tile, threadIdx.x % kWave);
 }
 
 // ---- persistent batch kernels: units are blocks of four tiles (tile passes)
@@ -429,16 +595,29 @@ __global__ __launch_bounds__(256) void integral_tile_write_batch(const BatchImag
         const BatchImage& im = imgs[i];
         const int tile = (u - pre[i]) * kWavesPerBlock + threadIdx.x / kWave;
         if (tile < im.strips * im.slabs)
-            tile_write_body(im.img_u8, im.pitch_u8, im.W, im.H, im.slabs, im.col_pitch, im.aligned != 0, im.colsum,
-                            im.rowsum, im.ii, im.ii_pitch, tile, threadIdx.x % kWave);
+            tile_write_body(im.img_u8, im.pitch_u8, im.W, im.H, im.slabs, im.col_pitch, im.aligned != 0,
+                            ScannedCarries{im.colsum, im.rowsum}, im.ii, im.ii_pitch, tile, threadIdx.x % kWave);
     }
+}
+
+}  // namespace
+
+namespace {
+
+int raw_groups(const IntegralPlan& p) { return (p.strips + kGroupStrips - 1) / kGroupStrips; }
+
+// Elements before the group table in the workspace (16-byte aligned).
+size_t group_offset(const IntegralPlan& p)
+{
+    return ((size_t)p.strips * (size_t)p.col_pitch + (size_t)p.H * (size_t)p.slabs + 3) / 4 * 4;
 }
 
 }  // namespace
 
 size_t IntegralPlan::workspace_bytes() const
 {
-    return sizeof(uint32_t) * ((size_t)strips * (size_t)col_pitch + (size_t)H * (size_t)slabs);
+    const size_t groups = (size_t)raw_groups(*this);
+    return sizeof(uint32_t) * (group_offset(*this) + (groups <= (size_t)kMaxRawGroups ? groups * (size_t)col_pitch : 0));
 }
 
 IntegralPlan plan_integral(int32_t W, int32_t H)
@@ -454,22 +633,6 @@ IntegralPlan plan_integral(int32_t W, int32_t H)
     return p;
 }
 
-namespace {
-
-// The carry scans and the tile writes, after the tile sums.
-void launch_carry_and_write(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, bool aligned,
-                            uint32_t* colsum, uint32_t* rowsum, uint32_t* ii, int64_t ii_pitch, int tile_blocks,
-                            hipStream_t stream)
-{
-    const int col_blocks = (int)((p.col_pitch + 255) / 256);
-    const int row_blocks = (p.H + 255) / 256;
-    hipLaunchKernelGGL(integral_carry_scan, dim3(col_blocks + row_blocks), dim3(256), 0, stream, colsum,
-                       rowsum, p.H, p.strips, p.slabs, p.col_pitch, col_blocks);
-    hipLaunchKernelGGL(integral_tile_write, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W,
-                       p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, ii, ii_pitch);
-}
-
-}  // namespace
 
 void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
                      int64_t ii_pitch, void* workspace, hipStream_t stream)
@@ -479,24 +642,43 @@ void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitc
     const bool aligned = (img_pitch % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 4 == 0);
     const int tiles = p.strips * p.slabs;
     const int tile_blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (raw_groups(p) <= kMaxRawGroups) {
+        uint32_t* group = colsum + group_offset(p);
+        hipLaunchKernelGGL(integral_group_sums, dim3(p.slabs * raw_groups(p)), dim3(256), 0, stream, img, img_pitch,
+                           p.W, p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, group);
+        hipLaunchKernelGGL(integral_tile_write_raw, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W,
+                           p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, group, ii, ii_pitch);
+        return;
+    }
     hipLaunchKernelGGL(integral_tile_sums, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W,
                        p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum);
-    launch_carry_and_write(p, img, img_pitch, aligned, colsum, rowsum, ii, ii_pitch, tile_blocks, stream);
+    const int col_blocks = (int)((p.col_pitch + 255) / 256);
+    const int row_blocks = (p.H + 255) / 256;
+    hipLaunchKernelGGL(integral_carry_scan, dim3(col_blocks + row_blocks), dim3(256), 0, stream, colsum,
+                       rowsum, p.H, p.strips, p.slabs, p.col_pitch, col_blocks);
+    hipLaunchKernelGGL(integral_tile_write, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W,
+                       p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, ii, ii_pitch);
 }
 
 void launch_integral_order(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
                            int64_t ii_pitch, void* workspace, const bd_keypoint* kps, int32_t n_kp,
                            int32_t* order, hipStream_t stream)
 {
+    if (raw_groups(p) > kMaxRawGroups) {  // tall images: the order on its own, then the three passes
+        launch_keypoint_order(kps, n_kp, p.W, p.H, order, stream);
+        launch_integral(p, img, img_pitch, ii, ii_pitch, workspace, stream);
+        return;
+    }
     uint32_t* colsum = static_cast<uint32_t*>(workspace);
     uint32_t* rowsum = colsum + (size_t)p.strips * (size_t)p.col_pitch;
+    uint32_t* group = colsum + group_offset(p);
     const bool aligned = (img_pitch % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 4 == 0);
-    const int tiles = p.strips * p.slabs;
-    const int tile_blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(integral_tile_sums_order, dim3(tile_blocks + 1), dim3(order_impl::kOrderThreads), 0, stream,
-                       img, img_pitch, p.W, p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, kps,
-                       n_kp, order_inv_cell(p.W, p.H), order);
-    launch_carry_and_write(p, img, img_pitch, aligned, colsum, rowsum, ii, ii_pitch, tile_blocks, stream);
+    const int tile_blocks = (p.strips * p.slabs + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(integral_group_sums_order, dim3(1 + p.slabs * raw_groups(p)), dim3(order_impl::kOrderThreads),
+                       0, stream, img, img_pitch, p.W, p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum,
+                       group, kps, n_kp, order_inv_cell(p.W, p.H), order);
+    hipLaunchKernelGGL(integral_tile_write_raw, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W, p.H,
+                       p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, group, ii, ii_pitch);
 }
 
 int integral_tile_blocks(const IntegralPlan& p) { return (p.strips * p.slabs + kWavesPerBlock - 1) / kWavesPerBlock; }
