@@ -100,8 +100,10 @@ const char* bd_version(void);
  *   ii       (H+1) rows of (W+1) uint32, row stride ii_pitch elements
  *            (>= W+1); ii[0][*] = ii[*][0] = 0 and ii[y+1][x+1] is the sum of
  *            img over rows <= y and columns <= x, modulo 2^32.
- * W, H >= 1 and (H+1) * ii_pitch < 2^31.  Three kernels: tile sums, carry
- * scans, tile prefixes; they use ~(W*H/16 + 1024) * 4 bytes of workspace.
+ * W, H >= 1 and (H+1) * ii_pitch < 2^31.  Two kernels for images of up to
+ * 2048 rows (tile and group sums, tile prefixes with their carries summed
+ * from the sums), three above (tile sums, carry scans, tile prefixes); about
+ * (W*H/16 * 1.25 + 1024) * 4 bytes of workspace.
  */
 int bd_build_integral(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H,
                       int64_t img_pitch, uint32_t* ii, int64_t ii_pitch, void* stream);
