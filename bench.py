@@ -166,7 +166,7 @@ def stage_work():
 # change to the kernels invalidates the counters.
 PMC_TRAFFIC = {
     "keypoint_order": (("order.hip", "order_body.hpp"), "b6dbfa27dc112f78", 44 * 2048 + 20 * 1024),
-    "integral": ("integral.hip", "a626f04ab56ad8c7", (371 + 1061 + 1390) * 2048 + (580 + 616 + 8158) * 1024),
+    "integral": ("integral.hip", "d7b9123cabefb030", (1074 + 1804) * 2048 + (971 + 8158) * 1024),
     "bad_describe": ("bad.hip", "73b96b61b0287a2a", 9644 * 2048 + 161 * 1024),
     "hashsift_features": ("hashsift.hip", "49cbd2d03e6da357", 9264 * 2048 + 2500 * 1024),
     "hashsift_project": ("hashsift.hip", "49cbd2d03e6da357", 2367 * 2048 + 312 * 1024),
