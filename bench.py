@@ -75,6 +75,8 @@ class Workload:
         self.B, self.t = T(w.B), T(w.t)
         self.order = [torch.empty((N_KP,), dtype=torch.int32, device=dev) for _ in range(2)]
         self.ii = [bd.integral_buffer(H, W, dev) for _ in range(2)]
+        # row-pair copies of the HashSIFT images, written by prepare_view in every step
+        self.rp = [torch.empty((H, W, 2), dtype=torch.float32, device=dev) for _ in range(2)]
         self.bad = [torch.empty((N_KP, BAD_BITS // 64), dtype=torch.uint64, device=dev) for _ in range(2)]
         self.hist = [torch.empty((N_KP, 128), dtype=torch.float32, device=dev) for _ in range(2)]
         self.hs = [torch.empty((N_KP, HS_BITS // 64), dtype=torch.uint64, device=dev) for _ in range(2)]
@@ -91,7 +93,7 @@ class Workload:
             "integral": lambda: [bd.build_integral(s.u8[v], out=s.ii[v]) for v in (0, 1)],
             "bad_describe": lambda: [bd.describe_bad(s.ii[v], s.kps[v], out=s.bad[v], order=s.order[v], table=s.table)
                                      for v in (0, 1)],
-            "hashsift_features": lambda: [bd.hashsift_features(s.f32[v], s.kps[v], out=s.hist[v], order=s.order[v])
+            "hashsift_features": lambda: [bd.hashsift_features(s.rp[v], s.kps[v], out=s.hist[v], order=s.order[v])
                                           for v in (0, 1)],
             "hashsift_project": lambda: [bd.hashsift_project(s.hist[v], s.B, s.t, s.kps[v], out=s.hs[v]) for v in (0, 1)],
             "match_bad256": lambda: bd.match_hamming_knn(s.bad[0], s.bad[1], K, s.idx[0], s.dist[0]),
@@ -102,9 +104,9 @@ class Workload:
         import paper_2108_08380_amd as bd
 
         s = self
-        bd.build_integral_order(s.u8[v], s.kps[v], out=s.ii[v], order=s.order[v])
+        bd.prepare_view(s.u8[v], s.kps[v], s.f32[v], out=s.ii[v], order=s.order[v], pairs=s.rp[v])
         bd.describe_bad(s.ii[v], s.kps[v], out=s.bad[v], order=s.order[v], table=s.table)
-        bd.hashsift_features(s.f32[v], s.kps[v], out=s.hist[v], order=s.order[v])
+        bd.hashsift_features(s.rp[v], s.kps[v], out=s.hist[v], order=s.order[v])
         bd.hashsift_project(s.hist[v], s.B, s.t, s.kps[v], out=s.hs[v])
 
     def step(self, only=""):
@@ -311,13 +313,17 @@ def describe_rates(wl, reps=200):
     def bad(v):
         bd.describe_bad(wl.ii[v], wl.kps[v], out=wl.bad[v], order=wl.order[v], table=wl.table)
 
-    def hs(v):
-        bd.hashsift_features(wl.f32[v], wl.kps[v], out=wl.hist[v], order=wl.order[v])
+    def prepare(v):
+        bd.prepare_view(wl.u8[v], wl.kps[v], wl.f32[v], out=wl.ii[v], order=wl.order[v], pairs=wl.rp[v])
+
+    def hs(v, img=None):
+        img = wl.f32[v] if img is None else img
+        bd.hashsift_features(img, wl.kps[v], out=wl.hist[v], order=wl.order[v])
         bd.hashsift_project(wl.hist[v], wl.B, wl.t, wl.kps[v], out=wl.hs[v])
 
     variants = {
         "describe_only": lambda v: (order(v), bad(v), hs(v)),
-        "integral_plus_describe": lambda v: (integral_order(v), bad(v), hs(v)),
+        "integral_plus_describe": lambda v: (prepare(v), bad(v), hs(v, wl.rp[v])),
         "bad256_only": lambda v: (order(v), bad(v)),
         "integral_plus_bad256": lambda v: (integral_order(v), bad(v)),
         "hashsift512_only": lambda v: (order(v), hs(v)),

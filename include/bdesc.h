@@ -44,6 +44,12 @@ extern "C" {
 
 #define BD_DTYPE_U8 0  /* grey levels 0..255; HashSIFT reads v / 255 */
 #define BD_DTYPE_F32 1 /* float32 grey levels */
+/* float32 grey levels stored as row pairs (HashSIFT only): element (y, x)
+ * is the float2 (I[y][x], I[min(y + 1, H - 1)][x]), W float2 per row, row
+ * stride a multiple of 8 bytes; bd_prepare_view writes it.  Same features as
+ * BD_DTYPE_F32 on I, bit for bit; the sampler reads a sample's four corner
+ * pixels with one 16-byte load instead of two 8-byte ones. */
+#define BD_DTYPE_F32_ROWPAIR 2
 
 #define BD_PREC_FP32 0 /* FP32 operands, FP32 MFMA */
 #define BD_PREC_BF16 1 /* bfloat16 operands (round to nearest even), FP32 accumulation */
@@ -136,6 +142,24 @@ int bd_build_integral_order(bd_context* ctx, const uint8_t* img, int32_t W, int3
                             int32_t* order, void* stream);
 
 /*
+ * Everything the describe calls of one view read, from one call:
+ * bd_build_integral_order plus, when hs_img is given, the row-pair copy of
+ * the view's float32 HashSIFT image (BD_DTYPE_F32_ROWPAIR) written to
+ * pairs, all in the same launches.
+ *   hs_img   H rows of W float32 (the HashSIFT source), row stride hs_pitch
+ *            bytes (a multiple of 4, >= 4 W); NULL with pairs NULL for none
+ *   pairs    H rows of W float2, row stride pairs_pitch bytes (a multiple of
+ *            8, >= 8 W): element (y, x) = (hs[y][x], hs[min(y+1, H-1)][x])
+ * Pass pairs to bd_hashsift_features / bd_describe_hashsift with dtype
+ * BD_DTYPE_F32_ROWPAIR and img_pitch = pairs_pitch: the features are those
+ * of hs_img, bit for bit.  Errors as in bd_build_integral_order, and
+ * BD_EINVAL for a missing half of the HashSIFT pair or bad pitches.
+ */
+int bd_prepare_view(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch, uint32_t* ii,
+                    int64_t ii_pitch, const bd_keypoint* kps, int32_t n_kp, int32_t* order, const float* hs_img,
+                    int64_t hs_pitch, float* pairs, int64_t pairs_pitch, void* stream);
+
+/*
  * BAD codes (Sec. III-A: weak descriptor h(x; f, theta) = +1 when
  * f(x; u1, u2, s) <= theta, f the difference of the mean grey levels of two
  * boxes of side s; the bits of h(x) = [h_1 .. h_K]).
@@ -174,8 +198,9 @@ int bd_describe_bad_table(bd_context* ctx, const uint32_t* ii, int32_t W, int32_
 /*
  * HashSIFT codes (Sec. III-B: D(x) = sgn(B [f(x); 1]) with f the SIFT
  * feature vector of the normalized 32x32 patch).
- *   img      H rows of W pixels (dtype BD_DTYPE_U8 or BD_DTYPE_F32), row
- *            stride img_pitch bytes (a multiple of 4 for f32)
+ *   img      H rows of W pixels (dtype BD_DTYPE_U8, BD_DTYPE_F32 or
+ *            BD_DTYPE_F32_ROWPAIR), row stride img_pitch bytes (a multiple
+ *            of 4 for f32, of 8 for row pairs)
  *   order    optional (NULL) processing order, as for bd_describe_bad
  *   B        n_bits x 128 float32, row major;  t  n_bits thresholds
  *            (the paper's last column of B is -t)

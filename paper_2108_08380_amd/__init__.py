@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbdesc.so")
 
 BD_OK, BD_EINVAL, BD_EUNSUPPORTED, BD_ENOMEM, BD_EDEVICE = 0, -1, -2, -3, -4
-BD_DTYPE_U8, BD_DTYPE_F32 = 0, 1
+BD_DTYPE_U8, BD_DTYPE_F32, BD_DTYPE_F32_ROWPAIR = 0, 1, 2
 BD_PREC_FP32, BD_PREC_BF16, BD_PREC_FP8 = 0, 1, 2
 _PRECISIONS = {"fp32": BD_PREC_FP32, "bf16": BD_PREC_BF16, "fp8": BD_PREC_FP8}
 DEFAULT_MARGIN = 1e-3
@@ -50,6 +50,7 @@ SIGNATURES = {
     "bd_describe_bad_table": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "bd_keypoint_order": ([_P, _P, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "bd_build_integral_order": ([_P, _P, _I32, _I32, _I64, _P, _I64, _P, _I32, _P, _P], ctypes.c_int),
+    "bd_prepare_view": ([_P, _P, _I32, _I32, _I64, _P, _I64, _P, _I32, _P, _P, _I64, _P, _I64, _P], ctypes.c_int),
     "bd_describe_bad": ([_P, _P, _I32, _I32, _I64, _P, _I32, _P, _P, _I32, _P, _P], ctypes.c_int),
     "bd_describe_hashsift": ([_P, _P, _I32, _I32, _I32, _I64, _P, _I32, _P, _P, _P, _I32, _I32, ctypes.c_float,
                               _P, _P, _P, _P, _P], ctypes.c_int),
@@ -296,6 +297,40 @@ def build_integral_order(img, kps, out=None, order=None):
     return out, order
 
 
+def prepare_view(img, kps, hs_img=None, out=None, order=None, pairs=None):
+    """Integral image, keypoint order and (with a float32 hs_img) the row-pair
+    copy of the HashSIFT image of one view in one call (bd_prepare_view)
+    -> (ii, order, pairs); pairs is an (H, W, 2) float32 tensor that
+    hashsift_features and describe_hashsift accept in place of hs_img."""
+    torch = _torch()
+    _require(img, torch.uint8, 2, "img")
+    _require(kps, torch.float32, 2, "kps")
+    _contig(kps, "kps")
+    H, W = img.shape
+    n = kps.shape[0]
+    if out is None:
+        out = integral_buffer(H, W, img.device)
+    _require(out, torch.uint32, 2, "out")
+    if order is None:
+        order = torch.empty((n,), dtype=torch.int32, device=img.device)
+    hs_ptr, hs_pitch, pairs_ptr, pairs_pitch = None, 0, None, 0
+    if hs_img is not None:
+        _require(hs_img, torch.float32, 2, "hs_img")
+        if tuple(hs_img.shape) != (H, W):
+            raise ValueError("hs_img must have the shape of img")
+        if pairs is None:
+            pairs = torch.empty((H, W, 2), dtype=torch.float32, device=img.device)
+        if _image_dtype(pairs) != BD_DTYPE_F32_ROWPAIR or tuple(pairs.shape) != (H, W, 2):
+            raise ValueError("pairs must be an (H, W, 2) float32 tensor with contiguous pairs")
+        hs_ptr, hs_pitch = hs_img.data_ptr(), hs_img.stride(0) * 4
+        pairs_ptr, pairs_pitch = pairs.data_ptr(), pairs.stride(0) * 4
+    dev, stream = _device_and_stream(img, kps, out, order, hs_img, pairs)
+    _check(lib().bd_prepare_view(context(dev, stream), img.data_ptr(), W, H, img.stride(0), out.data_ptr(),
+                                 out.stride(0), kps.data_ptr(), n, _order_arg(order, n), hs_ptr, hs_pitch, pairs_ptr,
+                                 pairs_pitch, stream))
+    return out, order, pairs
+
+
 def describe_bad(ii, kps, pairs=None, n_bits: int | None = None, out=None, order=None, table=None):
     """BAD codes from an integral image (bd_describe_bad, or bd_describe_bad_table
     when a compiled BadTable is given instead of pairs)."""
@@ -370,7 +405,7 @@ def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool =
     responses re-checked in FP32 (BF16/FP8 only)."""
     torch = _torch()
     dtype = _image_dtype(img)
-    _require(img, img.dtype, 2, "img")
+    _require(img, img.dtype, 3 if dtype == BD_DTYPE_F32_ROWPAIR else 2, "img")
     _require(kps, torch.float32, 2, "kps")
     _contig(kps, "kps")
     _require(B, torch.float32, 2, "B")
@@ -379,7 +414,7 @@ def describe_hashsift(img, kps, B, t, precision: str = "fp32", with_hist: bool =
     n_bits = B.shape[0]
     if B.shape[1] != 128 or t.shape != (n_bits,) or t.dtype != torch.float32:
         raise ValueError("B must be (n_bits, 128) float32 and t (n_bits,) float32")
-    H, W = img.shape
+    H, W = img.shape[:2]
     n = kps.shape[0]
     if out is None:
         out = torch.empty((n, n_bits // 64), dtype=torch.uint64, device=img.device)
@@ -407,7 +442,13 @@ def _counter_arg(c):
 
 
 def _image_dtype(img):
+    """Library dtype of a HashSIFT image: (H, W) uint8 or float32, or an
+    (H, W, 2) float32 row-pair image from prepare_view."""
     torch = _torch()
+    if img.dim() == 3:
+        if img.dtype != torch.float32 or img.shape[2] != 2 or img.stride(2) != 1 or img.stride(1) != 2:
+            raise TypeError("a row-pair image is an (H, W, 2) float32 tensor with contiguous pairs")
+        return BD_DTYPE_F32_ROWPAIR
     if img.dtype == torch.uint8:
         return BD_DTYPE_U8
     if img.dtype == torch.float32:
@@ -419,10 +460,10 @@ def hashsift_features(img, kps, out=None, order=None):
     """(n, 128) float32 L2-normalized HashSIFT features (bd_hashsift_features)."""
     torch = _torch()
     dtype = _image_dtype(img)
-    _require(img, img.dtype, 2, "img")
+    _require(img, img.dtype, 3 if dtype == BD_DTYPE_F32_ROWPAIR else 2, "img")
     _require(kps, torch.float32, 2, "kps")
     _contig(kps, "kps")
-    H, W = img.shape
+    H, W = img.shape[:2]
     n = kps.shape[0]
     if out is None:
         out = torch.empty((n, 128), dtype=torch.float32, device=img.device)

@@ -114,11 +114,13 @@ struct IntegralPlan {
 IntegralPlan plan_integral(int32_t W, int32_t H);
 void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
                      int64_t ii_pitch, void* workspace, hipStream_t stream);
-// launch_integral with the keypoint order of the same view computed in one
-// block of the first pass (order as launch_keypoint_order writes it).
-void launch_integral_order(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
-                           int64_t ii_pitch, void* workspace, const bd_keypoint* kps, int32_t n_kp,
-                           int32_t* order, hipStream_t stream);
+// launch_integral with, in the blocks of its first pass, the keypoint order
+// of the same view (as launch_keypoint_order writes it; n_kp > 0) and the
+// row-pair copy of its float HashSIFT image (hs non-null; pitches of hs and
+// pairs in elements: floats and float2).
+void launch_prepare_view(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
+                         int64_t ii_pitch, void* workspace, const bd_keypoint* kps, int32_t n_kp, int32_t* order,
+                         const float* hs, int64_t hs_pitch, float* pairs, int64_t pairs_pitch, hipStream_t stream);
 int integral_tile_blocks(const IntegralPlan& p);   // units of the tile passes
 int integral_carry_blocks(const IntegralPlan& p);  // units of the carry pass
 void launch_integral_batch(const BatchImage* imgs, int32_t n_img, const int32_t* tile_pre, const int32_t* carry_pre,

@@ -225,11 +225,14 @@ int bd_build_integral(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H,
     return check_launch(fn);
 }
 
-int bd_build_integral_order(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch,
-                            uint32_t* ii, int64_t ii_pitch, const bd_keypoint* kps, int32_t n_kp, int32_t* order,
-                            void* stream)
+namespace {
+
+// The integral image, keypoint order and optional row-pair image of one
+// view (bd_build_integral_order, bd_prepare_view).
+int prepare_view(const char* fn, bd_context* ctx, const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch,
+                 uint32_t* ii, int64_t ii_pitch, const bd_keypoint* kps, int32_t n_kp, int32_t* order,
+                 const float* hs_img, int64_t hs_pitch, float* pairs, int64_t pairs_pitch, void* stream)
 {
-    const char* fn = "bd_build_integral_order";
     if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
     if (img_pitch < W) return fail(BD_EINVAL, "%s: img_pitch %lld < W %d", fn, (long long)img_pitch, W);
     if (ii_pitch < (int64_t)W + 1) return fail(BD_EINVAL, "%s: ii_pitch %lld < W+1", fn, (long long)ii_pitch);
@@ -238,16 +241,46 @@ int bd_build_integral_order(bd_context* ctx, const uint8_t* img, int32_t W, int3
     if (!img || !ii) return fail(BD_EINVAL, "%s: null image or output pointer", fn);
     if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
     if (n_kp > 0 && (!kps || !order)) return fail(BD_EINVAL, "%s: null keypoint or order pointer", fn);
+    if (hs_img || pairs) {
+        if (!hs_img || !pairs) return fail(BD_EINVAL, "%s: hs_img and pairs go together", fn);
+        if (hs_pitch < 4 * (int64_t)W || hs_pitch % 4 != 0 || reinterpret_cast<uintptr_t>(hs_img) % 4 != 0)
+            return fail(BD_EINVAL, "%s: hs_pitch %lld must be a multiple of 4 and >= 4 W", fn, (long long)hs_pitch);
+        if (pairs_pitch < 8 * (int64_t)W || pairs_pitch % 8 != 0 || reinterpret_cast<uintptr_t>(pairs) % 8 != 0)
+            return fail(BD_EINVAL, "%s: pairs_pitch %lld must be a multiple of 8 and >= 8 W", fn,
+                        (long long)pairs_pitch);
+        if (!hashsift_image_fits(pairs_pitch, H))
+            return fail(BD_EINVAL, "%s: row-pair image needs pairs_pitch < 2^24, H < 2^24 and pairs_pitch * H <= 2^32",
+                        fn);
+    }
     if (int rc = check_ctx(ctx, fn)) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const IntegralPlan plan = plan_integral(W, H);
     void* ws = nullptr;
     if (int rc = reserve_workspace(ctx, plan.workspace_bytes(), s, &ws)) return rc;
-    if (n_kp == 0)
+    if (n_kp == 0 && !hs_img)
         launch_integral(plan, img, img_pitch, ii, ii_pitch, ws, s);
     else
-        launch_integral_order(plan, img, img_pitch, ii, ii_pitch, ws, kps, n_kp, order, s);
+        launch_prepare_view(plan, img, img_pitch, ii, ii_pitch, ws, kps, n_kp, order, hs_img, hs_pitch / 4, pairs,
+                            pairs_pitch / 8, s);
     return check_launch(fn);
+}
+
+}  // namespace
+
+int bd_build_integral_order(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch,
+                            uint32_t* ii, int64_t ii_pitch, const bd_keypoint* kps, int32_t n_kp, int32_t* order,
+                            void* stream)
+{
+    return prepare_view("bd_build_integral_order", ctx, img, W, H, img_pitch, ii, ii_pitch, kps, n_kp, order, nullptr,
+                        0, nullptr, 0, stream);
+}
+
+int bd_prepare_view(bd_context* ctx, const uint8_t* img, int32_t W, int32_t H, int64_t img_pitch, uint32_t* ii,
+                    int64_t ii_pitch, const bd_keypoint* kps, int32_t n_kp, int32_t* order, const float* hs_img,
+                    int64_t hs_pitch, float* pairs, int64_t pairs_pitch, void* stream)
+{
+    return prepare_view("bd_prepare_view", ctx, img, W, H, img_pitch, ii, ii_pitch, kps, n_kp, order, hs_img,
+                        hs_pitch, pairs, pairs_pitch, stream);
 }
 
 int bd_keypoint_order(bd_context* ctx, const bd_keypoint* kps, int32_t n_kp, int32_t W, int32_t H,
@@ -353,13 +386,16 @@ int bd_describe_bad_table(bd_context* ctx, const uint32_t* ii, int32_t W, int32_
     return check_launch(fn);
 }
 
-int check_image(const char* fn, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch)
+int check_image(const char* fn, int32_t dtype, int32_t W, int32_t H, int64_t img_pitch, const void* img)
 {
-    if (dtype != BD_DTYPE_U8 && dtype != BD_DTYPE_F32) return fail(BD_EUNSUPPORTED, "%s: dtype %d", fn, dtype);
+    if (dtype != BD_DTYPE_U8 && dtype != BD_DTYPE_F32 && dtype != BD_DTYPE_F32_ROWPAIR)
+        return fail(BD_EUNSUPPORTED, "%s: dtype %d", fn, dtype);
     if (W < 1 || H < 1) return fail(BD_EINVAL, "%s: image size %dx%d must be at least 1x1", fn, W, H);
-    const int64_t elem = dtype == BD_DTYPE_U8 ? 1 : 4;
+    const int64_t elem = dtype == BD_DTYPE_U8 ? 1 : dtype == BD_DTYPE_F32 ? 4 : 8;
     if (img_pitch < W * elem) return fail(BD_EINVAL, "%s: img_pitch %lld < row bytes", fn, (long long)img_pitch);
     if (dtype == BD_DTYPE_F32 && img_pitch % 4 != 0) return fail(BD_EINVAL, "%s: f32 img_pitch must be a multiple of 4", fn);
+    if (dtype == BD_DTYPE_F32_ROWPAIR && (img_pitch % 8 != 0 || reinterpret_cast<uintptr_t>(img) % 8 != 0))
+        return fail(BD_EINVAL, "%s: row-pair image and img_pitch must be 8-byte aligned", fn);
     if (!hashsift_image_fits(img_pitch, H))
         return fail(BD_EINVAL, "%s: image needs img_pitch < 2^24, H < 2^24 and img_pitch * H <= 2^32", fn);
     return BD_OK;
@@ -379,7 +415,7 @@ int bd_hashsift_features(bd_context* ctx, const void* img, int32_t dtype, int32_
                          float* hist, void* stream)
 {
     const char* fn = "bd_hashsift_features";
-    if (int rc = check_image(fn, dtype, W, H, img_pitch)) return rc;
+    if (int rc = check_image(fn, dtype, W, H, img_pitch, img)) return rc;
     if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
     if (n_kp > 0 && (!img || !kps || !hist)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
     if (int rc = check_ctx(ctx, fn)) return rc;
@@ -411,7 +447,7 @@ int bd_describe_hashsift(bd_context* ctx, const void* img, int32_t dtype, int32_
 {
     const char* fn = "bd_describe_hashsift";
     if (int rc = check_projection(fn, n_bits, precision, margin)) return rc;
-    if (int rc = check_image(fn, dtype, W, H, img_pitch)) return rc;
+    if (int rc = check_image(fn, dtype, W, H, img_pitch, img)) return rc;
     if (n_kp < 0) return fail(BD_EINVAL, "%s: n_kp %d < 0", fn, n_kp);
     if (n_kp > 0 && (!img || !kps || !B || !t || !codes)) return fail(BD_EINVAL, "%s: null pointer argument", fn);
     if (int rc = check_ctx(ctx, fn)) return rc;

@@ -130,6 +130,8 @@ __device__ __forceinline__ float pixel(const uint8_t* __restrict__ img, int64_t 
     const uint8_t* row = img + (int64_t)y * pitch;
     if constexpr (DT == BD_DTYPE_U8) {
         return (float)row[x];  // grey levels; the 1/255 scale cancels in the L2 normalization
+    } else if constexpr (DT == BD_DTYPE_F32_ROWPAIR) {
+        return reinterpret_cast<const float*>(row)[2 * x];  // first of the pair: row y
     } else {
         return reinterpret_cast<const float*>(row)[x];
     }
@@ -169,6 +171,8 @@ __device__ __forceinline__ float pixel_at(const uint8_t* __restrict__ img, uint3
 {
     if constexpr (DT == BD_DTYPE_U8) {
         return (float)img[row_off + (uint32_t)x];
+    } else if constexpr (DT == BD_DTYPE_F32_ROWPAIR) {
+        return *reinterpret_cast<const float*>(img + row_off + 8u * (uint32_t)x);
     } else {
         return *reinterpret_cast<const float*>(img + row_off + 4u * (uint32_t)x);
     }
@@ -234,7 +238,23 @@ __device__ __forceinline__ void fetch_fixed(const uint8_t* __restrict__ img, int
     fy = (float)(uint32_t)Y * 0x1p-32f;
     const uint32_t ra = __umul24((uint32_t)clampi(yi, hm1), upitch);
     const uint32_t rb = __umul24((uint32_t)clampi(yi + 1, hm1), upitch);
-    if constexpr (PAIR && DT == BD_DTYPE_F32) {
+    if constexpr (PAIR && DT == BD_DTYPE_F32_ROWPAIR) {
+        // one 16-byte load: (I[y][x], I[y+1][x], I[y][x+1], I[y+1][x+1]) at the
+        // column clamped to [0, W - 2]; rows as the pair stores them, so above
+        // row 0 (both rows clamp to 0) the weight of the second row is set to
+        // 0 (top + 0 * (bot - top) is top exactly), and from row H - 1 down the
+        // last row's pair holds that row twice
+        typedef float float4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+        const uint32_t xo = 8u * (uint32_t)clampi(xi, wm1 - 1);
+        const float4_a8 qd = *reinterpret_cast<const float4_a8*>(img + (ra + xo));
+        const bool left = xi < 0, right = xi >= wm1;
+        if (yi < 0) fy = 0.0f;
+        v[0] = right ? qd.z : qd.x;
+        v[1] = left ? qd.x : qd.z;
+        v[2] = right ? qd.w : qd.y;
+        v[3] = left ? qd.y : qd.w;
+        (void)rb;
+    } else if constexpr (PAIR && DT == BD_DTYPE_F32) {
         const uint32_t xo = 4u * (uint32_t)clampi(xi, wm1 - 1);
         const float2_a4 pa = *reinterpret_cast<const float2_a4*>(img + (ra + xo));
         const float2_a4 pb = *reinterpret_cast<const float2_a4*>(img + (rb + xo));
@@ -1260,6 +1280,9 @@ void launch_hashsift_hist(const void* img, int32_t dtype, int32_t W, int32_t H, 
     if (dtype == BD_DTYPE_U8)
         hipLaunchKernelGGL(hashsift_hist_kernel<BD_DTYPE_U8>, dim3(blocks), dim3(kHistWaves * kWave), 0, stream,
                            p, W, H, img_pitch, kps, n_kp, order, hist, invalid);
+    else if (dtype == BD_DTYPE_F32_ROWPAIR)
+        hipLaunchKernelGGL(hashsift_hist_kernel<BD_DTYPE_F32_ROWPAIR>, dim3(blocks), dim3(kHistWaves * kWave), 0,
+                           stream, p, W, H, img_pitch, kps, n_kp, order, hist, invalid);
     else
         hipLaunchKernelGGL(hashsift_hist_kernel<BD_DTYPE_F32>, dim3(blocks), dim3(kHistWaves * kWave), 0,
                            stream, p, W, H, img_pitch, kps, n_kp, order, hist, invalid);

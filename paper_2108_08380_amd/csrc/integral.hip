@@ -514,26 +514,53 @@ __global__ __launch_bounds__(256) void integral_group_sums(const uint8_t* __rest
     group_sums_body(img, pitch, W, H, strips, slabs, col_pitch, aligned, colsum, rowsum, group, blockIdx.x, part, tot);
 }
 
-// The group pass with the keypoint order of the same view alongside
-// (bd_build_integral_order): block 0 sorts the keypoints, blocks 1.. are the
-// group pass (its first kGroupStrips wavefronts).  The two jobs share no
-// data; in one launch the sort runs beside the sums instead of before them.
+// Rows b, b + n_blocks, ... of the row-pair copy of a float image (the
+// HashSIFT source of bd_prepare_view): element (y, x) = (I[y][x],
+// I[min(y + 1, H - 1)][x]).
+__device__ __forceinline__ void pack_rows_body(const float* __restrict__ hs, int64_t hs_pitch, int32_t W, int32_t H,
+                                               float2* __restrict__ pairs, int64_t pairs_pitch, int b, int n_blocks)
+{
+    for (int y = b; y < H; y += n_blocks) {
+        const float* r0 = hs + (int64_t)y * hs_pitch;
+        const float* r1 = hs + (int64_t)(y + 1 < H ? y + 1 : H - 1) * hs_pitch;
+        float2* out = pairs + (int64_t)y * pairs_pitch;
+        for (int x = threadIdx.x; x < W; x += blockDim.x) out[x] = make_float2(r0[x], r1[x]);
+    }
+}
+
+// The group pass with the rest of a view's preparation alongside
+// (bd_build_integral_order, bd_prepare_view): block 0 sorts the keypoints,
+// blocks 1 .. n_group are the group pass (its first kGroupStrips
+// wavefronts), the n_pack blocks after them write the row-pair copy of the
+// HashSIFT image (none without one).  The jobs share no data; in one launch
+// they run beside each other instead of one after another.
 __global__ __launch_bounds__(order_impl::kOrderThreads) void integral_group_sums_order(
     const uint8_t* __restrict__ img, int64_t pitch, int32_t W, int32_t H, int32_t strips, int32_t slabs,
     int64_t col_pitch, bool aligned, uint32_t* __restrict__ colsum, uint32_t* __restrict__ rowsum,
     uint32_t* __restrict__ group, const bd_keypoint* __restrict__ kps, int32_t n_kp, float inv_cell,
-    int32_t* __restrict__ order)
+    int32_t* __restrict__ order, int32_t n_group, const float* __restrict__ hs, int64_t hs_pitch,
+    float2* __restrict__ pairs, int64_t pairs_pitch, int32_t n_pack)
 {
     __shared__ uint32_t bins[order_impl::kOrderBins];
     __shared__ uint32_t opart[order_impl::kOrderThreads];
     __shared__ uint4 part[kGroupStrips][kWave];
     __shared__ uint32_t tot[kGroupStrips];
-    if (blockIdx.x == 0) {
+    const int b = (int)blockIdx.x;
+    if (b == 0) {
         order_impl::order_body(kps, n_kp, inv_cell, order, bins, opart);
-        return;
+    } else if (b <= n_group) {
+        group_sums_body(img, pitch, W, H, strips, slabs, col_pitch, aligned, colsum, rowsum, group, b - 1, part,
+                        tot);
+    } else {
+        pack_rows_body(hs, hs_pitch, W, H, pairs, pairs_pitch, b - 1 - n_group, n_pack);
     }
-    group_sums_body(img, pitch, W, H, strips, slabs, col_pitch, aligned, colsum, rowsum, group,
-                    (int)blockIdx.x - 1, part, tot);
+}
+
+__global__ __launch_bounds__(1024) void pack_rowpairs_kernel(const float* __restrict__ hs, int64_t hs_pitch,
+                                                             int32_t W, int32_t H, float2* __restrict__ pairs,
+                                                             int64_t pairs_pitch)
+{
+    pack_rows_body(hs, hs_pitch, W, H, pairs, pairs_pitch, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void integral_tile_write_raw(const uint8_t* __restrict__ img, int64_t pitch,
@@ -660,12 +687,16 @@ void launch_integral(const IntegralPlan& p, const uint8_t* img, int64_t img_pitc
                        p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, ii, ii_pitch);
 }
 
-void launch_integral_order(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
-                           int64_t ii_pitch, void* workspace, const bd_keypoint* kps, int32_t n_kp,
-                           int32_t* order, hipStream_t stream)
+void launch_prepare_view(const IntegralPlan& p, const uint8_t* img, int64_t img_pitch, uint32_t* ii,
+                         int64_t ii_pitch, void* workspace, const bd_keypoint* kps, int32_t n_kp, int32_t* order,
+                         const float* hs, int64_t hs_pitch, float* pairs, int64_t pairs_pitch, hipStream_t stream)
 {
-    if (raw_groups(p) > kMaxRawGroups) {  // tall images: the order on its own, then the three passes
-        launch_keypoint_order(kps, n_kp, p.W, p.H, order, stream);
+    const int n_pack = hs ? (p.H < 256 ? p.H : 256) : 0;  // pitches below are in elements
+    if (raw_groups(p) > kMaxRawGroups) {  // tall images: one launch per job, then the three passes
+        if (n_kp > 0) launch_keypoint_order(kps, n_kp, p.W, p.H, order, stream);
+        if (hs)
+            hipLaunchKernelGGL(pack_rowpairs_kernel, dim3(n_pack), dim3(1024), 0, stream, hs, hs_pitch, p.W, p.H,
+                               reinterpret_cast<float2*>(pairs), pairs_pitch);
         launch_integral(p, img, img_pitch, ii, ii_pitch, workspace, stream);
         return;
     }
@@ -674,9 +705,11 @@ void launch_integral_order(const IntegralPlan& p, const uint8_t* img, int64_t im
     uint32_t* group = colsum + group_offset(p);
     const bool aligned = (img_pitch % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 4 == 0);
     const int tile_blocks = (p.strips * p.slabs + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(integral_group_sums_order, dim3(1 + p.slabs * raw_groups(p)), dim3(order_impl::kOrderThreads),
-                       0, stream, img, img_pitch, p.W, p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum,
-                       group, kps, n_kp, order_inv_cell(p.W, p.H), order);
+    const int n_group = p.slabs * raw_groups(p);
+    hipLaunchKernelGGL(integral_group_sums_order, dim3(1 + n_group + n_pack), dim3(order_impl::kOrderThreads), 0,
+                       stream, img, img_pitch, p.W, p.H, p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum,
+                       group, kps, n_kp, order_inv_cell(p.W, p.H), order, n_group, hs, hs_pitch,
+                       reinterpret_cast<float2*>(pairs), pairs_pitch, n_pack);
     hipLaunchKernelGGL(integral_tile_write_raw, dim3(tile_blocks), dim3(256), 0, stream, img, img_pitch, p.W, p.H,
                        p.strips, p.slabs, p.col_pitch, aligned, colsum, rowsum, group, ii, ii_pitch);
 }

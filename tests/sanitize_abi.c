@@ -56,6 +56,12 @@ int main(void)
     EXPECT(bd_build_integral_order(NULL, p, 8, 5, 8, p, 9, p, -1, p, NULL), BD_EINVAL);
     EXPECT(bd_build_integral_order(NULL, p, 8, 5, 8, p, 9, NULL, 3, p, NULL), BD_EINVAL);
     EXPECT(bd_build_integral_order(NULL, p, 8, 5, 8, p, 9, NULL, 0, NULL, NULL), BD_EINVAL);
+    EXPECT(bd_prepare_view(NULL, p, 8, 5, 8, p, 9, p, 3, p, p, 32, NULL, 64, NULL), BD_EINVAL);
+    EXPECT(bd_prepare_view(NULL, p, 8, 5, 8, p, 9, p, 3, p, p, 28, p, 64, NULL), BD_EINVAL);
+    EXPECT(bd_prepare_view(NULL, p, 8, 5, 8, p, 9, p, 3, p, p, 32, p, 60, NULL), BD_EINVAL);
+    EXPECT(bd_prepare_view(NULL, p, 8, 5, 8, p, 9, p, 3, p, p, 32, p, 64, NULL), BD_EINVAL);
+    EXPECT(bd_prepare_view(NULL, p, 8, 5, 8, p, 9, p, 3, p, NULL, 0, NULL, 0, NULL), BD_EINVAL);
+    EXPECT(bd_hashsift_features(NULL, p, BD_DTYPE_F32_ROWPAIR, 10, 10, 84, p, 3, NULL, p, NULL), BD_EINVAL);
     EXPECT(bd_keypoint_order(NULL, p, 5, 0, 10, p, NULL), BD_EINVAL);
     EXPECT(bd_keypoint_order(NULL, p, -1, 10, 10, p, NULL), BD_EINVAL);
     EXPECT(bd_keypoint_order(NULL, NULL, 5, 10, 10, p, NULL), BD_EINVAL);

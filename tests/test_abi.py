@@ -103,6 +103,40 @@ def test_build_integral_order_validation(L):
     assert "null context" in err(L)
 
 
+def test_prepare_view_validation(L):
+    p, q = ctypes.c_void_p(16), ctypes.c_void_p(64)
+
+    def call(hs=q, hs_pitch=32, pairs=q, pairs_pitch=64, W=8, H=5, n=3, ctx=None):
+        return L.bd_prepare_view(ctx, p, W, H, W, p, W + 1, p, n, p, hs, hs_pitch, pairs, pairs_pitch, None)
+
+    assert call(W=0) == bd.BD_EINVAL and "at least 1x1" in err(L)
+    assert call(hs=None) == bd.BD_EINVAL and "together" in err(L)
+    assert call(pairs=None) == bd.BD_EINVAL and "together" in err(L)
+    assert call(hs_pitch=28) == bd.BD_EINVAL and "hs_pitch" in err(L)
+    assert call(hs_pitch=34) == bd.BD_EINVAL and "hs_pitch" in err(L)
+    assert call(hs=ctypes.c_void_p(66)) == bd.BD_EINVAL and "hs_pitch" in err(L)
+    assert call(pairs_pitch=56) == bd.BD_EINVAL and "pairs_pitch" in err(L)
+    assert call(pairs_pitch=68) == bd.BD_EINVAL and "pairs_pitch" in err(L)
+    assert call(pairs=ctypes.c_void_p(68)) == bd.BD_EINVAL and "pairs_pitch" in err(L)
+    assert call(pairs_pitch=1 << 24) == bd.BD_EINVAL and "2^24" in err(L)
+    assert call(n=-1) == bd.BD_EINVAL and "n_kp" in err(L)
+    assert call() == bd.BD_EINVAL and "null context" in err(L)
+    assert call(hs=None, pairs=None) == bd.BD_EINVAL and "null context" in err(L)
+
+
+def test_row_pair_image_validation(L):
+    p, q = ctypes.c_void_p(16), ctypes.c_void_p(20)
+    rp = bd.BD_DTYPE_F32_ROWPAIR
+    assert L.bd_hashsift_features(None, p, rp, 10, 10, 72, p, 3, None, p, None) == bd.BD_EINVAL
+    assert "row bytes" in err(L)
+    assert L.bd_hashsift_features(None, p, rp, 10, 10, 84, p, 3, None, p, None) == bd.BD_EINVAL
+    assert "8-byte" in err(L)
+    assert L.bd_hashsift_features(None, q, rp, 10, 10, 80, p, 3, None, p, None) == bd.BD_EINVAL
+    assert "8-byte" in err(L)
+    assert L.bd_hashsift_features(None, p, rp, 10, 10, 80, p, 3, None, p, None) == bd.BD_EINVAL
+    assert "null context" in err(L)
+
+
 def test_describe_bad_validation(L):
     p = ctypes.c_void_p(16)
     assert L.bd_describe_bad(None, p, 10, 10, 11, p, 4, None, p, 128, p, None) == bd.BD_EUNSUPPORTED

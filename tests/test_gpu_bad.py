@@ -158,6 +158,47 @@ def test_integral_and_order_in_one_call(dev, W, H, n):
     np.testing.assert_array_equal(keys[o_fused], keys[o_sep])
 
 
+@pytest.mark.parametrize("W,H,n", [(1920, 1080, 5000), (37, 29, 40), (3, 1, 2), (1, 7, 0), (4000, 3000, 9000)])
+def test_prepare_view(dev, W, H, n):
+    """bd_prepare_view: the integral image equals bd_build_integral's and the
+    order is bd_keypoint_order's up to ties, as for bd_build_integral_order,
+    and the row-pair copy of the HashSIFT image pairs each pixel with the one
+    below it (the last row with itself), bit for bit; taller images than the
+    two-launch form takes (4000 x 3000) go through the separate launches."""
+    rng = np.random.default_rng(W * 3 + n)
+    img = torch.from_numpy(synth.quantize_u8(synth.grey_image(rng, W, H, n_rect=20))).to(dev)
+    hs = torch.from_numpy(rng.standard_normal((H, W)).astype(np.float32)).to(dev)
+    kps_np = synth.keypoints(rng, n, W, H, border=0.0)
+    kps = bd.keypoints_tensor(kps_np, dev)
+    ii, order, rp = bd.prepare_view(img, kps, hs)
+    np.testing.assert_array_equal(to_np(ii), to_np(bd.build_integral(img)))
+    o = to_np(order)
+    keys = _cell_keys(kps_np, W, H)
+    np.testing.assert_array_equal(np.sort(o), np.arange(n))
+    np.testing.assert_array_equal(keys[o], keys[to_np(bd.keypoint_order(kps, W, H))])
+    h = to_np(hs)
+    below = np.concatenate([h[1:], h[-1:]], axis=0)
+    np.testing.assert_array_equal(to_np(rp), np.stack([h, below], axis=2))
+    ii2, order2, none = bd.prepare_view(img, kps)
+    assert none is None
+    np.testing.assert_array_equal(to_np(ii2), to_np(ii))
+    np.testing.assert_array_equal(keys[to_np(order2)], keys[o])
+
+
+def test_prepare_view_validation(dev):
+    """The HashSIFT image and its row-pair output must come together, match
+    the image's size and be float32 with 4- and 8-byte aligned rows."""
+    img = torch.zeros((6, 5), dtype=torch.uint8, device=dev)
+    kps = bd.keypoints_tensor(np.zeros(1, dtype=synth.KEYPOINT_DTYPE), dev)
+    with pytest.raises(ValueError):
+        bd.prepare_view(img, kps, torch.zeros((6, 4), dtype=torch.float32, device=dev))
+    with pytest.raises(TypeError):
+        bd.prepare_view(img, kps, torch.zeros((6, 5), dtype=torch.float64, device=dev))
+    with pytest.raises(ValueError):
+        bd.prepare_view(img, kps, torch.zeros((6, 5), dtype=torch.float32, device=dev),
+                        pairs=torch.zeros((6, 4, 2), dtype=torch.float32, device=dev))
+
+
 def test_ordered_describe_equals_unordered(ref, dev):
     w = synth.hashsift512_pair(n_kp=3000, n_bits=512, with_bad_bits=512)
     img = torch.from_numpy(w.extra["image1_u8"]).to(dev)

@@ -226,3 +226,80 @@ def test_empty_keypoint_set(dev, precision):
     assert bd.hashsift_project(hist0, B, t, precision=precision, recheck_count=count).shape == (0, 8)
     torch.cuda.synchronize()
     assert int(count.item()) == 0
+
+
+def row_pairs(img):
+    """Row-pair copy of a float image built with torch: (y, x) holds the
+    pixel and the one below it, the last row paired with itself."""
+    below = torch.cat([img[1:], img[-1:]], dim=0)
+    return torch.stack([img, below], dim=2).contiguous()
+
+
+def _row_pair_case(case):
+    rng = np.random.default_rng(hash(case) % 1000)
+    kps = None
+    if case == "workload":
+        w = synth.hashsift512_pair(n_kp=3000)
+        return w.image1, w.kp1
+    if case.startswith("narrow"):
+        width = int(case[-1])
+        img = rng.random((9, width)).astype(np.float32)
+        kps = np.zeros(6, dtype=synth.KEYPOINT_DTYPE)
+        kps[:] = [(0, 0, 1, 0), (width - 1, 8, 0.5, 1.0), (0.5, 4, 2.0, 2.0), (width + 3.0, -2, 1.0, 3.0),
+                  (-4.0, 10.5, 1.5, -2.0), (width * 0.5, 7.75, 0.25, 0.7)]
+        return img, kps
+    if case == "border":
+        H, W = 37, 53
+        img = rng.random((H, W)).astype(np.float32)
+        xs = [-3.0, -0.5, 0.0, 0.25, W - 1.0, W - 0.5, W + 2.0]
+        ys = [-3.0, -0.75, 0.0, 0.5, H - 1.5, H - 1.0, H - 0.25, H + 2.0]
+        pts = [(x, y) for x in xs for y in ys]
+        kps = np.zeros(len(pts), dtype=synth.KEYPOINT_DTYPE)
+        for i, (x, y) in enumerate(pts):
+            kps[i] = (x, y, rng.uniform(0.3, 3.0), rng.uniform(-math.pi, math.pi))
+        return img, kps
+    if case == "far":
+        img = rng.random((37, 41)).astype(np.float32)
+        kps = np.zeros(6, dtype=synth.KEYPOINT_DTYPE)
+        kps[:] = [(1.0e9, 20.0, 1.0, 0.5), (20.0, 18.0, 4.0e7, 0.2), (1.2e9, 20.0, 1.0, 0.5),
+                  (20.0, -3.0e9, 3.0, 2.0), (-2.0e9, -3.0e9, 3.0, 4.0), (40.5, 36.5, 1.0, 0.0)]
+        return img, kps
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["workload", "narrow1", "narrow2", "narrow3", "border", "far"])
+def test_row_pair_image_equals_float(ref, dev, case):
+    """An (H, W, 2) row-pair image gives the float image's features,
+    responses and codes bit for bit: on the 1920 x 1080 workload, on images
+    1 to 3 pixels wide, for keypoints whose samples fall above the first row,
+    below the last or beside the columns, and on the fixed-point and FP64
+    position paths.  The workload case is also held against the oracle."""
+    img_np, kps_np = _row_pair_case(case)
+    img = torch.from_numpy(img_np).to(dev)
+    rp = row_pairs(img)
+    kps = bd.keypoints_tensor(kps_np, dev)
+    B, t = synth.projection(np.random.default_rng(5), 512)
+    Bd, td = torch.from_numpy(B).to(dev), torch.from_numpy(t).to(dev)
+    a = to_np(bd.hashsift_features(img, kps)).view(np.uint32)
+    b = to_np(bd.hashsift_features(rp, kps)).view(np.uint32)
+    np.testing.assert_array_equal(a, b)
+    for x, y in zip(bd.describe_hashsift(img, kps, Bd, td, with_hist=True, with_resp=True),
+                    bd.describe_hashsift(rp, kps, Bd, td, with_hist=True, with_resp=True)):
+        np.testing.assert_array_equal(to_np(x), to_np(y))
+    if case == "workload":
+        compare(ref, dev, img_np, kps_np, B, t, "row-pair reference")
+
+
+def test_row_pair_image_validation(dev):
+    """Row-pair images must hold their pairs contiguously in float32."""
+    kps = bd.keypoints_tensor(np.zeros(1, dtype=synth.KEYPOINT_DTYPE), dev)
+    img = torch.zeros((8, 5), dtype=torch.float32, device=dev)
+    with pytest.raises(TypeError):
+        bd.hashsift_features(torch.zeros((8, 5, 2), dtype=torch.float64, device=dev), kps)
+    with pytest.raises(TypeError):
+        bd.hashsift_features(torch.zeros((8, 5, 3), dtype=torch.float32, device=dev), kps)
+    with pytest.raises(TypeError):
+        bd.hashsift_features(row_pairs(img).transpose(0, 1), kps)
+    odd = torch.zeros((8 * 11 + 1,), dtype=torch.float32, device=dev)[1:].view(8, 11)[:, :10].view(8, 5, 2)
+    with pytest.raises(bd.BDError, match="8-byte aligned"):
+        bd.hashsift_features(odd, kps)
