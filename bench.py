@@ -168,10 +168,10 @@ def stage_work():
 # change to the kernels invalidates the counters.
 PMC_TRAFFIC = {
     "keypoint_order": (("order.hip", "order_body.hpp"), "b6dbfa27dc112f78", 44 * 2048 + 20 * 1024),
-    "integral": ("integral.hip", "d7b9123cabefb030", (1074 + 1804) * 2048 + (971 + 8158) * 1024),
+    "integral": ("integral.hip", "db3e519d3c76c709", (1072 + 1806) * 2048 + (971 + 8159) * 1024),
     "bad_describe": ("bad.hip", "73b96b61b0287a2a", 9644 * 2048 + 161 * 1024),
-    "hashsift_features": ("hashsift.hip", "49cbd2d03e6da357", 9264 * 2048 + 2500 * 1024),
-    "hashsift_project": ("hashsift.hip", "49cbd2d03e6da357", 2367 * 2048 + 312 * 1024),
+    "hashsift_features": ("hashsift.hip", "73d50dc3bf827b93", 16993 * 2048 + 2500 * 1024),
+    "hashsift_project": ("hashsift.hip", "73d50dc3bf827b93", 2367 * 2048 + 312 * 1024),
     "match_bad256": ("hamming.hip", "b45b06214a9c6ad9", (882 + 300) * 2048 + (469 + 78) * 1024),
     "match_hashsift512": ("hamming.hip", "b45b06214a9c6ad9", (1684 + 300) * 2048 + (469 + 78) * 1024),
 }
@@ -185,7 +185,7 @@ PMC_TRAFFIC = {
 # accesses / (duration x 256 CUs x 2.4 GHz) is the kernel's fraction of that
 # rate.
 PMC_L1_ACCESSES = {
-    "hashsift_features": ("hashsift.hip", "49cbd2d03e6da357", 11332771),
+    "hashsift_features": ("hashsift.hip", "73d50dc3bf827b93", 5975756),
     "bad_describe": ("bad.hip", "73b96b61b0287a2a", 10315006),
 }
 L1_ACCESS_PEAK_PER_S = 256 * 2.4e9
