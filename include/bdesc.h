@@ -416,7 +416,8 @@ int bd_trl_hnm_bwd(bd_context* ctx, const float* A, const float* P, int32_t n, i
 /* One image of a batch.  img is a device u8 grey image (H rows, `pitch`
  * bytes apart) that feeds the integral image and BAD, and HashSIFT unless
  * hs_img is set: then HashSIFT reads hs_img (BD_DTYPE_U8 or BD_DTYPE_F32,
- * hs_pitch bytes between rows) instead.  The image's n_kp keypoints follow
+ * hs_pitch bytes between rows; row-pair images are BD_EUNSUPPORTED here)
+ * instead.  The image's n_kp keypoints follow
  * those of the previous images in the flat keypoint array. */
 typedef struct bd_batch_image {
     const uint8_t* img;

@@ -248,6 +248,9 @@ def test_batch_validation(L):
     imgs[1].hs_img, imgs[1].hs_dtype, imgs[1].hs_pitch = p, bd.BD_DTYPE_F32, 398
     assert create() == bd.BD_EINVAL and "HashSIFT pitch" in err(L)
     imgs[1].hs_pitch = 400
+    imgs[1].hs_dtype = bd.BD_DTYPE_F32_ROWPAIR  # single-image calls only
+    assert create() == bd.BD_EUNSUPPORTED and "HashSIFT dtype" in err(L)
+    imgs[1].hs_dtype = bd.BD_DTYPE_F32
     imgs[0].W, imgs[0].H, imgs[0].pitch = 50000, 50000, 50000
     assert create() == bd.BD_EINVAL and "32-bit" in err(L)
     imgs[0].W, imgs[0].H, imgs[0].pitch = 64, 48, 64

@@ -185,6 +185,32 @@ def test_prepare_view(dev, W, H, n):
     np.testing.assert_array_equal(keys[to_np(order2)], keys[o])
 
 
+def test_prepare_view_padded_rows(dev):
+    """bd_prepare_view and the row-pair histogram on padded rows: the
+    HashSIFT image and the row-pair copy are views of wider buffers (row
+    strides 1000 and 2004 floats for a 997-pixel row); the padding of the copy
+    is never written and the features equal those of the float image."""
+    rng = np.random.default_rng(77)
+    H, W, n = 301, 997, 700
+    img = torch.from_numpy(synth.quantize_u8(synth.grey_image(rng, W, H, n_rect=10))).to(dev)
+    hs_full = torch.from_numpy(rng.random((H, 1000)).astype(np.float32)).to(dev)
+    hs = hs_full[:, :W]
+    pairs_buf = torch.full((H * 2004 + 2,), -7.0, dtype=torch.float32, device=dev)
+    pairs = pairs_buf[:H * 2004].view(H, 2004)[:, :2 * W].view(H, W, 2)
+    kps_np = synth.keypoints(rng, n, W, H, border=0.0)
+    kps = bd.keypoints_tensor(kps_np, dev)
+    ii, order, rp = bd.prepare_view(img, kps, hs, pairs=pairs)
+    assert rp.data_ptr() == pairs.data_ptr()
+    np.testing.assert_array_equal(to_np(ii), to_np(bd.build_integral(img)))
+    h = to_np(hs)
+    np.testing.assert_array_equal(to_np(rp), np.stack([h, np.concatenate([h[1:], h[-1:]], axis=0)], axis=2))
+    pad = to_np(pairs_buf[:H * 2004].view(H, 2004)[:, 2 * W:])
+    assert (pad == -7.0).all() and to_np(pairs_buf[H * 2004:]).tolist() == [-7.0, -7.0]
+    a = to_np(bd.hashsift_features(hs, kps, order=order)).view(np.uint32)
+    b = to_np(bd.hashsift_features(rp, kps, order=order)).view(np.uint32)
+    np.testing.assert_array_equal(a, b)
+
+
 def test_prepare_view_validation(dev):
     """The HashSIFT image and its row-pair output must come together, match
     the image's size and be float32 with 4- and 8-byte aligned rows."""
