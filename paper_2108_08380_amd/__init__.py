@@ -314,6 +314,8 @@ def prepare_view(img, kps, hs_img=None, out=None, order=None, pairs=None):
     if order is None:
         order = torch.empty((n,), dtype=torch.int32, device=img.device)
     hs_ptr, hs_pitch, pairs_ptr, pairs_pitch = None, 0, None, 0
+    if hs_img is None and pairs is not None:
+        raise ValueError("pairs is written from hs_img: pass both or neither")
     if hs_img is not None:
         _require(hs_img, torch.float32, 2, "hs_img")
         if tuple(hs_img.shape) != (H, W):

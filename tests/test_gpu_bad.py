@@ -223,6 +223,8 @@ def test_prepare_view_validation(dev):
     with pytest.raises(ValueError):
         bd.prepare_view(img, kps, torch.zeros((6, 5), dtype=torch.float32, device=dev),
                         pairs=torch.zeros((6, 4, 2), dtype=torch.float32, device=dev))
+    with pytest.raises(ValueError, match="both or neither"):
+        bd.prepare_view(img, kps, pairs=torch.zeros((6, 5, 2), dtype=torch.float32, device=dev))
 
 
 def test_ordered_describe_equals_unordered(ref, dev):
