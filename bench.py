@@ -138,7 +138,8 @@ class Workload:
         cur.wait_stream(self.side)
 
 
-# algorithmic work per launch of each stage's main kernel (definitions in the design doc)
+# algorithmic work per launch of each stage's main kernel: what the stage's
+# definition requires per keypoint, pixel or pair, not what the kernel executes
 def stage_work():
     px = W * H
     return {
@@ -850,8 +851,8 @@ def cpu_baseline(sample: int, runs: int = 5):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is described "
-                                   "in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the library has no "
+                                   "multi-GPU path: each GPU would describe and match its own image pairs)"}))
         sys.exit(2)
     import torch
 
