@@ -137,8 +137,8 @@ def _cell_keys(kps, W, H):
     return spread(cell(kps["x"])) | (spread(cell(kps["y"])) << 1)
 
 
-@pytest.mark.parametrize("W,H,n", [(1920, 1080, 5000), (640, 480, 1000), (37, 29, 40), (4000, 3000, 20000),
-                                   (300, 200, 1), (300, 200, 0)])
+@pytest.mark.parametrize("W,H,n", [(1920, 1080, 5000), (1920, 1080, 12000), (640, 480, 1000), (37, 29, 40),
+                                   (4000, 3000, 20000), (300, 200, 1), (300, 200, 0)])
 def test_integral_and_order_in_one_call(dev, W, H, n):
     """bd_build_integral_order: the integral image equals bd_build_integral's
     bit for bit, and the order is a permutation whose cell keys never
@@ -158,13 +158,16 @@ def test_integral_and_order_in_one_call(dev, W, H, n):
     np.testing.assert_array_equal(keys[o_fused], keys[o_sep])
 
 
-@pytest.mark.parametrize("W,H,n", [(1920, 1080, 5000), (37, 29, 40), (3, 1, 2), (1, 7, 0), (4000, 3000, 9000)])
+@pytest.mark.parametrize("W,H,n", [(1920, 1080, 5000), (1920, 1080, 12000), (37, 29, 40), (3, 1, 2), (1, 7, 0),
+                                   (300, 2048, 100), (300, 2049, 100), (4000, 3000, 9000)])
 def test_prepare_view(dev, W, H, n):
     """bd_prepare_view: the integral image equals bd_build_integral's and the
     order is bd_keypoint_order's up to ties, as for bd_build_integral_order,
     and the row-pair copy of the HashSIFT image pairs each pixel with the one
-    below it (the last row with itself), bit for bit; taller images than the
-    two-launch form takes (4000 x 3000) go through the separate launches."""
+    below it (the last row with itself), bit for bit.  More than 8192
+    keypoints take the sort's second loop inside the first launch; 2048 rows
+    is the tallest image of the two-launch form, and 2049 or more rows go
+    through the separate launches."""
     rng = np.random.default_rng(W * 3 + n)
     img = torch.from_numpy(synth.quantize_u8(synth.grey_image(rng, W, H, n_rect=20))).to(dev)
     hs = torch.from_numpy(rng.standard_normal((H, W)).astype(np.float32)).to(dev)
