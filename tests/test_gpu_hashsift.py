@@ -236,7 +236,7 @@ def row_pairs(img):
 
 
 def _row_pair_case(case):
-    rng = np.random.default_rng(hash(case) % 1000)
+    rng = np.random.default_rng(sum(case.encode()))  # stable across processes, unlike hash()
     kps = None
     if case == "workload":
         w = synth.hashsift512_pair(n_kp=3000)
@@ -247,6 +247,13 @@ def _row_pair_case(case):
         kps = np.zeros(6, dtype=synth.KEYPOINT_DTYPE)
         kps[:] = [(0, 0, 1, 0), (width - 1, 8, 0.5, 1.0), (0.5, 4, 2.0, 2.0), (width + 3.0, -2, 1.0, 3.0),
                   (-4.0, 10.5, 1.5, -2.0), (width * 0.5, 7.75, 0.25, 0.7)]
+        return img, kps
+    if case.startswith("short"):
+        height = int(case[-1])
+        img = rng.random((height, 11)).astype(np.float32)
+        kps = np.zeros(5, dtype=synth.KEYPOINT_DTYPE)
+        kps[:] = [(5.0, 0.0, 1.0, 0.3), (2.5, height - 0.5, 0.7, 1.9), (0.0, -3.0, 2.0, -1.0),
+                  (10.0, height + 2.0, 1.5, 2.8), (7.25, 0.5, 0.4, 0.0)]
         return img, kps
     if case == "border":
         H, W = 37, 53
@@ -267,11 +274,12 @@ def _row_pair_case(case):
     raise ValueError(case)
 
 
-@pytest.mark.parametrize("case", ["workload", "narrow1", "narrow2", "narrow3", "border", "far"])
+@pytest.mark.parametrize("case", ["workload", "narrow1", "narrow2", "narrow3", "short1", "short2", "border", "far"])
 def test_row_pair_image_equals_float(ref, dev, case):
     """An (H, W, 2) row-pair image gives the float image's features,
     responses and codes bit for bit: on the 1920 x 1080 workload, on images
-    1 to 3 pixels wide, for keypoints whose samples fall above the first row,
+    1 to 3 pixels wide, on images of 1 and 2 rows, for keypoints whose
+    samples fall above the first row,
     below the last or beside the columns, and on the fixed-point and FP64
     position paths.  The workload case is also held against the oracle."""
     img_np, kps_np = _row_pair_case(case)
